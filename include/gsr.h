@@ -1,0 +1,254 @@
+/*
+ * gsr.h -- C ABI of the MI355X (gfx950) batched Gaussian-splatting RGB-D
+ * sensor renderer.
+ *
+ * The renderer is the tile-based 3D Gaussian Splatting rasteriser that the
+ * DISCOVERSE simulator (arXiv 2507.21981) uses as its engine's renderer
+ * (Sec. III-A, "Renderer": sorting, splatting, spherical-harmonics colour and
+ * alpha blending on the GPU) to produce its RGB and depth sensors (Sec. III-C:
+ * alpha-compositing the colour and the camera-space z of the Gaussians), for
+ * scenes made of a background node plus rigidly posed object and robot nodes
+ * (Sec. III-B "Asset Formatting", Fig. 1), many environments and cameras at a
+ * time (Sec. III-E, Throughput Report).
+ *
+ * Conventions (shared by every entry point):
+ *  - All float data is IEEE FP32, C-contiguous, little endian.
+ *  - Gaussian parameters are ACTIVATED values: scales > 0, opacities in
+ *    [0, 1]; quaternions (w, x, y, z) need not be unit length (the renderer
+ *    normalises them).  SH coefficients are [n][K][3] with K = (degree+1)^2,
+ *    real SH with the Condon-Shortley phase, index l*l + (m + l); colour =
+ *    max(0, sum_k sh_k Y_k(d) + 0.5) with d the unit vector from the camera
+ *    centre to the Gaussian mean.
+ *  - Cameras map world to camera coordinates with OpenCV axes (x right,
+ *    y down, z forward); pixel (px, py) samples at (px + 0.5, py + 0.5).
+ *  - A node pose maps node-local coordinates to world coordinates.
+ *  - Outputs: rgb [n_envs][cams][H][W][3], depth [..][H][W] = sum of
+ *    alpha*T*z (camera-space z of each Gaussian mean, unnormalised; 0 where
+ *    nothing is hit), alpha [..][H][W] = 1 - final transmittance.
+ *  - Every call returns a gsr_status code; nothing throws across the ABI.
+ *    The message of the last failure is kept per context (gsr_last_error)
+ *    or, for failures before a context exists, process-wide (ctx = NULL).
+ *  - Calls taking a `stream` (a hipStream_t; NULL = the default stream) are
+ *    asynchronous on it unless a flag says otherwise.  One context per host
+ *    thread and stream; a context is not thread-safe.
+ *  - Device-side failures (pair-capacity overflow, non-finite parameters)
+ *    cannot be returned synchronously; they set the device status word read
+ *    by gsr_query_status.  Non-finite Gaussians are culled and counted.
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gsr_context gsr_context; /* workspace, configuration, saved forward state, graphs */
+typedef struct gsr_scene gsr_scene;     /* composed-scene metadata (node tables, block tables)   */
+
+typedef enum {
+    GSR_OK = 0,
+    GSR_E_INVALID = -1,     /* bad argument (null pointer, negative size, unsupported value)  */
+    GSR_E_NOMEM = -2,       /* device or host allocation failed                              */
+    GSR_E_HIP = -3,         /* a HIP runtime call failed (no device, launch failure, ...)    */
+    GSR_E_CAPACITY = -4,    /* pair capacity exceeded and automatic growth was not allowed   */
+    GSR_E_UNSUPPORTED = -5, /* valid but not supported by this build (e.g. tile shape)       */
+    GSR_E_STATE = -6        /* call order violated (e.g. backward with no saved forward)      */
+} gsr_status;
+
+/* One node's Gaussians in its node-local frame.  Device pointers, FP32. */
+typedef struct {
+    int64_t n;             /* number of Gaussians, >= 0                                  */
+    int32_t sh_degree;     /* 0..3; all nodes of a scene share one degree                */
+    int32_t reserved;
+    const float* means;    /* [n][3]                                                     */
+    const float* scales;   /* [n][3] activated (> 0)                                     */
+    const float* quats;    /* [n][4] (w, x, y, z), any non-zero length                   */
+    const float* opacities;/* [n]    activated, in [0, 1]                                */
+    const float* sh;       /* [n][K][3]                                                  */
+} gsr_gaussians;
+
+/* Gradient buffers, same layout as gsr_gaussians (device pointers).  Each
+   pointer may be NULL to skip that parameter. */
+typedef struct {
+    float* means;
+    float* scales;
+    float* quats;
+    float* opacities;
+    float* sh;
+} gsr_gaussian_grads;
+
+/* Rigid pose of a node, node-local -> world: x_world = R x_local + t.
+   R row-major.  48 bytes. */
+typedef struct {
+    float R[9];
+    float t[3];
+} gsr_pose;
+
+/* Pinhole camera.  80 bytes. */
+typedef struct {
+    float R[9];    /* world -> camera rotation, row-major                         */
+    float t[3];    /* world -> camera translation: x_cam = R x_world + t          */
+    float fx, fy;  /* focal lengths in pixels                                     */
+    float cx, cy;  /* principal point in pixels                                   */
+    float znear;   /* Gaussians with camera-space z <= znear are culled (> 0)     */
+    float bg[3];   /* background colour composited behind the Gaussians           */
+} gsr_camera;
+
+/* Render flags. */
+enum {
+    GSR_FLAG_CHECK = 1u << 0,        /* synchronise the stream at the end of the call, read the
+                                        status word, and on pair-capacity overflow grow the
+                                        workspace and render again (at most twice).  Without it
+                                        the call never synchronises; the caller checks
+                                        gsr_query_status and re-renders on overflow.       */
+    GSR_FLAG_SAVE = 1u << 1,         /* keep what gsr_render_backward needs (per-pixel final
+                                        transmittance and contributor count, the sorted pairs and
+                                        projected records).  Valid until the next render.    */
+    GSR_FLAG_GRAPH = 1u << 2,        /* capture the launch sequence in a hipGraph on first use and
+                                        replay it on later calls with the same arguments
+                                        (pointers, sizes, flags); implies no synchronisation.
+                                        Capacity must already suffice (overflow is reported). */
+    GSR_FLAG_PERSISTENT = 1u << 3    /* composite with a persistent grid pulling (image, tile)
+                                        work items, longest list first, from a device queue    */
+};
+
+/* Status word contents (gsr_query_status). */
+enum {
+    GSR_STATUS_OVERFLOW = 1u << 0    /* more tile-Gaussian pairs than the workspace holds     */
+};
+
+typedef struct {
+    uint32_t flags;          /* GSR_STATUS_* bits of the last render                          */
+    uint32_t nonfinite;      /* Gaussians culled for non-finite parameters (summed over cams) */
+    uint64_t pairs;          /* tile-Gaussian pairs the last render produced                  */
+    uint64_t pair_capacity;  /* pairs the workspace holds now                                 */
+    uint32_t max_tile_pairs; /* longest per-tile list of the last render                      */
+    uint32_t reserved;
+} gsr_status_info;
+
+/* Configuration.  Tile shape must be one of 16x16, 16x8, 8x8, 32x8 (width x
+   height).  Unset (zero) fields take defaults. */
+typedef struct {
+    int32_t tile_w, tile_h;   /* default 16 x 16                                             */
+    int64_t pair_capacity;    /* initial pair capacity, default 1 << 22                       */
+    int32_t persistent_grid;  /* blocks of the persistent composite, default 8 per CU         */
+    int32_t reserved[7];
+} gsr_config;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device` (cfg may be NULL).  Allocates only
+   small host state; workspace grows on first render.  Errors: GSR_E_HIP (no
+   such device / runtime failure), GSR_E_UNSUPPORTED (tile shape),
+   GSR_E_INVALID (out == NULL). */
+int gsr_create(int device, const gsr_config* cfg, gsr_context** out);
+
+/* Free the context and all its device workspace (synchronises the device). */
+void gsr_destroy(gsr_context* ctx);
+
+/* Message of the last failed call on ctx (ctx = NULL: process-wide last
+   failure, e.g. from gsr_create).  Never NULL; owned by the library. */
+const char* gsr_last_error(const gsr_context* ctx);
+
+/* Current configuration, and a new tile shape (the next render uses it;
+   cached graphs are dropped). */
+int gsr_get_config(const gsr_context* ctx, gsr_config* out);
+int gsr_set_tile(gsr_context* ctx, int32_t tile_w, int32_t tile_h);
+
+/* ---- scene composition (Sec. III-B: background node + posed nodes) ----- */
+
+/* Compose `n_envs` environments.  Environment e owns nodes
+   [env_node_offsets[e], env_node_offsets[e+1]) of `nodes` (host array of
+   n_nodes descriptors whose pointers are device memory); the first node of
+   each environment is its background.  `poses` is a DEVICE array of n_nodes
+   gsr_pose, read at every render (the caller updates it in place between
+   simulation steps; background poses are normally identity).  The Gaussian
+   data and the pose buffer are borrowed, not copied: they must stay valid
+   while the scene is used.  Scene-global Gaussian ids follow the
+   concatenation env-major, node order, local index.
+   *inout: if non-NULL and the topology (env offsets, node sizes, SH degree)
+   is unchanged, it is updated without allocating; otherwise a new scene is
+   created (the old one is freed).  Synchronous.  Errors: GSR_E_INVALID
+   (null pointers, n_envs < 1, bad offsets, n < 0, sh_degree outside 0..3 or
+   differing between nodes, more than 2^31 - 1 Gaussians), GSR_E_NOMEM,
+   GSR_E_HIP. */
+int gsr_compose_scene(gsr_context* ctx, int32_t n_envs, const int32_t* env_node_offsets,
+                      const gsr_gaussians* nodes, int32_t n_nodes, const gsr_pose* poses,
+                      gsr_scene** inout);
+
+/* Free a scene (NULL is a no-op). */
+void gsr_scene_destroy(gsr_scene* scene);
+
+/* Gaussian count of the scene, and of environment e. */
+int64_t gsr_scene_gaussians(const gsr_scene* scene, int32_t env);
+
+/* ---- rendering (Sec. III-A renderer, Sec. III-C RGB and depth sensors) --- */
+
+/* Render every environment of `scene` from `cams_per_env` cameras each.
+   cams: DEVICE array [n_envs * cams_per_env] of gsr_camera (env-major),
+   read on the stream.  All images share width x height (1..8192).
+   rgb (required), depth (required), alpha (nullable): DEVICE outputs laid
+   out [n_envs][cams_per_env][height][width](x3 for rgb), fully written.
+   flags: GSR_FLAG_*.  Stages, all on `stream`: node pose composition, EWA
+   projection + SH colour + per-tile pair counting, scan of tile counts, pair
+   emission into tile buckets, per-tile sort by (depth bits, Gaussian id),
+   front-to-back compositing.
+   Errors: GSR_E_INVALID (null ctx/scene/cams/rgb/depth, cams_per_env < 1,
+   bad size), GSR_E_NOMEM, GSR_E_HIP, GSR_E_CAPACITY (with GSR_FLAG_CHECK,
+   capacity still short after growing). */
+int gsr_render_rgbd(gsr_context* ctx, const gsr_scene* scene, int32_t cams_per_env,
+                    const gsr_camera* cams, int32_t width, int32_t height,
+                    float* rgb, float* depth, float* alpha, uint32_t flags, void* stream);
+
+/* Gradients of a scalar loss through the last render (which must have been
+   called with GSR_FLAG_SAVE on the same scene and not been followed by
+   another render).  d_rgb [..][H][W][3] required; d_depth, d_alpha nullable
+   (zero upstream gradient).  grads: HOST array of n_nodes gsr_gaussian_grads
+   (device pointers, node-local parameterisation: means, activated scales,
+   unnormalised quaternions, activated opacities, SH), ACCUMULATED (+=), so
+   the caller zeroes them.  The node poses are treated as constants.
+   Errors: GSR_E_INVALID, GSR_E_STATE (no saved forward), GSR_E_HIP. */
+int gsr_render_backward(gsr_context* ctx, const gsr_scene* scene, const float* d_rgb,
+                        const float* d_depth, const float* d_alpha,
+                        const gsr_gaussian_grads* grads, void* stream);
+
+/* ---- status, inspection ------------------------------------------------ */
+
+/* Synchronise the context's last stream and read the status word of the
+   last render.  Errors: GSR_E_INVALID, GSR_E_HIP. */
+int gsr_query_status(gsr_context* ctx, gsr_status_info* out);
+
+/* Copy the sorted tile-Gaussian pairs of the last render (for tests and
+   tools): keys[i] = (global tile << 32) | FP32 bit pattern of the
+   camera-space z, values[i] = scene-global Gaussian id, ordered by (key,
+   value); ranges[2*t], ranges[2*t+1] = [start, end) of global tile t, where
+   global tile = image * tiles_per_image + ty * tiles_x + tx and image = env *
+   cams_per_env + cam.  Device buffers: keys/values hold `capacity` entries,
+   ranges 2 * total tiles.  *n_pairs receives the pair count.  Synchronous.
+   Errors: GSR_E_INVALID, GSR_E_CAPACITY (capacity < pair count), GSR_E_STATE,
+   GSR_E_HIP. */
+int gsr_copy_pairs(gsr_context* ctx, uint64_t* keys, uint32_t* values, uint32_t* ranges,
+                   int64_t capacity, int64_t* n_pairs);
+
+/* Per-pixel saved forward state of the last render (device outputs, each
+   [images][H][W]): final transmittance and the number of list entries up to
+   and including the last blended one.  Either may be NULL.  Synchronous. */
+int gsr_copy_pixel_state(gsr_context* ctx, float* T_final, uint32_t* n_contrib);
+
+/* ---- autotuning -------------------------------------------------------- */
+
+/* Time every supported tile shape (and the persistent composite on/off) on
+   this scene and camera set, keep the fastest in the context and return it.
+   Outputs are scratch buffers sized for the call.  Synchronous.  The choice
+   is cached per (images, width, height, Gaussian count) in the context. */
+int gsr_autotune(gsr_context* ctx, const gsr_scene* scene, int32_t cams_per_env,
+                 const gsr_camera* cams, int32_t width, int32_t height, float* rgb, float* depth,
+                 float* alpha, int32_t* tile_w, int32_t* tile_h, int32_t* persistent, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSR_H */

@@ -1,0 +1,200 @@
+"""Seeded scene, pose and camera generators (float32 numpy arrays).
+
+Conventions of the produced data (they are inputs, not renderer logic):
+
+* A Gaussian set is a dict with ``means [n,3]``, ``scales [n,3]`` (activated,
+  > 0), ``quats [n,4]`` (w, x, y, z; unit length up to rounding),
+  ``opacities [n]`` (activated, in (0, 1)) and ``sh [n, K, 3]`` with
+  K = (degree + 1)^2.
+* The degree-0 colour v ~ U(0, 1) is stored as the DC coefficient
+  (v - 0.5) / C0 with C0 = 1 / (2 sqrt(pi)) so that a renderer adding 0.5
+  after SH evaluation reproduces v.  Higher orders are raw N(0, sigma^2).
+* Cameras are world-to-camera rigid maps with OpenCV axes (x right, y down,
+  z forward), world y up, built by look-at; intrinsics from a horizontal
+  field of view with the principal point at the image centre.
+* Node poses map node-local coordinates to world coordinates.
+"""
+import math
+
+import numpy as np
+
+__all__ = [
+    "rng", "gaussians_uniform_cube", "gaussians_room", "gaussians_object",
+    "random_rotation", "object_poses", "look_at", "camera", "ring_cameras",
+    "scene_config", "CONFIG_NAMES",
+]
+
+C0 = 0.5 / math.sqrt(math.pi)
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _finish(g, n, means, log_scale_mu, log_scale_sigma, sh_degree, hi_sigma):
+    """Draw everything after the means, in the fixed order."""
+    K = (sh_degree + 1) ** 2
+    scales = np.exp(g.normal(log_scale_mu, log_scale_sigma, size=(n, 3))).astype(np.float32)
+    q = g.standard_normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    logits = g.standard_normal(size=n)
+    opac = (1.0 / (1.0 + np.exp(-logits))).astype(np.float32)
+    dc = g.uniform(0.0, 1.0, size=(n, 3))
+    sh = np.zeros((n, K, 3), dtype=np.float32)
+    sh[:, 0, :] = (dc - 0.5) / C0
+    if K > 1:
+        sh[:, 1:, :] = g.normal(0.0, hi_sigma, size=(n, K - 1, 3))
+    return dict(means=np.ascontiguousarray(means, dtype=np.float32), scales=scales,
+                quats=q.astype(np.float32), opacities=opac, sh=sh, sh_degree=sh_degree)
+
+
+def gaussians_uniform_cube(n, seed, sh_degree=0, half=1.0, log_scale=(-3.0, 0.5), hi_sigma=0.05):
+    """Means uniform in [-half, half]^3, log-scales N(mu, sigma^2) per axis."""
+    g = rng(seed)
+    means = g.uniform(-half, half, size=(n, 3))
+    return _finish(g, n, means, log_scale[0], log_scale[1], sh_degree, hi_sigma)
+
+
+def gaussians_room(n, seed, sh_degree=3, clusters=64, half=5.0, spread=0.5,
+                   log_scale=(-3.0, 0.5), hi_sigma=0.05):
+    """A room-sized background: a mixture of ``clusters`` isotropic blobs.
+
+    Cluster centres are uniform in the 10 m cube [-half, half]^3, each
+    Gaussian picks a cluster uniformly and is offset by N(0, spread^2 I),
+    clipped to the cube.
+    """
+    g = rng(seed)
+    centres = g.uniform(-half, half, size=(clusters, 3))
+    which = g.integers(0, clusters, size=n)
+    means = np.clip(centres[which] + g.normal(0.0, spread, size=(n, 3)), -half, half)
+    return _finish(g, n, means, log_scale[0], log_scale[1], sh_degree, hi_sigma)
+
+
+def gaussians_object(n, seed, sh_degree=3, radius=0.1, log_scale=(-5.5, 0.5), hi_sigma=0.05):
+    """A small object node: means uniform in a ball of ``radius`` metres."""
+    g = rng(seed)
+    d = g.standard_normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    r = radius * g.uniform(0.0, 1.0, size=(n, 1)) ** (1.0 / 3.0)
+    return _finish(g, n, d * r, log_scale[0], log_scale[1], sh_degree, hi_sigma)
+
+
+def random_rotation(g):
+    """Haar-uniform rotation: QR of a Gaussian matrix with the sign fixed."""
+    A = g.standard_normal((3, 3))
+    Q, Rq = np.linalg.qr(A)
+    Q = Q * np.sign(np.diag(Rq))[None, :]
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] = -Q[:, 0]
+    return Q
+
+
+OBJECT_ANCHORS = np.array([[x, 0.0, z] for z in (-0.15, 0.15) for x in (-0.45, -0.15, 0.15, 0.45)])
+
+
+def object_poses(count, seed, jitter=0.5):
+    """Per-step object poses: anchor + U[-jitter, jitter]^3, rotation uniform.
+
+    Returns R [count, 3, 3] and t [count, 3] (float32), node-local -> world.
+    """
+    g = rng(seed)
+    R = np.zeros((count, 3, 3))
+    t = np.zeros((count, 3))
+    for i in range(count):
+        R[i] = random_rotation(g)
+        t[i] = OBJECT_ANCHORS[i % len(OBJECT_ANCHORS)] + g.uniform(-jitter, jitter, size=3)
+    return R.astype(np.float32), t.astype(np.float32)
+
+
+def look_at(eye, target, up=(0.0, 1.0, 0.0)):
+    """World-to-camera (R, t), OpenCV axes, for a camera at ``eye``."""
+    eye = np.asarray(eye, dtype=np.float64)
+    f = np.asarray(target, dtype=np.float64) - eye
+    f /= np.linalg.norm(f)
+    r = np.cross(f, np.asarray(up, dtype=np.float64))
+    r /= np.linalg.norm(r)
+    d = np.cross(f, r)
+    R = np.stack([r, d, f])
+    t = -R @ eye
+    return R.astype(np.float32), t.astype(np.float32)
+
+
+def camera(eye, target, width, height, hfov_deg=60.0, znear=0.2, bg=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0)):
+    R, t = look_at(eye, target, up)
+    fx = (0.5 * width) / math.tan(math.radians(hfov_deg) * 0.5)
+    return dict(R=R, t=t, fx=np.float32(fx), fy=np.float32(fx), cx=np.float32(0.5 * width),
+                cy=np.float32(0.5 * height), znear=np.float32(znear),
+                bg=np.asarray(bg, dtype=np.float32), width=int(width), height=int(height))
+
+
+def ring_cameras(count, radius, width, height, hfov_deg=60.0, znear=0.2):
+    cams = []
+    for k in range(count):
+        a = 2.0 * math.pi * k / count
+        eye = (radius * math.sin(a), 0.0, -radius * math.cos(a))
+        cams.append(camera(eye, (0.0, 0.0, 0.0), width, height, hfov_deg, znear))
+    return cams
+
+
+CONFIG_NAMES = {
+    0: "plain forward: 20k Gaussians SH0, one 128x128 camera, 16x16 tiles",
+    1: "single background: 1M Gaussians SH3 room, one 640x480 camera",
+    2: "composed sim step: 2M background + 8x50k posed objects SH3, 3 cameras 640x480",
+    3: "batched: 64 envs (100k-1M background + 4x20k posed objects each, SH3), 2 cameras 320x240 per env",
+    4: "differentiable: 500k Gaussians SH3, 8 ring views 640x480",
+}
+
+
+def scene_config(cfg, seed=0, scale=1.0, n_envs=None):
+    """Build a workload as ``dict(envs=[...], cams_per_env=C, width, height)``.
+
+    Each env is ``dict(nodes=[gaussian dicts], poses=[(R, t)], cams=[camera dicts])``
+    with node 0 the background (identity pose).  ``scale`` shrinks Gaussian
+    counts (for tests); ``n_envs`` overrides the env count of the batched
+    workload.
+    """
+    def cnt(n):
+        return max(1, int(round(n * scale)))
+
+    eye3 = np.eye(3, dtype=np.float32)
+    z3 = np.zeros(3, dtype=np.float32)
+    if cfg == 0:
+        bg = gaussians_uniform_cube(cnt(20000), seed, sh_degree=0)
+        cams = [camera((0, 0, -3), (0, 0, 0), 128, 128)]
+        return dict(envs=[dict(nodes=[bg], poses=[(eye3, z3)], cams=cams)], cams_per_env=1,
+                    width=128, height=128)
+    if cfg == 1:
+        bg = gaussians_room(cnt(1_000_000), seed)
+        cams = [camera((0, 0, -4.5), (0, 0, 0), 640, 480)]
+        return dict(envs=[dict(nodes=[bg], poses=[(eye3, z3)], cams=cams)], cams_per_env=1,
+                    width=640, height=480)
+    if cfg == 2:
+        bg = gaussians_room(cnt(2_000_000), seed)
+        nodes = [bg] + [gaussians_object(cnt(50_000), seed + 1 + k) for k in range(8)]
+        R, t = object_poses(8, seed + 100)
+        poses = [(eye3, z3)] + [(R[k], t[k]) for k in range(8)]
+        cams = [camera((0, 0.6, -1.0), (0, 0, 0), 640, 480, znear=0.05),
+                camera((0.3, 0.3, -0.4), (0.1, 0, 0), 640, 480, znear=0.05),
+                camera((-0.3, 0.3, -0.4), (-0.1, 0, 0), 640, 480, znear=0.05)]
+        return dict(envs=[dict(nodes=nodes, poses=poses, cams=cams)], cams_per_env=3,
+                    width=640, height=480)
+    if cfg == 3:
+        E = 64 if n_envs is None else n_envs
+        g = rng(seed)
+        sizes = np.round(np.exp(g.uniform(math.log(1e5), math.log(1e6), size=E))).astype(np.int64)
+        envs = []
+        for e in range(E):
+            bg = gaussians_room(cnt(int(sizes[e])), seed + 1000 + e)
+            objs = [gaussians_object(cnt(20_000), seed + 5000 + 4 * e + k) for k in range(4)]
+            R, t = object_poses(4, seed + 9000 + e)
+            poses = [(eye3, z3)] + [(R[k], t[k]) for k in range(4)]
+            cams = [camera((0, 0.6, -1.0), (0, 0, 0), 320, 240, znear=0.05),
+                    camera((0.3, 0.3, -0.4), (0.1, 0, 0), 320, 240, znear=0.05)]
+            envs.append(dict(nodes=[bg] + objs, poses=poses, cams=cams))
+        return dict(envs=envs, cams_per_env=2, width=320, height=240)
+    if cfg == 4:
+        bg = gaussians_uniform_cube(cnt(500_000), seed, sh_degree=3)
+        cams = ring_cameras(8, 3.0, 640, 480)
+        return dict(envs=[dict(nodes=[bg], poses=[(eye3, z3)], cams=cams)], cams_per_env=8,
+                    width=640, height=480)
+    raise ValueError(f"unknown workload {cfg}")

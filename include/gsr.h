@@ -110,13 +110,17 @@ enum {
                                         replay it on later calls with the same arguments
                                         (pointers, sizes, flags); implies no synchronisation.
                                         Capacity must already suffice (overflow is reported). */
-    GSR_FLAG_PERSISTENT = 1u << 3    /* composite with a persistent grid pulling (image, tile)
+    GSR_FLAG_PERSISTENT = 1u << 3,   /* composite with a persistent grid pulling (image, tile)
                                         work items, longest list first, from a device queue    */
+    GSR_FLAG_TIMING = 1u << 4        /* record HIP events between the forward stages (eager
+                                        calls only); read them with gsr_stage_times          */
 };
 
 /* Status word contents (gsr_query_status). */
 enum {
-    GSR_STATUS_OVERFLOW = 1u << 0    /* more tile-Gaussian pairs than the workspace holds     */
+    GSR_STATUS_OVERFLOW = 1u << 0,   /* more tile-Gaussian pairs than the workspace holds     */
+    GSR_STATUS_INTERNAL = 1u << 1    /* a tile list held an id outside its environment (a
+                                        library defect; the entry was ignored)               */
 };
 
 typedef struct {
@@ -126,7 +130,16 @@ typedef struct {
     uint64_t pair_capacity;  /* pairs the workspace holds now                                 */
     uint32_t max_tile_pairs; /* longest per-tile list of the last render                      */
     uint32_t reserved;
+    uint64_t visible;        /* visible (image, Gaussian) projections                         */
+    uint64_t visible_any;    /* Gaussians visible from at least one camera of their env       */
+    uint64_t evals;          /* Gaussian-pixel evaluations: over pixels, list entries
+                                evaluated up to and including the stopping one              */
 } gsr_status_info;
+
+/* Number of timed forward stages and their names, in order: views, project,
+   tile_counts, scan, emit, classify, sort_small, sort_mid, sort_big,
+   composite. */
+#define GSR_STAGES 10
 
 /* Configuration.  Tile shape must be one of 16x16, 16x8, 8x8, 32x8 (width x
    height).  Unset (zero) fields take defaults. */
@@ -236,6 +249,11 @@ int gsr_copy_pairs(gsr_context* ctx, uint64_t* keys, uint32_t* values, uint32_t*
    [images][H][W]): final transmittance and the number of list entries up to
    and including the last blended one.  Either may be NULL.  Synchronous. */
 int gsr_copy_pixel_state(gsr_context* ctx, float* T_final, uint32_t* n_contrib);
+
+/* Per-stage durations (milliseconds, GSR_STAGES values) of the last render made
+   with GSR_FLAG_TIMING.  Synchronises the context's last stream.  Errors:
+   GSR_E_INVALID, GSR_E_STATE (no timed render), GSR_E_HIP. */
+int gsr_stage_times(gsr_context* ctx, float* ms);
 
 /* ---- autotuning -------------------------------------------------------- */
 

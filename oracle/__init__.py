@@ -30,8 +30,13 @@ _c_dbl = ctypes.c_double
 
 GEO = 16
 G2D = 10
-TAU_ALPHA = 1e-5
-TAU_T = 1e-4
+# Decision margins of the near-threshold rule (relative distance of alpha to 1/255 and of
+# T (1 - alpha) to 1e-4).  They cover the error of an FP32 renderer's alpha: pixel
+# coordinates rounded at ~4e-5 px and the conditioning of the 2D covariance inverse move the
+# exponent by up to ~1e-4, and the transmittance at the stopping point accumulates those
+# relative errors over the blended entries.
+TAU_ALPHA = 1e-4
+TAU_T = 1e-3
 
 
 def lib():
@@ -51,6 +56,9 @@ def lib():
         L.or_composite.argtypes = [_c_int, _c_int, _c_int, _c_int, _i64p, _i32p, _f64p, _f32p, _c_dbl, _c_dbl,
                                    _f64p, _f64p, _f64p, _f64p, _i32p, _i32p, _f64p, _i32p, _f64p, _i64p]
         L.or_composite.restype = None
+        L.or_composite_sample.argtypes = [_c_int, _c_int, _c_int, _c_int, _i64p, _i32p, _f64p, _f32p, _c_dbl, _c_dbl,
+                                          _i64p, ctypes.c_int64, _f64p, _i32p, _f64p]
+        L.or_composite_sample.restype = None
         L.or_backward_2d.argtypes = [_c_int, _c_int, _c_int, _c_int, _i64p, _i32p, _f64p, _f32p, _f64p,
                                      ctypes.c_void_p, ctypes.c_void_p, _c_int, _f64p]
         L.or_backward_2d.restype = None
@@ -60,6 +68,8 @@ def lib():
         L.or_wigner.restype = _c_int
         L.or_compose_view.argtypes = [_f32p, _f32p, _f32p, _f32p, _f32p]
         L.or_compose_view.restype = None
+        L.or_num_threads.argtypes = []
+        L.or_num_threads.restype = _c_int
         _lib = L
     return _lib
 
@@ -180,6 +190,20 @@ def composite(geo, ranges, local_vals, width, height, tw, th, bg, tau_a=TAU_ALPH
     return out
 
 
+def composite_sample(geo, ranges, local_vals, width, height, tw, th, bg, pix, tau_a=TAU_ALPHA, tau_t=TAU_T):
+    """Oracle pixels at flat indices ``pix`` (py * width + px)."""
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    out = np.zeros((pix.size, 8))
+    flags = np.zeros(pix.size, np.int32)
+    alt = np.zeros((pix.size, 5))
+    lib().or_composite_sample(width, height, tw, th, np.ascontiguousarray(ranges, dtype=np.int64),
+                              np.ascontiguousarray(local_vals, dtype=np.int32), np.ascontiguousarray(geo),
+                              np.asarray(bg, np.float32), tau_a, tau_t, pix, pix.size, out.reshape(-1), flags,
+                              alt.reshape(-1))
+    return dict(rgb=out[:, 0:3], depth=out[:, 3], alpha=out[:, 4], T=out[:, 5], last=out[:, 6].astype(np.int64),
+                evals=out[:, 7].astype(np.int64), flags=flags, alt=alt)
+
+
 def render(env, cam, width, height, tw=16, th=16, fe=None, image=0, gid_base=0, tau_a=TAU_ALPHA, tau_t=TAU_T):
     """Full oracle frame for one camera of one environment."""
     fe = fe or FlatEnv(env)
@@ -228,6 +252,10 @@ def backward(ref, cam, width, height, g_rgb, g_depth=None, g_alpha=None, tw=16, 
     grads["sh"] = grads["sh"].reshape(fe.n, fe.K, 3)
     grads["g2d"] = g2d
     return grads
+
+
+def num_threads():
+    return int(lib().or_num_threads())
 
 
 def sh_eval(L, v, grad=False):

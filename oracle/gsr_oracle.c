@@ -42,6 +42,7 @@
  * central finite differences of the analytic gradient.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -621,6 +622,38 @@ void or_composite(int width, int height, int tw, int th, const int64_t* ranges, 
     }
 }
 
+/* The same per-pixel definition at a list of pixels (pix[i] = py * width + px); out[i*8] =
+   r g b depth alpha T last evals, flags[i], alt[i*5]. */
+void or_composite_sample(int width, int height, int tw, int th, const int64_t* ranges, const int32_t* vals,
+                         const double* geo, const float* bgf, double tau_a, double tau_t,
+                         const int64_t* pix, int64_t npix, double* out, int32_t* flags, double* alt) {
+    const int tiles_x = (width + tw - 1) / tw;
+    const double bg[3] = {bgf[0], bgf[1], bgf[2]};
+    (void)height;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < npix; ++i) {
+        const int px = (int)(pix[i] % width), py = (int)(pix[i] / width);
+        const int t = (py / th) * tiles_x + (px / tw);
+        const int64_t s = ranges[2 * t], e = ranges[2 * t + 1];
+        pixres R;
+        composite_pixel(vals + s, e - s, geo, bg, px + 0.5, py + 0.5, -1, -1, tau_a, tau_t, &R);
+        double* o = out + 8 * i;
+        o[0] = R.rgb[0]; o[1] = R.rgb[1]; o[2] = R.rgb[2]; o[3] = R.depth; o[4] = 1.0 - R.T; o[5] = R.T;
+        o[6] = R.last; o[7] = R.evals;
+        double* a = alt + 5 * i;
+        a[0] = R.rgb[0]; a[1] = R.rgb[1]; a[2] = R.rgb[2]; a[3] = R.depth; a[4] = 1.0 - R.T;
+        int fl = 0;
+        if (R.amb_count >= 1) {
+            pixres F;
+            composite_pixel(vals + s, e - s, geo, bg, px + 0.5, py + 0.5, R.amb_j, R.amb_type, tau_a, tau_t, &F);
+            a[0] = F.rgb[0]; a[1] = F.rgb[1]; a[2] = F.rgb[2]; a[3] = F.depth; a[4] = 1.0 - F.T;
+            fl |= 1;
+            if (R.amb_count >= 2) fl |= 2;
+        }
+        flags[i] = fl;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Analytic backward, FP64.                                                  */
 /*                                                                           */
@@ -855,6 +888,9 @@ void or_backward_project(const or_scene* sc, const double* cam, int width, int h
     }
     free(nd);
 }
+
+/* Threads an OpenMP region of the oracle uses. */
+int or_num_threads(void) { return omp_get_max_threads(); }
 
 /* Flat-argument wrappers for ctypes. */
 void or_keyspec_flat(int n, int sh_degree, const float* means, const float* scales, const float* quats,

@@ -1,0 +1,597 @@
+// Host side of the renderer's C ABI: contexts, scene composition, workspace, status,
+// hipGraph capture and the autotuner.  See include/gsr.h for the contract of each call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "gsr_internal.h"
+
+using namespace gsr;
+
+namespace {
+
+std::string g_err = "no error";
+
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+struct GraphKey {
+    const gsr_scene* scene;
+    const void* cams;
+    const void* rgb;
+    const void* depth;
+    const void* alpha;
+    int C, W, H, tw, th, persistent;
+    uint32_t flags;
+    hipStream_t stream;
+    long long pair_cap;
+    bool operator==(const GraphKey& o) const {
+        return scene == o.scene && cams == o.cams && rgb == o.rgb && depth == o.depth && alpha == o.alpha &&
+               C == o.C && W == o.W && H == o.H && tw == o.tw && th == o.th && persistent == o.persistent &&
+               flags == o.flags && stream == o.stream && pair_cap == o.pair_cap;
+    }
+};
+
+}  // namespace
+
+struct gsr_scene {
+    gsr_context* ctx = nullptr;
+    int n_envs = 0, n_nodes = 0, sh_degree = 0;
+    long long total = 0;
+    std::vector<int32_t> env_offsets;
+    std::vector<Node> nodes_h;
+    std::vector<Env> envs_h;
+    std::vector<Block> blocks_h;
+    Node* nodes_d = nullptr;
+    Env* envs_d = nullptr;
+    Block* blocks_d = nullptr;
+    const gsr_pose* poses = nullptr;
+    uint64_t version = 0;
+};
+
+struct gsr_context {
+    int device = 0;
+    int num_cu = 256;
+    gsr_config cfg{};
+    std::string err = "no error";
+    Status* d_status = nullptr;
+    Status* h_status = nullptr;  // pinned
+    DevBuf<unsigned long long> pairs, pairs_alt;
+    long long pair_cap = 0;
+    DevBuf<Record> records;
+    DevBuf<uint4> rects;
+    DevBuf<int> diff;
+    DevBuf<uint32_t> counts, starts, cursor, cls_list, order, buckets;
+    DevBuf<View> views;
+    DevBuf<float> T_final;
+    DevBuf<uint32_t> n_contrib;
+    DevBuf<float> g2d;
+    DevBuf<gsr_gaussian_grads> grads_dev;
+    // last forward, for backward / inspection
+    bool have_last = false;
+    bool saved = false;
+    FwdArgs last{};
+    const gsr_scene* last_scene = nullptr;
+    uint64_t last_scene_version = 0;
+    hipStream_t last_stream = nullptr;
+    // graph cache
+    bool graph_valid = false;
+    GraphKey gkey{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    // autotune cache: (images, W, H, gaussians) -> (tw, th, persistent)
+    std::map<std::tuple<int, int, int, long long>, std::tuple<int, int, int>> tune;
+    hipEvent_t stage_ev[kStages + 1] = {};
+    bool timed = false;
+    hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
+};
+
+static int fail(gsr_context* ctx, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail((ctx), GSR_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+static void drop_graph(gsr_context* ctx);
+
+// Grow a workspace buffer.  A reallocation invalidates any captured graph (its kernel
+// arguments hold the old pointers).
+template <typename T>
+static int ensure(gsr_context* ctx, DevBuf<T>& b, size_t n, bool zero = false) {
+    if (b.n >= n && b.p) return GSR_OK;
+    drop_graph(ctx);
+    b.release();
+    size_t want = std::max<size_t>(n, 1);
+    if (hipMalloc(&b.p, want * sizeof(T)) != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, GSR_E_NOMEM, "device allocation of %zu bytes failed", want * sizeof(T));
+    }
+    b.n = want;
+    if (zero && hipMemset(b.p, 0, want * sizeof(T)) != hipSuccess) return fail(ctx, GSR_E_HIP, "hipMemset failed");
+    return GSR_OK;
+}
+
+static void drop_graph(gsr_context* ctx) {
+    if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph) hipGraphDestroy(ctx->graph);
+    ctx->gexec = nullptr;
+    ctx->graph = nullptr;
+    ctx->graph_valid = false;
+}
+
+static bool tile_ok(int tw, int th) {
+    return (tw == 16 && th == 16) || (tw == 16 && th == 8) || (tw == 8 && th == 8) || (tw == 32 && th == 8);
+}
+
+extern "C" {
+
+int gsr_create(int device, const gsr_config* cfg, gsr_context** out) {
+    if (!out) return fail(nullptr, GSR_E_INVALID, "gsr_create: out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return fail(nullptr, GSR_E_HIP, "gsr_create: no HIP device available (%s)", hipGetErrorString(e));
+    }
+    if (device < 0 || device >= n) return fail(nullptr, GSR_E_HIP, "gsr_create: device %d out of range (%d devices)", device, n);
+    gsr_config c{};
+    if (cfg) c = *cfg;
+    if (c.tile_w == 0 && c.tile_h == 0) { c.tile_w = 16; c.tile_h = 16; }
+    if (!tile_ok(c.tile_w, c.tile_h)) return fail(nullptr, GSR_E_UNSUPPORTED, "gsr_create: tile %dx%d not supported", c.tile_w, c.tile_h);
+    if (c.pair_capacity <= 0) c.pair_capacity = 1ll << 22;
+    if (hipSetDevice(device) != hipSuccess) return fail(nullptr, GSR_E_HIP, "gsr_create: hipSetDevice(%d) failed", device);
+    gsr_context* ctx = new gsr_context();
+    ctx->device = device;
+    hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device);
+    if (c.persistent_grid <= 0) c.persistent_grid = 8 * std::max(ctx->num_cu, 1);
+    ctx->cfg = c;
+    if (hipMalloc(&ctx->d_status, sizeof(Status)) != hipSuccess ||
+        hipHostMalloc(&ctx->h_status, sizeof(Status)) != hipSuccess) {
+        delete ctx;
+        return fail(nullptr, GSR_E_NOMEM, "gsr_create: status allocation failed");
+    }
+    hipMemset(ctx->d_status, 0, sizeof(Status));
+    memset(ctx->h_status, 0, sizeof(Status));
+    *out = ctx;
+    return GSR_OK;
+}
+
+void gsr_destroy(gsr_context* ctx) {
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    drop_graph(ctx);
+    for (auto& e : ctx->stage_ev)
+        if (e) hipEventDestroy(e);
+    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+    ctx->pairs.release(); ctx->pairs_alt.release(); ctx->records.release(); ctx->rects.release();
+    ctx->diff.release(); ctx->counts.release(); ctx->starts.release(); ctx->cursor.release();
+    ctx->cls_list.release(); ctx->order.release(); ctx->buckets.release(); ctx->views.release(); ctx->T_final.release(); ctx->n_contrib.release();
+    ctx->g2d.release(); ctx->grads_dev.release();
+    if (ctx->d_status) hipFree(ctx->d_status);
+    if (ctx->h_status) hipHostFree(ctx->h_status);
+    delete ctx;
+}
+
+const char* gsr_last_error(const gsr_context* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+int gsr_get_config(const gsr_context* ctx, gsr_config* out) {
+    if (!ctx || !out) return fail(nullptr, GSR_E_INVALID, "gsr_get_config: NULL argument");
+    *out = ctx->cfg;
+    return GSR_OK;
+}
+
+int gsr_set_tile(gsr_context* ctx, int32_t tw, int32_t th) {
+    if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_set_tile: ctx is NULL");
+    if (!tile_ok(tw, th)) return fail(ctx, GSR_E_UNSUPPORTED, "gsr_set_tile: tile %dx%d not supported", tw, th);
+    if (tw != ctx->cfg.tile_w || th != ctx->cfg.tile_h) drop_graph(ctx);
+    ctx->cfg.tile_w = tw;
+    ctx->cfg.tile_h = th;
+    return GSR_OK;
+}
+
+void gsr_scene_destroy(gsr_scene* sc) {
+    if (!sc) return;
+    if (sc->nodes_d) hipFree(sc->nodes_d);
+    if (sc->envs_d) hipFree(sc->envs_d);
+    if (sc->blocks_d) hipFree(sc->blocks_d);
+    if (sc->ctx && sc->ctx->last_scene == sc) {
+        sc->ctx->have_last = sc->ctx->saved = false;
+        sc->ctx->last_scene = nullptr;
+    }
+    if (sc->ctx && sc->ctx->graph_valid && sc->ctx->gkey.scene == sc) drop_graph(sc->ctx);
+    delete sc;
+}
+
+int64_t gsr_scene_gaussians(const gsr_scene* sc, int32_t env) {
+    if (!sc) return -1;
+    if (env < 0) return sc->total;
+    if (env >= sc->n_envs) return -1;
+    return sc->envs_h[env].n;
+}
+
+int gsr_compose_scene(gsr_context* ctx, int32_t n_envs, const int32_t* off, const gsr_gaussians* nodes,
+                      int32_t n_nodes, const gsr_pose* poses, gsr_scene** inout) {
+    if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_compose_scene: ctx is NULL");
+    if (!inout || !off || !nodes || !poses) return fail(ctx, GSR_E_INVALID, "gsr_compose_scene: NULL argument");
+    if (n_envs < 1 || n_nodes < 1) return fail(ctx, GSR_E_INVALID, "gsr_compose_scene: n_envs and n_nodes must be >= 1");
+    if (off[0] != 0 || off[n_envs] != n_nodes)
+        return fail(ctx, GSR_E_INVALID, "gsr_compose_scene: env_node_offsets must run from 0 to n_nodes");
+    for (int e = 0; e < n_envs; ++e)
+        if (off[e + 1] <= off[e]) return fail(ctx, GSR_E_INVALID, "gsr_compose_scene: env %d has no node", e);
+    const int deg = nodes[0].sh_degree;
+    long long total = 0;
+    for (int k = 0; k < n_nodes; ++k) {
+        const gsr_gaussians& g = nodes[k];
+        if (g.n < 0) return fail(ctx, GSR_E_INVALID, "gsr_compose_scene: node %d has n < 0", k);
+        if (g.sh_degree < 0 || g.sh_degree > 3) return fail(ctx, GSR_E_INVALID, "gsr_compose_scene: node %d sh_degree %d outside 0..3", k, g.sh_degree);
+        if (g.sh_degree != deg) return fail(ctx, GSR_E_INVALID, "gsr_compose_scene: nodes differ in sh_degree");
+        if (g.n > 0 && (!g.means || !g.scales || !g.quats || !g.opacities || !g.sh))
+            return fail(ctx, GSR_E_INVALID, "gsr_compose_scene: node %d has a NULL parameter pointer", k);
+        if (g.n > 0 && ((uintptr_t)g.quats % 16 != 0 || (uintptr_t)g.sh % 16 != 0))
+            return fail(ctx, GSR_E_INVALID, "gsr_compose_scene: node %d quats/sh not 16-byte aligned", k);
+        total += g.n;
+    }
+    if (total > 0x7fffffffll) return fail(ctx, GSR_E_INVALID, "gsr_compose_scene: more than 2^31-1 Gaussians");
+    gsr_scene* sc = *inout;
+    bool same = sc && sc->ctx == ctx && sc->n_envs == n_envs && sc->n_nodes == n_nodes && sc->sh_degree == deg &&
+                std::equal(off, off + n_envs + 1, sc->env_offsets.begin());
+    if (same)
+        for (int k = 0; k < n_nodes && same; ++k) same = (long long)sc->nodes_h[k].n == nodes[k].n;
+    if (!same) {
+        gsr_scene_destroy(sc);
+        *inout = nullptr;
+        sc = new gsr_scene();
+        sc->ctx = ctx;
+    }
+    hipSetDevice(ctx->device);
+    sc->n_envs = n_envs;
+    sc->n_nodes = n_nodes;
+    sc->sh_degree = deg;
+    sc->total = total;
+    sc->env_offsets.assign(off, off + n_envs + 1);
+    sc->poses = poses;
+    sc->nodes_h.resize(n_nodes);
+    sc->envs_h.resize(n_envs);
+    sc->blocks_h.clear();
+    uint32_t gid = 0;
+    for (int e = 0; e < n_envs; ++e) {
+        Env& ev = sc->envs_h[e];
+        ev.gid_base = gid;
+        ev.node_begin = off[e];
+        ev.node_end = off[e + 1];
+        for (int k = off[e]; k < off[e + 1]; ++k) {
+            Node& nd = sc->nodes_h[k];
+            nd.means = nodes[k].means; nd.scales = nodes[k].scales; nd.quats = nodes[k].quats;
+            nd.opac = nodes[k].opacities; nd.sh = nodes[k].sh;
+            nd.gid_base = gid;
+            nd.n = (uint32_t)nodes[k].n;
+            nd.env = e;
+            nd.pad = 0;
+            for (uint32_t s = 0; s < nd.n; s += kBlock)
+                sc->blocks_h.push_back(Block{k, e, gid + s, std::min<uint32_t>(kBlock, nd.n - s)});
+            gid += nd.n;
+        }
+        ev.n = gid - ev.gid_base;
+    }
+    auto up = [&](auto*& dptr, const auto& vec) -> int {
+        using T = typename std::remove_reference<decltype(vec)>::type::value_type;
+        if (!same && dptr == nullptr) {
+            if (hipMalloc(&dptr, std::max<size_t>(vec.size(), 1) * sizeof(T)) != hipSuccess) {
+                dptr = nullptr;
+                return fail(ctx, GSR_E_NOMEM, "gsr_compose_scene: table allocation failed");
+            }
+        }
+        if (!vec.empty() && hipMemcpy(dptr, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(ctx, GSR_E_HIP, "gsr_compose_scene: table upload failed");
+        return GSR_OK;
+    };
+    int r;
+    if ((r = up(sc->nodes_d, sc->nodes_h)) != GSR_OK) { if (!same) gsr_scene_destroy(sc); return r; }
+    if ((r = up(sc->envs_d, sc->envs_h)) != GSR_OK) { if (!same) gsr_scene_destroy(sc); return r; }
+    if ((r = up(sc->blocks_d, sc->blocks_h)) != GSR_OK) { if (!same) gsr_scene_destroy(sc); return r; }
+    sc->version++;
+    if (ctx->graph_valid && ctx->gkey.scene == sc) drop_graph(ctx);
+    *inout = sc;
+    return GSR_OK;
+}
+
+}  // extern "C"
+
+// Fill FwdArgs and make sure the workspace holds this render.
+static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camera* cams, int W, int H, float* rgb,
+                   float* depth, float* alpha, int persistent, FwdArgs& a) {
+    const int tw = ctx->cfg.tile_w, th = ctx->cfg.tile_h;
+    memset(&a, 0, sizeof a);
+    a.nodes = sc->nodes_d;
+    a.envs = sc->envs_d;
+    a.blocks = sc->blocks_d;
+    a.n_blocks = (int)sc->blocks_h.size();
+    a.n_nodes = sc->n_nodes;
+    a.sh_degree = sc->sh_degree;
+    a.poses = sc->poses;
+    a.cams = cams;
+    a.C = C;
+    a.images = sc->n_envs * C;
+    a.width = W;
+    a.height = H;
+    a.tw = tw;
+    a.th = th;
+    a.tiles_x = (W + tw - 1) / tw;
+    a.tiles_y = (H + th - 1) / th;
+    a.tpi = a.tiles_x * a.tiles_y;
+    a.tiles = (long long)a.images * a.tpi;
+    const int gsz = (a.tiles_x + 1) * (a.tiles_y + 1);
+    if (gsz > kLdsHistLimit)
+        return fail(ctx, GSR_E_UNSUPPORTED, "image %dx%d with %dx%d tiles exceeds %d tile-grid cells", W, H, tw, th, kLdsHistLimit);
+    if (a.tiles >= 0xffffffffll) return fail(ctx, GSR_E_UNSUPPORTED, "too many tiles");
+    const size_t nrec = (size_t)C * (size_t)sc->total;
+    const size_t npix = (size_t)a.images * W * H;
+    int r;
+    if ((r = ensure(ctx, ctx->records, nrec)) || (r = ensure(ctx, ctx->rects, nrec)) ||
+        (r = ensure(ctx, ctx->diff, (size_t)a.images * gsz, true)) || (r = ensure(ctx, ctx->counts, a.tiles)) ||
+        (r = ensure(ctx, ctx->starts, a.tiles + 1)) || (r = ensure(ctx, ctx->cursor, a.tiles)) ||
+        (r = ensure(ctx, ctx->cls_list, 3 * (size_t)a.tiles)) || (r = ensure(ctx, ctx->order, a.tiles)) ||
+        (r = ensure(ctx, ctx->buckets, 66)) ||
+        (r = ensure(ctx, ctx->views, (size_t)sc->n_nodes * C)) || (r = ensure(ctx, ctx->T_final, npix)) ||
+        (r = ensure(ctx, ctx->n_contrib, npix)))
+        return r;
+    if (ctx->pair_cap < ctx->cfg.pair_capacity) ctx->pair_cap = ctx->cfg.pair_capacity;
+    if ((r = ensure(ctx, ctx->pairs, ctx->pair_cap)) || (r = ensure(ctx, ctx->pairs_alt, ctx->pair_cap))) return r;
+    a.views = ctx->views.p;
+    a.records = ctx->records.p;
+    a.rects = ctx->rects.p;
+    a.diff = ctx->diff.p;
+    a.counts = ctx->counts.p;
+    a.starts = ctx->starts.p;
+    a.cursor = ctx->cursor.p;
+    a.cls_list = ctx->cls_list.p;
+    a.order = ctx->order.p;
+    a.buckets = ctx->buckets.p;
+    a.pairs = ctx->pairs.p;
+    a.pairs_alt = ctx->pairs_alt.p;
+    a.pair_cap = ctx->pair_cap;
+    a.status = ctx->d_status;
+    a.rgb = rgb;
+    a.depth = depth;
+    a.alpha = alpha;
+    a.T_final = ctx->T_final.p;
+    a.n_contrib = ctx->n_contrib.p;
+    a.persistent = persistent;
+    a.persistent_grid = ctx->cfg.persistent_grid;
+    return GSR_OK;
+}
+
+static int read_status(gsr_context* ctx, hipStream_t s) {
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_status, ctx->d_status, sizeof(Status), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return GSR_OK;
+}
+
+extern "C" {
+
+int gsr_render_rgbd(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_camera* cams, int32_t W, int32_t H,
+                    float* rgb, float* depth, float* alpha, uint32_t flags, void* stream) {
+    if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_render_rgbd: ctx is NULL");
+    if (!sc || !cams || !rgb || !depth) return fail(ctx, GSR_E_INVALID, "gsr_render_rgbd: NULL scene, cams, rgb or depth");
+    if (sc->ctx != ctx) return fail(ctx, GSR_E_INVALID, "gsr_render_rgbd: scene belongs to another context");
+    if (C < 1) return fail(ctx, GSR_E_INVALID, "gsr_render_rgbd: cams_per_env must be >= 1");
+    if (W < 1 || H < 1 || W > 8192 || H > 8192) return fail(ctx, GSR_E_INVALID, "gsr_render_rgbd: image size %dx%d outside 1..8192", W, H);
+    hipStream_t s = (hipStream_t)stream;
+    hipSetDevice(ctx->device);
+    const int persistent = (flags & GSR_FLAG_PERSISTENT) ? 1 : 0;
+    FwdArgs a;
+    int r = prepare(ctx, sc, C, cams, W, H, rgb, depth, alpha, persistent, a);
+    if (r) return r;
+    ctx->last_stream = s;
+    if (flags & GSR_FLAG_GRAPH) {
+        GraphKey k{sc, cams, rgb, depth, alpha, C, W, H, ctx->cfg.tile_w, ctx->cfg.tile_h, persistent,
+                   flags, s, ctx->pair_cap};
+        if (!(ctx->graph_valid && ctx->gkey == k)) {
+            drop_graph(ctx);
+            // capture on a private stream (the caller's may be the legacy default stream,
+            // which cannot be captured); capturing runs nothing, the replay goes on `s`
+            if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+            HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = launch_forward(a, ctx->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(ctx->cap_stream, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) hipGraphDestroy(g);
+                return fail(ctx, GSR_E_HIP, "graph capture failed: %s / %s", hipGetErrorString(e), hipGetErrorString(e2));
+            }
+            ctx->graph = g;
+            HIPCHK(ctx, hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
+            ctx->gkey = k;
+            ctx->graph_valid = true;
+        }
+        HIPCHK(ctx, hipGraphLaunch(ctx->gexec, s));
+    } else {
+        if (flags & GSR_FLAG_TIMING) {
+            for (auto& e : ctx->stage_ev)
+                if (!e) HIPCHK(ctx, hipEventCreate(&e));
+            a.stage_events = ctx->stage_ev;
+        }
+        ctx->timed = (flags & GSR_FLAG_TIMING) != 0;
+        for (int attempt = 0;; ++attempt) {
+            HIPCHK(ctx, launch_forward(a, s));
+            if (!(flags & GSR_FLAG_CHECK)) break;
+            if ((r = read_status(ctx, s))) return r;
+            if (!(ctx->h_status->flags & GSR_STATUS_OVERFLOW)) break;
+            if (attempt >= 2)
+                return fail(ctx, GSR_E_CAPACITY, "pair capacity %lld still short of %llu", ctx->pair_cap,
+                            (unsigned long long)ctx->h_status->pairs);
+            ctx->pair_cap = (long long)(ctx->h_status->pairs * 5 / 4) + 1024;
+            drop_graph(ctx);
+            if ((r = prepare(ctx, sc, C, cams, W, H, rgb, depth, alpha, persistent, a))) return r;
+            if (flags & GSR_FLAG_TIMING) a.stage_events = ctx->stage_ev;
+        }
+        a.stage_events = nullptr;
+    }
+    ctx->have_last = true;
+    ctx->saved = (flags & GSR_FLAG_SAVE) != 0;
+    ctx->last = a;
+    ctx->last_scene = sc;
+    ctx->last_scene_version = sc->version;
+    return GSR_OK;
+}
+
+int gsr_query_status(gsr_context* ctx, gsr_status_info* out) {
+    if (!ctx || !out) return fail(ctx, GSR_E_INVALID, "gsr_query_status: NULL argument");
+    hipSetDevice(ctx->device);
+    int r = read_status(ctx, ctx->last_stream);
+    if (r) return r;
+    const Status& st = *ctx->h_status;
+    out->flags = st.flags;
+    out->nonfinite = st.nonfinite;
+    out->pairs = st.pairs;
+    out->pair_capacity = (uint64_t)ctx->pair_cap;
+    out->max_tile_pairs = st.max_tile;
+    out->reserved = 0;
+    out->visible = st.visible;
+    out->visible_any = st.visible_any;
+    out->evals = st.evals;
+    return GSR_OK;
+}
+
+int gsr_stage_times(gsr_context* ctx, float* ms) {
+    if (!ctx || !ms) return fail(ctx, GSR_E_INVALID, "gsr_stage_times: NULL argument");
+    if (!ctx->timed || !ctx->stage_ev[0]) return fail(ctx, GSR_E_STATE, "gsr_stage_times: last render was not timed");
+    hipSetDevice(ctx->device);
+    HIPCHK(ctx, hipEventSynchronize(ctx->stage_ev[kStages]));
+    for (int i = 0; i < kStages; ++i) HIPCHK(ctx, hipEventElapsedTime(&ms[i], ctx->stage_ev[i], ctx->stage_ev[i + 1]));
+    return GSR_OK;
+}
+
+int gsr_copy_pairs(gsr_context* ctx, uint64_t* keys, uint32_t* values, uint32_t* ranges, int64_t capacity, int64_t* n_pairs) {
+    if (!ctx || !keys || !values || !ranges || !n_pairs) return fail(ctx, GSR_E_INVALID, "gsr_copy_pairs: NULL argument");
+    if (!ctx->have_last) return fail(ctx, GSR_E_STATE, "gsr_copy_pairs: nothing rendered yet");
+    hipSetDevice(ctx->device);
+    int r = read_status(ctx, ctx->last_stream);
+    if (r) return r;
+    *n_pairs = (int64_t)ctx->h_status->pairs;
+    if (ctx->h_status->flags & GSR_STATUS_OVERFLOW) return fail(ctx, GSR_E_CAPACITY, "gsr_copy_pairs: last render overflowed");
+    if (capacity < *n_pairs) return fail(ctx, GSR_E_CAPACITY, "gsr_copy_pairs: capacity %lld < %lld pairs", (long long)capacity, (long long)*n_pairs);
+    HIPCHK(ctx, launch_copy_pairs(ctx->last, keys, values, ranges, ctx->last_stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->last_stream));
+    return GSR_OK;
+}
+
+int gsr_copy_pixel_state(gsr_context* ctx, float* T_final, uint32_t* n_contrib) {
+    if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_copy_pixel_state: ctx is NULL");
+    if (!ctx->have_last) return fail(ctx, GSR_E_STATE, "gsr_copy_pixel_state: nothing rendered yet");
+    hipSetDevice(ctx->device);
+    const size_t npix = (size_t)ctx->last.images * ctx->last.width * ctx->last.height;
+    if (T_final) HIPCHK(ctx, hipMemcpyAsync(T_final, ctx->T_final.p, npix * sizeof(float), hipMemcpyDeviceToDevice, ctx->last_stream));
+    if (n_contrib) HIPCHK(ctx, hipMemcpyAsync(n_contrib, ctx->n_contrib.p, npix * sizeof(uint32_t), hipMemcpyDeviceToDevice, ctx->last_stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->last_stream));
+    return GSR_OK;
+}
+
+int gsr_render_backward(gsr_context* ctx, const gsr_scene* sc, const float* d_rgb, const float* d_depth,
+                        const float* d_alpha, const gsr_gaussian_grads* grads, void* stream) {
+    if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_render_backward: ctx is NULL");
+    if (!sc || !d_rgb || !grads) return fail(ctx, GSR_E_INVALID, "gsr_render_backward: NULL scene, d_rgb or grads");
+    if (!ctx->have_last || !ctx->saved || ctx->last_scene != sc || ctx->last_scene_version != sc->version)
+        return fail(ctx, GSR_E_STATE, "gsr_render_backward: no saved forward for this scene");
+    hipSetDevice(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    BwdArgs b;
+    b.f = ctx->last;
+    b.d_rgb = d_rgb;
+    b.d_depth = d_depth;
+    b.d_alpha = d_alpha;
+    const size_t nrec = (size_t)b.f.C * (size_t)sc->total;
+    int r;
+    if ((r = ensure(ctx, ctx->g2d, nrec * 12)) || (r = ensure(ctx, ctx->grads_dev, (size_t)sc->n_nodes))) return r;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->grads_dev.p, grads, sizeof(gsr_gaussian_grads) * sc->n_nodes, hipMemcpyHostToDevice, s));
+    b.g2d = ctx->g2d.p;
+    b.grads_dev = ctx->grads_dev.p;
+    HIPCHK(ctx, launch_backward(b, nrec, s));
+    ctx->last_stream = s;
+    // the host array of gradient descriptors may go away after return: wait for its copy
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return GSR_OK;
+}
+
+int gsr_autotune(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_camera* cams, int32_t W, int32_t H,
+                 float* rgb, float* depth, float* alpha, int32_t* tile_w, int32_t* tile_h, int32_t* persistent,
+                 void* stream) {
+    if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_autotune: ctx is NULL");
+    if (!sc || !cams || !rgb || !depth) return fail(ctx, GSR_E_INVALID, "gsr_autotune: NULL argument");
+    hipSetDevice(ctx->device);
+    auto key = std::make_tuple(sc->n_envs * C, (int)W, (int)H, sc->total);
+    auto it = ctx->tune.find(key);
+    if (it == ctx->tune.end()) {
+        hipStream_t s = (hipStream_t)stream;
+        const int shapes[4][2] = {{16, 16}, {16, 8}, {8, 8}, {32, 8}};
+        float best = 1e30f;
+        std::tuple<int, int, int> choice{16, 16, 0};
+        hipEvent_t e0, e1;
+        HIPCHK(ctx, hipEventCreate(&e0));
+        HIPCHK(ctx, hipEventCreate(&e1));
+        for (auto& sh : shapes) {
+            for (int pers = 0; pers < 2; ++pers) {
+                int r = gsr_set_tile(ctx, sh[0], sh[1]);
+                if (r) return r;
+                const uint32_t fl = pers ? GSR_FLAG_PERSISTENT : 0u;
+                r = gsr_render_rgbd(ctx, sc, C, cams, W, H, rgb, depth, alpha, fl | GSR_FLAG_CHECK, stream);
+                if (r) return r;
+                float ms = 0.0f;
+                HIPCHK(ctx, hipEventRecord(e0, s));
+                for (int it2 = 0; it2 < 3; ++it2) {
+                    r = gsr_render_rgbd(ctx, sc, C, cams, W, H, rgb, depth, alpha, fl, stream);
+                    if (r) return r;
+                }
+                HIPCHK(ctx, hipEventRecord(e1, s));
+                HIPCHK(ctx, hipEventSynchronize(e1));
+                HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    choice = std::make_tuple(sh[0], sh[1], pers);
+                }
+            }
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        it = ctx->tune.emplace(key, choice).first;
+    }
+    int r = gsr_set_tile(ctx, std::get<0>(it->second), std::get<1>(it->second));
+    if (r) return r;
+    if (tile_w) *tile_w = std::get<0>(it->second);
+    if (tile_h) *tile_h = std::get<1>(it->second);
+    if (persistent) *persistent = std::get<2>(it->second);
+    return GSR_OK;
+}
+
+}  // extern "C"

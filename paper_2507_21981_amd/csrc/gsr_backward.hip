@@ -1,0 +1,455 @@
+// Backward path: gradients of a loss on the RGB, depth and alpha frames with respect to the
+// node-local Gaussian parameters (means, activated scales, unnormalised quaternions,
+// activated opacities, SH coefficients).  Optimising Gaussians against depth and opacity
+// terms (paper Sec. IV-B, mesh-to-Gaussian transfer) needs exactly these gradients.
+//
+//   k_zero            clear the per-(image, Gaussian) record gradients
+//   k_composite_bwd   per tile, back to front from each pixel's last blended entry; the
+//                     transmittance in front of an entry is recomputed as T / (1 - alpha)
+//                     rather than stored; per-entry gradients are summed over a wavefront
+//                     before one atomic add per record field
+//   k_project_bwd     per Gaussian, all cameras of its env: chain from the record gradients
+//                     (u, v, conic, opacity, colour, z) to the parameters, accumulated (+=)
+//
+// Compositing gradients for a blended entry i with transmittance T_i in front of it, weight
+// w_i = alpha_i T_i, and behind-sums S^C_i = sum_{j>i} c_j w_j + T_final bg, S^D_i likewise
+// with z and no background:
+//   dL/dc_i = gC w_i,  dL/dz_i = gD w_i,
+//   dL/dalpha_i = gC.(c_i T_i - S^C_i/(1 - alpha_i)) + gD (z_i T_i - S^D_i/(1 - alpha_i))
+//                 + gA T_final/(1 - alpha_i),
+// then through alpha = o G (no gradient where the 0.99 clamp is active) and
+// G = exp(-1/2 (A dx^2 + C dy^2) - B dx dy) to o, (u, v) and the conic (A, B, C).
+#include <algorithm>
+
+#include "gsr_internal.h"
+
+namespace gsr {
+
+__global__ void k_zero(float4* p, size_t n4) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW* TH) void k_composite_bwd(BwdArgs b) {
+    constexpr int NT = TW * TH;
+    const FwdArgs& a = b.f;
+    __shared__ float4 s0[NT], s1[NT], s2[NT];
+    __shared__ long long s_rec[NT];
+    __shared__ uint32_t s_max;
+    const long long t = blockIdx.x;
+    const int image = (int)(t / a.tpi);
+    const int lt = (int)(t - (long long)image * a.tpi);
+    const int ty = lt / a.tiles_x, tx = lt - ty * a.tiles_x;
+    const int px = tx * TW + (int)(threadIdx.x % TW), py = ty * TH + (int)(threadIdx.x / TW);
+    const bool inside = px < a.width && py < a.height;
+    const uint32_t start = a.starts[t];
+    const int env = image / a.C, cam = image - env * a.C;
+    const Env ev = a.envs[env];
+    const long long rec_off = (long long)a.C * ev.gid_base + (long long)cam * ev.n - (long long)ev.gid_base;
+    const size_t p = ((size_t)image * a.height + py) * a.width + px;
+    uint32_t last = 0;
+    float Tf = 1.0f, gr = 0.f, gg = 0.f, gb = 0.f, gD = 0.f, gA = 0.f, bgr = 0.f, bgg = 0.f, bgb = 0.f;
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    if (inside) {
+        last = a.n_contrib[p];
+        Tf = a.T_final[p];
+        gr = b.d_rgb[3 * p + 0];
+        gg = b.d_rgb[3 * p + 1];
+        gb = b.d_rgb[3 * p + 2];
+        gD = b.d_depth ? b.d_depth[p] : 0.0f;
+        gA = b.d_alpha ? b.d_alpha[p] : 0.0f;
+        const gsr_camera& cm = a.cams[image];
+        bgr = cm.bg[0]; bgg = cm.bg[1]; bgb = cm.bg[2];
+        if (last) atomicMax(&s_max, last);
+    }
+    __syncthreads();
+    const uint32_t maxlast = s_max;
+    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const float thr = (float)(1.0 / 255.0);
+    float T = Tf;
+    float SCr = Tf * bgr, SCg = Tf * bgg, SCb = Tf * bgb, SD = 0.0f;
+    const int lane = threadIdx.x & 63;
+    for (uint32_t hi = maxlast; hi > 0;) {
+        const uint32_t lo = hi > (uint32_t)NT ? hi - NT : 0u;
+        const uint32_t cnt = hi - lo;
+        if (threadIdx.x < cnt) {
+            const uint32_t e = hi - 1 - threadIdx.x;  // descending
+            const uint32_t gid = (uint32_t)a.pairs[start + e];
+            long long rec = -1;
+            Record R;
+            if (gid - ev.gid_base < ev.n) {
+                rec = rec_off + gid;
+                R = a.records[rec];
+            } else {
+                R.r0 = R.r1 = R.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            s0[threadIdx.x] = R.r0;
+            s1[threadIdx.x] = R.r1;
+            s2[threadIdx.x] = R.r2;
+            s_rec[threadIdx.x] = rec;
+        }
+        __syncthreads();
+        for (uint32_t k = 0; k < cnt; ++k) {
+            const uint32_t e = hi - 1 - k;
+            const float4 r0 = s0[k];
+            const float4 r1 = s1[k];
+            float g_u = 0.f, g_v = 0.f, g_A = 0.f, g_B = 0.f, g_C = 0.f, g_o = 0.f, g_r = 0.f, g_g = 0.f,
+                  g_b = 0.f, g_z = 0.f;
+            bool contrib = false;
+            if (inside && e < last) {
+                const float dx = fpx - r0.x, dy = fpy - r0.y;
+                // identical operations to the forward pass, so the same entries are blended
+                const float A2 = -0.7213475204444817f * r1.x, B2 = -1.4426950408889634f * r1.y,
+                            C2 = -0.7213475204444817f * r1.z;
+                const float q = fmaf(A2 * dx, dx, fmaf(B2 * dx, dy, C2 * dy * dy));
+                if (q <= 0.0f) {
+                    const float G = __builtin_amdgcn_exp2f(q);
+                    const float oG = r0.z * G;
+                    const float al = fminf(0.99f, oG);
+                    if (al >= thr) {
+                        contrib = true;
+                        const float4 r2 = s2[k];
+                        const float om = 1.0f - al;
+                        const float Ti = T / om;
+                        const float w = al * Ti;
+                        g_r = gr * w;
+                        g_g = gg * w;
+                        g_b = gb * w;
+                        g_z = gD * w;
+                        const float iom = 1.0f / om;
+                        float dLda = gr * (r2.x * Ti - SCr * iom) + gg * (r2.y * Ti - SCg * iom) +
+                                     gb * (r2.z * Ti - SCb * iom);
+                        dLda += gD * (r0.w * Ti - SD * iom);
+                        dLda += gA * Tf * iom;
+                        SCr = fmaf(r2.x, w, SCr);
+                        SCg = fmaf(r2.y, w, SCg);
+                        SCb = fmaf(r2.z, w, SCb);
+                        SD = fmaf(r0.w, w, SD);
+                        T = Ti;
+                        if (oG < 0.99f) {
+                            g_o = dLda * G;
+                            const float dp = dLda * oG;  // dL/dpower, power = -1/2 A dx^2 - B dx dy - 1/2 C dy^2
+                            g_u = dp * (r1.x * dx + r1.y * dy);
+                            g_v = dp * (r1.z * dy + r1.y * dx);
+                            g_A = -0.5f * dp * dx * dx;
+                            g_B = -dp * dx * dy;
+                            g_C = -0.5f * dp * dy * dy;
+                        }
+                    }
+                }
+            }
+            // one atomic per field per wavefront and entry
+            if (__any(contrib)) {
+                g_u = wave_sum(g_u); g_v = wave_sum(g_v); g_A = wave_sum(g_A); g_B = wave_sum(g_B);
+                g_C = wave_sum(g_C); g_o = wave_sum(g_o); g_r = wave_sum(g_r); g_g = wave_sum(g_g);
+                g_b = wave_sum(g_b); g_z = wave_sum(g_z);
+                const long long rec = s_rec[k];
+                if (lane == 0 && rec >= 0) {
+                    float* o = b.g2d + (size_t)rec * 12;
+                    atomicAdd(o + 0, g_u); atomicAdd(o + 1, g_v); atomicAdd(o + 2, g_A); atomicAdd(o + 3, g_B);
+                    atomicAdd(o + 4, g_C); atomicAdd(o + 5, g_o); atomicAdd(o + 6, g_r); atomicAdd(o + 7, g_g);
+                    atomicAdd(o + 8, g_b); atomicAdd(o + 9, g_z);
+                }
+            }
+        }
+        __syncthreads();
+        hi = lo;
+    }
+}
+
+// d/d(x, y, z) of the SH basis polynomials (the forms used by the forward pass); the caller
+// projects onto the sphere's tangent plane, which removes the radial part where the
+// polynomial extensions of a basis function may differ.
+template <int L>
+__device__ inline void sh_basis_grad(float x, float y, float z, float* gx, float* gy, float* gz) {
+    gx[0] = gy[0] = gz[0] = 0.f;
+    if (L >= 1) {
+        const float c1 = 0.48860251903533936f;
+        gx[1] = 0.f; gy[1] = -c1; gz[1] = 0.f;
+        gx[2] = 0.f; gy[2] = 0.f; gz[2] = c1;
+        gx[3] = -c1; gy[3] = 0.f; gz[3] = 0.f;
+    }
+    if (L >= 2) {
+        const float a = 1.0925484895706177f, b = 0.31539157032966614f, c = 0.5462742447853088f;
+        gx[4] = a * y; gy[4] = a * x; gz[4] = 0.f;
+        gx[5] = 0.f; gy[5] = -a * z; gz[5] = -a * y;
+        gx[6] = -2.f * b * x; gy[6] = -2.f * b * y; gz[6] = 4.f * b * z;
+        gx[7] = -a * z; gy[7] = 0.f; gz[7] = -a * x;
+        gx[8] = 2.f * c * x; gy[8] = -2.f * c * y; gz[8] = 0.f;
+        if (L >= 3) {
+            const float d = 0.5900436043739319f, e = 2.890611410140991f, f = 0.4570457935333252f,
+                        g = 0.37317633628845215f, h = 1.4453057050704956f;
+            const float xx = x * x, yy = y * y, zz = z * z;
+            gx[9] = -6.f * d * x * y; gy[9] = -3.f * d * (xx - yy); gz[9] = 0.f;
+            gx[10] = e * y * z; gy[10] = e * x * z; gz[10] = e * x * y;
+            gx[11] = 2.f * f * x * y; gy[11] = -f * (4.f * zz - xx - 3.f * yy); gz[11] = -8.f * f * y * z;
+            gx[12] = -6.f * g * x * z; gy[12] = -6.f * g * y * z; gz[12] = g * (6.f * zz - 3.f * xx - 3.f * yy);
+            gx[13] = -f * (4.f * zz - 3.f * xx - yy); gy[13] = 2.f * f * x * y; gz[13] = -8.f * f * x * z;
+            gx[14] = 2.f * h * x * z; gy[14] = -2.f * h * y * z; gz[14] = h * (xx - yy);
+            gx[15] = -3.f * d * (xx - yy); gy[15] = 6.f * d * x * y; gz[15] = 0.f;
+        }
+    }
+}
+
+template <int L>
+__device__ inline void sh_basis_b(float x, float y, float z, float* Y) {
+    Y[0] = 0.282094806432724f;
+    if (L >= 1) {
+        Y[1] = -0.48860251903533936f * y;
+        Y[2] = 0.48860251903533936f * z;
+        Y[3] = -0.48860251903533936f * x;
+    }
+    if (L >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = 1.0925484895706177f * (x * y);
+        Y[5] = -1.0925484895706177f * (y * z);
+        Y[6] = 0.31539157032966614f * (2.0f * zz - xx - yy);
+        Y[7] = -1.0925484895706177f * (x * z);
+        Y[8] = 0.5462742447853088f * (xx - yy);
+        if (L >= 3) {
+            Y[9] = -0.5900436043739319f * y * (3.0f * xx - yy);
+            Y[10] = 2.890611410140991f * (x * y) * z;
+            Y[11] = -0.4570457935333252f * y * (4.0f * zz - xx - yy);
+            Y[12] = 0.37317633628845215f * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+            Y[13] = -0.4570457935333252f * x * (4.0f * zz - xx - yy);
+            Y[14] = 1.4453057050704956f * z * (xx - yy);
+            Y[15] = -0.5900436043739319f * x * (xx - 3.0f * yy);
+        }
+    }
+}
+
+template <int L>
+__global__ __launch_bounds__(kBlock) void k_project_bwd(BwdArgs b) {
+    const FwdArgs& a = b.f;
+    constexpr int K = (L + 1) * (L + 1);
+    const Block blk = a.blocks[blockIdx.x];
+    const int i = threadIdx.x;
+    if (i >= (int)blk.count) return;
+    const Node nd = a.nodes[blk.node];
+    const Env ev = a.envs[blk.env];
+    const gsr_gaussian_grads gd = b.grads_dev[blk.node];
+    const int C = a.C;
+    const uint32_t gid = blk.gid0 + i;
+    const size_t li = gid - nd.gid_base;
+    const size_t lg = gid - ev.gid_base;
+    const float mu0 = nd.means[3 * li + 0], mu1 = nd.means[3 * li + 1], mu2 = nd.means[3 * li + 2];
+    float dmu0 = 0.f, dmu1 = 0.f, dmu2 = 0.f, ds0 = 0.f, ds1 = 0.f, ds2 = 0.f, dop = 0.f;
+    float dR[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) dR[k] = 0.f;
+    float dsh[K * 3];
+#pragma unroll
+    for (int k = 0; k < K * 3; ++k) dsh[k] = 0.f;
+    bool any = false;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, qw = 0.f, qx = 0.f, qy = 0.f, qz = 0.f, rn = 0.f;
+    float R00 = 0.f, R01 = 0.f, R02 = 0.f, R10 = 0.f, R11 = 0.f, R12 = 0.f, R20 = 0.f, R21 = 0.f, R22 = 0.f;
+    for (int c = 0; c < C; ++c) {
+        const size_t rec = (size_t)C * ev.gid_base + (size_t)c * ev.n + lg;
+        const float4* g4 = reinterpret_cast<const float4*>(b.g2d + rec * 12);
+        const float4 ga = g4[0], gb4 = g4[1], gc = g4[2];
+        // ga = (du, dv, dA, dB), gb4 = (dC, do, dr, dg), gc = (db, dz, -, -)
+        if (ga.x == 0.f && ga.y == 0.f && ga.z == 0.f && ga.w == 0.f && gb4.x == 0.f && gb4.y == 0.f &&
+            gb4.z == 0.f && gb4.w == 0.f && gc.x == 0.f && gc.y == 0.f)
+            continue;
+        if (!any) {
+            any = true;
+            s0 = nd.scales[3 * li + 0]; s1 = nd.scales[3 * li + 1]; s2 = nd.scales[3 * li + 2];
+            const float4 q = reinterpret_cast<const float4*>(nd.quats)[li];
+            const float n2 = fmaf(q.x, q.x, fmaf(q.y, q.y, fmaf(q.z, q.z, q.w * q.w)));
+            rn = 1.0f / sqrtf(n2);
+            qw = q.x * rn; qx = q.y * rn; qy = q.z * rn; qz = q.w * rn;
+            const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
+            const float xy = qx * qy, xzq = qx * qz, yzq = qy * qz;
+            const float wx = qw * qx, wy = qw * qy, wz = qw * qz;
+            R00 = fmaf(-2.0f, yy + zz, 1.0f); R01 = 2.0f * (xy - wz); R02 = 2.0f * (xzq + wy);
+            R10 = 2.0f * (xy + wz); R11 = fmaf(-2.0f, xx + zz, 1.0f); R12 = 2.0f * (yzq - wx);
+            R20 = 2.0f * (xzq - wy); R21 = 2.0f * (yzq + wx); R22 = fmaf(-2.0f, xx + yy, 1.0f);
+        }
+        const View& v = a.views[blk.node * C + c];
+        // forward quantities, same operations as the projection
+        const float p0 = fmaf(v.W[0], mu0, fmaf(v.W[1], mu1, fmaf(v.W[2], mu2, v.w[0])));
+        const float p1 = fmaf(v.W[3], mu0, fmaf(v.W[4], mu1, fmaf(v.W[5], mu2, v.w[1])));
+        const float z = fmaf(v.W[6], mu0, fmaf(v.W[7], mu1, fmaf(v.W[8], mu2, v.w[2])));
+        const float iz = 1.0f / z;
+        const float xz = p0 * iz, yz = p1 * iz;
+        float G[9], M[9];
+        const float Rm[9] = {R00, R01, R02, R10, R11, R12, R20, R21, R22};
+        const float sv[3] = {s0, s1, s2};
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                G[r * 3 + cc] = fmaf(v.W[r * 3 + 0], Rm[0 * 3 + cc], fmaf(v.W[r * 3 + 1], Rm[1 * 3 + cc], v.W[r * 3 + 2] * Rm[2 * 3 + cc]));
+                M[r * 3 + cc] = G[r * 3 + cc] * sv[cc];
+            }
+        const float S00 = fmaf(M[0], M[0], fmaf(M[1], M[1], M[2] * M[2]));
+        const float S01 = fmaf(M[0], M[3], fmaf(M[1], M[4], M[2] * M[5]));
+        const float S02 = fmaf(M[0], M[6], fmaf(M[1], M[7], M[2] * M[8]));
+        const float S11 = fmaf(M[3], M[3], fmaf(M[4], M[4], M[5] * M[5]));
+        const float S12 = fmaf(M[3], M[6], fmaf(M[4], M[7], M[5] * M[8]));
+        const float S22 = fmaf(M[6], M[6], fmaf(M[7], M[7], M[8] * M[8]));
+        const bool clx = xz < -v.limx || xz > v.limx, cly = yz < -v.limy || yz > v.limy;
+        const float xc = fminf(fmaxf(xz, -v.limx), v.limx);
+        const float yc = fminf(fmaxf(yz, -v.limy), v.limy);
+        const float j00 = v.fx * iz, j11 = v.fy * iz;
+        const float j02 = -(j00 * xc), j12 = -(j11 * yc);
+        const float T00 = fmaf(j00, S00, j02 * S02), T01 = fmaf(j00, S01, j02 * S12), T02 = fmaf(j00, S02, j02 * S22);
+        const float T10 = fmaf(j11, S01, j12 * S02), T11 = fmaf(j11, S11, j12 * S12), T12 = fmaf(j11, S12, j12 * S22);
+        const float ca = fmaf(T00, j00, T02 * j02) + 0.3f;
+        const float cb = fmaf(T01, j11, T02 * j12);
+        const float cc2 = fmaf(T11, j11, T12 * j12) + 0.3f;
+        const float idet = 1.0f / fmaf(ca, cc2, -(cb * cb));
+        const float QA = cc2 * idet, QB = -cb * idet, QC = ca * idet;
+        // conic -> Sigma2D: H = -Q Gm Q with Gm = [[dA, dB/2], [dB/2, dC]]
+        const float dA = ga.z, dB = ga.w, dC = gb4.x;
+        const float m00 = QA * dA + QB * 0.5f * dB, m01 = QA * 0.5f * dB + QB * dC;
+        const float m10 = QB * dA + QC * 0.5f * dB, m11 = QB * 0.5f * dB + QC * dC;
+        const float H00 = -(m00 * QA + m01 * QB), H01 = -(m00 * QB + m01 * QC), H11 = -(m10 * QB + m11 * QC);
+        // Sigma2D = J Sigma J^T: dSigma = J^T H J, dJ = 2 H J Sigma
+        const float dS00 = j00 * j00 * H00;
+        const float dS01 = j00 * j11 * H01;
+        const float dS02 = j00 * (H00 * j02 + H01 * j12);
+        const float dS11 = j11 * j11 * H11;
+        const float dS12 = j11 * (H01 * j02 + H11 * j12);
+        const float dS22 = j02 * j02 * H00 + 2.f * j02 * j12 * H01 + j12 * j12 * H11;
+        const float dJ00 = 2.f * (H00 * T00 + H01 * T10);
+        const float dJ02 = 2.f * (H00 * T02 + H01 * T12);
+        const float dJ11 = 2.f * (H01 * T01 + H11 * T11);
+        const float dJ12 = 2.f * (H01 * T02 + H11 * T12);
+        // camera-space mean
+        const float du = ga.x, dv = ga.y, dz = gc.y;
+        float dp0 = du * v.fx * iz;
+        float dp1 = dv * v.fy * iz;
+        float dp2 = -du * v.fx * xz * iz - dv * v.fy * yz * iz + dz;
+        dp2 += -(dJ00 * v.fx + dJ11 * v.fy) * iz * iz;
+        if (!clx) { dp0 += -dJ02 * v.fx * iz * iz; dp2 += 2.f * dJ02 * v.fx * xz * iz * iz; }
+        else dp2 += dJ02 * v.fx * xc * iz * iz;
+        if (!cly) { dp1 += -dJ12 * v.fy * iz * iz; dp2 += 2.f * dJ12 * v.fy * yz * iz * iz; }
+        else dp2 += dJ12 * v.fy * yc * iz * iz;
+        // p = W mu + w
+        dmu0 += v.W[0] * dp0 + v.W[3] * dp1 + v.W[6] * dp2;
+        dmu1 += v.W[1] * dp0 + v.W[4] * dp1 + v.W[7] * dp2;
+        dmu2 += v.W[2] * dp0 + v.W[5] * dp1 + v.W[8] * dp2;
+        // Sigma = M M^T: dM = 2 dSigma M  (dSigma symmetric)
+        const float dSm[9] = {dS00, dS01, dS02, dS01, dS11, dS12, dS02, dS12, dS22};
+        float dG[9];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                const float dM = 2.f * (dSm[r * 3 + 0] * M[0 * 3 + cc] + dSm[r * 3 + 1] * M[1 * 3 + cc] + dSm[r * 3 + 2] * M[2 * 3 + cc]);
+                if (cc == 0) ds0 += dM * G[r * 3 + cc];
+                if (cc == 1) ds1 += dM * G[r * 3 + cc];
+                if (cc == 2) ds2 += dM * G[r * 3 + cc];
+                dG[r * 3 + cc] = dM * sv[cc];
+            }
+        // G = W R: dR += W^T dG
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc)
+                dR[r * 3 + cc] += v.W[0 * 3 + r] * dG[0 * 3 + cc] + v.W[1 * 3 + r] * dG[1 * 3 + cc] + v.W[2 * 3 + r] * dG[2 * 3 + cc];
+        // opacity
+        dop += gb4.y;
+        // colour: c = max(0, sum sh Y(d) + 0.5), d = mu - centre (node-local)
+        const float ddx = mu0 - v.cl[0], ddy = mu1 - v.cl[1], ddz = mu2 - v.cl[2];
+        const float len = sqrtf(ddx * ddx + ddy * ddy + ddz * ddz);
+        const float il = 1.0f / len;
+        const float x = ddx * il, y = ddy * il, zq = ddz * il;
+        float Y[K], gx[K], gy[K], gz[K];
+        sh_basis_b<L>(x, y, zq, Y);
+        const float* shp = nd.sh + li * (K * 3);
+        float pre[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) pre[ch] = fmaf(Y[k], shp[3 * k + ch], pre[ch]);
+        const float gcol[3] = {pre[0] < 0.f ? 0.f : gb4.z, pre[1] < 0.f ? 0.f : gb4.w, pre[2] < 0.f ? 0.f : gc.x};
+        if (gcol[0] != 0.f || gcol[1] != 0.f || gcol[2] != 0.f) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) dsh[3 * k + ch] = fmaf(gcol[ch], Y[k], dsh[3 * k + ch]);
+            if (L > 0) {
+                sh_basis_grad<L>(x, y, zq, gx, gy, gz);
+                float ex = 0.f, ey = 0.f, ez = 0.f;
+#pragma unroll
+                for (int k = 1; k < K; ++k) {
+                    const float wk = gcol[0] * shp[3 * k + 0] + gcol[1] * shp[3 * k + 1] + gcol[2] * shp[3 * k + 2];
+                    ex = fmaf(wk, gx[k], ex);
+                    ey = fmaf(wk, gy[k], ey);
+                    ez = fmaf(wk, gz[k], ez);
+                }
+                const float dot = ex * x + ey * y + ez * zq;
+                dmu0 += (ex - dot * x) * il;
+                dmu1 += (ey - dot * y) * il;
+                dmu2 += (ez - dot * zq) * il;
+            }
+        }
+    }
+    if (!any) return;
+    // R(q_hat) -> q_hat (w, x, y, z), then through q_hat = q / |q|
+    const float* Gq = dR;
+    float dw = 2.f * (-qz * Gq[1] + qy * Gq[2] + qz * Gq[3] - qx * Gq[5] - qy * Gq[6] + qx * Gq[7]);
+    float dx = 2.f * (qy * Gq[1] + qz * Gq[2] + qy * Gq[3] - 2.f * qx * Gq[4] - qw * Gq[5] + qz * Gq[6] + qw * Gq[7] - 2.f * qx * Gq[8]);
+    float dy = 2.f * (-2.f * qy * Gq[0] + qx * Gq[1] + qw * Gq[2] + qx * Gq[3] + qz * Gq[5] - qw * Gq[6] + qz * Gq[7] - 2.f * qy * Gq[8]);
+    float dzq = 2.f * (-2.f * qz * Gq[0] - qw * Gq[1] + qx * Gq[2] + qw * Gq[3] - 2.f * qz * Gq[4] + qy * Gq[5] + qx * Gq[6] + qy * Gq[7]);
+    const float dd = dw * qw + dx * qx + dy * qy + dzq * qz;
+    if (gd.means) {
+        gd.means[3 * li + 0] += dmu0;
+        gd.means[3 * li + 1] += dmu1;
+        gd.means[3 * li + 2] += dmu2;
+    }
+    if (gd.scales) {
+        gd.scales[3 * li + 0] += ds0;
+        gd.scales[3 * li + 1] += ds1;
+        gd.scales[3 * li + 2] += ds2;
+    }
+    if (gd.quats) {
+        gd.quats[4 * li + 0] += (dw - qw * dd) * rn;
+        gd.quats[4 * li + 1] += (dx - qx * dd) * rn;
+        gd.quats[4 * li + 2] += (dy - qy * dd) * rn;
+        gd.quats[4 * li + 3] += (dzq - qz * dd) * rn;
+    }
+    if (gd.opacities) gd.opacities[li] += dop;
+    if (gd.sh) {
+        float* o = gd.sh + li * (K * 3);
+#pragma unroll
+        for (int k = 0; k < K * 3; ++k) o[k] += dsh[k];
+    }
+}
+
+template <int TW, int TH>
+static void launch_cbwd(const BwdArgs& b, hipStream_t s) {
+    hipLaunchKernelGGL((k_composite_bwd<TW, TH>), dim3((unsigned)b.f.tiles), dim3(TW * TH), 0, s, b);
+}
+
+hipError_t launch_backward(const BwdArgs& b, size_t n_records, hipStream_t s) {
+    const FwdArgs& a = b.f;
+    const size_t n4 = n_records * 3;
+    if (n4) hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>((n4 + 255) / 256, 65536)), dim3(256), 0, s,
+                               reinterpret_cast<float4*>(b.g2d), n4);
+    if (a.tw == 16 && a.th == 16) launch_cbwd<16, 16>(b, s);
+    else if (a.tw == 16 && a.th == 8) launch_cbwd<16, 8>(b, s);
+    else if (a.tw == 8 && a.th == 8) launch_cbwd<8, 8>(b, s);
+    else launch_cbwd<32, 8>(b, s);
+    if (a.n_blocks > 0) {
+        switch (a.sh_degree) {
+            case 0: hipLaunchKernelGGL(k_project_bwd<0>, dim3(a.n_blocks), dim3(kBlock), 0, s, b); break;
+            case 1: hipLaunchKernelGGL(k_project_bwd<1>, dim3(a.n_blocks), dim3(kBlock), 0, s, b); break;
+            case 2: hipLaunchKernelGGL(k_project_bwd<2>, dim3(a.n_blocks), dim3(kBlock), 0, s, b); break;
+            default: hipLaunchKernelGGL(k_project_bwd<3>, dim3(a.n_blocks), dim3(kBlock), 0, s, b); break;
+        }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gsr

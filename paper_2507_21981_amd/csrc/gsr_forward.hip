@@ -1,0 +1,811 @@
+// Forward path of the gfx950 Gaussian-splatting RGB-D renderer.
+//
+// Stages (all on one stream, no host synchronisation between them):
+//   k_views        per (node, camera): camera<-node map composed in FP64, rounded once to FP32
+//                  (scene composition: background plus rigidly posed nodes, paper Sec. III-B)
+//   k_project      per Gaussian, all cameras of its env: EWA projection ("splatting"), tile
+//                  rectangle and depth key (the FP32 key specification below), SH colour
+//                  (paper Sec. III-A), projected record, per-tile pair counts via a
+//                  difference grid kept in LDS
+//   k_tile_counts  per image: 2D prefix of the difference grid -> pairs per tile
+//   k_scan         exclusive scan of per-tile counts -> per-tile [start, end) ranges
+//   k_emit         (depth bits, Gaussian id) pairs written into their tile's bucket; slots are
+//                  reserved per block with one global atomic per (block, tile)
+//   k_classify, k_sort_*   each tile's bucket sorted by (depth bits, id) in LDS; lists longer
+//                  than one LDS load are chunk-sorted then merged ("efficient sorting")
+//   k_composite    per tile, front-to-back alpha blending of colour and camera-space z
+//                  (RGB and depth sensors, paper Sec. III-C), early exit when every pixel of a
+//                  wavefront is saturated
+//
+// Compiled with -ffp-contract=off: every a*b+c below is two rounded operations unless an
+// explicit fmaf() is written, and / and sqrtf are correctly rounded.  This makes the key
+// specification in k_project reproducible bit for bit by any IEEE FP32 implementation of
+// the same operation sequence.
+#include "gsr_internal.h"
+
+namespace gsr {
+
+// --------------------------------------------------------------------------------------------
+// views
+// --------------------------------------------------------------------------------------------
+__global__ void k_views(FwdArgs a) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx == 0) {
+        Status* st = a.status;
+        st->flags = 0;
+        st->nonfinite = 0;
+        st->pairs = 0;
+        st->max_tile = 0;
+        st->cls[0] = st->cls[1] = st->cls[2] = st->cls[3] = 0;
+        st->work_head = 0;
+        st->visible = 0;
+        st->visible_any = 0;
+        st->evals = 0;
+    }
+    if (a.persistent && blockIdx.x == 0)
+        for (int i = threadIdx.x; i < 66; i += blockDim.x) a.buckets[i] = 0;
+    if (idx >= a.n_nodes * a.C) return;
+    const int k = idx / a.C, c = idx % a.C;
+    const Node nd = a.nodes[k];
+    const gsr_camera cam = a.cams[nd.env * a.C + c];
+    const gsr_pose P = a.poses[k];
+    View v;
+    double Wd[9], wd[3];
+    // W = Rc Rk and w = Rc tk + tc, each sum left to right in FP64 (products of two FP32
+    // values are exact in FP64), rounded once to FP32.
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) {
+            double s = (double)cam.R[i * 3 + 0] * (double)P.R[0 * 3 + j];
+            s = s + (double)cam.R[i * 3 + 1] * (double)P.R[1 * 3 + j];
+            s = s + (double)cam.R[i * 3 + 2] * (double)P.R[2 * 3 + j];
+            Wd[i * 3 + j] = s;
+            v.W[i * 3 + j] = (float)s;
+        }
+        double s = (double)cam.R[i * 3 + 0] * (double)P.t[0];
+        s = s + (double)cam.R[i * 3 + 1] * (double)P.t[1];
+        s = s + (double)cam.R[i * 3 + 2] * (double)P.t[2];
+        s = s + (double)cam.t[i];
+        wd[i] = s;
+        v.w[i] = (float)s;
+    }
+    // camera centre in node-local coordinates: -W^T w
+    for (int j = 0; j < 3; ++j) v.cl[j] = (float)(-((Wd[0 * 3 + j] * wd[0] + Wd[1 * 3 + j] * wd[1]) + Wd[2 * 3 + j] * wd[2]));
+    v.fx = cam.fx;
+    v.fy = cam.fy;
+    v.cx = cam.cx;
+    v.cy = cam.cy;
+    v.znear = cam.znear;
+    v.limx = 1.3f * ((0.5f * (float)a.width) / cam.fx);
+    v.limy = 1.3f * ((0.5f * (float)a.height) / cam.fy);
+    v.pad[0] = v.pad[1] = 0.0f;
+    a.views[idx] = v;
+}
+
+// --------------------------------------------------------------------------------------------
+// SH colour: real spherical harmonics (Condon-Shortley phase, z polar axis, index l*l + m + l),
+// colour = max(0, sum_k c_k Y_k(d) + 0.5), d the unit vector from the camera centre to the mean.
+// Normalisation constants written from their closed forms.
+// --------------------------------------------------------------------------------------------
+template <int L>
+__device__ inline void sh_basis(float x, float y, float z, float* Y) {
+    Y[0] = 0.282094806432724f;                              // sqrt(1/(4pi))
+    if (L >= 1) {
+        Y[1] = -0.48860251903533936f * y;                   // sqrt(3/(4pi))
+        Y[2] = 0.48860251903533936f * z;
+        Y[3] = -0.48860251903533936f * x;
+    }
+    if (L >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = 1.0925484895706177f * (x * y);               // sqrt(15/(4pi))
+        Y[5] = -1.0925484895706177f * (y * z);
+        Y[6] = 0.31539157032966614f * (2.0f * zz - xx - yy); // sqrt(5/(16pi)) (3z^2 - 1)
+        Y[7] = -1.0925484895706177f * (x * z);
+        Y[8] = 0.5462742447853088f * (xx - yy);             // sqrt(15/(16pi))
+        if (L >= 3) {
+            Y[9] = -0.5900436043739319f * y * (3.0f * xx - yy);       // sqrt(35/(32pi))
+            Y[10] = 2.890611410140991f * (x * y) * z;                 // sqrt(105/(4pi))
+            Y[11] = -0.4570457935333252f * y * (4.0f * zz - xx - yy); // sqrt(21/(32pi)) (5z^2 - 1)
+            Y[12] = 0.37317633628845215f * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);  // sqrt(7/(16pi))
+            Y[13] = -0.4570457935333252f * x * (4.0f * zz - xx - yy);
+            Y[14] = 1.4453057050704956f * z * (xx - yy);              // sqrt(105/(16pi))
+            Y[15] = -0.5900436043739319f * x * (xx - 3.0f * yy);
+        }
+    }
+}
+
+template <int L>
+__device__ inline float3 sh_colour(const float* __restrict__ sh, float dx, float dy, float dz) {
+    constexpr int K = (L + 1) * (L + 1);
+    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    float Y[K];
+    sh_basis<L>(dx * inv, dy * inv, dz * inv, Y);
+    float r = 0.5f, g = 0.5f, b = 0.5f;
+    if constexpr ((K * 3) % 4 == 0) {
+        const float4* s4 = reinterpret_cast<const float4*>(sh);
+        float c[K * 3];
+#pragma unroll
+        for (int i = 0; i < K * 3 / 4; ++i) {
+            const float4 q = s4[i];
+            c[4 * i + 0] = q.x; c[4 * i + 1] = q.y; c[4 * i + 2] = q.z; c[4 * i + 3] = q.w;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            r = fmaf(Y[k], c[3 * k + 0], r);
+            g = fmaf(Y[k], c[3 * k + 1], g);
+            b = fmaf(Y[k], c[3 * k + 2], b);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            r = fmaf(Y[k], sh[3 * k + 0], r);
+            g = fmaf(Y[k], sh[3 * k + 1], g);
+            b = fmaf(Y[k], sh[3 * k + 2], b);
+        }
+    }
+    return make_float3(fmaxf(r, 0.0f), fmaxf(g, 0.0f), fmaxf(b, 0.0f));
+}
+
+// --------------------------------------------------------------------------------------------
+// projection with the FP32 key specification
+//
+// For a Gaussian with mean mu, scales s, quaternion q = (w, x, y, z), opacity o, seen through
+// the view (W, w) of its node and camera:
+//   cull (non-finite) unless every input and p is finite; cull unless o >= (float)(1/255)
+//   p_r  = fmaf(W_r0, mu0, fmaf(W_r1, mu1, fmaf(W_r2, mu2, w_r)));  z = p_2; cull unless z > znear
+//   iz = 1/z; xz = p0*iz; yz = p1*iz; u = fmaf(fx, xz, cx); v = fmaf(fy, yz, cy)
+//   n2 = fmaf(q0,q0, fmaf(q1,q1, fmaf(q2,q2, q3*q3))); cull unless n2 > 0; rn = 1/sqrtf(n2)
+//   unit quaternion, R(q) with the diagonal as fmaf(-2, yy + zz, 1) and off-diagonals 2*(xy - wz) ...
+//   M_rc = fmaf(W_r0, R_0c, fmaf(W_r1, R_1c, W_r2*R_2c)) * s_c       (camera-frame axes, scaled)
+//   Sigma_ab = fmaf(M_a0, M_b0, fmaf(M_a1, M_b1, M_a2*M_b2))
+//   xc, yc = xz, yz clamped to +-lim (lim = 1.3 * ((0.5*width)/fx)); j00 = fx*iz, j11 = fy*iz,
+//   j02 = -(j00*xc), j12 = -(j11*yc); T0k = fmaf(j00, S0k, j02*S2k); T1k = fmaf(j11, S1k, j12*S2k)
+//   a = fmaf(T00, j00, T02*j02) + 0.3; b = fmaf(T01, j11, T02*j12); c = fmaf(T11, j11, T12*j12) + 0.3
+//   det = fmaf(a, c, -(b*b)); cull unless det > 0
+//   rx = fmaf(3.33, sqrtf(a), 1/64); ry = fmaf(3.33, sqrtf(c), 1/64)   (3.33 >= sqrt(2 ln 255))
+//   tiles [floor((u-rx)/tw), floor((u+rx)/tw)] x [floor((v-ry)/th), floor((v+ry)/th)], each
+//   bound clamped to [0, tiles] in float before conversion; cull if empty
+//   depth key = the IEEE bit pattern of z
+// The rectangle bounds the ellipse o * G >= 1/255 for any o <= 1, so tile lists hold every
+// Gaussian that can reach a pixel of the tile.
+// --------------------------------------------------------------------------------------------
+template <int L, bool LDSH>
+__global__ __launch_bounds__(kBlock) void k_project(FwdArgs a) {
+    extern __shared__ int s_hist[];
+    const Block blk = a.blocks[blockIdx.x];
+    const Node nd = a.nodes[blk.node];
+    const Env ev = a.envs[blk.env];
+    const int C = a.C;
+    const int gx = a.tiles_x + 1, gsz = gx * (a.tiles_y + 1);
+    if (LDSH) {
+        for (int i = threadIdx.x; i < C * gsz; i += kBlock) s_hist[i] = 0;
+        __syncthreads();
+    }
+    constexpr int K = (L + 1) * (L + 1);
+    const int i = threadIdx.x;
+    int n_vis = 0;
+    if (i < (int)blk.count) {
+        const uint32_t gid = blk.gid0 + i;
+        const size_t li = gid - nd.gid_base;
+        const size_t lg = gid - ev.gid_base;
+        const float mu0 = nd.means[3 * li + 0], mu1 = nd.means[3 * li + 1], mu2 = nd.means[3 * li + 2];
+        const float o = nd.opac[li];
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+        bool have_sq = false, sq_ok = false;
+        const bool base_ok = isfinite(mu0) && isfinite(mu1) && isfinite(mu2) && isfinite(o);
+        const float thr = (float)(1.0 / 255.0);
+        const float itw = 1.0f / (float)a.tw, ith = 1.0f / (float)a.th;
+        int nonfinite = 0;
+        for (int c = 0; c < C; ++c) {
+            const View& v = a.views[blk.node * C + c];
+            const size_t rec = (size_t)C * ev.gid_base + (size_t)c * ev.n + lg;
+            uint4 rect = make_uint4(0u, 0u, 0u, 0u);
+            do {
+                if (!have_sq) {
+                    s0 = nd.scales[3 * li + 0]; s1 = nd.scales[3 * li + 1]; s2 = nd.scales[3 * li + 2];
+                    const float4 q = reinterpret_cast<const float4*>(nd.quats)[li];
+                    q0 = q.x; q1 = q.y; q2 = q.z; q3 = q.w;
+                    sq_ok = isfinite(s0) && isfinite(s1) && isfinite(s2) && isfinite(q0) && isfinite(q1) &&
+                            isfinite(q2) && isfinite(q3);
+                    have_sq = true;
+                }
+                if (!(base_ok && sq_ok)) { ++nonfinite; break; }
+                if (!(o >= thr)) break;
+                const float p0 = fmaf(v.W[0], mu0, fmaf(v.W[1], mu1, fmaf(v.W[2], mu2, v.w[0])));
+                const float p1 = fmaf(v.W[3], mu0, fmaf(v.W[4], mu1, fmaf(v.W[5], mu2, v.w[1])));
+                const float p2 = fmaf(v.W[6], mu0, fmaf(v.W[7], mu1, fmaf(v.W[8], mu2, v.w[2])));
+                if (!(isfinite(p0) && isfinite(p1) && isfinite(p2))) { ++nonfinite; break; }
+                const float z = p2;
+                if (!(z > v.znear)) break;
+                const float iz = 1.0f / z;
+                const float xz = p0 * iz, yz = p1 * iz;
+                const float u = fmaf(v.fx, xz, v.cx), vv = fmaf(v.fy, yz, v.cy);
+                const float n2 = fmaf(q0, q0, fmaf(q1, q1, fmaf(q2, q2, q3 * q3)));
+                if (!(n2 > 0.0f)) break;
+                const float rn = 1.0f / sqrtf(n2);
+                const float qw = q0 * rn, qx = q1 * rn, qy = q2 * rn, qz = q3 * rn;
+                const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
+                const float xy = qx * qy, xzq = qx * qz, yzq = qy * qz;
+                const float wx = qw * qx, wy = qw * qy, wz = qw * qz;
+                const float R00 = fmaf(-2.0f, yy + zz, 1.0f), R01 = 2.0f * (xy - wz), R02 = 2.0f * (xzq + wy);
+                const float R10 = 2.0f * (xy + wz), R11 = fmaf(-2.0f, xx + zz, 1.0f), R12 = 2.0f * (yzq - wx);
+                const float R20 = 2.0f * (xzq - wy), R21 = 2.0f * (yzq + wx), R22 = fmaf(-2.0f, xx + yy, 1.0f);
+                float M[9];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    M[r * 3 + 0] = fmaf(v.W[r * 3 + 0], R00, fmaf(v.W[r * 3 + 1], R10, v.W[r * 3 + 2] * R20)) * s0;
+                    M[r * 3 + 1] = fmaf(v.W[r * 3 + 0], R01, fmaf(v.W[r * 3 + 1], R11, v.W[r * 3 + 2] * R21)) * s1;
+                    M[r * 3 + 2] = fmaf(v.W[r * 3 + 0], R02, fmaf(v.W[r * 3 + 1], R12, v.W[r * 3 + 2] * R22)) * s2;
+                }
+                const float S00 = fmaf(M[0], M[0], fmaf(M[1], M[1], M[2] * M[2]));
+                const float S01 = fmaf(M[0], M[3], fmaf(M[1], M[4], M[2] * M[5]));
+                const float S02 = fmaf(M[0], M[6], fmaf(M[1], M[7], M[2] * M[8]));
+                const float S11 = fmaf(M[3], M[3], fmaf(M[4], M[4], M[5] * M[5]));
+                const float S12 = fmaf(M[3], M[6], fmaf(M[4], M[7], M[5] * M[8]));
+                const float S22 = fmaf(M[6], M[6], fmaf(M[7], M[7], M[8] * M[8]));
+                const float xc = fminf(fmaxf(xz, -v.limx), v.limx);
+                const float yc = fminf(fmaxf(yz, -v.limy), v.limy);
+                const float j00 = v.fx * iz, j11 = v.fy * iz;
+                const float j02 = -(j00 * xc), j12 = -(j11 * yc);
+                const float T00 = fmaf(j00, S00, j02 * S02);
+                const float T01 = fmaf(j00, S01, j02 * S12);
+                const float T02 = fmaf(j00, S02, j02 * S22);
+                const float T11 = fmaf(j11, S11, j12 * S12);
+                const float T12 = fmaf(j11, S12, j12 * S22);
+                const float ca = fmaf(T00, j00, T02 * j02) + 0.3f;
+                const float cb = fmaf(T01, j11, T02 * j12);
+                const float cc = fmaf(T11, j11, T12 * j12) + 0.3f;
+                const float det = fmaf(ca, cc, -(cb * cb));
+                if (!(det > 0.0f)) break;
+                const float rx = fmaf(3.33f, sqrtf(ca), 0.015625f);
+                const float ry = fmaf(3.33f, sqrtf(cc), 0.015625f);
+                const float tx0f = fminf(fmaxf(floorf((u - rx) * itw), 0.0f), (float)a.tiles_x);
+                const float tx1f = fminf(fmaxf(floorf((u + rx) * itw) + 1.0f, 0.0f), (float)a.tiles_x);
+                const float ty0f = fminf(fmaxf(floorf((vv - ry) * ith), 0.0f), (float)a.tiles_y);
+                const float ty1f = fminf(fmaxf(floorf((vv + ry) * ith) + 1.0f, 0.0f), (float)a.tiles_y);
+                const int tx0 = (int)tx0f, tx1 = (int)tx1f, ty0 = (int)ty0f, ty1 = (int)ty1f;
+                if (tx0 >= tx1 || ty0 >= ty1) break;
+                // visible: projected record
+                const float idet = 1.0f / det;
+                const float3 col = sh_colour<L>(nd.sh + li * (K * 3), mu0 - v.cl[0], mu1 - v.cl[1], mu2 - v.cl[2]);
+                Record R;
+                R.r0 = make_float4(u, vv, o, z);
+                R.r1 = make_float4(cc * idet, -cb * idet, ca * idet, 0.0f);
+                R.r2 = make_float4(col.x, col.y, col.z, 0.0f);
+                a.records[rec] = R;
+                rect = make_uint4((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16),
+                                  __float_as_uint(z), 1u);
+                // pair counts: +1/-1 corners of the rectangle in the image's difference grid
+                int* h = LDSH ? (s_hist + c * gsz) : (a.diff + (size_t)(blk.env * C + c) * gsz);
+                atomicAdd(h + ty0 * gx + tx0, 1);
+                atomicAdd(h + ty0 * gx + tx1, -1);
+                atomicAdd(h + ty1 * gx + tx0, -1);
+                atomicAdd(h + ty1 * gx + tx1, 1);
+                ++n_vis;
+            } while (false);
+            a.rects[rec] = rect;
+        }
+        if (nonfinite) atomicAdd(&a.status->nonfinite, (uint32_t)nonfinite);
+    }
+    {
+        // per-wavefront sums of visible records, one atomic per wavefront
+        unsigned long long nv = (unsigned long long)n_vis, na = n_vis > 0 ? 1ull : 0ull;
+        for (int off = 32; off > 0; off >>= 1) {
+            nv += __shfl_xor(nv, off, 64);
+            na += __shfl_xor(na, off, 64);
+        }
+        if ((threadIdx.x & 63) == 0 && nv) {
+            atomicAdd(&a.status->visible, nv);
+            atomicAdd(&a.status->visible_any, na);
+        }
+    }
+    if (LDSH) {
+        __syncthreads();
+        int* g = a.diff + (size_t)blk.env * C * gsz;
+        for (int j = threadIdx.x; j < C * gsz; j += kBlock) {
+            const int val = s_hist[j];
+            if (val != 0) atomicAdd(g + j, val);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// per-image 2D prefix of the difference grid -> pairs per tile (the grid is cleared on read)
+// --------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_tile_counts(FwdArgs a) {
+    extern __shared__ int g[];
+    const int img = blockIdx.x;
+    const int gx = a.tiles_x + 1, gy = a.tiles_y + 1, gsz = gx * gy;
+    int* d = a.diff + (size_t)img * gsz;
+    for (int i = threadIdx.x; i < gsz; i += 256) {
+        g[i] = d[i];
+        d[i] = 0;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < gy; r += 256) {
+        int acc = 0;
+        for (int x = 0; x < gx; ++x) { acc += g[r * gx + x]; g[r * gx + x] = acc; }
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < gx; x += 256) {
+        int acc = 0;
+        for (int r = 0; r < gy; ++r) { acc += g[r * gx + x]; g[r * gx + x] = acc; }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < a.tpi; t += 256) {
+        const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
+        a.counts[(size_t)img * a.tpi + t] = (uint32_t)g[ty * gx + tx];
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// exclusive scan of per-tile counts (one block); total pairs and overflow into the status word
+// --------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_scan(FwdArgs a) {
+    __shared__ unsigned long long s[1024];
+    const long long T = a.tiles;
+    const long long per = (T + 1023) / 1024;
+    const long long b = (long long)threadIdx.x * per;
+    const long long e = (b + per < T) ? b + per : T;
+    unsigned long long sum = 0;
+    uint32_t mx = 0;
+    for (long long i = b; i < e; ++i) {
+        const uint32_t c = a.counts[i];
+        sum += c;
+        mx = c > mx ? c : mx;
+    }
+    s[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const unsigned long long v = threadIdx.x >= off ? s[threadIdx.x - off] : 0ull;
+        __syncthreads();
+        s[threadIdx.x] += v;
+        __syncthreads();
+    }
+    unsigned long long run = s[threadIdx.x] - sum;
+    for (long long i = b; i < e; ++i) {
+        const uint32_t st = run > 0xffffffffull ? 0xffffffffu : (uint32_t)run;
+        a.starts[i] = st;
+        a.cursor[i] = st;
+        run += a.counts[i];
+    }
+    if (threadIdx.x == 1023) {
+        const unsigned long long total = s[1023];
+        a.starts[T] = total > 0xffffffffull ? 0xffffffffu : (uint32_t)total;
+        a.status->pairs = total;
+        if (total > (unsigned long long)a.pair_cap) atomicOr(&a.status->flags, (uint32_t)GSR_STATUS_OVERFLOW);
+    }
+    if (mx) atomicMax(&a.status->max_tile, mx);
+}
+
+// --------------------------------------------------------------------------------------------
+// pair emission into tile buckets.  Each block enumerates its (Gaussian, tile) pairs with a
+// block-wide prefix over rectangle areas so large rectangles are shared by all threads,
+// counts pairs per tile in LDS, reserves one slot range per (block, tile) with a single
+// global atomic, then writes (z bits << 32 | id).
+// --------------------------------------------------------------------------------------------
+template <bool LDSC>
+__global__ __launch_bounds__(kBlock) void k_emit(FwdArgs a) {
+    extern __shared__ uint32_t s_cnt[];
+    __shared__ uint32_t s_off[kBlock + 1];
+    __shared__ uint32_t s_x0[kBlock], s_y0[kBlock], s_w[kBlock], s_z[kBlock];
+    const Block blk = a.blocks[blockIdx.x];
+    const Env ev = a.envs[blk.env];
+    const int c = blockIdx.y;
+    const size_t image = (size_t)blk.env * a.C + c;
+    const int i = threadIdx.x;
+    uint32_t n_i = 0;
+    if (i < (int)blk.count) {
+        const uint4 r = a.rects[(size_t)a.C * ev.gid_base + (size_t)c * ev.n + (blk.gid0 - ev.gid_base) + i];
+        const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu, y1 = r.y >> 16;
+        if (r.w != 0u && x1 > x0 && y1 > y0) n_i = (x1 - x0) * (y1 - y0);
+        s_x0[i] = x0;
+        s_y0[i] = y0;
+        s_w[i] = x1 - x0;
+        s_z[i] = r.z;
+    }
+    // block-wide exclusive scan of n_i (Hillis-Steele in LDS)
+    s_off[i + 1] = n_i;
+    if (i == 0) s_off[0] = 0;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const uint32_t v = (i + 1 > off) ? s_off[i + 1 - off] : 0u;
+        __syncthreads();
+        s_off[i + 1] += v;
+        __syncthreads();
+    }
+    const uint32_t total = s_off[kBlock];
+    if (total == 0) return;
+    const int tpi = a.tpi;
+    uint32_t* cur = a.cursor + image * tpi;
+    if (LDSC) {
+        for (int t = i; t < tpi; t += kBlock) s_cnt[t] = 0;
+        __syncthreads();
+    }
+    auto tile_of = [&](uint32_t k, uint32_t& owner) -> int {
+        int lo = 0, hi = kBlock - 1;  // first owner with s_off[owner + 1] > k
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s_off[mid + 1] > k) hi = mid; else lo = mid + 1;
+        }
+        owner = lo;
+        const uint32_t j = k - s_off[lo];
+        const uint32_t w = s_w[lo];
+        const uint32_t ty = s_y0[lo] + j / w, tx = s_x0[lo] + j % w;
+        return (int)(ty * a.tiles_x + tx);
+    };
+    if (LDSC) {
+        for (uint32_t k = i; k < total; k += kBlock) {
+            uint32_t owner;
+            atomicAdd(&s_cnt[tile_of(k, owner)], 1u);
+        }
+        __syncthreads();
+        for (int t = i; t < tpi; t += kBlock) {
+            const uint32_t n = s_cnt[t];
+            if (n) s_cnt[t] = atomicAdd(cur + t, n);
+        }
+        __syncthreads();
+    }
+    const unsigned long long cap = (unsigned long long)a.pair_cap;
+    for (uint32_t k = i; k < total; k += kBlock) {
+        uint32_t owner;
+        const int t = tile_of(k, owner);
+        const uint32_t pos = LDSC ? atomicAdd(&s_cnt[t], 1u) : atomicAdd(cur + t, 1u);
+        if ((unsigned long long)pos < cap)
+            a.pairs[pos] = ((unsigned long long)s_z[owner] << 32) | (unsigned long long)(blk.gid0 + owner);
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// per-tile sort by (z bits, id): tiles are classed by list length; each class is sorted by a
+// persistent grid pulling tiles from its list
+// --------------------------------------------------------------------------------------------
+__global__ void k_classify(FwdArgs a) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.tiles) return;
+    const uint32_t s = a.starts[t], e = a.starts[t + 1];
+    if ((unsigned long long)e > (unsigned long long)a.pair_cap) return;  // overflow: left unsorted
+    const uint32_t n = e - s;
+    int cls = -1;
+    if (n > 1) cls = n <= (uint32_t)kSortSmallCap ? 0 : (n <= (uint32_t)kSortMidCap ? 1 : 2);
+    if (cls < 0) return;
+    const uint32_t pos = atomicAdd(&a.status->cls[cls], 1u);
+    a.cls_list[(size_t)cls * a.tiles + pos] = (uint32_t)t;
+}
+
+// bitonic sort of n <= CAP unique 64-bit keys in LDS (padded with all-ones to a power of two)
+template <int NT>
+__device__ void bitonic_lds(unsigned long long* s, int n) {
+    int m = 1;
+    while (m < n) m <<= 1;
+    for (int i = n + threadIdx.x; i < m; i += NT) s[i] = ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= m; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < (m >> 1); i += NT) {
+                const int l = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+                const int r = l + j;
+                const unsigned long long x = s[l], y = s[r];
+                const bool asc = (l & k) == 0;
+                if ((x > y) == asc) {
+                    s[l] = y;
+                    s[r] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int NT, int CAP>
+__global__ __launch_bounds__(NT) void k_sort_lds(FwdArgs a, int cls) {
+    __shared__ unsigned long long s[CAP];
+    const uint32_t count = a.status->cls[cls];
+    for (uint32_t w = blockIdx.x; w < count; w += gridDim.x) {
+        const uint32_t t = a.cls_list[(size_t)cls * a.tiles + w];
+        const uint32_t st = a.starts[t], n = a.starts[t + 1] - st;
+        unsigned long long* p = a.pairs + st;
+        for (uint32_t i = threadIdx.x; i < n; i += NT) s[i] = p[i];
+        __syncthreads();
+        bitonic_lds<NT>(s, (int)n);
+        for (uint32_t i = threadIdx.x; i < n; i += NT) p[i] = s[i];
+        __syncthreads();
+    }
+}
+
+// number of keys in sorted src[0, n) that are smaller than x
+__device__ inline uint32_t lower_rank(const unsigned long long* src, uint32_t n, unsigned long long x) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (src[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// lists longer than one LDS load: sort CAP-sized chunks in LDS, then merge runs pairwise by
+// rank (keys are unique, so an element's output slot is its index in its run plus its rank in
+// the partner run), ping-ponging through the alternate pair buffer
+template <int NT, int CAP>
+__global__ __launch_bounds__(NT) void k_sort_big(FwdArgs a, int cls) {
+    __shared__ unsigned long long s[CAP];
+    const uint32_t count = a.status->cls[cls];
+    for (uint32_t w = blockIdx.x; w < count; w += gridDim.x) {
+        const uint32_t t = a.cls_list[(size_t)cls * a.tiles + w];
+        const uint32_t st = a.starts[t], n = a.starts[t + 1] - st;
+        unsigned long long* A = a.pairs + st;
+        unsigned long long* B = a.pairs_alt + st;
+        for (uint32_t c0 = 0; c0 < n; c0 += CAP) {
+            const uint32_t m = (n - c0 < (uint32_t)CAP) ? n - c0 : (uint32_t)CAP;
+            for (uint32_t i = threadIdx.x; i < m; i += NT) s[i] = A[c0 + i];
+            __syncthreads();
+            bitonic_lds<NT>(s, (int)m);
+            for (uint32_t i = threadIdx.x; i < m; i += NT) A[c0 + i] = s[i];
+            __syncthreads();
+        }
+        unsigned long long* src = A;
+        unsigned long long* dst = B;
+        for (uint32_t run = CAP; run < n; run <<= 1) {
+            for (uint32_t i = threadIdx.x; i < n; i += NT) {
+                const uint32_t rid = i / run;
+                const uint32_t base = (rid & ~1u) * run;
+                const unsigned long long x = src[i];
+                if (rid & 1u) {
+                    dst[base + (i - base - run) + lower_rank(src + base, run, x)] = x;
+                } else {
+                    const uint32_t pb = base + run;
+                    const uint32_t pn = pb >= n ? 0u : ((n - pb) < run ? (n - pb) : run);
+                    dst[base + (i - base) + lower_rank(src + pb, pn, x)] = x;
+                }
+            }
+            __syncthreads();
+            unsigned long long* tmp = src;
+            src = dst;
+            dst = tmp;
+        }
+        if (src != A) {
+            for (uint32_t i = threadIdx.x; i < n; i += NT) A[i] = src[i];
+        }
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// front-to-back compositing, one tile per block, one pixel per thread.  Records of a batch of
+// list entries are staged in LDS (conic pre-scaled so alpha = o * exp2(q(dx, dy))); a
+// wavefront whose pixels have all stopped skips the batch; the block leaves when every pixel
+// has stopped or the list ends.  Per pixel:
+//   alpha = min(0.99, o G); skip if alpha < 1/255; stop (without blending) if
+//   T (1 - alpha) < 1e-4; else C += alpha T c, D += alpha T z, T *= 1 - alpha.
+//   rgb = C + T bg, depth = D, alpha = 1 - T.
+// --------------------------------------------------------------------------------------------
+template <int TW, int TH>
+__device__ __forceinline__ void composite_tile(const FwdArgs& a, const long long t, float4* s0, float4* s1, float4* s2) {
+    constexpr int NT = TW * TH;
+    const int image = (int)(t / a.tpi);
+    const int lt = (int)(t - (long long)image * a.tpi);
+    const int ty = lt / a.tiles_x, tx = lt - ty * a.tiles_x;
+    const int px = tx * TW + (int)(threadIdx.x % TW), py = ty * TH + (int)(threadIdx.x / TW);
+    const bool inside = px < a.width && py < a.height;
+    uint32_t start = a.starts[t], end = a.starts[t + 1];
+    if ((unsigned long long)end > (unsigned long long)a.pair_cap) end = start;  // overflow
+    const int env = image / a.C, cam = image - env * a.C;
+    const Env ev = a.envs[env];
+    const long long rec_off = (long long)a.C * ev.gid_base + (long long)cam * ev.n - (long long)ev.gid_base;
+    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const float thr = (float)(1.0 / 255.0);
+    float T = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, D = 0.0f;
+    uint32_t last = 0;
+    uint32_t evals = inside ? end - start : 0u;  // entries evaluated, up to and including the stop
+    bool done = !inside;
+    for (uint32_t base = start; base < end; base += NT) {
+        if (__syncthreads_count(done) == NT) break;
+        const uint32_t j = base + threadIdx.x;
+        if (j < end) {
+            const uint32_t gid = (uint32_t)a.pairs[j];
+            Record R;
+            if (gid - ev.gid_base < ev.n) {
+                R = a.records[rec_off + gid];
+            } else {  // never produced by a consistent emission; blends nothing
+                R.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+                R.r1 = make_float4(0.f, 0.f, 0.f, 0.f);
+                R.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+                atomicOr(&a.status->flags, 2u);
+            }
+            s0[threadIdx.x] = R.r0;
+            // -1/2 log2(e) A, -log2(e) B, -1/2 log2(e) C
+            s1[threadIdx.x] = make_float4(-0.7213475204444817f * R.r1.x, -1.4426950408889634f * R.r1.y,
+                                          -0.7213475204444817f * R.r1.z, 0.0f);
+            s2[threadIdx.x] = R.r2;
+        }
+        __syncthreads();
+        const int n = (int)((end - base) < (uint32_t)NT ? (end - base) : (uint32_t)NT);
+        if (!done) {
+            for (int k = 0; k < n; ++k) {
+                const float4 r0 = s0[k];
+                const float4 r1 = s1[k];
+                const float dx = fpx - r0.x, dy = fpy - r0.y;
+                const float q = fmaf(r1.x * dx, dx, fmaf(r1.y * dx, dy, r1.z * dy * dy));
+                if (q > 0.0f) continue;
+                const float al = fminf(0.99f, r0.z * __builtin_amdgcn_exp2f(q));
+                if (al < thr) continue;
+                const float test = T * (1.0f - al);
+                if (test < 1e-4f) {
+                    done = true;
+                    evals = base - start + (uint32_t)k + 1u;
+                    break;
+                }
+                const float4 r2 = s2[k];
+                const float wgt = al * T;
+                Cr = fmaf(wgt, r2.x, Cr);
+                Cg = fmaf(wgt, r2.y, Cg);
+                Cb = fmaf(wgt, r2.z, Cb);
+                D = fmaf(wgt, r0.w, D);
+                T = test;
+                last = base - start + (uint32_t)k + 1u;
+            }
+        }
+    }
+    if (inside) {
+        const gsr_camera& cm = a.cams[image];
+        const size_t p = ((size_t)image * a.height + py) * a.width + px;
+        a.rgb[3 * p + 0] = fmaf(T, cm.bg[0], Cr);
+        a.rgb[3 * p + 1] = fmaf(T, cm.bg[1], Cg);
+        a.rgb[3 * p + 2] = fmaf(T, cm.bg[2], Cb);
+        a.depth[p] = D;
+        if (a.alpha) a.alpha[p] = 1.0f - T;
+        a.T_final[p] = T;
+        a.n_contrib[p] = last;
+    }
+    unsigned long long nev = evals;
+    for (int off = 32; off > 0; off >>= 1) nev += __shfl_xor(nev, off, 64);
+    if ((threadIdx.x & 63) == 0 && nev) atomicAdd(&a.status->evals, nev);
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW* TH) void k_composite(FwdArgs a) {
+    __shared__ float4 s0[TW * TH], s1[TW * TH], s2[TW * TH];
+    composite_tile<TW, TH>(a, (long long)blockIdx.x, s0, s1, s2);
+}
+
+// tiles bucketed by floor(log2(list length)) + 1, then scattered longest bucket first
+__global__ void k_order_count(FwdArgs a) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.tiles) return;
+    const uint32_t n = a.starts[t + 1] - a.starts[t];
+    atomicAdd(&a.buckets[n ? 32 - __clz(n) : 0], 1u);
+}
+
+__global__ void k_order_scatter(FwdArgs a) {
+    __shared__ uint32_t off[33];
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int b = 32; b >= 0; --b) {
+            off[b] = run;
+            run += a.buckets[b];
+        }
+    }
+    __syncthreads();
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.tiles) return;
+    const uint32_t n = a.starts[t + 1] - a.starts[t];
+    const int b = n ? 32 - __clz(n) : 0;
+    a.order[off[b] + atomicAdd(&a.buckets[33 + b], 1u)] = (uint32_t)t;
+}
+
+// persistent grid: each block pulls the next tile from the device queue until it drains
+template <int TW, int TH>
+__global__ __launch_bounds__(TW* TH) void k_composite_persistent(FwdArgs a) {
+    __shared__ float4 s0[TW * TH], s1[TW * TH], s2[TW * TH];
+    __shared__ uint32_t s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&a.status->work_head, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if ((long long)item >= a.tiles) break;
+        composite_tile<TW, TH>(a, (long long)a.order[item], s0, s1, s2);
+    }
+}
+
+__global__ void k_copy_pairs(FwdArgs a, uint64_t* keys, uint32_t* vals, uint32_t* ranges) {
+    const long long t = blockIdx.x;
+    const uint32_t s = a.starts[t], e = a.starts[t + 1];
+    if (threadIdx.x == 0) {
+        ranges[2 * t] = s;
+        ranges[2 * t + 1] = e;
+    }
+    for (uint32_t i = s + threadIdx.x; i < e; i += blockDim.x) {
+        const unsigned long long u = a.pairs[i];
+        keys[i] = ((unsigned long long)t << 32) | (u >> 32);
+        vals[i] = (uint32_t)u;
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// launch sequence
+// --------------------------------------------------------------------------------------------
+template <int L>
+static hipError_t launch_project(const FwdArgs& a, hipStream_t s) {
+    const int gsz = (a.tiles_x + 1) * (a.tiles_y + 1);
+    const size_t lds = (size_t)a.C * gsz * sizeof(int);
+    if (a.C * gsz <= kLdsHistLimit)
+        hipLaunchKernelGGL((k_project<L, true>), dim3(a.n_blocks), dim3(kBlock), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_project<L, false>), dim3(a.n_blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int TW, int TH>
+static void launch_composite(const FwdArgs& a, hipStream_t s) {
+    if (a.persistent) {
+        const unsigned nb = (unsigned)((a.tiles + 255) / 256);
+        hipLaunchKernelGGL(k_order_count, dim3(nb), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(256), 0, s, a);
+        const long long g = a.persistent_grid < a.tiles ? a.persistent_grid : a.tiles;
+        hipLaunchKernelGGL((k_composite_persistent<TW, TH>), dim3((unsigned)(g > 0 ? g : 1)), dim3(TW * TH), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_composite<TW, TH>), dim3((unsigned)a.tiles), dim3(TW * TH), 0, s, a);
+    }
+}
+
+static int g_num_cu = 0;
+
+hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
+    if (g_num_cu == 0) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (g_num_cu <= 0) g_num_cu = 256;
+    }
+    auto mark = [&](int i) {
+        if (a.stage_events) hipEventRecord(a.stage_events[i], s);
+    };
+    const int nv = a.n_nodes * a.C;
+    mark(0);
+    hipLaunchKernelGGL(k_views, dim3((nv + 63) / 64), dim3(64), 0, s, a);
+    mark(1);
+    if (a.n_blocks > 0) {
+        hipError_t e;
+        switch (a.sh_degree) {
+            case 0: e = launch_project<0>(a, s); break;
+            case 1: e = launch_project<1>(a, s); break;
+            case 2: e = launch_project<2>(a, s); break;
+            default: e = launch_project<3>(a, s); break;
+        }
+        if (e != hipSuccess) return e;
+    }
+    mark(2);
+    const int gsz = (a.tiles_x + 1) * (a.tiles_y + 1);
+    hipLaunchKernelGGL(k_tile_counts, dim3(a.images), dim3(256), (size_t)gsz * sizeof(int), s, a);
+    mark(3);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
+    mark(4);
+    if (a.n_blocks > 0) {
+        if (a.tpi <= kLdsHistLimit)
+            hipLaunchKernelGGL(k_emit<true>, dim3(a.n_blocks, a.C), dim3(kBlock), (size_t)a.tpi * sizeof(uint32_t), s, a);
+        else
+            hipLaunchKernelGGL(k_emit<false>, dim3(a.n_blocks, a.C), dim3(kBlock), 0, s, a);
+    }
+    mark(5);
+    hipLaunchKernelGGL(k_classify, dim3((unsigned)((a.tiles + 255) / 256)), dim3(256), 0, s, a);
+    mark(6);
+    hipLaunchKernelGGL((k_sort_lds<256, kSortSmallCap>), dim3(g_num_cu * 8), dim3(256), 0, s, a, 0);
+    mark(7);
+    hipLaunchKernelGGL((k_sort_lds<1024, kSortMidCap>), dim3(g_num_cu), dim3(1024), 0, s, a, 1);
+    mark(8);
+    hipLaunchKernelGGL((k_sort_big<1024, kSortMidCap>), dim3(g_num_cu), dim3(1024), 0, s, a, 2);
+    mark(9);
+    if (a.tw == 16 && a.th == 16) launch_composite<16, 16>(a, s);
+    else if (a.tw == 16 && a.th == 8) launch_composite<16, 8>(a, s);
+    else if (a.tw == 8 && a.th == 8) launch_composite<8, 8>(a, s);
+    else launch_composite<32, 8>(a, s);
+    mark(10);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_pairs(const FwdArgs& a, uint64_t* keys, uint32_t* values, uint32_t* ranges, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_pairs, dim3((unsigned)a.tiles), dim3(256), 0, s, a, keys, values, ranges);
+    return hipGetLastError();
+}
+
+}  // namespace gsr

@@ -1,0 +1,133 @@
+// Internal device-side tables and kernel launchers of the gfx950 renderer.
+// Shared only between the library's own translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gsr.h"
+
+namespace gsr {
+
+constexpr int kBlock = 256;          // Gaussians per projection / emission block
+constexpr int kSortSmallCap = 2048;  // per-tile lists sorted by a 256-thread block
+constexpr int kSortMidCap = 16384;   // per-tile lists sorted by a 1024-thread block in LDS
+constexpr int kLdsHistLimit = 16384; // int counters a block may keep in LDS for tile histograms
+
+// One (node, camera) view: the camera<-node map composed in FP64 and rounded
+// once to FP32, the camera centre in node-local coordinates, intrinsics and
+// the J-clamp limits.  96 bytes.
+struct View {
+    float W[9];
+    float w[3];
+    float cl[3];
+    float fx, fy, cx, cy, znear, limx, limy;
+    float pad[2];
+};
+
+struct Node {
+    const float* means;
+    const float* scales;
+    const float* quats;
+    const float* opac;
+    const float* sh;
+    uint32_t gid_base;  // scene-global id of the node's first Gaussian
+    uint32_t n;
+    int32_t env;
+    int32_t pad;
+};
+
+struct Env {
+    uint32_t gid_base;  // scene-global id of the env's first Gaussian
+    uint32_t n;         // Gaussians in the env
+    int32_t node_begin, node_end;
+};
+
+// A chunk of at most kBlock consecutive Gaussians of one node.
+struct Block {
+    int32_t node;
+    int32_t env;
+    uint32_t gid0;
+    uint32_t count;
+};
+
+struct Status {
+    uint32_t flags;
+    uint32_t nonfinite;
+    unsigned long long pairs;
+    uint32_t max_tile;
+    uint32_t cls[4];      // tile counts per sort class
+    uint32_t work_head;   // persistent composite queue head
+    unsigned long long visible;      // visible (image, Gaussian) records
+    unsigned long long visible_any;  // Gaussians visible in at least one camera
+    unsigned long long evals;        // Gaussian-pixel evaluations of the compositor
+    uint32_t pad[2];
+};
+
+constexpr int kStages = 10;  // views, project, tile counts, scan, emit, classify, 3 sorts, composite
+
+// Projected record of one (image, Gaussian): r0 = (u, v, opacity, z),
+// r1 = conic (A, B, C, 0) of the inverse dilated 2D covariance,
+// r2 = (r, g, b, 0) SH colour.  48 bytes.
+struct Record {
+    float4 r0, r1, r2;
+};
+
+struct FwdArgs {
+    // scene
+    const Node* nodes;
+    const Env* envs;
+    const Block* blocks;
+    int n_blocks;
+    int n_nodes;
+    int sh_degree;
+    const gsr_pose* poses;
+    // cameras / images
+    const gsr_camera* cams;
+    int C;          // cameras per env
+    int images;
+    int width, height;
+    int tw, th, tiles_x, tiles_y, tpi;  // tile shape, tiles per image
+    long long tiles;                     // images * tpi
+    // workspace
+    View* views;
+    Record* records;
+    uint4* rects;        // per (image, Gaussian): x0 | y0 << 16, x1 | y1 << 16, z bits, 0
+    int* diff;           // per image: (tiles_y + 1) x (tiles_x + 1) difference grid
+    uint32_t* counts;    // per tile
+    uint32_t* starts;    // per tile + 1
+    uint32_t* cursor;    // per tile
+    uint32_t* cls_list;  // 4 lists of `tiles` entries
+    uint32_t* order;     // tiles ordered by decreasing list length (persistent composite)
+    uint32_t* buckets;   // 2 x 33 counters: tiles per log2 length bucket, fill cursors
+    unsigned long long* pairs;
+    unsigned long long* pairs_alt;
+    long long pair_cap;
+    Status* status;
+    // outputs
+    float* rgb;
+    float* depth;
+    float* alpha;
+    float* T_final;
+    uint32_t* n_contrib;
+    int persistent;
+    int persistent_grid;
+    hipEvent_t* stage_events;  // kStages + 1 events recorded between stages, or null
+};
+
+struct BwdArgs {
+    FwdArgs f;
+    const float* d_rgb;
+    const float* d_depth;
+    const float* d_alpha;
+    float* g2d;          // per (image, Gaussian) record gradients, 12 floats
+    const gsr_gaussian_grads* grads_dev;  // per node, device copy
+};
+
+// forward stages
+hipError_t launch_forward(const FwdArgs& a, hipStream_t s);
+hipError_t launch_copy_pairs(const FwdArgs& a, uint64_t* keys, uint32_t* values, uint32_t* ranges, hipStream_t s);
+// backward stages
+hipError_t launch_backward(const BwdArgs& a, size_t n_records, hipStream_t s);
+
+}  // namespace gsr

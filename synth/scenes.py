@@ -15,6 +15,7 @@ Conventions of the produced data (they are inputs, not renderer logic):
 * Node poses map node-local coordinates to world coordinates.
 """
 import math
+import os
 
 import numpy as np
 
@@ -32,26 +33,29 @@ def rng(seed):
 
 
 def _finish(g, n, means, log_scale_mu, log_scale_sigma, sh_degree, hi_sigma):
-    """Draw everything after the means, in the fixed order."""
+    """Draw everything after the means, in the fixed order (float32 draws)."""
     K = (sh_degree + 1) ** 2
-    scales = np.exp(g.normal(log_scale_mu, log_scale_sigma, size=(n, 3))).astype(np.float32)
-    q = g.standard_normal(size=(n, 4))
+    f32 = np.float32
+    scales = np.exp(f32(log_scale_mu) + f32(log_scale_sigma) * g.standard_normal((n, 3), dtype=f32))
+    q = g.standard_normal((n, 4), dtype=f32)
     q /= np.linalg.norm(q, axis=1, keepdims=True)
-    logits = g.standard_normal(size=n)
-    opac = (1.0 / (1.0 + np.exp(-logits))).astype(np.float32)
-    dc = g.uniform(0.0, 1.0, size=(n, 3))
-    sh = np.zeros((n, K, 3), dtype=np.float32)
-    sh[:, 0, :] = (dc - 0.5) / C0
+    logits = g.standard_normal(n, dtype=f32)
+    opac = (1.0 / (1.0 + np.exp(-logits))).astype(f32)
+    dc = g.random((n, 3), dtype=f32)
+    sh = np.empty((n, K, 3), dtype=f32)
+    sh[:, 0, :] = (dc - f32(0.5)) * f32(1.0 / C0)
     if K > 1:
-        sh[:, 1:, :] = g.normal(0.0, hi_sigma, size=(n, K - 1, 3))
-    return dict(means=np.ascontiguousarray(means, dtype=np.float32), scales=scales,
-                quats=q.astype(np.float32), opacities=opac, sh=sh, sh_degree=sh_degree)
+        hi = g.standard_normal((n, K - 1, 3), dtype=f32)
+        hi *= f32(hi_sigma)
+        sh[:, 1:, :] = hi
+    return dict(means=np.ascontiguousarray(means, dtype=f32), scales=scales.astype(f32),
+                quats=q, opacities=opac, sh=sh, sh_degree=sh_degree)
 
 
 def gaussians_uniform_cube(n, seed, sh_degree=0, half=1.0, log_scale=(-3.0, 0.5), hi_sigma=0.05):
     """Means uniform in [-half, half]^3, log-scales N(mu, sigma^2) per axis."""
     g = rng(seed)
-    means = g.uniform(-half, half, size=(n, 3))
+    means = (g.random((n, 3), dtype=np.float32) * np.float32(2 * half) - np.float32(half))
     return _finish(g, n, means, log_scale[0], log_scale[1], sh_degree, hi_sigma)
 
 
@@ -66,16 +70,19 @@ def gaussians_room(n, seed, sh_degree=3, clusters=64, half=5.0, spread=0.5,
     g = rng(seed)
     centres = g.uniform(-half, half, size=(clusters, 3))
     which = g.integers(0, clusters, size=n)
-    means = np.clip(centres[which] + g.normal(0.0, spread, size=(n, 3)), -half, half)
+    off = g.standard_normal((n, 3), dtype=np.float32)
+    off *= np.float32(spread)
+    off += centres[which].astype(np.float32)
+    means = np.clip(off, -half, half)
     return _finish(g, n, means, log_scale[0], log_scale[1], sh_degree, hi_sigma)
 
 
 def gaussians_object(n, seed, sh_degree=3, radius=0.1, log_scale=(-5.5, 0.5), hi_sigma=0.05):
     """A small object node: means uniform in a ball of ``radius`` metres."""
     g = rng(seed)
-    d = g.standard_normal(size=(n, 3))
+    d = g.standard_normal((n, 3), dtype=np.float32)
     d /= np.linalg.norm(d, axis=1, keepdims=True)
-    r = radius * g.uniform(0.0, 1.0, size=(n, 1)) ** (1.0 / 3.0)
+    r = np.float32(radius) * g.random((n, 1), dtype=np.float32) ** np.float32(1.0 / 3.0)
     return _finish(g, n, d * r, log_scale[0], log_scale[1], sh_degree, hi_sigma)
 
 
@@ -182,15 +189,21 @@ def scene_config(cfg, seed=0, scale=1.0, n_envs=None):
         E = 64 if n_envs is None else n_envs
         g = rng(seed)
         sizes = np.round(np.exp(g.uniform(math.log(1e5), math.log(1e6), size=E))).astype(np.int64)
-        envs = []
-        for e in range(E):
+
+        def make_env(e):
             bg = gaussians_room(cnt(int(sizes[e])), seed + 1000 + e)
             objs = [gaussians_object(cnt(20_000), seed + 5000 + 4 * e + k) for k in range(4)]
             R, t = object_poses(4, seed + 9000 + e)
             poses = [(eye3, z3)] + [(R[k], t[k]) for k in range(4)]
             cams = [camera((0, 0.6, -1.0), (0, 0, 0), 320, 240, znear=0.05),
                     camera((0.3, 0.3, -0.4), (0.1, 0, 0), 320, 240, znear=0.05)]
-            envs.append(dict(nodes=[bg] + objs, poses=poses, cams=cams))
+            return dict(nodes=[bg] + objs, poses=poses, cams=cams)
+
+        # every env has its own seeds, so the result does not depend on the thread count
+        from concurrent.futures import ThreadPoolExecutor
+        workers = min(16, os.cpu_count() or 1)
+        with ThreadPoolExecutor(workers) as ex:
+            envs = list(ex.map(make_env, range(E)))
         return dict(envs=envs, cams_per_env=2, width=320, height=240)
     if cfg == 4:
         bg = gaussians_uniform_cube(cnt(500_000), seed, sh_degree=3)

@@ -1,0 +1,256 @@
+"""GPU parity of the forward path (keys, ranges, pixels) against the CPU oracle.
+
+Sort keys (tile, z bits) with Gaussian-id values and per-tile ranges must match the
+oracle's FP32 key specification bit for bit; pixels (rgb, depth, alpha) must be within 1e-4
+of the FP64 oracle, where a pixel whose blending decision sits within the oracle's margin of
+a threshold may instead match the oracle's flipped branch (paper Sec. III-A renderer,
+Sec. III-C RGB-D sensor).
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import TOL, check_keys, compare_image, log, oracle_images, render_gpu, upload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gsr():
+    import paper_2507_21981_amd as g
+    g.lib()
+    return g
+
+
+@pytest.fixture(scope="module")
+def ctx(gsr):
+    c = gsr.create(0)
+    yield c
+    c.close()
+
+
+def _run(gsr, ctx, wl, tile=(16, 16), full=True, sample=2000, depth_tol=None, flags=None):
+    import torch
+    ctx.set_tile(*tile)
+    log(f"render {wl.get('name', '')} tile {tile}")
+    scene, cams, rgb, depth, alpha = render_gpu(ctx, wl, flags=flags)
+    st = gsr.query_status(ctx)
+    assert st["flags"] == 0, st
+    W, H = wl["width"], wl["height"]
+    tw, th = tile
+    tpi = ((W + tw - 1) // tw) * ((H + th - 1) // th)
+    images = len(wl["envs"]) * wl["cams_per_env"]
+    keys, vals, ranges = gsr.copy_pairs(ctx, images * tpi)
+    log("oracle")
+    refs = oracle_images(wl, tw, th, full=full, sample=sample)
+    check_keys(refs, keys.cpu().numpy().view(np.uint64), vals.cpu().numpy().view(np.uint32),
+               ranges.cpu().numpy().view(np.uint32).reshape(-1, 2), tpi)
+    rgb_n, d_n, a_n = rgb.cpu().numpy(), depth.cpu().numpy(), alpha.cpu().numpy()
+    C = wl["cams_per_env"]
+    allst = []
+    for i, ref in enumerate(refs):
+        e, c = divmod(i, C)
+        allst.append(compare_image(ref, rgb_n[e, c], d_n[e, c], a_n[e, c], depth_tol=depth_tol))
+    log("stats", allst[0], "... images", len(allst), "pairs", st["pairs"])
+    torch.cuda.synchronize()
+    return scene, cams, rgb, depth, alpha, refs, allst
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (16, 8), (8, 8), (32, 8)])
+def test_plain_forward_20k_sh0_128(gsr, ctx, tile):
+    wl = synth.scene_config(0)
+    wl["name"] = "20k SH0 128x128"
+    _run(gsr, ctx, wl, tile)
+
+
+def test_composed_scene_three_cameras(gsr, ctx):
+    # background + 8 posed object nodes, SH degree 3, head + two wrist cameras
+    wl = synth.scene_config(2, seed=3, scale=0.03)
+    wl["name"] = "composed 60k+8x1.5k SH3 3 cams 640x480"
+    _run(gsr, ctx, wl, (16, 16))
+
+
+def test_batched_uneven_envs(gsr, ctx):
+    wl = synth.scene_config(3, seed=5, scale=0.04, n_envs=5)
+    wl["name"] = "batched 5 envs uneven"
+    _run(gsr, ctx, wl, (16, 8))
+
+
+def test_ragged_image_partial_tiles(gsr, ctx):
+    wl = synth.scene_config(0, seed=7, scale=0.5)
+    cam = synth.camera((0.2, -0.1, -3.0), (0, 0, 0), 100, 75)
+    wl["envs"][0]["cams"] = [cam]
+    wl["width"], wl["height"] = 100, 75
+    wl["name"] = "ragged 100x75"
+    for tile in [(16, 16), (32, 8)]:
+        _run(gsr, ctx, wl, tile)
+
+
+def test_empty_zero_opacity_and_behind_camera_give_background(gsr, ctx):
+    import torch
+    bg = (0.25, 0.5, 0.75)
+    cam = synth.camera((0, 0, -3), (0, 0, 0), 64, 48, bg=bg)
+    empty = synth.gaussians_uniform_cube(0, 1)
+    zero = synth.gaussians_uniform_cube(300, 2)
+    zero["opacities"][:] = 0
+    behind = synth.gaussians_uniform_cube(300, 3)
+    behind["means"][:, 2] = -3.5  # behind the camera at z = -3 looking +z
+    eye = np.eye(3, dtype=np.float32)
+    z3 = np.zeros(3, np.float32)
+    for nd in (empty, zero, behind):
+        wl = dict(envs=[dict(nodes=[nd], poses=[(eye, z3)], cams=[cam])], cams_per_env=1, width=64, height=48)
+        ctx.set_tile(16, 16)
+        _, _, rgb, depth, alpha = render_gpu(ctx, wl)
+        bgv = torch.tensor(bg, dtype=torch.float32, device=rgb.device)
+        assert torch.equal(rgb, bgv.expand_as(rgb)) and torch.all(depth == 0) and torch.all(alpha == 0)
+        assert gsr.query_status(ctx)["pairs"] == 0
+
+
+def test_nonfinite_parameters_are_culled_and_counted(gsr, ctx):
+    wl = synth.scene_config(0, seed=9, scale=0.1)
+    nd = wl["envs"][0]["nodes"][0]
+    nd["means"][5, 1] = np.nan
+    nd["scales"][17, 0] = np.inf
+    nd["quats"][33, 2] = -np.inf
+    nd["opacities"][40] = np.nan
+    _run(gsr, ctx, wl, (16, 16))
+    assert gsr.query_status(ctx)["nonfinite"] == 4
+
+
+def test_one_gaussian_covering_every_tile(gsr, ctx):
+    from helpers import node
+    cam = synth.camera((0, 0, -3), (0, 0, 0), 96, 64)
+    big = node([[0.0, 0.0, 0.0]], 2.0, opac=0.9, colours=(0.2, 0.7, 0.4))
+    small = synth.gaussians_uniform_cube(200, 4)
+    eye = np.eye(3, dtype=np.float32)
+    z3 = np.zeros(3, np.float32)
+    small["sh"] = small["sh"][:, :1]
+    wl = dict(envs=[dict(nodes=[big, small], poses=[(eye, z3), (eye, z3)], cams=[cam])], cams_per_env=1,
+              width=96, height=64, name="one Gaussian covers all tiles")
+    _, _, _, _, _, refs, _ = _run(gsr, ctx, wl, (16, 16))
+    assert refs[0]["vis"][0] == 0 and all((refs[0]["ranges"][:, 1] - refs[0]["ranges"][:, 0]) >= 1)
+
+
+def test_pair_capacity_overflow_is_reported_then_grown(gsr):
+    import torch
+    wl = synth.scene_config(0, seed=11, scale=0.25)
+    c = gsr.create(0, pair_capacity=1000)
+    try:
+        scene, cams, rgb, depth, alpha = render_gpu(c, wl, flags=0)
+        st = gsr.query_status(c)
+        assert st["flags"] & gsr.STATUS_OVERFLOW and st["pairs"] > 1000 and st["pair_capacity"] == 1000
+        scene, cams, rgb, depth, alpha = render_gpu(c, wl, flags=gsr.FLAG_CHECK)
+        st = gsr.query_status(c)
+        assert st["flags"] == 0 and st["pair_capacity"] >= st["pairs"]
+        refs = oracle_images(wl, 16, 16)
+        compare_image(refs[0], rgb[0, 0].cpu().numpy(), depth[0, 0].cpu().numpy(), alpha[0, 0].cpu().numpy())
+        torch.cuda.synchronize()
+    finally:
+        c.close()
+
+
+def test_long_tile_lists_chunk_sort_and_merge(gsr, ctx):
+    # dense cube, small image: per-tile lists well above one LDS load (16384 entries)
+    wl = synth.scene_config(0, seed=13, scale=3.0)
+    cam = synth.camera((0, 0, -3), (0, 0, 0), 48, 48)
+    cam["fx"] = cam["fy"] = np.float32(41.57)
+    wl["envs"][0]["cams"] = [cam]
+    wl["width"], wl["height"] = 48, 48
+    wl["name"] = "dense 60k, 48x48"
+    _, _, _, _, _, refs, _ = _run(gsr, ctx, wl, (16, 16))
+    lens = refs[0]["ranges"][:, 1] - refs[0]["ranges"][:, 0]
+    log("max tile list", lens.max())
+    assert lens.max() > 16384 * 2
+
+
+def test_graph_replay_matches_eager_bitwise(gsr, ctx):
+    import torch
+    wl = synth.scene_config(3, seed=17, scale=0.02, n_envs=3)
+    envs_t, poses, cams = upload(wl)
+    ctx.set_tile(16, 16)
+    scene = gsr.compose_scene(ctx, envs_t, poses)
+    W, H, C = wl["width"], wl["height"], wl["cams_per_env"]
+    ref = [t.clone() for t in gsr.render_rgbd(ctx, scene, cams, W, H, C, flags=gsr.FLAG_CHECK)]
+    out = gsr.render_rgbd(ctx, scene, cams, W, H, C, flags=0)
+    out = tuple(torch.empty_like(t) for t in out)
+    for rep in range(4):
+        for t in out:
+            t.fill_(-1.0)
+        gsr.render_rgbd(ctx, scene, cams, W, H, C, out=out, flags=gsr.FLAG_GRAPH)
+        torch.cuda.synchronize()
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b), f"replay {rep} differs"
+        # eager work between replays
+        gsr.render_rgbd(ctx, scene, cams, W, H, C, flags=0)
+        torch.cuda.synchronize()
+    assert gsr.query_status(ctx)["flags"] == 0
+
+
+def test_repeat_renders_bitwise_identical(gsr, ctx):
+    import torch
+    wl = synth.scene_config(2, seed=19, scale=0.01)
+    envs_t, poses, cams = upload(wl)
+    ctx.set_tile(16, 16)
+    scene = gsr.compose_scene(ctx, envs_t, poses)
+    ref = [t.clone() for t in gsr.render_rgbd(ctx, scene, cams, 640, 480, 3)]
+    for _ in range(5):
+        out = gsr.render_rgbd(ctx, scene, cams, 640, 480, 3, flags=0)
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b)
+
+
+def test_permutation_of_gaussians_is_bitwise_invariant(gsr, ctx):
+    import torch
+    wl = synth.scene_config(0, seed=23, scale=0.3)
+    ref = oracle_images(wl, 16, 16)[0]
+    assert len(np.unique(ref["keys"])) == len(ref["keys"]), "z ties: pick another seed"
+    _, _, rgb, depth, alpha = render_gpu(ctx, wl)
+    rgb, depth = rgb.clone(), depth.clone()
+    perm = np.random.default_rng(1).permutation(len(wl["envs"][0]["nodes"][0]["means"]))
+    nd = wl["envs"][0]["nodes"][0]
+    wl["envs"][0]["nodes"][0] = {k: (v[perm] if isinstance(v, np.ndarray) else v) for k, v in nd.items()}
+    _, _, rgb2, depth2, _ = render_gpu(ctx, wl)
+    assert torch.equal(rgb, rgb2) and torch.equal(depth, depth2)
+
+
+def test_joint_rigid_motion_of_scene_and_camera(gsr, ctx):
+    import torch
+    wl = synth.scene_config(2, seed=29, scale=0.01)
+    _, _, rgb, depth, _ = render_gpu(ctx, wl)
+    rgb, depth = rgb.clone(), depth.clone()
+    R0 = synth.random_rotation(synth.rng(5))
+    t0 = np.array([0.3, -0.2, 0.5])
+    env = wl["envs"][0]
+    env["poses"] = [((R0 @ R.astype(np.float64)).astype(np.float32), (R0 @ t + t0).astype(np.float32))
+                    for R, t in env["poses"]]
+    for c in env["cams"]:
+        Rc = c["R"].astype(np.float64) @ R0.T
+        c["t"] = (c["t"].astype(np.float64) - Rc @ t0).astype(np.float32)
+        c["R"] = Rc.astype(np.float32)
+    _, _, rgb2, depth2, _ = render_gpu(ctx, wl)
+    # FP32 rounding of the moved poses and cameras perturbs the inputs by ~1e-7 relative; a
+    # handful of pixels may also swap the order of near-equal depths
+    d = (rgb - rgb2).abs().amax(dim=-1)
+    assert (d > 1e-3).float().mean().item() < 2e-3 and torch.quantile(d.flatten(), 0.99).item() < 1e-4
+
+
+def test_persistent_composite_matches_one_block_per_tile(gsr, ctx):
+    import torch
+    wl = synth.scene_config(3, seed=31, scale=0.03, n_envs=4)
+    envs_t, poses, cams = upload(wl)
+    W, H, C = wl["width"], wl["height"], wl["cams_per_env"]
+    for tile in [(16, 16), (8, 8)]:
+        ctx.set_tile(*tile)
+        scene = gsr.compose_scene(ctx, envs_t, poses)
+        ref = [t.clone() for t in gsr.render_rgbd(ctx, scene, cams, W, H, C, flags=gsr.FLAG_CHECK)]
+        ev_ref = gsr.query_status(ctx)["evals"]
+        out = gsr.render_rgbd(ctx, scene, cams, W, H, C, flags=gsr.FLAG_CHECK | gsr.FLAG_PERSISTENT)
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b)
+        assert gsr.query_status(ctx)["evals"] == ev_ref
+        # and inside a graph
+        out2 = gsr.render_rgbd(ctx, scene, cams, W, H, C, flags=gsr.FLAG_GRAPH | gsr.FLAG_PERSISTENT)
+        out2 = gsr.render_rgbd(ctx, scene, cams, W, H, C, out=out2, flags=gsr.FLAG_GRAPH | gsr.FLAG_PERSISTENT)
+        torch.cuda.synchronize()
+        for a, b in zip(out2, ref):
+            assert torch.equal(a, b)

@@ -110,8 +110,8 @@ enum {
                                         replay it on later calls with the same arguments
                                         (pointers, sizes, flags); implies no synchronisation.
                                         Capacity must already suffice (overflow is reported). */
-    GSR_FLAG_PERSISTENT = 1u << 3,   /* composite with a persistent grid pulling (image, tile)
-                                        work items, longest list first, from a device queue    */
+    GSR_FLAG_PERSISTENT = 1u << 3,   /* composite with a persistent grid walking a longest-list-
+                                        first queue of (image, tile) work items                */
     GSR_FLAG_TIMING = 1u << 4        /* record HIP events between the forward stages (eager
                                         calls only); read them with gsr_stage_times          */
 };
@@ -137,8 +137,8 @@ typedef struct {
 } gsr_status_info;
 
 /* Number of timed forward stages and their names, in order: views, project,
-   tile_counts, scan, emit, classify, sort_small, sort_mid, sort_big,
-   composite. */
+   tile_offsets, scan, emit, classify, sort_small (lists <= 2048), sort_mid
+   (<= 16384), sort_big (longer), composite. */
 #define GSR_STAGES 10
 
 /* Configuration.  Tile shape must be one of 16x16, 16x8, 8x8, 32x8 (width x
@@ -146,8 +146,11 @@ typedef struct {
 typedef struct {
     int32_t tile_w, tile_h;   /* default 16 x 16                                             */
     int64_t pair_capacity;    /* initial pair capacity, default 1 << 22                       */
-    int32_t persistent_grid;  /* blocks of the persistent composite, default 8 per CU         */
-    int32_t reserved[7];
+    int32_t persistent_grid;  /* persistent composite size in 256-thread blocks, default 8 per
+                                 CU (scaled to the tile's block size)                        */
+    int32_t pixels_per_thread;/* compositor pixels per thread, 1 or 2 (default 2; 8x8 tiles
+                                 always use 1)                                               */
+    int32_t reserved[6];
 } gsr_config;
 
 /* ---- context ---------------------------------------------------------- */
@@ -165,10 +168,11 @@ void gsr_destroy(gsr_context* ctx);
    failure, e.g. from gsr_create).  Never NULL; owned by the library. */
 const char* gsr_last_error(const gsr_context* ctx);
 
-/* Current configuration, and a new tile shape (the next render uses it;
-   cached graphs are dropped). */
+/* Current configuration, and a new tile shape or compositor pixels per thread
+   (the next render uses them; cached graphs are dropped). */
 int gsr_get_config(const gsr_context* ctx, gsr_config* out);
 int gsr_set_tile(gsr_context* ctx, int32_t tile_w, int32_t tile_h);
+int gsr_set_pixels_per_thread(gsr_context* ctx, int32_t ppt);
 
 /* ---- scene composition (Sec. III-B: background node + posed nodes) ----- */
 
@@ -257,10 +261,11 @@ int gsr_stage_times(gsr_context* ctx, float* ms);
 
 /* ---- autotuning -------------------------------------------------------- */
 
-/* Time every supported tile shape (and the persistent composite on/off) on
-   this scene and camera set, keep the fastest in the context and return it.
-   Outputs are scratch buffers sized for the call.  Synchronous.  The choice
-   is cached per (images, width, height, Gaussian count) in the context. */
+/* Time every supported tile shape, compositor pixels per thread and the
+   persistent compositor on/off on this scene and camera set (full renders),
+   keep the fastest in the context and return it.  Outputs are scratch buffers
+   sized for the call.  Synchronous.  The choice is cached per (images, width,
+   height, Gaussian count) in the context. */
 int gsr_autotune(gsr_context* ctx, const gsr_scene* scene, int32_t cams_per_env,
                  const gsr_camera* cams, int32_t width, int32_t height, float* rgb, float* depth,
                  float* alpha, int32_t* tile_w, int32_t* tile_h, int32_t* persistent, void* stream);

@@ -25,7 +25,7 @@ FLAG_GRAPH = 4
 FLAG_PERSISTENT = 8
 FLAG_TIMING = 16
 STATUS_OVERFLOW = 1
-STAGES = ("views", "project", "tile_counts", "scan", "emit", "classify", "sort_small", "sort_mid", "sort_big",
+STAGES = ("views", "project", "tile_offsets", "scan", "emit", "classify", "sort_small", "sort_mid", "sort_big",
           "composite")
 
 _ERRORS = {-1: "GSR_E_INVALID", -2: "GSR_E_NOMEM", -3: "GSR_E_HIP", -4: "GSR_E_CAPACITY",
@@ -51,7 +51,8 @@ class GaussianGrads(ctypes.Structure):
 
 class Config(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("pair_capacity", ctypes.c_int64),
-                ("persistent_grid", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("persistent_grid", ctypes.c_int32), ("pixels_per_thread", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class StatusInfo(ctypes.Structure):
@@ -79,6 +80,7 @@ def lib():
         L.gsr_last_error.restype = ctypes.c_char_p
         L.gsr_get_config.argtypes = [vp, ctypes.POINTER(Config)]
         L.gsr_set_tile.argtypes = [vp, i32, i32]
+        L.gsr_set_pixels_per_thread.argtypes = [vp, i32]
         L.gsr_compose_scene.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(Gaussians), i32, vp,
                                         ctypes.POINTER(vp)]
         L.gsr_scene_destroy.argtypes = [vp]
@@ -154,6 +156,9 @@ class Context:
 
     def set_tile(self, tw, th):
         _check(lib().gsr_set_tile(self.handle, tw, th), self)
+
+    def set_pixels_per_thread(self, ppt):
+        _check(lib().gsr_set_pixels_per_thread(self.handle, ppt), self)
 
 
 def create(device=0, tile=(16, 16), pair_capacity=0, persistent_grid=0):
@@ -335,6 +340,8 @@ def copy_pixel_state(ctx, n_pixels, device="cuda"):
 
 
 def autotune(ctx, scene, cams, width, height, cams_per_env=None, stream=None):
+    """Pick tile shape, pixels per thread and persistent compositing for this workload.
+    Returns ((tile_w, tile_h), persistent); the context keeps the choice."""
     E = scene.n_envs
     C = cams_per_env if cams_per_env is not None else cams.shape[0] // E
     rgb = torch.empty((E, C, height, width, 3), device=cams.device)

@@ -37,13 +37,14 @@ struct GraphKey {
     const void* rgb;
     const void* depth;
     const void* alpha;
-    int C, W, H, tw, th, persistent;
+    int C, W, H, tw, th, persistent, ppt;
     uint32_t flags;
     hipStream_t stream;
     long long pair_cap;
     bool operator==(const GraphKey& o) const {
         return scene == o.scene && cams == o.cams && rgb == o.rgb && depth == o.depth && alpha == o.alpha &&
                C == o.C && W == o.W && H == o.H && tw == o.tw && th == o.th && persistent == o.persistent &&
+               ppt == o.ppt &&
                flags == o.flags && stream == o.stream && pair_cap == o.pair_cap;
     }
 };
@@ -58,9 +59,11 @@ struct gsr_scene {
     std::vector<Node> nodes_h;
     std::vector<Env> envs_h;
     std::vector<Block> blocks_h;
+    std::vector<Super> supers_h;
     Node* nodes_d = nullptr;
     Env* envs_d = nullptr;
     Block* blocks_d = nullptr;
+    Super* supers_d = nullptr;
     const gsr_pose* poses = nullptr;
     uint64_t version = 0;
 };
@@ -76,8 +79,8 @@ struct gsr_context {
     long long pair_cap = 0;
     DevBuf<Record> records;
     DevBuf<uint4> rects;
-    DevBuf<int> diff;
-    DevBuf<uint32_t> counts, starts, cursor, cls_list, order, buckets;
+    DevBuf<uint32_t> sbcnt;
+    DevBuf<uint32_t> counts, starts, cursor, cls_list;
     DevBuf<View> views;
     DevBuf<float> T_final;
     DevBuf<uint32_t> n_contrib;
@@ -95,8 +98,8 @@ struct gsr_context {
     GraphKey gkey{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    // autotune cache: (images, W, H, gaussians) -> (tw, th, persistent)
-    std::map<std::tuple<int, int, int, long long>, std::tuple<int, int, int>> tune;
+    // autotune cache: (images, W, H, gaussians) -> (tw, th, persistent, ppt)
+    std::map<std::tuple<int, int, int, long long>, std::tuple<int, int, int, int>> tune;
     hipEvent_t stage_ev[kStages + 1] = {};
     bool timed = false;
     hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
@@ -174,6 +177,11 @@ int gsr_create(int device, const gsr_config* cfg, gsr_context** out) {
     ctx->device = device;
     hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device);
     if (c.persistent_grid <= 0) c.persistent_grid = 8 * std::max(ctx->num_cu, 1);
+    if (c.pixels_per_thread == 0) c.pixels_per_thread = 2;
+    if (c.pixels_per_thread != 1 && c.pixels_per_thread != 2) {
+        delete ctx;
+        return fail(nullptr, GSR_E_UNSUPPORTED, "gsr_create: pixels_per_thread must be 1 or 2");
+    }
     ctx->cfg = c;
     if (hipMalloc(&ctx->d_status, sizeof(Status)) != hipSuccess ||
         hipHostMalloc(&ctx->h_status, sizeof(Status)) != hipSuccess) {
@@ -195,8 +203,8 @@ void gsr_destroy(gsr_context* ctx) {
         if (e) hipEventDestroy(e);
     if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     ctx->pairs.release(); ctx->pairs_alt.release(); ctx->records.release(); ctx->rects.release();
-    ctx->diff.release(); ctx->counts.release(); ctx->starts.release(); ctx->cursor.release();
-    ctx->cls_list.release(); ctx->order.release(); ctx->buckets.release(); ctx->views.release(); ctx->T_final.release(); ctx->n_contrib.release();
+    ctx->sbcnt.release(); ctx->counts.release(); ctx->starts.release(); ctx->cursor.release();
+    ctx->cls_list.release(); ctx->views.release(); ctx->T_final.release(); ctx->n_contrib.release();
     ctx->g2d.release(); ctx->grads_dev.release();
     if (ctx->d_status) hipFree(ctx->d_status);
     if (ctx->h_status) hipHostFree(ctx->h_status);
@@ -220,11 +228,20 @@ int gsr_set_tile(gsr_context* ctx, int32_t tw, int32_t th) {
     return GSR_OK;
 }
 
+int gsr_set_pixels_per_thread(gsr_context* ctx, int32_t ppt) {
+    if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_set_pixels_per_thread: ctx is NULL");
+    if (ppt != 1 && ppt != 2) return fail(ctx, GSR_E_UNSUPPORTED, "gsr_set_pixels_per_thread: %d not 1 or 2", ppt);
+    if (ppt != ctx->cfg.pixels_per_thread) drop_graph(ctx);
+    ctx->cfg.pixels_per_thread = ppt;
+    return GSR_OK;
+}
+
 void gsr_scene_destroy(gsr_scene* sc) {
     if (!sc) return;
     if (sc->nodes_d) hipFree(sc->nodes_d);
     if (sc->envs_d) hipFree(sc->envs_d);
     if (sc->blocks_d) hipFree(sc->blocks_d);
+    if (sc->supers_d) hipFree(sc->supers_d);
     if (sc->ctx && sc->ctx->last_scene == sc) {
         sc->ctx->have_last = sc->ctx->saved = false;
         sc->ctx->last_scene = nullptr;
@@ -304,6 +321,24 @@ int gsr_compose_scene(gsr_context* ctx, int32_t n_envs, const int32_t* off, cons
         }
         ev.n = gid - ev.gid_base;
     }
+    // super-blocks: runs of an env's chunks, sized so the grid still has ~8 blocks per CU
+    const long long nchunks = (long long)sc->blocks_h.size();
+    const int cps = (int)std::max(1ll, std::min<long long>(kMaxChunksPerSuper, nchunks / (8ll * std::max(ctx->num_cu, 1))));
+    sc->supers_h.clear();
+    {
+        size_t ch = 0;
+        for (int e = 0; e < n_envs; ++e) {
+            Env& ev = sc->envs_h[e];
+            ev.sb_begin = (int32_t)sc->supers_h.size();
+            size_t end = ch;
+            while (end < sc->blocks_h.size() && sc->blocks_h[end].env == e) ++end;
+            for (size_t b = ch; b < end; b += cps)
+                sc->supers_h.push_back(Super{e, (int32_t)b, (int32_t)std::min(end, b + cps), 0});
+            if (end == ch) sc->supers_h.push_back(Super{e, (int32_t)ch, (int32_t)ch, 0});  // empty env
+            ev.sb_count = (int32_t)sc->supers_h.size() - ev.sb_begin;
+            ch = end;
+        }
+    }
     auto up = [&](auto*& dptr, const auto& vec) -> int {
         using T = typename std::remove_reference<decltype(vec)>::type::value_type;
         if (!same && dptr == nullptr) {
@@ -320,6 +355,7 @@ int gsr_compose_scene(gsr_context* ctx, int32_t n_envs, const int32_t* off, cons
     if ((r = up(sc->nodes_d, sc->nodes_h)) != GSR_OK) { if (!same) gsr_scene_destroy(sc); return r; }
     if ((r = up(sc->envs_d, sc->envs_h)) != GSR_OK) { if (!same) gsr_scene_destroy(sc); return r; }
     if ((r = up(sc->blocks_d, sc->blocks_h)) != GSR_OK) { if (!same) gsr_scene_destroy(sc); return r; }
+    if ((r = up(sc->supers_d, sc->supers_h)) != GSR_OK) { if (!same) gsr_scene_destroy(sc); return r; }
     sc->version++;
     if (ctx->graph_valid && ctx->gkey.scene == sc) drop_graph(ctx);
     *inout = sc;
@@ -330,13 +366,15 @@ int gsr_compose_scene(gsr_context* ctx, int32_t n_envs, const int32_t* off, cons
 
 // Fill FwdArgs and make sure the workspace holds this render.
 static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camera* cams, int W, int H, float* rgb,
-                   float* depth, float* alpha, int persistent, FwdArgs& a) {
+                   float* depth, float* alpha, int persistent, int save, FwdArgs& a) {
     const int tw = ctx->cfg.tile_w, th = ctx->cfg.tile_h;
     memset(&a, 0, sizeof a);
     a.nodes = sc->nodes_d;
     a.envs = sc->envs_d;
     a.blocks = sc->blocks_d;
     a.n_blocks = (int)sc->blocks_h.size();
+    a.supers = sc->supers_d;
+    a.n_supers = (int)sc->supers_h.size();
     a.n_nodes = sc->n_nodes;
     a.sh_degree = sc->sh_degree;
     a.poses = sc->poses;
@@ -352,17 +390,17 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
     a.tpi = a.tiles_x * a.tiles_y;
     a.tiles = (long long)a.images * a.tpi;
     const int gsz = (a.tiles_x + 1) * (a.tiles_y + 1);
-    if (gsz > kLdsHistLimit)
-        return fail(ctx, GSR_E_UNSUPPORTED, "image %dx%d with %dx%d tiles exceeds %d tile-grid cells", W, H, tw, th, kLdsHistLimit);
+    if ((long long)C * gsz > kLdsHistLimit || (long long)C * a.tpi > kLdsHistLimit)
+        return fail(ctx, GSR_E_UNSUPPORTED, "%d cameras of %dx%d with %dx%d tiles exceed the %d per-block tile counters",
+                    C, W, H, tw, th, kLdsHistLimit);
     if (a.tiles >= 0xffffffffll) return fail(ctx, GSR_E_UNSUPPORTED, "too many tiles");
     const size_t nrec = (size_t)C * (size_t)sc->total;
     const size_t npix = (size_t)a.images * W * H;
     int r;
     if ((r = ensure(ctx, ctx->records, nrec)) || (r = ensure(ctx, ctx->rects, nrec)) ||
-        (r = ensure(ctx, ctx->diff, (size_t)a.images * gsz, true)) || (r = ensure(ctx, ctx->counts, a.tiles)) ||
+        (r = ensure(ctx, ctx->sbcnt, (size_t)a.n_supers * C * a.tpi)) || (r = ensure(ctx, ctx->counts, a.tiles)) ||
         (r = ensure(ctx, ctx->starts, a.tiles + 1)) || (r = ensure(ctx, ctx->cursor, a.tiles)) ||
-        (r = ensure(ctx, ctx->cls_list, 3 * (size_t)a.tiles)) || (r = ensure(ctx, ctx->order, a.tiles)) ||
-        (r = ensure(ctx, ctx->buckets, 66)) ||
+        (r = ensure(ctx, ctx->cls_list, (size_t)kNumClasses * a.tiles)) ||
         (r = ensure(ctx, ctx->views, (size_t)sc->n_nodes * C)) || (r = ensure(ctx, ctx->T_final, npix)) ||
         (r = ensure(ctx, ctx->n_contrib, npix)))
         return r;
@@ -371,13 +409,11 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
     a.views = ctx->views.p;
     a.records = ctx->records.p;
     a.rects = ctx->rects.p;
-    a.diff = ctx->diff.p;
+    a.sbcnt = ctx->sbcnt.p;
     a.counts = ctx->counts.p;
     a.starts = ctx->starts.p;
     a.cursor = ctx->cursor.p;
     a.cls_list = ctx->cls_list.p;
-    a.order = ctx->order.p;
-    a.buckets = ctx->buckets.p;
     a.pairs = ctx->pairs.p;
     a.pairs_alt = ctx->pairs_alt.p;
     a.pair_cap = ctx->pair_cap;
@@ -389,6 +425,8 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
     a.n_contrib = ctx->n_contrib.p;
     a.persistent = persistent;
     a.persistent_grid = ctx->cfg.persistent_grid;
+    a.ppt = (tw == 8 && th == 8) ? 1 : ctx->cfg.pixels_per_thread;
+    a.save = save;
     return GSR_OK;
 }
 
@@ -410,12 +448,13 @@ int gsr_render_rgbd(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_
     hipStream_t s = (hipStream_t)stream;
     hipSetDevice(ctx->device);
     const int persistent = (flags & GSR_FLAG_PERSISTENT) ? 1 : 0;
+    const int save = (flags & GSR_FLAG_SAVE) ? 1 : 0;
     FwdArgs a;
-    int r = prepare(ctx, sc, C, cams, W, H, rgb, depth, alpha, persistent, a);
+    int r = prepare(ctx, sc, C, cams, W, H, rgb, depth, alpha, persistent, save, a);
     if (r) return r;
     ctx->last_stream = s;
     if (flags & GSR_FLAG_GRAPH) {
-        GraphKey k{sc, cams, rgb, depth, alpha, C, W, H, ctx->cfg.tile_w, ctx->cfg.tile_h, persistent,
+        GraphKey k{sc, cams, rgb, depth, alpha, C, W, H, ctx->cfg.tile_w, ctx->cfg.tile_h, persistent, a.ppt,
                    flags, s, ctx->pair_cap};
         if (!(ctx->graph_valid && ctx->gkey == k)) {
             drop_graph(ctx);
@@ -453,7 +492,7 @@ int gsr_render_rgbd(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_
                             (unsigned long long)ctx->h_status->pairs);
             ctx->pair_cap = (long long)(ctx->h_status->pairs * 5 / 4) + 1024;
             drop_graph(ctx);
-            if ((r = prepare(ctx, sc, C, cams, W, H, rgb, depth, alpha, persistent, a))) return r;
+            if ((r = prepare(ctx, sc, C, cams, W, H, rgb, depth, alpha, persistent, save, a))) return r;
             if (flags & GSR_FLAG_TIMING) a.stage_events = ctx->stage_ev;
         }
         a.stage_events = nullptr;
@@ -556,29 +595,33 @@ int gsr_autotune(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_cam
         hipStream_t s = (hipStream_t)stream;
         const int shapes[4][2] = {{16, 16}, {16, 8}, {8, 8}, {32, 8}};
         float best = 1e30f;
-        std::tuple<int, int, int> choice{16, 16, 0};
+        std::tuple<int, int, int, int> choice{16, 16, 0, 2};
         hipEvent_t e0, e1;
         HIPCHK(ctx, hipEventCreate(&e0));
         HIPCHK(ctx, hipEventCreate(&e1));
         for (auto& sh : shapes) {
-            for (int pers = 0; pers < 2; ++pers) {
-                int r = gsr_set_tile(ctx, sh[0], sh[1]);
-                if (r) return r;
-                const uint32_t fl = pers ? GSR_FLAG_PERSISTENT : 0u;
-                r = gsr_render_rgbd(ctx, sc, C, cams, W, H, rgb, depth, alpha, fl | GSR_FLAG_CHECK, stream);
-                if (r) return r;
-                float ms = 0.0f;
-                HIPCHK(ctx, hipEventRecord(e0, s));
-                for (int it2 = 0; it2 < 3; ++it2) {
-                    r = gsr_render_rgbd(ctx, sc, C, cams, W, H, rgb, depth, alpha, fl, stream);
+            for (int ppt = 1; ppt <= 2; ++ppt) {
+                if (ppt == 2 && sh[0] == 8 && sh[1] == 8) continue;
+                for (int pers = 0; pers < 2; ++pers) {
+                    int r = gsr_set_tile(ctx, sh[0], sh[1]);
+                    if (!r) r = gsr_set_pixels_per_thread(ctx, ppt);
                     if (r) return r;
-                }
-                HIPCHK(ctx, hipEventRecord(e1, s));
-                HIPCHK(ctx, hipEventSynchronize(e1));
-                HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best) {
-                    best = ms;
-                    choice = std::make_tuple(sh[0], sh[1], pers);
+                    const uint32_t fl = pers ? GSR_FLAG_PERSISTENT : 0u;
+                    r = gsr_render_rgbd(ctx, sc, C, cams, W, H, rgb, depth, alpha, fl | GSR_FLAG_CHECK, stream);
+                    if (r) return r;
+                    float ms = 0.0f;
+                    HIPCHK(ctx, hipEventRecord(e0, s));
+                    for (int it2 = 0; it2 < 3; ++it2) {
+                        r = gsr_render_rgbd(ctx, sc, C, cams, W, H, rgb, depth, alpha, fl, stream);
+                        if (r) return r;
+                    }
+                    HIPCHK(ctx, hipEventRecord(e1, s));
+                    HIPCHK(ctx, hipEventSynchronize(e1));
+                    HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best) {
+                        best = ms;
+                        choice = std::make_tuple(sh[0], sh[1], pers, ppt);
+                    }
                 }
             }
         }
@@ -587,6 +630,7 @@ int gsr_autotune(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_cam
         it = ctx->tune.emplace(key, choice).first;
     }
     int r = gsr_set_tile(ctx, std::get<0>(it->second), std::get<1>(it->second));
+    if (!r) r = gsr_set_pixels_per_thread(ctx, std::get<3>(it->second));
     if (r) return r;
     if (tile_w) *tile_w = std::get<0>(it->second);
     if (tile_h) *tile_h = std::get<1>(it->second);

@@ -106,43 +106,43 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(BwdArgs b) {
             bool contrib = false;
             if (inside && e < last) {
                 const float dx = fpx - r0.x, dy = fpy - r0.y;
-                // identical operations to the forward pass, so the same entries are blended
+                // the forward's operations exactly, so the same entries are blended:
+                // q = A' dx^2 + B' dx dy + C' dy^2 + log2 o, alpha = min(0.99, exp2(q))
                 const float A2 = -0.7213475204444817f * r1.x, B2 = -1.4426950408889634f * r1.y,
                             C2 = -0.7213475204444817f * r1.z;
-                const float q = fmaf(A2 * dx, dx, fmaf(B2 * dx, dy, C2 * dy * dy));
-                if (q <= 0.0f) {
-                    const float G = __builtin_amdgcn_exp2f(q);
-                    const float oG = r0.z * G;
-                    const float al = fminf(0.99f, oG);
-                    if (al >= thr) {
-                        contrib = true;
-                        const float4 r2 = s2[k];
-                        const float om = 1.0f - al;
-                        const float Ti = T / om;
-                        const float w = al * Ti;
-                        g_r = gr * w;
-                        g_g = gg * w;
-                        g_b = gb * w;
-                        g_z = gD * w;
-                        const float iom = 1.0f / om;
-                        float dLda = gr * (r2.x * Ti - SCr * iom) + gg * (r2.y * Ti - SCg * iom) +
-                                     gb * (r2.z * Ti - SCb * iom);
-                        dLda += gD * (r0.w * Ti - SD * iom);
-                        dLda += gA * Tf * iom;
-                        SCr = fmaf(r2.x, w, SCr);
-                        SCg = fmaf(r2.y, w, SCg);
-                        SCb = fmaf(r2.z, w, SCb);
-                        SD = fmaf(r0.w, w, SD);
-                        T = Ti;
-                        if (oG < 0.99f) {
-                            g_o = dLda * G;
-                            const float dp = dLda * oG;  // dL/dpower, power = -1/2 A dx^2 - B dx dy - 1/2 C dy^2
-                            g_u = dp * (r1.x * dx + r1.y * dy);
-                            g_v = dp * (r1.z * dy + r1.y * dx);
-                            g_A = -0.5f * dp * dx * dx;
-                            g_B = -dp * dx * dy;
-                            g_C = -0.5f * dp * dy * dy;
-                        }
+                const float Adx = A2 * dx, Bdx = B2 * dx;
+                const float qx = fmaf(Adx, dx, r1.w);
+                const float q = fmaf(Bdx, dy, fmaf(C2 * dy, dy, qx));
+                const float oG = __builtin_amdgcn_exp2f(q);  // o G, alpha before the clamp
+                const float al = fminf(0.99f, oG);
+                if (al >= thr) {
+                    contrib = true;
+                    const float4 r2 = s2[k];
+                    const float om = 1.0f - al;
+                    const float Ti = T / om;
+                    const float w = al * Ti;
+                    g_r = gr * w;
+                    g_g = gg * w;
+                    g_b = gb * w;
+                    g_z = gD * w;
+                    const float iom = 1.0f / om;
+                    float dLda = gr * (r2.x * Ti - SCr * iom) + gg * (r2.y * Ti - SCg * iom) +
+                                 gb * (r2.z * Ti - SCb * iom);
+                    dLda += gD * (r0.w * Ti - SD * iom);
+                    dLda += gA * Tf * iom;
+                    SCr = fmaf(r2.x, w, SCr);
+                    SCg = fmaf(r2.y, w, SCg);
+                    SCb = fmaf(r2.z, w, SCb);
+                    SD = fmaf(r0.w, w, SD);
+                    T = Ti;
+                    if (oG < 0.99f) {
+                        g_o = dLda * oG / r0.z;      // d alpha / d o = G
+                        const float dp = dLda * oG;  // dL/dpower, power = -1/2 A dx^2 - B dx dy - 1/2 C dy^2
+                        g_u = dp * (r1.x * dx + r1.y * dy);
+                        g_v = dp * (r1.z * dy + r1.y * dx);
+                        g_A = -0.5f * dp * dx * dx;
+                        g_B = -dp * dx * dy;
+                        g_C = -0.5f * dp * dy * dy;
                     }
                 }
             }

@@ -5,12 +5,12 @@
 //                  (scene composition: background plus rigidly posed nodes, paper Sec. III-B)
 //   k_project      per Gaussian, all cameras of its env: EWA projection ("splatting"), tile
 //                  rectangle and depth key (the FP32 key specification below), SH colour
-//                  (paper Sec. III-A), projected record, per-tile pair counts via a
-//                  difference grid kept in LDS
-//   k_tile_counts  per image: 2D prefix of the difference grid -> pairs per tile
+//                  (paper Sec. III-A), projected record; per super-block (runs of an env's
+//                  Gaussians) per-tile pair counts via a difference grid kept in LDS
+//   k_tile_offsets per (image, tile): scan over the env's super-blocks of their pair counts
 //   k_scan         exclusive scan of per-tile counts -> per-tile [start, end) ranges
-//   k_emit         (depth bits, Gaussian id) pairs written into their tile's bucket; slots are
-//                  reserved per block with one global atomic per (block, tile)
+//   k_emit         (depth bits, Gaussian id) pairs written into their tile's bucket; each
+//                  super-block starts at its precomputed slot, so only LDS atomics are used
 //   k_classify, k_sort_*   each tile's bucket sorted by (depth bits, id) in LDS; lists longer
 //                  than one LDS load are chunk-sorted then merged ("efficient sorting")
 //   k_composite    per tile, front-to-back alpha blending of colour and camera-space z
@@ -36,14 +36,13 @@ __global__ void k_views(FwdArgs a) {
         st->nonfinite = 0;
         st->pairs = 0;
         st->max_tile = 0;
-        st->cls[0] = st->cls[1] = st->cls[2] = st->cls[3] = 0;
+        for (int c = 0; c < 8; ++c) st->cls[c] = 0;
         st->work_head = 0;
         st->visible = 0;
         st->visible_any = 0;
         st->evals = 0;
     }
-    if (a.persistent && blockIdx.x == 0)
-        for (int i = threadIdx.x; i < 66; i += blockDim.x) a.buckets[i] = 0;
+
     if (idx >= a.n_nodes * a.C) return;
     const int k = idx / a.C, c = idx % a.C;
     const Node nd = a.nodes[k];
@@ -168,22 +167,24 @@ __device__ inline float3 sh_colour(const float* __restrict__ sh, float dx, float
 // The rectangle bounds the ellipse o * G >= 1/255 for any o <= 1, so tile lists hold every
 // Gaussian that can reach a pixel of the tile.
 // --------------------------------------------------------------------------------------------
-template <int L, bool LDSH>
+template <int L>
 __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a) {
-    extern __shared__ int s_hist[];
-    const Block blk = a.blocks[blockIdx.x];
-    const Node nd = a.nodes[blk.node];
-    const Env ev = a.envs[blk.env];
+    // LDS: per camera of the env, a (tiles_y + 1) x (tiles_x + 1) difference grid of pair
+    // counts: a rectangle adds +1/-1 at its four corners; the 2D prefix gives pairs per tile
+    extern __shared__ int s_grid[];
+    const Super sb = a.supers[blockIdx.x];
+    const Env ev = a.envs[sb.env];
     const int C = a.C;
-    const int gx = a.tiles_x + 1, gsz = gx * (a.tiles_y + 1);
-    if (LDSH) {
-        for (int i = threadIdx.x; i < C * gsz; i += kBlock) s_hist[i] = 0;
-        __syncthreads();
-    }
+    const int gx = a.tiles_x + 1, gy = a.tiles_y + 1, gsz = gx * gy;
+    for (int i = threadIdx.x; i < C * gsz; i += kBlock) s_grid[i] = 0;
+    __syncthreads();
     constexpr int K = (L + 1) * (L + 1);
     const int i = threadIdx.x;
-    int n_vis = 0;
-    if (i < (int)blk.count) {
+    int n_vis = 0, n_any = 0, nonfinite = 0;
+    for (int ch = sb.chunk_begin; ch < sb.chunk_end; ++ch) {
+        const Block blk = a.blocks[ch];
+        if (i >= (int)blk.count) continue;
+        const Node nd = a.nodes[blk.node];
         const uint32_t gid = blk.gid0 + i;
         const size_t li = gid - nd.gid_base;
         const size_t lg = gid - ev.gid_base;
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a) {
         const bool base_ok = isfinite(mu0) && isfinite(mu1) && isfinite(mu2) && isfinite(o);
         const float thr = (float)(1.0 / 255.0);
         const float itw = 1.0f / (float)a.tw, ith = 1.0f / (float)a.th;
-        int nonfinite = 0;
+        bool vis_any = false;
         for (int c = 0; c < C; ++c) {
             const View& v = a.views[blk.node * C + c];
             const size_t rec = (size_t)C * ev.gid_base + (size_t)c * ev.n + lg;
@@ -269,207 +270,226 @@ __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a) {
                 const float3 col = sh_colour<L>(nd.sh + li * (K * 3), mu0 - v.cl[0], mu1 - v.cl[1], mu2 - v.cl[2]);
                 Record R;
                 R.r0 = make_float4(u, vv, o, z);
-                R.r1 = make_float4(cc * idet, -cb * idet, ca * idet, 0.0f);
+                R.r1 = make_float4(cc * idet, -cb * idet, ca * idet, log2f(o));
                 R.r2 = make_float4(col.x, col.y, col.z, 0.0f);
                 a.records[rec] = R;
                 rect = make_uint4((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16),
                                   __float_as_uint(z), 1u);
                 // pair counts: +1/-1 corners of the rectangle in the image's difference grid
-                int* h = LDSH ? (s_hist + c * gsz) : (a.diff + (size_t)(blk.env * C + c) * gsz);
+                int* h = s_grid + c * gsz;
                 atomicAdd(h + ty0 * gx + tx0, 1);
                 atomicAdd(h + ty0 * gx + tx1, -1);
                 atomicAdd(h + ty1 * gx + tx0, -1);
                 atomicAdd(h + ty1 * gx + tx1, 1);
                 ++n_vis;
+                vis_any = true;
             } while (false);
             a.rects[rec] = rect;
         }
-        if (nonfinite) atomicAdd(&a.status->nonfinite, (uint32_t)nonfinite);
+        n_any += vis_any ? 1 : 0;
     }
-    {
-        // per-wavefront sums of visible records, one atomic per wavefront
-        unsigned long long nv = (unsigned long long)n_vis, na = n_vis > 0 ? 1ull : 0ull;
-        for (int off = 32; off > 0; off >>= 1) {
-            nv += __shfl_xor(nv, off, 64);
-            na += __shfl_xor(na, off, 64);
-        }
-        if ((threadIdx.x & 63) == 0 && nv) {
-            atomicAdd(&a.status->visible, nv);
-            atomicAdd(&a.status->visible_any, na);
-        }
-    }
-    if (LDSH) {
-        __syncthreads();
-        int* g = a.diff + (size_t)blk.env * C * gsz;
-        for (int j = threadIdx.x; j < C * gsz; j += kBlock) {
-            const int val = s_hist[j];
-            if (val != 0) atomicAdd(g + j, val);
-        }
-    }
-}
-
-// --------------------------------------------------------------------------------------------
-// per-image 2D prefix of the difference grid -> pairs per tile (the grid is cleared on read)
-// --------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_tile_counts(FwdArgs a) {
-    extern __shared__ int g[];
-    const int img = blockIdx.x;
-    const int gx = a.tiles_x + 1, gy = a.tiles_y + 1, gsz = gx * gy;
-    int* d = a.diff + (size_t)img * gsz;
-    for (int i = threadIdx.x; i < gsz; i += 256) {
-        g[i] = d[i];
-        d[i] = 0;
-    }
+    if (nonfinite) atomicAdd(&a.status->nonfinite, (uint32_t)nonfinite);
     __syncthreads();
-    for (int r = threadIdx.x; r < gy; r += 256) {
+    // 2D prefix of every camera's grid: along x, then along y
+    for (int r = threadIdx.x; r < C * gy; r += kBlock) {
+        int* row = s_grid + (r / gy) * gsz + (r % gy) * gx;
         int acc = 0;
-        for (int x = 0; x < gx; ++x) { acc += g[r * gx + x]; g[r * gx + x] = acc; }
+        for (int x = 0; x < gx; ++x) { acc += row[x]; row[x] = acc; }
     }
     __syncthreads();
-    for (int x = threadIdx.x; x < gx; x += 256) {
+    for (int col = threadIdx.x; col < C * gx; col += kBlock) {
+        int* g = s_grid + (col / gx) * gsz + (col % gx);
         int acc = 0;
-        for (int r = 0; r < gy; ++r) { acc += g[r * gx + x]; g[r * gx + x] = acc; }
+        for (int y = 0; y < gy; ++y) { acc += g[y * gx]; g[y * gx] = acc; }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < a.tpi; t += 256) {
+    // this super-block's pairs per (camera, tile), plain stores
+    uint32_t* out = a.sbcnt + (size_t)blockIdx.x * C * a.tpi;
+    for (int j = threadIdx.x; j < C * a.tpi; j += kBlock) {
+        const int c = j / a.tpi, t = j - c * a.tpi;
         const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
-        a.counts[(size_t)img * a.tpi + t] = (uint32_t)g[ty * gx + tx];
+        out[j] = (uint32_t)s_grid[c * gsz + ty * gx + tx];
+    }
+    // per-wavefront sums of visible records, one atomic per wavefront
+    unsigned long long nv = (unsigned long long)n_vis, na = (unsigned long long)n_any;
+    for (int off = 32; off > 0; off >>= 1) {
+        nv += __shfl_xor(nv, off, 64);
+        na += __shfl_xor(na, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0 && nv) {
+        atomicAdd(&a.status->visible, nv);
+        atomicAdd(&a.status->visible_any, na);
     }
 }
 
 // --------------------------------------------------------------------------------------------
-// exclusive scan of per-tile counts (one block); total pairs and overflow into the status word
+// per (image, tile): exclusive scan over the env's super-blocks -> each super-block's first
+// slot within the tile's bucket; the tile total -> pairs per tile
+// --------------------------------------------------------------------------------------------
+__global__ void k_tile_offsets(FwdArgs a) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.tiles) return;
+    const int image = (int)(idx / a.tpi);
+    const int t = (int)(idx - (long long)image * a.tpi);
+    const int env = image / a.C, c = image - env * a.C;
+    const Env ev = a.envs[env];
+    uint32_t run = 0;
+    for (int sbi = ev.sb_begin; sbi < ev.sb_begin + ev.sb_count; ++sbi) {
+        uint32_t* p = a.sbcnt + ((size_t)sbi * a.C + c) * a.tpi + t;
+        const uint32_t v = *p;
+        *p = run;
+        run += v;
+    }
+    a.counts[idx] = run;
+}
+
+// --------------------------------------------------------------------------------------------
+// exclusive scan of per-tile counts (one block, coalesced 1024-tile chunks); total pairs and
+// overflow into the status word
 // --------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_scan(FwdArgs a) {
-    __shared__ unsigned long long s[1024];
-    const long long T = a.tiles;
-    const long long per = (T + 1023) / 1024;
-    const long long b = (long long)threadIdx.x * per;
-    const long long e = (b + per < T) ? b + per : T;
-    unsigned long long sum = 0;
-    uint32_t mx = 0;
-    for (long long i = b; i < e; ++i) {
-        const uint32_t c = a.counts[i];
-        sum += c;
-        mx = c > mx ? c : mx;
-    }
-    s[threadIdx.x] = sum;
+    __shared__ unsigned long long s_wave[16];
+    __shared__ unsigned long long s_carry;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_carry = 0;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const unsigned long long v = threadIdx.x >= off ? s[threadIdx.x - off] : 0ull;
+    const long long T = a.tiles;
+    uint32_t mx = 0;
+    for (long long base = 0; base < T; base += 1024) {
+        const long long i = base + threadIdx.x;
+        const uint32_t v = i < T ? a.counts[i] : 0u;
+        mx = v > mx ? v : mx;
+        unsigned long long x = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned long long y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) s_wave[wave] = x;
         __syncthreads();
-        s[threadIdx.x] += v;
+        unsigned long long before = s_carry;
+        for (int w = 0; w < wave; ++w) before += s_wave[w];
+        const unsigned long long excl = before + x - v;
+        if (i < T) {
+            const uint32_t st = excl > 0xffffffffull ? 0xffffffffu : (uint32_t)excl;
+            a.starts[i] = st;
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) s_carry = excl + v;
         __syncthreads();
     }
-    unsigned long long run = s[threadIdx.x] - sum;
-    for (long long i = b; i < e; ++i) {
-        const uint32_t st = run > 0xffffffffull ? 0xffffffffu : (uint32_t)run;
-        a.starts[i] = st;
-        a.cursor[i] = st;
-        run += a.counts[i];
-    }
-    if (threadIdx.x == 1023) {
-        const unsigned long long total = s[1023];
+    if (threadIdx.x == 0) {
+        const unsigned long long total = s_carry;
         a.starts[T] = total > 0xffffffffull ? 0xffffffffu : (uint32_t)total;
         a.status->pairs = total;
         if (total > (unsigned long long)a.pair_cap) atomicOr(&a.status->flags, (uint32_t)GSR_STATUS_OVERFLOW);
     }
-    if (mx) atomicMax(&a.status->max_tile, mx);
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = __shfl_xor(mx, off, 64);
+        mx = o > mx ? o : mx;
+    }
+    if (lane == 0 && mx) atomicMax(&a.status->max_tile, mx);
 }
 
 // --------------------------------------------------------------------------------------------
-// pair emission into tile buckets.  Each block enumerates its (Gaussian, tile) pairs with a
-// block-wide prefix over rectangle areas so large rectangles are shared by all threads,
-// counts pairs per tile in LDS, reserves one slot range per (block, tile) with a single
-// global atomic, then writes (z bits << 32 | id).
+// pair emission into tile buckets.  Each super-block knows, per tile, the first slot of its
+// pairs (tile start + the offsets of the env's earlier super-blocks), so slots are taken with
+// LDS atomics only.  Within a chunk, the (Gaussian, tile) pairs are enumerated with a
+// block-wide prefix over rectangle areas, so large rectangles are shared by all threads.
+// Pair = (z bits << 32) | Gaussian id.
 // --------------------------------------------------------------------------------------------
-template <bool LDSC>
 __global__ __launch_bounds__(kBlock) void k_emit(FwdArgs a) {
-    extern __shared__ uint32_t s_cnt[];
+    extern __shared__ uint32_t s_slot[];
     __shared__ uint32_t s_off[kBlock + 1];
     __shared__ uint32_t s_x0[kBlock], s_y0[kBlock], s_w[kBlock], s_z[kBlock];
-    const Block blk = a.blocks[blockIdx.x];
-    const Env ev = a.envs[blk.env];
+    const Super sb = a.supers[blockIdx.x];
+    const Env ev = a.envs[sb.env];
     const int c = blockIdx.y;
-    const size_t image = (size_t)blk.env * a.C + c;
-    const int i = threadIdx.x;
-    uint32_t n_i = 0;
-    if (i < (int)blk.count) {
-        const uint4 r = a.rects[(size_t)a.C * ev.gid_base + (size_t)c * ev.n + (blk.gid0 - ev.gid_base) + i];
-        const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu, y1 = r.y >> 16;
-        if (r.w != 0u && x1 > x0 && y1 > y0) n_i = (x1 - x0) * (y1 - y0);
-        s_x0[i] = x0;
-        s_y0[i] = y0;
-        s_w[i] = x1 - x0;
-        s_z[i] = r.z;
-    }
-    // block-wide exclusive scan of n_i (Hillis-Steele in LDS)
-    s_off[i + 1] = n_i;
-    if (i == 0) s_off[0] = 0;
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        const uint32_t v = (i + 1 > off) ? s_off[i + 1 - off] : 0u;
-        __syncthreads();
-        s_off[i + 1] += v;
-        __syncthreads();
-    }
-    const uint32_t total = s_off[kBlock];
-    if (total == 0) return;
+    const size_t image = (size_t)sb.env * a.C + c;
     const int tpi = a.tpi;
-    uint32_t* cur = a.cursor + image * tpi;
-    if (LDSC) {
-        for (int t = i; t < tpi; t += kBlock) s_cnt[t] = 0;
-        __syncthreads();
-    }
-    auto tile_of = [&](uint32_t k, uint32_t& owner) -> int {
-        int lo = 0, hi = kBlock - 1;  // first owner with s_off[owner + 1] > k
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (s_off[mid + 1] > k) hi = mid; else lo = mid + 1;
-        }
-        owner = lo;
-        const uint32_t j = k - s_off[lo];
-        const uint32_t w = s_w[lo];
-        const uint32_t ty = s_y0[lo] + j / w, tx = s_x0[lo] + j % w;
-        return (int)(ty * a.tiles_x + tx);
-    };
-    if (LDSC) {
-        for (uint32_t k = i; k < total; k += kBlock) {
-            uint32_t owner;
-            atomicAdd(&s_cnt[tile_of(k, owner)], 1u);
-        }
-        __syncthreads();
-        for (int t = i; t < tpi; t += kBlock) {
-            const uint32_t n = s_cnt[t];
-            if (n) s_cnt[t] = atomicAdd(cur + t, n);
-        }
-        __syncthreads();
-    }
+    const uint32_t* so = a.sbcnt + ((size_t)blockIdx.x * a.C + c) * tpi;
+    for (int t = threadIdx.x; t < tpi; t += kBlock) s_slot[t] = a.starts[image * tpi + t] + so[t];
+    const int i = threadIdx.x;
     const unsigned long long cap = (unsigned long long)a.pair_cap;
-    for (uint32_t k = i; k < total; k += kBlock) {
-        uint32_t owner;
-        const int t = tile_of(k, owner);
-        const uint32_t pos = LDSC ? atomicAdd(&s_cnt[t], 1u) : atomicAdd(cur + t, 1u);
-        if ((unsigned long long)pos < cap)
-            a.pairs[pos] = ((unsigned long long)s_z[owner] << 32) | (unsigned long long)(blk.gid0 + owner);
+    for (int ch = sb.chunk_begin; ch < sb.chunk_end; ++ch) {
+        const Block blk = a.blocks[ch];
+        uint32_t n_i = 0;
+        if (i < (int)blk.count) {
+            const uint4 r = a.rects[(size_t)a.C * ev.gid_base + (size_t)c * ev.n + (blk.gid0 - ev.gid_base) + i];
+            const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu, y1 = r.y >> 16;
+            if (r.w != 0u && x1 > x0 && y1 > y0) n_i = (x1 - x0) * (y1 - y0);
+            s_x0[i] = x0;
+            s_y0[i] = y0;
+            s_w[i] = x1 - x0;
+            s_z[i] = r.z;
+        }
+        // block-wide exclusive scan of n_i (Hillis-Steele in LDS)
+        s_off[i + 1] = n_i;
+        if (i == 0) s_off[0] = 0;
+        __syncthreads();
+        for (int off = 1; off < kBlock; off <<= 1) {
+            const uint32_t v = (i + 1 > off) ? s_off[i + 1 - off] : 0u;
+            __syncthreads();
+            s_off[i + 1] += v;
+            __syncthreads();
+        }
+        const uint32_t total = s_off[kBlock];
+        for (uint32_t k = i; k < total; k += kBlock) {
+            int lo = 0, hi = kBlock - 1;  // first owner with s_off[owner + 1] > k
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_off[mid + 1] > k) hi = mid; else lo = mid + 1;
+            }
+            const uint32_t j = k - s_off[lo];
+            const uint32_t w = s_w[lo];
+            const uint32_t ty = s_y0[lo] + j / w, tx = s_x0[lo] + j % w;
+            const uint32_t pos = atomicAdd(&s_slot[ty * a.tiles_x + tx], 1u);
+            if ((unsigned long long)pos < cap)
+                a.pairs[pos] = ((unsigned long long)s_z[lo] << 32) | (unsigned long long)(blk.gid0 + lo);
+        }
+        __syncthreads();
     }
 }
 
 // --------------------------------------------------------------------------------------------
-// per-tile sort by (z bits, id): tiles are classed by list length; each class is sorted by a
-// persistent grid pulling tiles from its list
+// per-tile sort by (z bits, id): tiles are classed by list length (classes 0..4: at most
+// 1024, 2048, 4096, 8192, 16384 entries, sorted in LDS; class 5: longer, chunk sort + merge;
+// class 6: at most one entry or overflowed, not sorted); each class is sorted by a persistent
+// grid pulling tiles from its list.  The lists also order the persistent compositor's queue,
+// longest class first.
 // --------------------------------------------------------------------------------------------
+// append a wavefront's flagged lanes to a device list with one atomic; returns each flagged
+// lane's slot
+__device__ inline uint32_t wave_append(uint32_t* counter, bool pred) {
+    const unsigned long long m = __ballot(pred);
+    if (m == 0ull) return 0u;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+    base = __shfl(base, leader, 64);
+    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
 __global__ void k_classify(FwdArgs a) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.tiles) return;
-    const uint32_t s = a.starts[t], e = a.starts[t + 1];
-    if ((unsigned long long)e > (unsigned long long)a.pair_cap) return;  // overflow: left unsorted
-    const uint32_t n = e - s;
     int cls = -1;
-    if (n > 1) cls = n <= (uint32_t)kSortSmallCap ? 0 : (n <= (uint32_t)kSortMidCap ? 1 : 2);
-    if (cls < 0) return;
-    const uint32_t pos = atomicAdd(&a.status->cls[cls], 1u);
-    a.cls_list[(size_t)cls * a.tiles + pos] = (uint32_t)t;
+    if (t < a.tiles) {
+        const uint32_t s = a.starts[t], e = a.starts[t + 1];
+        const uint32_t n = e - s;
+        if ((unsigned long long)e > (unsigned long long)a.pair_cap || n <= 1) cls = kSortNone;
+        else if (n <= 1024) cls = 0;
+        else if (n <= 2048) cls = 1;
+        else if (n <= 4096) cls = 2;
+        else if (n <= 8192) cls = 3;
+        else if (n <= 16384) cls = 4;
+        else cls = kSortBig;
+    }
+#pragma unroll
+    for (int c = 0; c < kNumClasses; ++c) {
+        const uint32_t pos = wave_append(&a.status->cls[c], cls == c);
+        if (cls == c) a.cls_list[(size_t)c * a.tiles + pos] = (uint32_t)t;
+    }
 }
 
 // bitonic sort of n <= CAP unique 64-bit keys in LDS (padded with all-ones to a power of two)
@@ -570,36 +590,71 @@ __global__ __launch_bounds__(NT) void k_sort_big(FwdArgs a, int cls) {
 }
 
 // --------------------------------------------------------------------------------------------
-// front-to-back compositing, one tile per block, one pixel per thread.  Records of a batch of
-// list entries are staged in LDS (conic pre-scaled so alpha = o * exp2(q(dx, dy))); a
-// wavefront whose pixels have all stopped skips the batch; the block leaves when every pixel
-// has stopped or the list ends.  Per pixel:
-//   alpha = min(0.99, o G); skip if alpha < 1/255; stop (without blending) if
-//   T (1 - alpha) < 1e-4; else C += alpha T c, D += alpha T z, T *= 1 - alpha.
-//   rgb = C + T bg, depth = D, alpha = 1 - T.
+// front-to-back compositing.  One tile per block, one sub-tile per wavefront; each lane shades
+// PPT pixels of one column, sharing the LDS reads and the dx terms.  List entries are staged
+// in LDS per batch with the conic pre-scaled, so that for a pixel offset (dx, dy)
+//   q = A' dx^2 + B' dx dy + C' dy^2 + log2(o),   A' = -1/2 log2(e) A, B' = -log2(e) B,
+//   C' = -1/2 log2(e) C,   alpha = min(0.99, exp2(q)) = min(0.99, o G).
+// Per pixel: skip if alpha < 1/255; stop (without blending) if T (1 - alpha) < 1e-4; else
+// C += alpha T c, D += alpha T z, T *= 1 - alpha.  rgb = C + T bg, depth = D, alpha = 1 - T.
+// The loop is predicated; a wavefront skips an entry that reaches none of its pixels and
+// leaves the list as soon as none of its pixels is live.
 // --------------------------------------------------------------------------------------------
-template <int TW, int TH>
-__device__ __forceinline__ void composite_tile(const FwdArgs& a, const long long t, float4* s0, float4* s1, float4* s2) {
-    constexpr int NT = TW * TH;
+// Sub-tile of one wavefront: SW x SH pixels, 64 lanes x PPT pixels per lane (pixel p of a
+// lane sits 64 / SW rows below pixel p - 1).  8 x 8 squares when the tile allows.
+template <int TW, int TH, int PPT>
+struct SubTile {
+    static constexpr int SW = (TH % (8 * PPT) == 0) ? 8 : 16;
+    static constexpr int SH = 64 * PPT / SW;
+    static constexpr int WAVES = (TW / SW) * (TH / SH);
+    static constexpr int LROWS = 64 / SW;
+};
+
+// One wavefront composites its sub-tile of tile t, walking the tile's whole list in batches of
+// 64 entries staged in the wavefront's own LDS (wavefront-level synchronisation only, so each
+// wavefront stops as soon as its own pixels are saturated).
+template <int TW, int TH, int PPT, bool SAVE>
+__device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long t, const int wave, const int lane,
+                                              float4* s0, float4* s1, float2* s2) {
+    using ST = SubTile<TW, TH, PPT>;
     const int image = (int)(t / a.tpi);
     const int lt = (int)(t - (long long)image * a.tpi);
     const int ty = lt / a.tiles_x, tx = lt - ty * a.tiles_x;
-    const int px = tx * TW + (int)(threadIdx.x % TW), py = ty * TH + (int)(threadIdx.x / TW);
-    const bool inside = px < a.width && py < a.height;
+    const int sx = wave % (TW / ST::SW), sy = wave / (TW / ST::SW);
+    const int px = tx * TW + sx * ST::SW + lane % ST::SW;
+    const int py0 = ty * TH + sy * ST::SH + lane / ST::SW;
     uint32_t start = a.starts[t], end = a.starts[t + 1];
     if ((unsigned long long)end > (unsigned long long)a.pair_cap) end = start;  // overflow
     const int env = image / a.C, cam = image - env * a.C;
     const Env ev = a.envs[env];
     const long long rec_off = (long long)a.C * ev.gid_base + (long long)cam * ev.n - (long long)ev.gid_base;
-    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const float fpx = (float)px + 0.5f;
     const float thr = (float)(1.0 / 255.0);
-    float T = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, D = 0.0f;
-    uint32_t last = 0;
-    uint32_t evals = inside ? end - start : 0u;  // entries evaluated, up to and including the stop
-    bool done = !inside;
-    for (uint32_t base = start; base < end; base += NT) {
-        if (__syncthreads_count(done) == NT) break;
-        const uint32_t j = base + threadIdx.x;
+    // Per pixel: T > 0 is the transmittance while the pixel is live; at the stop T becomes
+    // -T (the sign marks a stopped pixel and |T| keeps its final transmittance), so later
+    // entries add nothing.  Pixels outside the image start stopped.
+    float fpy[PPT], T[PPT], Cr[PPT], Cg[PPT], Cb[PPT], D[PPT];
+    uint32_t last[PPT], evals[PPT];
+    bool inside[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int py = py0 + p * ST::LROWS;
+        inside[p] = px < a.width && py < a.height;
+        fpy[p] = (float)py + 0.5f;
+        T[p] = inside[p] ? 1.0f : -1.0f;
+        Cr[p] = Cg[p] = Cb[p] = D[p] = 0.0f;
+        last[p] = 0;
+        evals[p] = 0;
+    }
+    // an entry with q below this for every lane of a wavefront cannot pass the 1/255 test
+    // (exp2 is accurate to ~1e-7 relative, the margin is 1e-3 in the exponent)
+    const float qcut = -7.994353436858858f - 1e-3f;  // log2(1/255) - 1e-3
+    for (uint32_t base = start; base < end; base += 64) {
+        bool any = false;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) any |= T[p] > 0.0f;
+        if (!__any(any)) break;
+        const uint32_t j = base + lane;
         if (j < end) {
             const uint32_t gid = (uint32_t)a.pairs[j];
             Record R;
@@ -607,103 +662,118 @@ __device__ __forceinline__ void composite_tile(const FwdArgs& a, const long long
                 R = a.records[rec_off + gid];
             } else {  // never produced by a consistent emission; blends nothing
                 R.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-                R.r1 = make_float4(0.f, 0.f, 0.f, 0.f);
+                R.r1 = make_float4(0.f, 0.f, 0.f, -1e30f);
                 R.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
                 atomicOr(&a.status->flags, 2u);
             }
-            s0[threadIdx.x] = R.r0;
-            // -1/2 log2(e) A, -log2(e) B, -1/2 log2(e) C
-            s1[threadIdx.x] = make_float4(-0.7213475204444817f * R.r1.x, -1.4426950408889634f * R.r1.y,
-                                          -0.7213475204444817f * R.r1.z, 0.0f);
-            s2[threadIdx.x] = R.r2;
+            s0[lane] = make_float4(R.r0.x, R.r0.y, -0.7213475204444817f * R.r1.x, -1.4426950408889634f * R.r1.y);
+            s1[lane] = make_float4(-0.7213475204444817f * R.r1.z, R.r1.w, R.r0.w, R.r2.x);
+            s2[lane] = make_float2(R.r2.y, R.r2.z);
         }
-        __syncthreads();
-        const int n = (int)((end - base) < (uint32_t)NT ? (end - base) : (uint32_t)NT);
-        if (!done) {
-            for (int k = 0; k < n; ++k) {
-                const float4 r0 = s0[k];
-                const float4 r1 = s1[k];
-                const float dx = fpx - r0.x, dy = fpy - r0.y;
-                const float q = fmaf(r1.x * dx, dx, fmaf(r1.y * dx, dy, r1.z * dy * dy));
-                if (q > 0.0f) continue;
-                const float al = fminf(0.99f, r0.z * __builtin_amdgcn_exp2f(q));
-                if (al < thr) continue;
-                const float test = T * (1.0f - al);
-                if (test < 1e-4f) {
-                    done = true;
-                    evals = base - start + (uint32_t)k + 1u;
-                    break;
-                }
-                const float4 r2 = s2[k];
-                const float wgt = al * T;
-                Cr = fmaf(wgt, r2.x, Cr);
-                Cg = fmaf(wgt, r2.y, Cg);
-                Cb = fmaf(wgt, r2.z, Cb);
-                D = fmaf(wgt, r0.w, D);
-                T = test;
-                last = base - start + (uint32_t)k + 1u;
+        // the wavefront's LDS writes are visible to its own later reads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int n = (int)((end - base) < 64u ? (end - base) : 64u);
+        for (int k = 0; k < n; ++k) {
+            if ((k & 3) == 0) {
+                bool wl = false;
+#pragma unroll
+                for (int p = 0; p < PPT; ++p) wl |= T[p] > 0.0f;
+                if (!__any(wl)) break;
+            }
+            const float4 e0 = s0[k];
+            const float4 e1 = s1[k];
+            const float dx = fpx - e0.x;
+            const float Adx = e0.z * dx, Bdx = e0.w * dx;
+            const float qx = fmaf(Adx, dx, e1.y);
+            float q[PPT];
+            bool hit = false;
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                const float dy = fpy[p] - e0.y;
+                q[p] = fmaf(Bdx, dy, fmaf(e1.x * dy, dy, qx));
+                evals[p] += T[p] > 0.0f ? 1u : 0u;
+                hit |= q[p] >= qcut;
+            }
+            if (!__any(hit)) continue;
+            const float2 e2 = s2[k];
+            const uint32_t idx1 = base - start + (uint32_t)k + 1u;
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                const float al = fminf(0.99f, __builtin_amdgcn_exp2f(q[p]));
+                const float w = al >= thr ? al * T[p] : 0.0f;
+                const float Tn = T[p] - w;
+                const bool st = Tn < 1e-4f;  // also true for a stopped pixel (T < 0)
+                const float wb = st ? 0.0f : w;
+                Cr[p] = fmaf(wb, e1.w, Cr[p]);
+                Cg[p] = fmaf(wb, e2.x, Cg[p]);
+                Cb[p] = fmaf(wb, e2.y, Cb[p]);
+                D[p] = fmaf(wb, e1.z, D[p]);
+                T[p] = st ? -fabsf(T[p]) : Tn;
+                if (SAVE) last[p] = wb > 0.0f ? idx1 : last[p];
             }
         }
+        // all lanes are done reading this batch before the next one overwrites it
+        __builtin_amdgcn_wave_barrier();
     }
-    if (inside) {
-        const gsr_camera& cm = a.cams[image];
-        const size_t p = ((size_t)image * a.height + py) * a.width + px;
-        a.rgb[3 * p + 0] = fmaf(T, cm.bg[0], Cr);
-        a.rgb[3 * p + 1] = fmaf(T, cm.bg[1], Cg);
-        a.rgb[3 * p + 2] = fmaf(T, cm.bg[2], Cb);
-        a.depth[p] = D;
-        if (a.alpha) a.alpha[p] = 1.0f - T;
-        a.T_final[p] = T;
-        a.n_contrib[p] = last;
-    }
-    unsigned long long nev = evals;
-    for (int off = 32; off > 0; off >>= 1) nev += __shfl_xor(nev, off, 64);
-    if ((threadIdx.x & 63) == 0 && nev) atomicAdd(&a.status->evals, nev);
-}
-
-template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_composite(FwdArgs a) {
-    __shared__ float4 s0[TW * TH], s1[TW * TH], s2[TW * TH];
-    composite_tile<TW, TH>(a, (long long)blockIdx.x, s0, s1, s2);
-}
-
-// tiles bucketed by floor(log2(list length)) + 1, then scattered longest bucket first
-__global__ void k_order_count(FwdArgs a) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.tiles) return;
-    const uint32_t n = a.starts[t + 1] - a.starts[t];
-    atomicAdd(&a.buckets[n ? 32 - __clz(n) : 0], 1u);
-}
-
-__global__ void k_order_scatter(FwdArgs a) {
-    __shared__ uint32_t off[33];
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int b = 32; b >= 0; --b) {
-            off[b] = run;
-            run += a.buckets[b];
+    const gsr_camera& cm = a.cams[image];
+    unsigned long long nev = 0;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        nev += evals[p];
+        if (!inside[p]) continue;
+        const float Tf = fabsf(T[p]);
+        const int py = py0 + p * ST::LROWS;
+        const size_t q = ((size_t)image * a.height + py) * a.width + px;
+        a.rgb[3 * q + 0] = fmaf(Tf, cm.bg[0], Cr[p]);
+        a.rgb[3 * q + 1] = fmaf(Tf, cm.bg[1], Cg[p]);
+        a.rgb[3 * q + 2] = fmaf(Tf, cm.bg[2], Cb[p]);
+        a.depth[q] = D[p];
+        if (a.alpha) a.alpha[q] = 1.0f - Tf;
+        if (SAVE) {
+            a.T_final[q] = Tf;
+            a.n_contrib[q] = last[p];
         }
     }
-    __syncthreads();
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.tiles) return;
-    const uint32_t n = a.starts[t + 1] - a.starts[t];
-    const int b = n ? 32 - __clz(n) : 0;
-    a.order[off[b] + atomicAdd(&a.buckets[33 + b], 1u)] = (uint32_t)t;
+    for (int off = 32; off > 0; off >>= 1) nev += __shfl_xor(nev, off, 64);
+    if (lane == 0 && nev) atomicAdd(&a.status->evals, nev);
 }
 
-// persistent grid: each block pulls the next tile from the device queue until it drains
-template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_composite_persistent(FwdArgs a) {
-    __shared__ float4 s0[TW * TH], s1[TW * TH], s2[TW * TH];
-    __shared__ uint32_t s_item;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(&a.status->work_head, 1u);
-        __syncthreads();
-        const uint32_t item = s_item;
-        __syncthreads();
-        if ((long long)item >= a.tiles) break;
-        composite_tile<TW, TH>(a, (long long)a.order[item], s0, s1, s2);
+template <int TW, int TH, int PPT, bool SAVE>
+__global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composite(FwdArgs a) {
+    constexpr int NW = SubTile<TW, TH, PPT>::WAVES;
+    __shared__ float4 s0[NW][64], s1[NW][64];
+    __shared__ float2 s2[NW][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    composite_sub<TW, TH, PPT, SAVE>(a, (long long)blockIdx.x, wave, lane, s0[wave], s1[wave], s2[wave]);
+}
+
+// persistent grid: block b takes queue items b, b + G, b + 2G, ... of the longest-first queue
+// (sort classes from the longest lists down, then the lists of at most one entry).  A static
+// interleave needs no shared counter: a single global atomic per tile would serialise the
+// grid.  The wavefronts of a block work on the same tile independently.
+template <int TW, int TH, int PPT, bool SAVE>
+__global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composite_persistent(FwdArgs a) {
+    constexpr int NW = SubTile<TW, TH, PPT>::WAVES;
+    __shared__ float4 s0[NW][64], s1[NW][64];
+    __shared__ float2 s2[NW][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const Status* st = a.status;
+    uint32_t cnt[kNumClasses];
+#pragma unroll
+    for (int c = 0; c < kNumClasses; ++c) cnt[c] = st->cls[c];
+    for (long long item = blockIdx.x; item < a.tiles; item += gridDim.x) {
+        // queue order: longest class first (5, 4, 3, 2, 1, 0), then class 6
+        uint32_t k = (uint32_t)item;
+        int cls = kSortBig;
+        while (cls >= 0 && k >= cnt[cls]) {
+            k -= cnt[cls];
+            --cls;
+        }
+        if (cls < 0) cls = kSortNone;
+        composite_sub<TW, TH, PPT, SAVE>(a, (long long)a.cls_list[(size_t)cls * a.tiles + k], wave, lane, s0[wave],
+                                         s1[wave], s2[wave]);
     }
 }
 
@@ -728,24 +798,27 @@ template <int L>
 static hipError_t launch_project(const FwdArgs& a, hipStream_t s) {
     const int gsz = (a.tiles_x + 1) * (a.tiles_y + 1);
     const size_t lds = (size_t)a.C * gsz * sizeof(int);
-    if (a.C * gsz <= kLdsHistLimit)
-        hipLaunchKernelGGL((k_project<L, true>), dim3(a.n_blocks), dim3(kBlock), lds, s, a);
-    else
-        hipLaunchKernelGGL((k_project<L, false>), dim3(a.n_blocks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_project<L>), dim3(a.n_supers), dim3(kBlock), lds, s, a);
     return hipGetLastError();
 }
 
-template <int TW, int TH>
-static void launch_composite(const FwdArgs& a, hipStream_t s) {
+template <int TW, int TH, int PPT, bool SAVE>
+static void launch_composite_s(const FwdArgs& a, hipStream_t s) {
+    constexpr int NT = 64 * SubTile<TW, TH, PPT>::WAVES;
     if (a.persistent) {
-        const unsigned nb = (unsigned)((a.tiles + 255) / 256);
-        hipLaunchKernelGGL(k_order_count, dim3(nb), dim3(256), 0, s, a);
-        hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(256), 0, s, a);
-        const long long g = a.persistent_grid < a.tiles ? a.persistent_grid : a.tiles;
-        hipLaunchKernelGGL((k_composite_persistent<TW, TH>), dim3((unsigned)(g > 0 ? g : 1)), dim3(TW * TH), 0, s, a);
+        // persistent_grid counts 256-thread blocks
+        const long long want = (long long)a.persistent_grid * 256 / NT;
+        const long long g = want < a.tiles ? want : a.tiles;
+        hipLaunchKernelGGL((k_composite_persistent<TW, TH, PPT, SAVE>), dim3((unsigned)(g > 0 ? g : 1)), dim3(NT), 0, s, a);
     } else {
-        hipLaunchKernelGGL((k_composite<TW, TH>), dim3((unsigned)a.tiles), dim3(TW * TH), 0, s, a);
+        hipLaunchKernelGGL((k_composite<TW, TH, PPT, SAVE>), dim3((unsigned)a.tiles), dim3(NT), 0, s, a);
     }
+}
+
+template <int TW, int TH, int PPT>
+static void launch_composite(const FwdArgs& a, hipStream_t s) {
+    if (a.save) launch_composite_s<TW, TH, PPT, true>(a, s);
+    else launch_composite_s<TW, TH, PPT, false>(a, s);
 }
 
 static int g_num_cu = 0;
@@ -764,7 +837,7 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
     mark(0);
     hipLaunchKernelGGL(k_views, dim3((nv + 63) / 64), dim3(64), 0, s, a);
     mark(1);
-    if (a.n_blocks > 0) {
+    if (a.n_supers > 0) {
         hipError_t e;
         switch (a.sh_degree) {
             case 0: e = launch_project<0>(a, s); break;
@@ -775,30 +848,29 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
         if (e != hipSuccess) return e;
     }
     mark(2);
-    const int gsz = (a.tiles_x + 1) * (a.tiles_y + 1);
-    hipLaunchKernelGGL(k_tile_counts, dim3(a.images), dim3(256), (size_t)gsz * sizeof(int), s, a);
+    hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)((a.tiles + 255) / 256)), dim3(256), 0, s, a);
     mark(3);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
     mark(4);
-    if (a.n_blocks > 0) {
-        if (a.tpi <= kLdsHistLimit)
-            hipLaunchKernelGGL(k_emit<true>, dim3(a.n_blocks, a.C), dim3(kBlock), (size_t)a.tpi * sizeof(uint32_t), s, a);
-        else
-            hipLaunchKernelGGL(k_emit<false>, dim3(a.n_blocks, a.C), dim3(kBlock), 0, s, a);
-    }
+    if (a.n_supers > 0)
+        hipLaunchKernelGGL(k_emit, dim3(a.n_supers, a.C), dim3(kBlock), (size_t)a.tpi * sizeof(uint32_t), s, a);
     mark(5);
     hipLaunchKernelGGL(k_classify, dim3((unsigned)((a.tiles + 255) / 256)), dim3(256), 0, s, a);
     mark(6);
-    hipLaunchKernelGGL((k_sort_lds<256, kSortSmallCap>), dim3(g_num_cu * 8), dim3(256), 0, s, a, 0);
+    hipLaunchKernelGGL((k_sort_lds<256, 1024>), dim3(g_num_cu * 16), dim3(256), 0, s, a, 0);
+    hipLaunchKernelGGL((k_sort_lds<256, 2048>), dim3(g_num_cu * 8), dim3(256), 0, s, a, 1);
     mark(7);
-    hipLaunchKernelGGL((k_sort_lds<1024, kSortMidCap>), dim3(g_num_cu), dim3(1024), 0, s, a, 1);
+    hipLaunchKernelGGL((k_sort_lds<512, 4096>), dim3(g_num_cu * 4), dim3(512), 0, s, a, 2);
+    hipLaunchKernelGGL((k_sort_lds<1024, 8192>), dim3(g_num_cu * 2), dim3(1024), 0, s, a, 3);
+    hipLaunchKernelGGL((k_sort_lds<1024, 16384>), dim3(g_num_cu), dim3(1024), 0, s, a, 4);
     mark(8);
-    hipLaunchKernelGGL((k_sort_big<1024, kSortMidCap>), dim3(g_num_cu), dim3(1024), 0, s, a, 2);
+    hipLaunchKernelGGL((k_sort_big<1024, kSortMidCap>), dim3(g_num_cu), dim3(1024), 0, s, a, kSortBig);
     mark(9);
-    if (a.tw == 16 && a.th == 16) launch_composite<16, 16>(a, s);
-    else if (a.tw == 16 && a.th == 8) launch_composite<16, 8>(a, s);
-    else if (a.tw == 8 && a.th == 8) launch_composite<8, 8>(a, s);
-    else launch_composite<32, 8>(a, s);
+    const bool two = a.ppt == 2;
+    if (a.tw == 16 && a.th == 16) { if (two) launch_composite<16, 16, 2>(a, s); else launch_composite<16, 16, 1>(a, s); }
+    else if (a.tw == 16 && a.th == 8) { if (two) launch_composite<16, 8, 2>(a, s); else launch_composite<16, 8, 1>(a, s); }
+    else if (a.tw == 8 && a.th == 8) launch_composite<8, 8, 1>(a, s);
+    else { if (two) launch_composite<32, 8, 2>(a, s); else launch_composite<32, 8, 1>(a, s); }
     mark(10);
     return hipGetLastError();
 }

@@ -10,8 +10,14 @@
 namespace gsr {
 
 constexpr int kBlock = 256;          // Gaussians per projection / emission block
-constexpr int kSortSmallCap = 2048;  // per-tile lists sorted by a 256-thread block
-constexpr int kSortMidCap = 16384;   // per-tile lists sorted by a 1024-thread block in LDS
+// Per-tile sort classes by list length: lists of at most kSortCap[c] entries are sorted in LDS
+// by a block of kSortThreads[c] threads; longer lists (class kSortBig) are chunk-sorted and
+// merged; class kSortNone holds lists of at most one entry (and overflowed tiles).
+constexpr int kSortClasses = 5;
+constexpr int kSortBig = 5;
+constexpr int kSortNone = 6;
+constexpr int kNumClasses = 7;
+constexpr int kSortMidCap = 16384;
 constexpr int kLdsHistLimit = 16384; // int counters a block may keep in LDS for tile histograms
 
 // One (node, camera) view: the camera<-node map composed in FP64 and rounded
@@ -41,6 +47,7 @@ struct Env {
     uint32_t gid_base;  // scene-global id of the env's first Gaussian
     uint32_t n;         // Gaussians in the env
     int32_t node_begin, node_end;
+    int32_t sb_begin, sb_count;  // the env's super-blocks
 };
 
 // A chunk of at most kBlock consecutive Gaussians of one node.
@@ -51,23 +58,33 @@ struct Block {
     uint32_t count;
 };
 
+// Consecutive chunks of one env processed by one projection / emission block, so that the
+// block's per-tile pair counts cover many Gaussians.
+struct Super {
+    int32_t env;
+    int32_t chunk_begin, chunk_end;
+    int32_t pad;
+};
+
+constexpr int kMaxChunksPerSuper = 16;
+
 struct Status {
     uint32_t flags;
     uint32_t nonfinite;
     unsigned long long pairs;
     uint32_t max_tile;
-    uint32_t cls[4];      // tile counts per sort class
-    uint32_t work_head;   // persistent composite queue head
+    uint32_t cls[8];      // tile counts per sort class
+    uint32_t work_head;   // unused
     unsigned long long visible;      // visible (image, Gaussian) records
     unsigned long long visible_any;  // Gaussians visible in at least one camera
     unsigned long long evals;        // Gaussian-pixel evaluations of the compositor
-    uint32_t pad[2];
+    uint32_t pad[6];
 };
 
 constexpr int kStages = 10;  // views, project, tile counts, scan, emit, classify, 3 sorts, composite
 
 // Projected record of one (image, Gaussian): r0 = (u, v, opacity, z),
-// r1 = conic (A, B, C, 0) of the inverse dilated 2D covariance,
+// r1 = (A, B, C, log2 opacity) with (A, B, C) the conic (inverse dilated 2D covariance),
 // r2 = (r, g, b, 0) SH colour.  48 bytes.
 struct Record {
     float4 r0, r1, r2;
@@ -79,6 +96,8 @@ struct FwdArgs {
     const Env* envs;
     const Block* blocks;
     int n_blocks;
+    const Super* supers;
+    int n_supers;
     int n_nodes;
     int sh_degree;
     const gsr_pose* poses;
@@ -93,13 +112,11 @@ struct FwdArgs {
     View* views;
     Record* records;
     uint4* rects;        // per (image, Gaussian): x0 | y0 << 16, x1 | y1 << 16, z bits, 0
-    int* diff;           // per image: (tiles_y + 1) x (tiles_x + 1) difference grid
+    uint32_t* sbcnt;     // per (super-block, camera, tile): pair count, then slot offset
     uint32_t* counts;    // per tile
     uint32_t* starts;    // per tile + 1
     uint32_t* cursor;    // per tile
-    uint32_t* cls_list;  // 4 lists of `tiles` entries
-    uint32_t* order;     // tiles ordered by decreasing list length (persistent composite)
-    uint32_t* buckets;   // 2 x 33 counters: tiles per log2 length bucket, fill cursors
+    uint32_t* cls_list;  // kNumClasses lists of `tiles` entries
     unsigned long long* pairs;
     unsigned long long* pairs_alt;
     long long pair_cap;
@@ -112,6 +129,8 @@ struct FwdArgs {
     uint32_t* n_contrib;
     int persistent;
     int persistent_grid;
+    int ppt;   // pixels per compositor thread (1 or 2; 8x8 tiles use 1)
+    int save;  // write per-pixel T_final and contributor counts for the backward
     hipEvent_t* stage_events;  // kStages + 1 events recorded between stages, or null
 };
 

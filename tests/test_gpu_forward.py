@@ -201,9 +201,15 @@ def test_repeat_renders_bitwise_identical(gsr, ctx):
 
 def test_permutation_of_gaussians_is_bitwise_invariant(gsr, ctx):
     import torch
-    wl = synth.scene_config(0, seed=23, scale=0.3)
-    ref = oracle_images(wl, 16, 16)[0]
-    assert len(np.unique(ref["keys"])) == len(ref["keys"]), "z ties: pick another seed"
+    # the first seed whose keys (tile, z bits) are all distinct: equal keys are ordered by id,
+    # which a permutation changes
+    for seed in range(23, 60):
+        wl = synth.scene_config(0, seed=seed, scale=0.3)
+        ref = oracle_images(wl, 16, 16)[0]
+        if len(np.unique(ref["keys"])) == len(ref["keys"]):
+            break
+    else:
+        pytest.fail("no tie-free seed")
     _, _, rgb, depth, alpha = render_gpu(ctx, wl)
     rgb, depth = rgb.clone(), depth.clone()
     perm = np.random.default_rng(1).permutation(len(wl["envs"][0]["nodes"][0]["means"]))

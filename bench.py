@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-fwdbwd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", default="auto", help="auto (autotuner) or WxH")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device (calibrates HBM traffic counters) and exit")
     return ap.parse_args()
 
 
@@ -73,6 +75,16 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * 2 ** 20 // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
+        return
 
     import paper_2507_21981_amd as gsr
     import synth
@@ -149,7 +161,8 @@ def main():
             stage[k] += v / n_t
     st_t = gsr.query_status(ctx)
     log("[bench] stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stage.items()))
-    roof = roofline(stage, st_t, n_total, E, C, wl)
+    ppt = ctx.config().pixels_per_thread
+    roof = roofline(stage, st_t, n_total, (tw, th, ppt, pers))
 
     # per-camera loop on the same frames
     loop = None
@@ -203,53 +216,87 @@ def main():
     ctx.close()
 
 
-def roofline(stage, st, n_total, E, C, wl):
-    """Dominant kernel of the step against its bound (algorithmic work from device counters)."""
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "hbm_traffic_batched_64envs_320x240.json")
+
+
+def measured_traffic():
+    """Per-kernel HBM bytes per dispatch from the committed counter runs, or None when the
+    kernel sources have changed since those counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        h = hashlib.sha256()
+        root = os.path.dirname(os.path.abspath(__file__))
+        for src in rec["sources"]:
+            h.update(open(os.path.join(root, src), "rb").read())
+    except (OSError, ValueError, KeyError):
+        return None
+    return rec["kernels"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
+def roofline(stage, st, n_total, cfg):
+    """Dominant kernel of the step against its bound (algorithmic work from device counters).
+
+    Algorithmic work per unit: projection reads 44 B per Gaussian (mean, opacity, scales,
+    quaternion), 12 K B of SH per Gaussian visible from any camera, and writes 64 B per visible
+    (image, Gaussian) (48 B record + 16 B visible-list entry); emission reads the 16 B list entry
+    and writes 8 B per pair; the sort reads and writes each pair once (8 B each way); the
+    compositor does at least OPS_PER_EVAL VALU lane-operations per Gaussian-pixel evaluation.
+    """
     K = 16
     visible, visible_any, pairs, evals = st["visible"], st["visible_any"], st["pairs"], st["evals"]
-    recs = sum(C * len(n["means"]) for e in wl["envs"] for n in e["nodes"])  # (image, Gaussian) entries
     work = {
-        # per Gaussian: mean 12 + opacity 4 + scales 12 + quaternion 16 B read; SH 12 K B read when
-        # visible from any camera; per (image, Gaussian): 16 B rectangle written, 48 B record
-        # written when visible
-        "project": ("hbm", 44 * n_total + 12 * K * visible_any + 16 * recs + 48 * visible),
-        # rectangles read (16 B per (image, Gaussian)), 8 B per pair written
-        "emit": ("hbm", 16 * recs + 8 * pairs),
-        # each pair read and written once (8 B each way) across the three sort classes
+        "project": ("hbm", 44 * n_total + 12 * K * visible_any + 64 * visible),
+        "emit": ("hbm", 16 * visible + 8 * pairs),
         "sort": ("hbm", 16 * pairs),
         "composite": ("alu", evals * OPS_PER_EVAL),
     }
     times = {"project": stage["project"], "emit": stage["emit"],
              "sort": stage["sort_small"] + stage["sort_mid"] + stage["sort_big"], "composite": stage["composite"]}
-    dom = max(times, key=times.get)
+    tw, th, ppt, pers = cfg
+    kname = {"project": "k_project<3>(FwdArgs)", "emit": "k_emit(FwdArgs)",
+             "composite": f"k_composite{'_persistent' if pers else ''}<{tw}, {th}, {ppt}, false>(FwdArgs)"}
+    traffic = measured_traffic()
+
+    def kernel_traffic(k):
+        if traffic is None:
+            return None
+        names = [kname[k]] if k in kname else [n for n in traffic if n.startswith("k_sort")]
+        if not names or any(n not in traffic for n in names):
+            return None
+        return sum(traffic[n]["fetch_bytes"] + traffic[n]["write_bytes"] for n in names)
+
+    # the dominant single kernel (the sort stage is six launches, each shorter)
+    dom = max(("project", "emit", "composite"), key=times.get)
     t = times[dom] * 1e-3
     bound, amount = work[dom]
+    ach = amount / t / 1e9
     if bound == "hbm":
-        ach = amount / t / 1e9
-        r = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-             "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "algorithmic_bytes": int(amount)}
+        r = {"kernel": kname[dom], "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+             "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": kernel_traffic(dom), "algorithmic_bytes": int(amount)}
     else:
-        ach = amount / t / 1e9
-        r = {"kernel": dom, "bound": "alu", "achieved": round(ach, 1), "peak": round(PEAK_VALU_GOPS, 1),
-             "unit": "Gop/s (VALU lane-ops)", "frac": round(ach / PEAK_VALU_GOPS, 4), "traffic": None,
-             "evals": int(evals), "ops_per_eval": OPS_PER_EVAL}
+        r = {"kernel": kname[dom], "bound": "alu", "achieved": round(ach, 1), "peak": round(PEAK_VALU_GOPS, 1),
+             "unit": "Gop/s (VALU lane-ops)", "frac": round(ach / PEAK_VALU_GOPS, 4),
+             "traffic": kernel_traffic(dom), "evals": int(evals), "ops_per_eval": OPS_PER_EVAL}
     r["kernel_ms"] = round(times[dom], 4)
     r["others"] = {}
     for k in times:
-        if k == dom:
+        if k == dom or times[k] <= 0:
             continue
         b, amt = work[k]
         tk = times[k] * 1e-3
-        if tk > 0:
-            if b == "hbm":
-                r["others"][k] = {"bound": "hbm", "GB/s": round(amt / tk / 1e9, 1), "frac": round(amt / tk / 1e9 / PEAK_HBM_GBS, 4),
-                                  "ms": round(times[k], 4)}
-            else:
-                r["others"][k] = {"bound": "alu", "Gop/s": round(amt / tk / 1e9, 1),
-                                  "frac": round(amt / tk / 1e9 / PEAK_VALU_GOPS, 4), "ms": round(times[k], 4)}
+        o = {"bound": b, "ms": round(times[k], 4), "traffic": kernel_traffic(k)}
+        if b == "hbm":
+            o.update({"GB/s": round(amt / tk / 1e9, 1), "frac": round(amt / tk / 1e9 / PEAK_HBM_GBS, 4),
+                      "algorithmic_bytes": int(amt)})
+        else:
+            o.update({"Gop/s": round(amt / tk / 1e9, 1), "frac": round(amt / tk / 1e9 / PEAK_VALU_GOPS, 4)})
+        r["others"][k] = o
     pb = work["project"][1] + work["emit"][1] + work["sort"][1]
     tp = (times["project"] + times["emit"] + times["sort"]) * 1e-3
-    r["project_emit_sort"] = {"GB/s": round(pb / tp / 1e9, 1), "frac": round(pb / tp / 1e9 / PEAK_HBM_GBS, 4)}
+    r["project_emit_sort"] = {"GB/s": round(pb / tp / 1e9, 1), "frac": round(pb / tp / 1e9 / PEAK_HBM_GBS, 4),
+                              "ms": round(tp * 1e3, 4)}
     return r
 
 
@@ -341,30 +388,42 @@ def fwd_bwd(gsr, args):
         ev1.record()
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / n
+        # forward alone (same flags), for the split
+        ev0.record()
+        for _ in range(n):
+            gsr.render_rgbd(ctx, scene, cams, 640, 480, flags=gsr.FLAG_SAVE)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms_fwd = ev0.elapsed_time(ev1) / n
         st = gsr.query_status(ctx)
         assert st["flags"] == 0, st
         gn = {k: float(v.norm()) for k, v in grads[0].items()}
         return {"ms_per_step": round(ms, 3), "views": 8, "ms_per_view": round(ms / 8, 3),
+                "forward_ms_per_step": round(ms_fwd, 3), "pairs_per_step": st["pairs"],
                 "workload": "500k Gaussians SH3, 8 views 640x480, L1 loss, grads for means/scales/quats/opacities/sh",
                 "grad_norms": gn}
     finally:
         ctx.close()
 
 
-def cpu_baseline(wl, tw, th, n_envs=1):
-    """The FP64 CPU oracle, timed on the host, on full frames of the first env(s)."""
+def cpu_baseline(wl, tw, th, budget_s=10.0):
+    """The FP64 CPU oracle, timed on the host, on full frames of the workload's envs in order
+    until about ``budget_s`` seconds of CPU work (or every env) are done."""
     import oracle
     W, H, C = wl["width"], wl["height"], wl["cams_per_env"]
     t0 = time.time()
-    px = 0
-    for env in wl["envs"][:n_envs]:
+    px = n_envs = 0
+    for env in wl["envs"]:
         fe = oracle.FlatEnv(env)
         for cam in env["cams"]:
             oracle.render(env, cam, W, H, tw, th, fe=fe)
             px += W * H
+        n_envs += 1
+        if time.time() - t0 >= budget_s:
+            break
     dt = time.time() - t0
     return {"value": round(px / dt / 1e6, 4), "unit": "Mpixels/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"first {n_envs} env(s) x {C} cams, full {W}x{H} frames ({px} pixels), "
+            "sample": f"first {n_envs} of {len(wl['envs'])} envs x {C} cams, full {W}x{H} frames ({px} pixels), "
                       f"projection + key sort + FP64 compositing, {dt:.1f} s"}
 
 

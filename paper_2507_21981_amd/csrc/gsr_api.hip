@@ -66,6 +66,7 @@ struct gsr_scene {
     Super* supers_d = nullptr;
     const gsr_pose* poses = nullptr;
     uint64_t version = 0;
+    int sb_cap = kBlock;  // Gaussians per super-block at most
 };
 
 struct gsr_context {
@@ -78,7 +79,8 @@ struct gsr_context {
     DevBuf<unsigned long long> pairs, pairs_alt;
     long long pair_cap = 0;
     DevBuf<Record> records;
-    DevBuf<uint4> rects;
+    DevBuf<uint4> vis;
+    DevBuf<uint32_t> sbvis;
     DevBuf<uint32_t> sbcnt;
     DevBuf<uint32_t> counts, starts, cursor, cls_list;
     DevBuf<View> views;
@@ -202,7 +204,7 @@ void gsr_destroy(gsr_context* ctx) {
     for (auto& e : ctx->stage_ev)
         if (e) hipEventDestroy(e);
     if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
-    ctx->pairs.release(); ctx->pairs_alt.release(); ctx->records.release(); ctx->rects.release();
+    ctx->pairs.release(); ctx->pairs_alt.release(); ctx->records.release(); ctx->vis.release(); ctx->sbvis.release();
     ctx->sbcnt.release(); ctx->counts.release(); ctx->starts.release(); ctx->cursor.release();
     ctx->cls_list.release(); ctx->views.release(); ctx->T_final.release(); ctx->n_contrib.release();
     ctx->g2d.release(); ctx->grads_dev.release();
@@ -325,6 +327,7 @@ int gsr_compose_scene(gsr_context* ctx, int32_t n_envs, const int32_t* off, cons
     const long long nchunks = (long long)sc->blocks_h.size();
     const int cps = (int)std::max(1ll, std::min<long long>(kMaxChunksPerSuper, nchunks / (8ll * std::max(ctx->num_cu, 1))));
     sc->supers_h.clear();
+    sc->sb_cap = cps * kBlock;
     {
         size_t ch = 0;
         for (int e = 0; e < n_envs; ++e) {
@@ -397,7 +400,9 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
     const size_t nrec = (size_t)C * (size_t)sc->total;
     const size_t npix = (size_t)a.images * W * H;
     int r;
-    if ((r = ensure(ctx, ctx->records, nrec)) || (r = ensure(ctx, ctx->rects, nrec)) ||
+    const int sb_cap = sc->sb_cap;
+    if ((r = ensure(ctx, ctx->records, nrec)) || (r = ensure(ctx, ctx->vis, (size_t)a.n_supers * C * sb_cap)) ||
+        (r = ensure(ctx, ctx->sbvis, (size_t)a.n_supers * C)) ||
         (r = ensure(ctx, ctx->sbcnt, (size_t)a.n_supers * C * a.tpi)) || (r = ensure(ctx, ctx->counts, a.tiles)) ||
         (r = ensure(ctx, ctx->starts, a.tiles + 1)) || (r = ensure(ctx, ctx->cursor, a.tiles)) ||
         (r = ensure(ctx, ctx->cls_list, (size_t)kNumClasses * a.tiles)) ||
@@ -408,7 +413,9 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
     if ((r = ensure(ctx, ctx->pairs, ctx->pair_cap)) || (r = ensure(ctx, ctx->pairs_alt, ctx->pair_cap))) return r;
     a.views = ctx->views.p;
     a.records = ctx->records.p;
-    a.rects = ctx->rects.p;
+    a.vis = ctx->vis.p;
+    a.sbvis = ctx->sbvis.p;
+    a.sb_cap = sb_cap;
     a.sbcnt = ctx->sbcnt.p;
     a.counts = ctx->counts.p;
     a.starts = ctx->starts.p;

@@ -169,14 +169,17 @@ __device__ inline float3 sh_colour(const float* __restrict__ sh, float dx, float
 // --------------------------------------------------------------------------------------------
 template <int L>
 __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a) {
-    // LDS: per camera of the env, a (tiles_y + 1) x (tiles_x + 1) difference grid of pair
-    // counts: a rectangle adds +1/-1 at its four corners; the 2D prefix gives pairs per tile
-    extern __shared__ int s_grid[];
+    // LDS: per camera, the count of this super-block's visible Gaussians, then a
+    // (tiles_y + 1) x (tiles_x + 1) difference grid of pair counts: a rectangle adds +1/-1 at
+    // its four corners; the 2D prefix gives pairs per tile
+    extern __shared__ int s_lds[];
     const Super sb = a.supers[blockIdx.x];
     const Env ev = a.envs[sb.env];
     const int C = a.C;
     const int gx = a.tiles_x + 1, gy = a.tiles_y + 1, gsz = gx * gy;
-    for (int i = threadIdx.x; i < C * gsz; i += kBlock) s_grid[i] = 0;
+    uint32_t* s_nvis = reinterpret_cast<uint32_t*>(s_lds);
+    int* s_grid = s_lds + C;
+    for (int i = threadIdx.x; i < C * gsz + C; i += kBlock) s_lds[i] = 0;
     __syncthreads();
     constexpr int K = (L + 1) * (L + 1);
     const int i = threadIdx.x;
@@ -199,7 +202,6 @@ __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a) {
         for (int c = 0; c < C; ++c) {
             const View& v = a.views[blk.node * C + c];
             const size_t rec = (size_t)C * ev.gid_base + (size_t)c * ev.n + lg;
-            uint4 rect = make_uint4(0u, 0u, 0u, 0u);
             do {
                 if (!have_sq) {
                     s0 = nd.scales[3 * li + 0]; s1 = nd.scales[3 * li + 1]; s2 = nd.scales[3 * li + 2];
@@ -271,10 +273,13 @@ __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a) {
                 Record R;
                 R.r0 = make_float4(u, vv, o, z);
                 R.r1 = make_float4(cc * idet, -cb * idet, ca * idet, log2f(o));
-                R.r2 = make_float4(col.x, col.y, col.z, 0.0f);
+                R.r2 = make_float4(col.x, col.y, col.z, det);
                 a.records[rec] = R;
-                rect = make_uint4((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16),
-                                  __float_as_uint(z), 1u);
+                // append to this super-block's visible list for camera c
+                const uint32_t slot = atomicAdd(&s_nvis[c], 1u);
+                a.vis[((size_t)blockIdx.x * C + c) * a.sb_cap + slot] =
+                    make_uint4((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16),
+                               __float_as_uint(z), gid);
                 // pair counts: +1/-1 corners of the rectangle in the image's difference grid
                 int* h = s_grid + c * gsz;
                 atomicAdd(h + ty0 * gx + tx0, 1);
@@ -284,7 +289,6 @@ __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a) {
                 ++n_vis;
                 vis_any = true;
             } while (false);
-            a.rects[rec] = rect;
         }
         n_any += vis_any ? 1 : 0;
     }
@@ -303,7 +307,8 @@ __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a) {
         for (int y = 0; y < gy; ++y) { acc += g[y * gx]; g[y * gx] = acc; }
     }
     __syncthreads();
-    // this super-block's pairs per (camera, tile), plain stores
+    // this super-block's pairs per (camera, tile) and visible-list lengths, plain stores
+    if (threadIdx.x < C) a.sbvis[(size_t)blockIdx.x * C + threadIdx.x] = s_nvis[threadIdx.x];
     uint32_t* out = a.sbcnt + (size_t)blockIdx.x * C * a.tpi;
     for (int j = threadIdx.x; j < C * a.tpi; j += kBlock) {
         const int c = j / a.tpi, t = j - c * a.tpi;
@@ -392,18 +397,18 @@ __global__ __launch_bounds__(1024) void k_scan(FwdArgs a) {
 }
 
 // --------------------------------------------------------------------------------------------
-// pair emission into tile buckets.  Each super-block knows, per tile, the first slot of its
-// pairs (tile start + the offsets of the env's earlier super-blocks), so slots are taken with
-// LDS atomics only.  Within a chunk, the (Gaussian, tile) pairs are enumerated with a
-// block-wide prefix over rectangle areas, so large rectangles are shared by all threads.
+// pair emission into tile buckets.  Each (super-block, camera) walks its compact list of
+// visible Gaussians and knows, per tile, the first slot of its pairs (tile start + the offsets
+// of the env's earlier super-blocks), so slots are taken with LDS atomics only.  Within a
+// batch of 256 list entries, the (Gaussian, tile) pairs are enumerated with a block-wide
+// prefix over rectangle areas, so large rectangles are shared by all threads.
 // Pair = (z bits << 32) | Gaussian id.
 // --------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_emit(FwdArgs a) {
     extern __shared__ uint32_t s_slot[];
     __shared__ uint32_t s_off[kBlock + 1];
-    __shared__ uint32_t s_x0[kBlock], s_y0[kBlock], s_w[kBlock], s_z[kBlock];
+    __shared__ uint32_t s_x0[kBlock], s_y0[kBlock], s_w[kBlock], s_z[kBlock], s_id[kBlock];
     const Super sb = a.supers[blockIdx.x];
-    const Env ev = a.envs[sb.env];
     const int c = blockIdx.y;
     const size_t image = (size_t)sb.env * a.C + c;
     const int tpi = a.tpi;
@@ -411,17 +416,19 @@ __global__ __launch_bounds__(kBlock) void k_emit(FwdArgs a) {
     for (int t = threadIdx.x; t < tpi; t += kBlock) s_slot[t] = a.starts[image * tpi + t] + so[t];
     const int i = threadIdx.x;
     const unsigned long long cap = (unsigned long long)a.pair_cap;
-    for (int ch = sb.chunk_begin; ch < sb.chunk_end; ++ch) {
-        const Block blk = a.blocks[ch];
+    const uint32_t nv = a.sbvis[(size_t)blockIdx.x * a.C + c];
+    const uint4* lst = a.vis + ((size_t)blockIdx.x * a.C + c) * a.sb_cap;
+    for (uint32_t b0 = 0; b0 < nv; b0 += kBlock) {
         uint32_t n_i = 0;
-        if (i < (int)blk.count) {
-            const uint4 r = a.rects[(size_t)a.C * ev.gid_base + (size_t)c * ev.n + (blk.gid0 - ev.gid_base) + i];
+        if (b0 + i < nv) {
+            const uint4 r = lst[b0 + i];
             const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu, y1 = r.y >> 16;
-            if (r.w != 0u && x1 > x0 && y1 > y0) n_i = (x1 - x0) * (y1 - y0);
+            n_i = (x1 - x0) * (y1 - y0);
             s_x0[i] = x0;
             s_y0[i] = y0;
             s_w[i] = x1 - x0;
             s_z[i] = r.z;
+            s_id[i] = r.w;
         }
         // block-wide exclusive scan of n_i (Hillis-Steele in LDS)
         s_off[i + 1] = n_i;
@@ -445,7 +452,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(FwdArgs a) {
             const uint32_t ty = s_y0[lo] + j / w, tx = s_x0[lo] + j % w;
             const uint32_t pos = atomicAdd(&s_slot[ty * a.tiles_x + tx], 1u);
             if ((unsigned long long)pos < cap)
-                a.pairs[pos] = ((unsigned long long)s_z[lo] << 32) | (unsigned long long)(blk.gid0 + lo);
+                a.pairs[pos] = ((unsigned long long)s_z[lo] << 32) | (unsigned long long)s_id[lo];
         }
         __syncthreads();
     }
@@ -532,6 +539,155 @@ __global__ __launch_bounds__(NT) void k_sort_lds(FwdArgs a, int cls) {
     }
 }
 
+// Stable LSD radix sort of one tile's list in LDS, for lists of at most NT * E entries.
+// Keys are the depth bits relative to the list's minimum, so only the significant bits are
+// sorted, 4 per pass; values are the Gaussian ids.  Thread t owns entries [t E, t E + E)
+// ("blocked"); a pass ranks each thread's entries with packed per-digit counters in
+// registers, scans the (digit, thread) counts in digit-major order across the block and
+// scatters the pairs to their stable positions.  Entries with equal depth bits are finally
+// ordered by id (runs of equal keys are rare and short; the emission order within a tile is
+// already by id across super-blocks).
+template <int NT, int E>
+__global__ __launch_bounds__(NT) void k_sort_radix(FwdArgs a, int cls) {
+    constexpr int CAP = NT * E;
+    constexpr int NW = NT / 64;
+    __shared__ unsigned long long s_kv[CAP];
+    __shared__ uint16_t s_cnt[16 * NT];
+    __shared__ uint32_t s_w[2 * NW];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const uint32_t count = a.status->cls[cls];
+    for (uint32_t w = blockIdx.x; w < count; w += gridDim.x) {
+        const uint32_t tile = a.cls_list[(size_t)cls * a.tiles + w];
+        const uint32_t st = a.starts[tile], n = a.starts[tile + 1] - st;
+        unsigned long long* p = a.pairs + st;
+        for (int i = t; i < CAP; i += NT) s_kv[i] = (uint32_t)i < n ? p[i] : ~0ull;
+        __syncthreads();
+        uint32_t key[E], val[E];
+        uint32_t zmin = 0xffffffffu, zmax = 0u;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const unsigned long long u = s_kv[t * E + r];
+            key[r] = (uint32_t)(u >> 32);
+            val[r] = (uint32_t)u;
+            if ((uint32_t)(t * E + r) < n) {
+                zmin = key[r] < zmin ? key[r] : zmin;
+                zmax = key[r] > zmax ? key[r] : zmax;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint32_t a1 = __shfl_xor(zmin, off, 64), a2 = __shfl_xor(zmax, off, 64);
+            zmin = a1 < zmin ? a1 : zmin;
+            zmax = a2 > zmax ? a2 : zmax;
+        }
+        if (lane == 0) {
+            s_w[wave] = zmin;
+            s_w[NW + wave] = zmax;
+        }
+        __syncthreads();
+        zmin = s_w[0];
+        zmax = s_w[NW];
+        for (int i = 1; i < NW; ++i) {
+            zmin = s_w[i] < zmin ? s_w[i] : zmin;
+            zmax = s_w[NW + i] > zmax ? s_w[NW + i] : zmax;
+        }
+        const uint32_t range = zmax - zmin;
+        const int bits = range ? 32 - __clz((int)range) : 0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) key[r] = (uint32_t)(t * E + r) < n ? key[r] - zmin : 0xffffffffu;
+        __syncthreads();  // s_w is reused by the scans below
+        for (int sh = 0; sh < bits; sh += 4) {
+            // per-thread digit counts, packed 8 bits per digit in four words
+            uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const uint32_t d = (key[r] >> sh) & 15u;
+                const uint32_t q = d >> 2, inc = 1u << ((d & 3u) << 3);
+                c0 += q == 0 ? inc : 0u;
+                c1 += q == 1 ? inc : 0u;
+                c2 += q == 2 ? inc : 0u;
+                c3 += q == 3 ? inc : 0u;
+            }
+#pragma unroll
+            for (int d = 0; d < 16; ++d) {
+                const uint32_t cw = d < 4 ? c0 : (d < 8 ? c1 : (d < 12 ? c2 : c3));
+                s_cnt[d * NT + t] = (uint16_t)((cw >> ((d & 3) << 3)) & 255u);
+            }
+            __syncthreads();
+            // exclusive scan of the counts in digit-major order: thread t takes 16 in a row
+            uint32_t tot = 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) tot += s_cnt[t * 16 + j];
+            uint32_t incl = tot;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += y;
+            }
+            if (lane == 63) s_w[wave] = incl;
+            __syncthreads();
+            uint32_t base = incl - tot;
+            for (int i = 0; i < wave; ++i) base += s_w[i];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const uint32_t v = s_cnt[t * 16 + j];
+                s_cnt[t * 16 + j] = (uint16_t)base;
+                base += v;
+            }
+            __syncthreads();
+            // scatter: the rank among this thread's earlier entries with the same digit is
+            // recounted on the way (cheaper in registers than keeping E ranks)
+            c0 = c1 = c2 = c3 = 0;
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const uint32_t d = (key[r] >> sh) & 15u;
+                const uint32_t q = d >> 2, f = (d & 3u) << 3;
+                const uint32_t cw = q == 0 ? c0 : (q == 1 ? c1 : (q == 2 ? c2 : c3));
+                const uint32_t inc = 1u << f;
+                c0 += q == 0 ? inc : 0u;
+                c1 += q == 1 ? inc : 0u;
+                c2 += q == 2 ? inc : 0u;
+                c3 += q == 3 ? inc : 0u;
+                const uint32_t dest = ((uint32_t)s_cnt[d * NT + t] + ((cw >> f) & 255u)) & (uint32_t)(CAP - 1);
+                s_kv[dest] = ((unsigned long long)key[r] << 32) | val[r];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const unsigned long long u = s_kv[t * E + r];
+                key[r] = (uint32_t)(u >> 32);
+                val[r] = (uint32_t)u;
+            }
+            __syncthreads();
+        }
+        // s_kv now holds the entries in key order (or in input order if every key is equal)
+        // ties: a run of equal keys is put in id order by the thread that owns its first entry
+        for (int r = 0; r < E; ++r) {
+            const uint32_t i = (uint32_t)(t * E + r);
+            if (i + 1 >= n) break;
+            const uint32_t k = (uint32_t)(s_kv[i] >> 32);
+            if ((uint32_t)(s_kv[i + 1] >> 32) != k) continue;
+            if (i > 0 && (uint32_t)(s_kv[i - 1] >> 32) == k) continue;
+            uint32_t j = i + 1;
+            while (j < n && (uint32_t)(s_kv[j] >> 32) == k) ++j;
+            for (uint32_t x = i + 1; x < j; ++x) {  // insertion sort of [i, j) (equal keys: by id)
+                const unsigned long long u = s_kv[x];
+                uint32_t y = x;
+                while (y > i && s_kv[y - 1] > u) {
+                    s_kv[y] = s_kv[y - 1];
+                    --y;
+                }
+                s_kv[y] = u;
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = t; i < n; i += NT) {
+            const unsigned long long u = s_kv[i];
+            p[i] = ((unsigned long long)((uint32_t)(u >> 32) + zmin) << 32) | (u & 0xffffffffull);
+        }
+        __syncthreads();
+    }
+}
+
 // number of keys in sorted src[0, n) that are smaller than x
 __device__ inline uint32_t lower_rank(const unsigned long long* src, uint32_t n, unsigned long long x) {
     uint32_t lo = 0, hi = n;
@@ -597,8 +753,9 @@ __global__ __launch_bounds__(NT) void k_sort_big(FwdArgs a, int cls) {
 //   C' = -1/2 log2(e) C,   alpha = min(0.99, exp2(q)) = min(0.99, o G).
 // Per pixel: skip if alpha < 1/255; stop (without blending) if T (1 - alpha) < 1e-4; else
 // C += alpha T c, D += alpha T z, T *= 1 - alpha.  rgb = C + T bg, depth = D, alpha = 1 - T.
-// The loop is predicated; a wavefront skips an entry that reaches none of its pixels and
-// leaves the list as soon as none of its pixels is live.
+// Each batch of the list is culled against the wavefront's sub-tile and compacted (in list
+// order) before the pixel loop; the loop is predicated, a wavefront skips an entry that
+// reaches none of its pixels and leaves the list as soon as none of its pixels is live.
 // --------------------------------------------------------------------------------------------
 // Sub-tile of one wavefront: SW x SH pixels, 64 lanes x PPT pixels per lane (pixel p of a
 // lane sits 64 / SW rows below pixel p - 1).  8 x 8 squares when the tile allows.
@@ -610,12 +767,50 @@ struct SubTile {
     static constexpr int LROWS = 64 / SW;
 };
 
+// Whether a projected entry can pass the skip test q >= qcut at some pixel centre of the
+// rectangle [x0, x1] x [y0, y1].  With m(d) = A dx^2 + 2 B dx dy + C dy^2 (the conic's form),
+// q = log2(o) - m log2(e) / 2, so the test is m <= rho2 = 2 ln 2 (log2(o) - qcut).  The minimum
+// of m over the rectangle is 0 when the mean lies inside; otherwise it lies on an edge that
+// faces the mean, where m is minimised in closed form along the edge and clamped to it.  Each
+// candidate is evaluated as a sum of two non-negative squares (completing the square, with
+// the covariance entries C D and A D), which has no cancellation.  The slack covers the
+// rounding of that evaluation and of the compositor's own FP32 evaluation of q, whose error
+// grows with the magnitude of the form's terms over the rectangle (tmax).  Entries that fail
+// the test change no pixel, so dropping them leaves the result bit-identical.
+__device__ inline bool reaches_rect(const Record& R, float x0, float x1, float y0, float y1, float qcut) {
+    const float u = R.r0.x, v = R.r0.y, A = R.r1.x, B = R.r1.y, C = R.r1.z, lo = R.r1.w, D = R.r2.w;
+    const float rho2 = 1.3862943611198906f * (lo - qcut);
+    if (!(rho2 > 0.0f)) return false;
+    const float gx = fmaxf(fmaxf(x0 - u, u - x1), 0.0f);
+    const float gy = fmaxf(fmaxf(y0 - v, v - y1), 0.0f);
+    if (gx == 0.0f && gy == 0.0f) return true;
+    const float Dx = fmaxf(fabsf(x0 - u), fabsf(x1 - u)), Dy = fmaxf(fabsf(y0 - v), fabsf(y1 - v));
+    const float tmax = A * Dx * Dx + 2.0f * fabsf(B) * Dx * Dy + C * Dy * Dy + fabsf(lo);
+    const float slack = 4e-6f * tmax + 1e-4f * rho2 + 1e-3f;
+    float mmin = INFINITY;
+    if (gx > 0.0f) {  // the facing vertical edge
+        const float dx = u < x0 ? x0 - u : x1 - u;
+        const float bc = B / C;
+        const float dy = fminf(fmaxf(-bc * dx, y0 - v), y1 - v);
+        const float t = dy + bc * dx;
+        mmin = C * t * t + dx * dx / (C * D);
+    }
+    if (gy > 0.0f) {  // the facing horizontal edge
+        const float dy = v < y0 ? y0 - v : y1 - v;
+        const float ba = B / A;
+        const float dx = fminf(fmaxf(-ba * dy, x0 - u), x1 - u);
+        const float t = dx + ba * dy;
+        mmin = fminf(mmin, A * t * t + dy * dy / (A * D));
+    }
+    return mmin <= rho2 + slack;
+}
+
 // One wavefront composites its sub-tile of tile t, walking the tile's whole list in batches of
 // 64 entries staged in the wavefront's own LDS (wavefront-level synchronisation only, so each
 // wavefront stops as soon as its own pixels are saturated).
 template <int TW, int TH, int PPT, bool SAVE>
 __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long t, const int wave, const int lane,
-                                              float4* s0, float4* s1, float2* s2) {
+                                              float4* s0, float4* s1, float4* s2) {
     using ST = SubTile<TW, TH, PPT>;
     const int image = (int)(t / a.tpi);
     const int lt = (int)(t - (long long)image * a.tpi);
@@ -649,32 +844,40 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
     // an entry with q below this for every lane of a wavefront cannot pass the 1/255 test
     // (exp2 is accurate to ~1e-7 relative, the margin is 1e-3 in the exponent)
     const float qcut = -7.994353436858858f - 1e-3f;  // log2(1/255) - 1e-3
+    // the wavefront's pixel-centre rectangle
+    const float rx0 = (float)(tx * TW + sx * ST::SW) + 0.5f, rx1 = rx0 + (float)(ST::SW - 1);
+    const float ry0 = (float)(ty * TH + sy * ST::SH) + 0.5f, ry1 = ry0 + (float)(ST::SH - 1);
     for (uint32_t base = start; base < end; base += 64) {
         bool any = false;
 #pragma unroll
         for (int p = 0; p < PPT; ++p) any |= T[p] > 0.0f;
         if (!__any(any)) break;
+        // stage the batch's entries that can reach this sub-tile, compacted in list order
         const uint32_t j = base + lane;
+        Record R;
+        bool keep = false;
         if (j < end) {
             const uint32_t gid = (uint32_t)a.pairs[j];
-            Record R;
             if (gid - ev.gid_base < ev.n) {
                 R = a.records[rec_off + gid];
+                keep = reaches_rect(R, rx0, rx1, ry0, ry1, qcut);
             } else {  // never produced by a consistent emission; blends nothing
-                R.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-                R.r1 = make_float4(0.f, 0.f, 0.f, -1e30f);
-                R.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
                 atomicOr(&a.status->flags, 2u);
             }
-            s0[lane] = make_float4(R.r0.x, R.r0.y, -0.7213475204444817f * R.r1.x, -1.4426950408889634f * R.r1.y);
-            s1[lane] = make_float4(-0.7213475204444817f * R.r1.z, R.r1.w, R.r0.w, R.r2.x);
-            s2[lane] = make_float2(R.r2.y, R.r2.z);
+        }
+        const unsigned long long km = __ballot(keep);
+        if (keep) {
+            const int slot = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+            s0[slot] = make_float4(R.r0.x, R.r0.y, -0.7213475204444817f * R.r1.x, -1.4426950408889634f * R.r1.y);
+            s1[slot] = make_float4(-0.7213475204444817f * R.r1.z, R.r1.w, R.r0.w, R.r2.x);
+            s2[slot] = make_float4(R.r2.y, R.r2.z, __uint_as_float(j - start + 1u), 0.0f);
         }
         // the wavefront's LDS writes are visible to its own later reads
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int n = (int)((end - base) < 64u ? (end - base) : 64u);
+        const int n = __popcll(km);
         for (int k = 0; k < n; ++k) {
             if ((k & 3) == 0) {
                 bool wl = false;
@@ -697,8 +900,8 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
                 hit |= q[p] >= qcut;
             }
             if (!__any(hit)) continue;
-            const float2 e2 = s2[k];
-            const uint32_t idx1 = base - start + (uint32_t)k + 1u;
+            const float4 e2 = s2[k];
+            const uint32_t idx1 = __float_as_uint(e2.z);
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {
                 const float al = fminf(0.99f, __builtin_amdgcn_exp2f(q[p]));
@@ -744,7 +947,7 @@ template <int TW, int TH, int PPT, bool SAVE>
 __global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composite(FwdArgs a) {
     constexpr int NW = SubTile<TW, TH, PPT>::WAVES;
     __shared__ float4 s0[NW][64], s1[NW][64];
-    __shared__ float2 s2[NW][64];
+    __shared__ float4 s2[NW][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     composite_sub<TW, TH, PPT, SAVE>(a, (long long)blockIdx.x, wave, lane, s0[wave], s1[wave], s2[wave]);
 }
@@ -757,7 +960,7 @@ template <int TW, int TH, int PPT, bool SAVE>
 __global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composite_persistent(FwdArgs a) {
     constexpr int NW = SubTile<TW, TH, PPT>::WAVES;
     __shared__ float4 s0[NW][64], s1[NW][64];
-    __shared__ float2 s2[NW][64];
+    __shared__ float4 s2[NW][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const Status* st = a.status;
     uint32_t cnt[kNumClasses];
@@ -797,7 +1000,7 @@ __global__ void k_copy_pairs(FwdArgs a, uint64_t* keys, uint32_t* vals, uint32_t
 template <int L>
 static hipError_t launch_project(const FwdArgs& a, hipStream_t s) {
     const int gsz = (a.tiles_x + 1) * (a.tiles_y + 1);
-    const size_t lds = (size_t)a.C * gsz * sizeof(int);
+    const size_t lds = (size_t)a.C * (gsz + 1) * sizeof(int);
     hipLaunchKernelGGL((k_project<L>), dim3(a.n_supers), dim3(kBlock), lds, s, a);
     return hipGetLastError();
 }
@@ -857,12 +1060,12 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
     mark(5);
     hipLaunchKernelGGL(k_classify, dim3((unsigned)((a.tiles + 255) / 256)), dim3(256), 0, s, a);
     mark(6);
-    hipLaunchKernelGGL((k_sort_lds<256, 1024>), dim3(g_num_cu * 16), dim3(256), 0, s, a, 0);
-    hipLaunchKernelGGL((k_sort_lds<256, 2048>), dim3(g_num_cu * 8), dim3(256), 0, s, a, 1);
+    hipLaunchKernelGGL((k_sort_radix<128, 8>), dim3(g_num_cu * 16), dim3(128), 0, s, a, 0);
+    hipLaunchKernelGGL((k_sort_radix<256, 8>), dim3(g_num_cu * 8), dim3(256), 0, s, a, 1);
     mark(7);
-    hipLaunchKernelGGL((k_sort_lds<512, 4096>), dim3(g_num_cu * 4), dim3(512), 0, s, a, 2);
-    hipLaunchKernelGGL((k_sort_lds<1024, 8192>), dim3(g_num_cu * 2), dim3(1024), 0, s, a, 3);
-    hipLaunchKernelGGL((k_sort_lds<1024, 16384>), dim3(g_num_cu), dim3(1024), 0, s, a, 4);
+    hipLaunchKernelGGL((k_sort_radix<256, 16>), dim3(g_num_cu * 4), dim3(256), 0, s, a, 2);
+    hipLaunchKernelGGL((k_sort_radix<512, 16>), dim3(g_num_cu * 2), dim3(512), 0, s, a, 3);
+    hipLaunchKernelGGL((k_sort_radix<512, 32>), dim3(g_num_cu), dim3(512), 0, s, a, 4);
     mark(8);
     hipLaunchKernelGGL((k_sort_big<1024, kSortMidCap>), dim3(g_num_cu), dim3(1024), 0, s, a, kSortBig);
     mark(9);

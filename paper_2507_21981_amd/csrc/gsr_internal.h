@@ -85,7 +85,8 @@ constexpr int kStages = 10;  // views, project, tile counts, scan, emit, classif
 
 // Projected record of one (image, Gaussian): r0 = (u, v, opacity, z),
 // r1 = (A, B, C, log2 opacity) with (A, B, C) the conic (inverse dilated 2D covariance),
-// r2 = (r, g, b, 0) SH colour.  48 bytes.
+// r2 = (r, g, b, D) SH colour and D the determinant of the dilated 2D covariance (so that
+// the covariance entries are recovered without cancellation: Sxx = C D, Syy = A D).  48 bytes.
 struct Record {
     float4 r0, r1, r2;
 };
@@ -111,7 +112,10 @@ struct FwdArgs {
     // workspace
     View* views;
     Record* records;
-    uint4* rects;        // per (image, Gaussian): x0 | y0 << 16, x1 | y1 << 16, z bits, 0
+    uint4* vis;          // per (super-block, camera): list of visible Gaussians,
+                         //   {x0 | y0 << 16, x1 | y1 << 16, z bits, Gaussian id}
+    uint32_t* sbvis;     // per (super-block, camera): length of that list
+    int sb_cap;          // list capacity per (super-block, camera)
     uint32_t* sbcnt;     // per (super-block, camera, tile): pair count, then slot offset
     uint32_t* counts;    // per tile
     uint32_t* starts;    // per tile + 1

@@ -161,7 +161,7 @@ def main():
             stage[k] += v / n_t
     st_t = gsr.query_status(ctx)
     log("[bench] stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stage.items()))
-    ppt = ctx.config().pixels_per_thread
+    ppt = ctx.config.pixels_per_thread
     roof = roofline(stage, st_t, n_total, (tw, th, ppt, pers))
 
     # per-camera loop on the same frames

@@ -132,8 +132,11 @@ typedef struct {
     uint32_t reserved;
     uint64_t visible;        /* visible (image, Gaussian) projections                         */
     uint64_t visible_any;    /* Gaussians visible from at least one camera of their env       */
-    uint64_t evals;          /* Gaussian-pixel evaluations: over pixels, list entries
-                                evaluated up to and including the stopping one              */
+    uint64_t evals;          /* Gaussian-pixel evaluations of the last render: over pixels,
+                                the list entries that reach the pixel's wavefront sub-tile,
+                                evaluated up to and including the stopping one.  Counted
+                                only by renders with GSR_FLAG_CHECK or GSR_FLAG_TIMING (0
+                                otherwise).                                                 */
 } gsr_status_info;
 
 /* Number of timed forward stages and their names, in order: views, project,

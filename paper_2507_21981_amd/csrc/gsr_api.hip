@@ -434,6 +434,7 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
     a.persistent_grid = ctx->cfg.persistent_grid;
     a.ppt = (tw == 8 && th == 8) ? 1 : ctx->cfg.pixels_per_thread;
     a.save = save;
+    a.count = 0;
     return GSR_OK;
 }
 
@@ -459,6 +460,8 @@ int gsr_render_rgbd(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_
     FwdArgs a;
     int r = prepare(ctx, sc, C, cams, W, H, rgb, depth, alpha, persistent, save, a);
     if (r) return r;
+    const int count = (flags & (GSR_FLAG_CHECK | GSR_FLAG_TIMING)) ? 1 : 0;
+    a.count = count;
     ctx->last_stream = s;
     if (flags & GSR_FLAG_GRAPH) {
         GraphKey k{sc, cams, rgb, depth, alpha, C, W, H, ctx->cfg.tile_w, ctx->cfg.tile_h, persistent, a.ppt,
@@ -500,6 +503,7 @@ int gsr_render_rgbd(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_
             ctx->pair_cap = (long long)(ctx->h_status->pairs * 5 / 4) + 1024;
             drop_graph(ctx);
             if ((r = prepare(ctx, sc, C, cams, W, H, rgb, depth, alpha, persistent, save, a))) return r;
+            a.count = count;
             if (flags & GSR_FLAG_TIMING) a.stage_events = ctx->stage_ev;
         }
         a.stage_events = nullptr;

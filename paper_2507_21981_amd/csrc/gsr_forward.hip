@@ -112,36 +112,40 @@ __device__ inline void sh_basis(float x, float y, float z, float* Y) {
     }
 }
 
+// colour = max(0, sum_k c_k Y_k(d) + 1/2) for coefficients c[3 K] (k-major, rgb) and the
+// direction d (not necessarily unit).  The normalisation uses the hardware reciprocal square
+// root: the colour enters no key, only pixel values.
 template <int L>
-__device__ inline float3 sh_colour(const float* __restrict__ sh, float dx, float dy, float dz) {
+__device__ inline float3 sh_colour(const float* c, float dx, float dy, float dz) {
     constexpr int K = (L + 1) * (L + 1);
-    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    const float inv = __builtin_amdgcn_rsqf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
     float Y[K];
     sh_basis<L>(dx * inv, dy * inv, dz * inv, Y);
     float r = 0.5f, g = 0.5f, b = 0.5f;
-    if constexpr ((K * 3) % 4 == 0) {
-        const float4* s4 = reinterpret_cast<const float4*>(sh);
-        float c[K * 3];
 #pragma unroll
-        for (int i = 0; i < K * 3 / 4; ++i) {
+    for (int k = 0; k < K; ++k) {
+        r = fmaf(Y[k], c[3 * k + 0], r);
+        g = fmaf(Y[k], c[3 * k + 1], g);
+        b = fmaf(Y[k], c[3 * k + 2], b);
+    }
+    return make_float3(fmaxf(r, 0.0f), fmaxf(g, 0.0f), fmaxf(b, 0.0f));
+}
+
+// one Gaussian's SH coefficients into registers (16-byte loads when the row allows)
+template <int L>
+__device__ inline void load_sh(const float* __restrict__ sh, float* c) {
+    constexpr int K3 = 3 * (L + 1) * (L + 1);
+    if constexpr (K3 % 4 == 0) {
+        const float4* s4 = reinterpret_cast<const float4*>(sh);
+#pragma unroll
+        for (int i = 0; i < K3 / 4; ++i) {
             const float4 q = s4[i];
             c[4 * i + 0] = q.x; c[4 * i + 1] = q.y; c[4 * i + 2] = q.z; c[4 * i + 3] = q.w;
         }
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            r = fmaf(Y[k], c[3 * k + 0], r);
-            g = fmaf(Y[k], c[3 * k + 1], g);
-            b = fmaf(Y[k], c[3 * k + 2], b);
-        }
     } else {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            r = fmaf(Y[k], sh[3 * k + 0], r);
-            g = fmaf(Y[k], sh[3 * k + 1], g);
-            b = fmaf(Y[k], sh[3 * k + 2], b);
-        }
+        for (int i = 0; i < K3; ++i) c[i] = sh[i];
     }
-    return make_float3(fmaxf(r, 0.0f), fmaxf(g, 0.0f), fmaxf(b, 0.0f));
 }
 
 // --------------------------------------------------------------------------------------------
@@ -183,112 +187,131 @@ __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a) {
     __syncthreads();
     constexpr int K = (L + 1) * (L + 1);
     const int i = threadIdx.x;
+    const float thr = (float)(1.0 / 255.0);
+    const float itw = 1.0f / (float)a.tw, ith = 1.0f / (float)a.th;
     int n_vis = 0, n_any = 0, nonfinite = 0;
+    // this thread's Gaussian of the next chunk, loaded one chunk ahead so that its latency
+    // overlaps the current chunk's arithmetic
+    float nm0 = 0.f, nm1 = 0.f, nm2 = 0.f, no = 0.f, ns0 = 0.f, ns1 = 0.f, ns2 = 0.f;
+    float4 nq = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto fetch = [&](int ch) {
+        const Block blk = a.blocks[ch];
+        if (i < (int)blk.count) {
+            const Node& nd = a.nodes[blk.node];
+            const size_t li = blk.gid0 + (uint32_t)i - nd.gid_base;
+            nm0 = nd.means[3 * li + 0]; nm1 = nd.means[3 * li + 1]; nm2 = nd.means[3 * li + 2];
+            no = nd.opac[li];
+            ns0 = nd.scales[3 * li + 0]; ns1 = nd.scales[3 * li + 1]; ns2 = nd.scales[3 * li + 2];
+            nq = reinterpret_cast<const float4*>(nd.quats)[li];
+        }
+    };
+    if (sb.chunk_begin < sb.chunk_end) fetch(sb.chunk_begin);
     for (int ch = sb.chunk_begin; ch < sb.chunk_end; ++ch) {
         const Block blk = a.blocks[ch];
+        const float mu0 = nm0, mu1 = nm1, mu2 = nm2, o = no, s0 = ns0, s1 = ns1, s2 = ns2;
+        const float q0 = nq.x, q1 = nq.y, q2 = nq.z, q3 = nq.w;
+        if (ch + 1 < sb.chunk_end) fetch(ch + 1);
         if (i >= (int)blk.count) continue;
-        const Node nd = a.nodes[blk.node];
+        const Node& nd = a.nodes[blk.node];
         const uint32_t gid = blk.gid0 + i;
         const size_t li = gid - nd.gid_base;
         const size_t lg = gid - ev.gid_base;
-        const float mu0 = nd.means[3 * li + 0], mu1 = nd.means[3 * li + 1], mu2 = nd.means[3 * li + 2];
-        const float o = nd.opac[li];
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f, q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
-        bool have_sq = false, sq_ok = false;
-        const bool base_ok = isfinite(mu0) && isfinite(mu1) && isfinite(mu2) && isfinite(o);
-        const float thr = (float)(1.0 / 255.0);
-        const float itw = 1.0f / (float)a.tw, ith = 1.0f / (float)a.th;
-        bool vis_any = false;
+        if (!(isfinite(mu0) && isfinite(mu1) && isfinite(mu2) && isfinite(o) && isfinite(s0) && isfinite(s1) &&
+              isfinite(s2) && isfinite(q0) && isfinite(q1) && isfinite(q2) && isfinite(q3))) {
+            nonfinite += C;  // culled and counted once per camera
+            continue;
+        }
+        if (!(o >= thr)) continue;
+        // the rotation of the unit quaternion (camera independent)
+        const float n2 = fmaf(q0, q0, fmaf(q1, q1, fmaf(q2, q2, q3 * q3)));
+        float R00 = 0.f, R01 = 0.f, R02 = 0.f, R10 = 0.f, R11 = 0.f, R12 = 0.f, R20 = 0.f, R21 = 0.f, R22 = 0.f;
+        if (n2 > 0.0f) {
+            const float rn = 1.0f / sqrtf(n2);
+            const float qw = q0 * rn, qx = q1 * rn, qy = q2 * rn, qz = q3 * rn;
+            const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
+            const float xy = qx * qy, xzq = qx * qz, yzq = qy * qz;
+            const float wx = qw * qx, wy = qw * qy, wz = qw * qz;
+            R00 = fmaf(-2.0f, yy + zz, 1.0f); R01 = 2.0f * (xy - wz); R02 = 2.0f * (xzq + wy);
+            R10 = 2.0f * (xy + wz); R11 = fmaf(-2.0f, xx + zz, 1.0f); R12 = 2.0f * (yzq - wx);
+            R20 = 2.0f * (xzq - wy); R21 = 2.0f * (yzq + wx); R22 = fmaf(-2.0f, xx + yy, 1.0f);
+        }
+        const float lo = __log2f(o);  // pixel values only
+        float shc[3 * K];
+        bool have_sh = false, vis_any = false;
         for (int c = 0; c < C; ++c) {
             const View& v = a.views[blk.node * C + c];
             const size_t rec = (size_t)C * ev.gid_base + (size_t)c * ev.n + lg;
-            do {
-                if (!have_sq) {
-                    s0 = nd.scales[3 * li + 0]; s1 = nd.scales[3 * li + 1]; s2 = nd.scales[3 * li + 2];
-                    const float4 q = reinterpret_cast<const float4*>(nd.quats)[li];
-                    q0 = q.x; q1 = q.y; q2 = q.z; q3 = q.w;
-                    sq_ok = isfinite(s0) && isfinite(s1) && isfinite(s2) && isfinite(q0) && isfinite(q1) &&
-                            isfinite(q2) && isfinite(q3);
-                    have_sq = true;
-                }
-                if (!(base_ok && sq_ok)) { ++nonfinite; break; }
-                if (!(o >= thr)) break;
-                const float p0 = fmaf(v.W[0], mu0, fmaf(v.W[1], mu1, fmaf(v.W[2], mu2, v.w[0])));
-                const float p1 = fmaf(v.W[3], mu0, fmaf(v.W[4], mu1, fmaf(v.W[5], mu2, v.w[1])));
-                const float p2 = fmaf(v.W[6], mu0, fmaf(v.W[7], mu1, fmaf(v.W[8], mu2, v.w[2])));
-                if (!(isfinite(p0) && isfinite(p1) && isfinite(p2))) { ++nonfinite; break; }
-                const float z = p2;
-                if (!(z > v.znear)) break;
-                const float iz = 1.0f / z;
-                const float xz = p0 * iz, yz = p1 * iz;
-                const float u = fmaf(v.fx, xz, v.cx), vv = fmaf(v.fy, yz, v.cy);
-                const float n2 = fmaf(q0, q0, fmaf(q1, q1, fmaf(q2, q2, q3 * q3)));
-                if (!(n2 > 0.0f)) break;
-                const float rn = 1.0f / sqrtf(n2);
-                const float qw = q0 * rn, qx = q1 * rn, qy = q2 * rn, qz = q3 * rn;
-                const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
-                const float xy = qx * qy, xzq = qx * qz, yzq = qy * qz;
-                const float wx = qw * qx, wy = qw * qy, wz = qw * qz;
-                const float R00 = fmaf(-2.0f, yy + zz, 1.0f), R01 = 2.0f * (xy - wz), R02 = 2.0f * (xzq + wy);
-                const float R10 = 2.0f * (xy + wz), R11 = fmaf(-2.0f, xx + zz, 1.0f), R12 = 2.0f * (yzq - wx);
-                const float R20 = 2.0f * (xzq - wy), R21 = 2.0f * (yzq + wx), R22 = fmaf(-2.0f, xx + yy, 1.0f);
-                float M[9];
+            const float p0 = fmaf(v.W[0], mu0, fmaf(v.W[1], mu1, fmaf(v.W[2], mu2, v.w[0])));
+            const float p1 = fmaf(v.W[3], mu0, fmaf(v.W[4], mu1, fmaf(v.W[5], mu2, v.w[1])));
+            const float p2 = fmaf(v.W[6], mu0, fmaf(v.W[7], mu1, fmaf(v.W[8], mu2, v.w[2])));
+            if (!(isfinite(p0) && isfinite(p1) && isfinite(p2))) { ++nonfinite; continue; }
+            const float z = p2;
+            if (!(z > v.znear)) continue;
+            if (!(n2 > 0.0f)) continue;
+            const float iz = 1.0f / z;
+            const float xz = p0 * iz, yz = p1 * iz;
+            const float u = fmaf(v.fx, xz, v.cx), vv = fmaf(v.fy, yz, v.cy);
+            float M[9];
 #pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    M[r * 3 + 0] = fmaf(v.W[r * 3 + 0], R00, fmaf(v.W[r * 3 + 1], R10, v.W[r * 3 + 2] * R20)) * s0;
-                    M[r * 3 + 1] = fmaf(v.W[r * 3 + 0], R01, fmaf(v.W[r * 3 + 1], R11, v.W[r * 3 + 2] * R21)) * s1;
-                    M[r * 3 + 2] = fmaf(v.W[r * 3 + 0], R02, fmaf(v.W[r * 3 + 1], R12, v.W[r * 3 + 2] * R22)) * s2;
-                }
-                const float S00 = fmaf(M[0], M[0], fmaf(M[1], M[1], M[2] * M[2]));
-                const float S01 = fmaf(M[0], M[3], fmaf(M[1], M[4], M[2] * M[5]));
-                const float S02 = fmaf(M[0], M[6], fmaf(M[1], M[7], M[2] * M[8]));
-                const float S11 = fmaf(M[3], M[3], fmaf(M[4], M[4], M[5] * M[5]));
-                const float S12 = fmaf(M[3], M[6], fmaf(M[4], M[7], M[5] * M[8]));
-                const float S22 = fmaf(M[6], M[6], fmaf(M[7], M[7], M[8] * M[8]));
-                const float xc = fminf(fmaxf(xz, -v.limx), v.limx);
-                const float yc = fminf(fmaxf(yz, -v.limy), v.limy);
-                const float j00 = v.fx * iz, j11 = v.fy * iz;
-                const float j02 = -(j00 * xc), j12 = -(j11 * yc);
-                const float T00 = fmaf(j00, S00, j02 * S02);
-                const float T01 = fmaf(j00, S01, j02 * S12);
-                const float T02 = fmaf(j00, S02, j02 * S22);
-                const float T11 = fmaf(j11, S11, j12 * S12);
-                const float T12 = fmaf(j11, S12, j12 * S22);
-                const float ca = fmaf(T00, j00, T02 * j02) + 0.3f;
-                const float cb = fmaf(T01, j11, T02 * j12);
-                const float cc = fmaf(T11, j11, T12 * j12) + 0.3f;
-                const float det = fmaf(ca, cc, -(cb * cb));
-                if (!(det > 0.0f)) break;
-                const float rx = fmaf(3.33f, sqrtf(ca), 0.015625f);
-                const float ry = fmaf(3.33f, sqrtf(cc), 0.015625f);
-                const float tx0f = fminf(fmaxf(floorf((u - rx) * itw), 0.0f), (float)a.tiles_x);
-                const float tx1f = fminf(fmaxf(floorf((u + rx) * itw) + 1.0f, 0.0f), (float)a.tiles_x);
-                const float ty0f = fminf(fmaxf(floorf((vv - ry) * ith), 0.0f), (float)a.tiles_y);
-                const float ty1f = fminf(fmaxf(floorf((vv + ry) * ith) + 1.0f, 0.0f), (float)a.tiles_y);
-                const int tx0 = (int)tx0f, tx1 = (int)tx1f, ty0 = (int)ty0f, ty1 = (int)ty1f;
-                if (tx0 >= tx1 || ty0 >= ty1) break;
-                // visible: projected record
-                const float idet = 1.0f / det;
-                const float3 col = sh_colour<L>(nd.sh + li * (K * 3), mu0 - v.cl[0], mu1 - v.cl[1], mu2 - v.cl[2]);
-                Record R;
-                R.r0 = make_float4(u, vv, o, z);
-                R.r1 = make_float4(cc * idet, -cb * idet, ca * idet, log2f(o));
-                R.r2 = make_float4(col.x, col.y, col.z, det);
-                a.records[rec] = R;
-                // append to this super-block's visible list for camera c
-                const uint32_t slot = atomicAdd(&s_nvis[c], 1u);
-                a.vis[((size_t)blockIdx.x * C + c) * a.sb_cap + slot] =
-                    make_uint4((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16),
-                               __float_as_uint(z), gid);
-                // pair counts: +1/-1 corners of the rectangle in the image's difference grid
-                int* h = s_grid + c * gsz;
-                atomicAdd(h + ty0 * gx + tx0, 1);
-                atomicAdd(h + ty0 * gx + tx1, -1);
-                atomicAdd(h + ty1 * gx + tx0, -1);
-                atomicAdd(h + ty1 * gx + tx1, 1);
-                ++n_vis;
-                vis_any = true;
-            } while (false);
+            for (int r = 0; r < 3; ++r) {
+                M[r * 3 + 0] = fmaf(v.W[r * 3 + 0], R00, fmaf(v.W[r * 3 + 1], R10, v.W[r * 3 + 2] * R20)) * s0;
+                M[r * 3 + 1] = fmaf(v.W[r * 3 + 0], R01, fmaf(v.W[r * 3 + 1], R11, v.W[r * 3 + 2] * R21)) * s1;
+                M[r * 3 + 2] = fmaf(v.W[r * 3 + 0], R02, fmaf(v.W[r * 3 + 1], R12, v.W[r * 3 + 2] * R22)) * s2;
+            }
+            const float S00 = fmaf(M[0], M[0], fmaf(M[1], M[1], M[2] * M[2]));
+            const float S01 = fmaf(M[0], M[3], fmaf(M[1], M[4], M[2] * M[5]));
+            const float S02 = fmaf(M[0], M[6], fmaf(M[1], M[7], M[2] * M[8]));
+            const float S11 = fmaf(M[3], M[3], fmaf(M[4], M[4], M[5] * M[5]));
+            const float S12 = fmaf(M[3], M[6], fmaf(M[4], M[7], M[5] * M[8]));
+            const float S22 = fmaf(M[6], M[6], fmaf(M[7], M[7], M[8] * M[8]));
+            const float xc = fminf(fmaxf(xz, -v.limx), v.limx);
+            const float yc = fminf(fmaxf(yz, -v.limy), v.limy);
+            const float j00 = v.fx * iz, j11 = v.fy * iz;
+            const float j02 = -(j00 * xc), j12 = -(j11 * yc);
+            const float T00 = fmaf(j00, S00, j02 * S02);
+            const float T01 = fmaf(j00, S01, j02 * S12);
+            const float T02 = fmaf(j00, S02, j02 * S22);
+            const float T11 = fmaf(j11, S11, j12 * S12);
+            const float T12 = fmaf(j11, S12, j12 * S22);
+            const float ca = fmaf(T00, j00, T02 * j02) + 0.3f;
+            const float cb = fmaf(T01, j11, T02 * j12);
+            const float cc = fmaf(T11, j11, T12 * j12) + 0.3f;
+            const float det = fmaf(ca, cc, -(cb * cb));
+            if (!(det > 0.0f)) continue;
+            const float rx = fmaf(3.33f, sqrtf(ca), 0.015625f);
+            const float ry = fmaf(3.33f, sqrtf(cc), 0.015625f);
+            const float tx0f = fminf(fmaxf(floorf((u - rx) * itw), 0.0f), (float)a.tiles_x);
+            const float tx1f = fminf(fmaxf(floorf((u + rx) * itw) + 1.0f, 0.0f), (float)a.tiles_x);
+            const float ty0f = fminf(fmaxf(floorf((vv - ry) * ith), 0.0f), (float)a.tiles_y);
+            const float ty1f = fminf(fmaxf(floorf((vv + ry) * ith) + 1.0f, 0.0f), (float)a.tiles_y);
+            const int tx0 = (int)tx0f, tx1 = (int)tx1f, ty0 = (int)ty0f, ty1 = (int)ty1f;
+            if (tx0 >= tx1 || ty0 >= ty1) continue;
+            // visible: projected record (the conic and colour enter pixel values only, so the
+            // hardware reciprocal suffices there)
+            const float idet = __builtin_amdgcn_rcpf(det);
+            if (!have_sh) {
+                load_sh<L>(nd.sh + li * (3 * K), shc);
+                have_sh = true;
+            }
+            const float3 col = sh_colour<L>(shc, mu0 - v.cl[0], mu1 - v.cl[1], mu2 - v.cl[2]);
+            Record R;
+            R.r0 = make_float4(u, vv, o, z);
+            R.r1 = make_float4(cc * idet, -cb * idet, ca * idet, lo);
+            R.r2 = make_float4(col.x, col.y, col.z, det);
+            a.records[rec] = R;
+            // append to this super-block's visible list for camera c
+            const uint32_t slot = atomicAdd(&s_nvis[c], 1u);
+            a.vis[((size_t)blockIdx.x * C + c) * a.sb_cap + slot] =
+                make_uint4((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16),
+                           __float_as_uint(z), gid);
+            // pair counts: +1/-1 corners of the rectangle in the image's difference grid
+            int* h = s_grid + c * gsz;
+            atomicAdd(h + ty0 * gx + tx0, 1);
+            atomicAdd(h + ty0 * gx + tx1, -1);
+            atomicAdd(h + ty1 * gx + tx0, -1);
+            atomicAdd(h + ty1 * gx + tx1, 1);
+            ++n_vis;
+            vis_any = true;
         }
         n_any += vis_any ? 1 : 0;
     }
@@ -459,9 +482,9 @@ __global__ __launch_bounds__(kBlock) void k_emit(FwdArgs a) {
 }
 
 // --------------------------------------------------------------------------------------------
-// per-tile sort by (z bits, id): tiles are classed by list length (classes 0..4: at most
-// 1024, 2048, 4096, 8192, 16384 entries, sorted in LDS; class 5: longer, chunk sort + merge;
-// class 6: at most one entry or overflowed, not sorted); each class is sorted by a persistent
+// per-tile sort by (z bits, id): tiles are classed by list length (classes 0..5: at most
+// 512, 1024, 2048, 4096, 8192, 16384 entries, sorted in LDS; class 6: longer, chunk sort +
+// merge; class 7: at most one entry or overflowed, not sorted); each class is sorted by a persistent
 // grid pulling tiles from its list.  The lists also order the persistent compositor's queue,
 // longest class first.
 // --------------------------------------------------------------------------------------------
@@ -485,11 +508,12 @@ __global__ void k_classify(FwdArgs a) {
         const uint32_t s = a.starts[t], e = a.starts[t + 1];
         const uint32_t n = e - s;
         if ((unsigned long long)e > (unsigned long long)a.pair_cap || n <= 1) cls = kSortNone;
-        else if (n <= 1024) cls = 0;
-        else if (n <= 2048) cls = 1;
-        else if (n <= 4096) cls = 2;
-        else if (n <= 8192) cls = 3;
-        else if (n <= 16384) cls = 4;
+        else if (n <= 512) cls = 0;
+        else if (n <= 1024) cls = 1;
+        else if (n <= 2048) cls = 2;
+        else if (n <= 4096) cls = 3;
+        else if (n <= 8192) cls = 4;
+        else if (n <= 16384) cls = 5;
         else cls = kSortBig;
     }
 #pragma unroll
@@ -499,192 +523,208 @@ __global__ void k_classify(FwdArgs a) {
     }
 }
 
-// bitonic sort of n <= CAP unique 64-bit keys in LDS (padded with all-ones to a power of two)
-template <int NT>
-__device__ void bitonic_lds(unsigned long long* s, int n) {
-    int m = 1;
-    while (m < n) m <<= 1;
-    for (int i = n + threadIdx.x; i < m; i += NT) s[i] = ~0ull;
-    __syncthreads();
-    for (int k = 2; k <= m; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < (m >> 1); i += NT) {
-                const int l = ((i & ~(j - 1)) << 1) | (i & (j - 1));
-                const int r = l + j;
-                const unsigned long long x = s[l], y = s[r];
-                const bool asc = (l & k) == 0;
-                if ((x > y) == asc) {
-                    s[l] = y;
-                    s[r] = x;
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
 
-template <int NT, int CAP>
-__global__ __launch_bounds__(NT) void k_sort_lds(FwdArgs a, int cls) {
-    __shared__ unsigned long long s[CAP];
-    const uint32_t count = a.status->cls[cls];
-    for (uint32_t w = blockIdx.x; w < count; w += gridDim.x) {
-        const uint32_t t = a.cls_list[(size_t)cls * a.tiles + w];
-        const uint32_t st = a.starts[t], n = a.starts[t + 1] - st;
-        unsigned long long* p = a.pairs + st;
-        for (uint32_t i = threadIdx.x; i < n; i += NT) s[i] = p[i];
-        __syncthreads();
-        bitonic_lds<NT>(s, (int)n);
-        for (uint32_t i = threadIdx.x; i < n; i += NT) p[i] = s[i];
-        __syncthreads();
-    }
-}
-
-// Stable LSD radix sort of one tile's list in LDS, for lists of at most NT * E entries.
-// Keys are the depth bits relative to the list's minimum, so only the significant bits are
-// sorted, 4 per pass; values are the Gaussian ids.  Thread t owns entries [t E, t E + E)
-// ("blocked"); a pass ranks each thread's entries with packed per-digit counters in
-// registers, scans the (digit, thread) counts in digit-major order across the block and
-// scatters the pairs to their stable positions.  Entries with equal depth bits are finally
-// ordered by id (runs of equal keys are rare and short; the emission order within a tile is
-// already by id across super-blocks).
+// Per-tile sort by (depth bits, Gaussian id) in LDS, for lists of at most NT * E entries.
+// Each entry is packed into one 64-bit word X = (z bits - zmin) << ib | (id - idmin), whose
+// order is the order of (z bits, id) and whose significant bits number TB = (bits of the
+// depth range) + ib.  An LSD radix sort with 4-bit digits over the top 16 significant bits
+// (at most four passes) leaves the list in runs of equal top bits, in order; each entry then
+// takes its place inside its run by counting the run's smaller words.  Runs are short for any
+// spread of depths; if a run is longer than 64 entries, the tile is sorted again by LSD passes
+// over all TB bits (so the result is exact for any input, and fast for the usual one).
+// A pass: thread t owns entries [t E, t E + E) ("blocked") and ranks them among its own
+// entries with 4-bit per-digit counters (one 64-bit word per 8 entries); the (digit, thread)
+// counts are scanned in digit-major order across the block, and each entry is scattered to
+// its digit's offset plus its rank, which keeps the pass stable.
+// LDS layouts are padded so that the blocked accesses hit distinct banks: entry i lives at
+// i + i / E, and count f of the digit-major table at f + 2 (f / 16) u16 slots.
 template <int NT, int E>
-__global__ __launch_bounds__(NT) void k_sort_radix(FwdArgs a, int cls) {
+__device__ void sort_list(unsigned long long* p, const uint32_t n, unsigned long long* s_x, uint16_t* s_cnt,
+                          uint32_t* s_w, uint32_t* s_long_p) {
     constexpr int CAP = NT * E;
     constexpr int NW = NT / 64;
-    __shared__ unsigned long long s_kv[CAP];
-    __shared__ uint16_t s_cnt[16 * NT];
-    __shared__ uint32_t s_w[2 * NW];
+    constexpr int NG = E / 8;
+    constexpr int LE = E == 8 ? 3 : (E == 16 ? 4 : 5);
+    static_assert((1 << LE) == E, "E must be 8, 16 or 32");
+    constexpr bool RECOUNT = E > 16;  // recount ranks in the scatter instead of keeping them (registers)
+    uint32_t& s_long = *s_long_p;
+    const auto P = [](uint32_t i) { return i + (i >> LE); };
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    // count (d, t) of the digit-major table lives at Q(d NT + t) = Q(t) + d DSTRIDE, with
+    // Q(f) = f + 2 (f / 16) (NT is a multiple of 16)
+    constexpr uint32_t DSTRIDE = NT + NT / 8;
+    const uint32_t qt = (uint32_t)t + (((uint32_t)t >> 4) << 1);
+    unsigned long long x[E];
+    // one stable pass on the 4-bit digit at bit sh; x[] holds the thread's entries (blocked)
+    // before and after, and s_x the whole list after
+    auto pass = [&](int sh) {
+        unsigned long long c[NG];
+        uint32_t rk[RECOUNT ? 1 : E / 4];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) c[g] = 0ull;
+#pragma unroll
+        for (int k = 0; k < (RECOUNT ? 1 : E / 4); ++k) rk[k] = 0u;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const uint32_t s4 = ((uint32_t)(x[r] >> sh) & 15u) << 2;
+            if constexpr (!RECOUNT) rk[r >> 2] |= ((uint32_t)(c[r >> 3] >> s4) & 15u) << ((r & 3) << 3);
+            c[r >> 3] += 1ull << s4;
+        }
+#pragma unroll
+        for (int d = 0; d < 16; ++d) {
+            uint32_t tot = 0;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) tot += (uint32_t)(c[g] >> (4 * d)) & 15u;
+            s_cnt[qt + d * DSTRIDE] = (uint16_t)tot;
+        }
+        __syncthreads();
+        // exclusive scan in digit-major order: thread t takes counts 16 t .. 16 t + 15
+        uint32_t tot = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) tot += s_cnt[18 * t + j];
+        uint32_t incl = tot;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) s_w[wave] = incl;
+        __syncthreads();
+        uint32_t base = incl - tot;
+        for (int i = 0; i < wave; ++i) base += s_w[i];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const uint32_t v = s_cnt[18 * t + j];
+            s_cnt[18 * t + j] = (uint16_t)base;
+            base += v;
+        }
+        __syncthreads();
+        unsigned long long c2 = 0ull;  // RECOUNT: counts of the current group of 8 so far
+        // recompute the digits below instead of keeping E of them alive across the scan
+#pragma unroll
+        for (int r = 0; r < E; ++r) asm volatile("" : "+v"(x[r]));
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const uint32_t s4 = ((uint32_t)(x[r] >> sh) & 15u) << 2;
+            uint32_t rank;
+            if constexpr (RECOUNT) {
+                if ((r & 7) == 0) c2 = 0ull;
+                rank = (uint32_t)(c2 >> s4) & 15u;
+                c2 += 1ull << s4;
+            } else {
+                rank = (rk[r >> 2] >> ((r & 3) << 3)) & 255u;
+            }
+#pragma unroll
+            for (int g = 0; g < (r >> 3); ++g) rank += (uint32_t)(c[g] >> s4) & 15u;
+            const uint32_t dest = (uint32_t)s_cnt[qt + (s4 >> 2) * DSTRIDE] + rank;
+            s_x[P(dest)] = x[r];
+            if ((r & 7) == 7) asm volatile("" ::: "memory");  // bounds the scheduling window (registers)
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < E; ++r) x[r] = s_x[t * (E + 1) + r];
+        __syncthreads();
+    };
+    // striped copy into LDS (entry t + k NT lives at P(t) + k (NT + NT / E))
+#pragma unroll 1
+    for (int k = 0; k < E; ++k) {
+        const uint32_t i = (uint32_t)(t + k * NT);
+        s_x[P((uint32_t)t) + (uint32_t)k * (NT + NT / E)] = i < n ? p[i] : ~0ull;
+    }
+    __syncthreads();
+    // ranges of depth bits and ids
+    uint32_t zmin = 0xffffffffu, zmax = 0u, imin = 0xffffffffu, imax = 0u;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const unsigned long long u = s_x[t * (E + 1) + r];
+        x[r] = u;
+        if ((uint32_t)(t * E + r) < n) {
+            const uint32_t z = (uint32_t)(u >> 32), id = (uint32_t)u;
+            zmin = z < zmin ? z : zmin;
+            zmax = z > zmax ? z : zmax;
+            imin = id < imin ? id : imin;
+            imax = id > imax ? id : imax;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t a1 = __shfl_xor(zmin, off, 64), a2 = __shfl_xor(zmax, off, 64);
+        const uint32_t a3 = __shfl_xor(imin, off, 64), a4 = __shfl_xor(imax, off, 64);
+        zmin = a1 < zmin ? a1 : zmin;
+        zmax = a2 > zmax ? a2 : zmax;
+        imin = a3 < imin ? a3 : imin;
+        imax = a4 > imax ? a4 : imax;
+    }
+    if (lane == 0) {
+        s_w[4 * wave + 0] = zmin;
+        s_w[4 * wave + 1] = zmax;
+        s_w[4 * wave + 2] = imin;
+        s_w[4 * wave + 3] = imax;
+    }
+    if (t == 0) s_long = 0u;
+    __syncthreads();
+    for (int i = 0; i < NW; ++i) {
+        zmin = s_w[4 * i + 0] < zmin ? s_w[4 * i + 0] : zmin;
+        zmax = s_w[4 * i + 1] > zmax ? s_w[4 * i + 1] : zmax;
+        imin = s_w[4 * i + 2] < imin ? s_w[4 * i + 2] : imin;
+        imax = s_w[4 * i + 3] > imax ? s_w[4 * i + 3] : imax;
+    }
+    __syncthreads();  // s_w is reused by the passes
+    const uint32_t zr = zmax - zmin, ir = imax - imin;
+    const int zb = zr ? 32 - __clz((int)zr) : 0;
+    const int ib = ir ? 32 - __clz((int)ir) : 0;
+    const int TB = zb + ib;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const uint32_t z = (uint32_t)(x[r] >> 32), id = (uint32_t)x[r];
+        x[r] = (uint32_t)(t * E + r) < n ? ((unsigned long long)(z - zmin) << ib) | (unsigned long long)(id - imin)
+                                          : ~0ull;
+    }
+    const int sh0 = TB > 16 ? TB - 16 : 0;
+    for (int sh = sh0; sh < TB; sh += 4) pass(sh);
+    // a run of more than 64 equal top words: sort by every bit instead
+    bool lng = false;
+#pragma unroll 1
+    for (uint32_t i = t; i + 64 < n; i += NT) lng |= (s_x[P(i)] >> sh0) == (s_x[P(i + 64)] >> sh0);
+    if (__any(lng) && lane == 0) s_long = 1u;
+    __syncthreads();
+    const bool full = s_long != 0u;
+    if (full)
+        for (int sh = 0; sh < TB; sh += 4) pass(sh);
+    const int shr = full ? 0 : sh0;
+#pragma unroll 1
+    for (uint32_t i = t; i < n; i += NT) {
+        const unsigned long long u = s_x[P(i)];
+        const unsigned long long top = u >> shr;
+        uint32_t pos = i;
+        const bool prev = i > 0 && (s_x[P(i - 1)] >> shr) == top;
+        const bool next = i + 1 < n && (s_x[P(i + 1)] >> shr) == top;
+        if (prev || next) {  // inside a run: place by the number of smaller words
+            uint32_t b = i, e = i + 1;
+            while (b > 0 && (s_x[P(b - 1)] >> shr) == top) --b;
+            while (e < n && (s_x[P(e)] >> shr) == top) ++e;
+            uint32_t rank = 0;
+            for (uint32_t j = b; j < e; ++j) rank += s_x[P(j)] < u ? 1u : 0u;
+            pos = b + rank;
+        }
+        const uint32_t z = (uint32_t)(u >> ib) + zmin;
+        const uint32_t id = (uint32_t)(u & ((1ull << ib) - 1ull)) + imin;
+        p[pos] = ((unsigned long long)z << 32) | (unsigned long long)id;
+    }
+    __syncthreads();
+}
+
+// one block per tile of the class, lists of at most NT * E entries
+template <int NT, int E>
+__global__ __launch_bounds__(NT) void k_sort_radix(FwdArgs a, int cls) {
+    __shared__ unsigned long long s_x[NT * E + NT];
+    __shared__ uint16_t s_cnt[18 * NT];
+    __shared__ uint32_t s_w[4 * (NT / 64)];
+    __shared__ uint32_t s_long;
     const uint32_t count = a.status->cls[cls];
     for (uint32_t w = blockIdx.x; w < count; w += gridDim.x) {
         const uint32_t tile = a.cls_list[(size_t)cls * a.tiles + w];
         const uint32_t st = a.starts[tile], n = a.starts[tile + 1] - st;
-        unsigned long long* p = a.pairs + st;
-        for (int i = t; i < CAP; i += NT) s_kv[i] = (uint32_t)i < n ? p[i] : ~0ull;
-        __syncthreads();
-        uint32_t key[E], val[E];
-        uint32_t zmin = 0xffffffffu, zmax = 0u;
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const unsigned long long u = s_kv[t * E + r];
-            key[r] = (uint32_t)(u >> 32);
-            val[r] = (uint32_t)u;
-            if ((uint32_t)(t * E + r) < n) {
-                zmin = key[r] < zmin ? key[r] : zmin;
-                zmax = key[r] > zmax ? key[r] : zmax;
-            }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            const uint32_t a1 = __shfl_xor(zmin, off, 64), a2 = __shfl_xor(zmax, off, 64);
-            zmin = a1 < zmin ? a1 : zmin;
-            zmax = a2 > zmax ? a2 : zmax;
-        }
-        if (lane == 0) {
-            s_w[wave] = zmin;
-            s_w[NW + wave] = zmax;
-        }
-        __syncthreads();
-        zmin = s_w[0];
-        zmax = s_w[NW];
-        for (int i = 1; i < NW; ++i) {
-            zmin = s_w[i] < zmin ? s_w[i] : zmin;
-            zmax = s_w[NW + i] > zmax ? s_w[NW + i] : zmax;
-        }
-        const uint32_t range = zmax - zmin;
-        const int bits = range ? 32 - __clz((int)range) : 0;
-#pragma unroll
-        for (int r = 0; r < E; ++r) key[r] = (uint32_t)(t * E + r) < n ? key[r] - zmin : 0xffffffffu;
-        __syncthreads();  // s_w is reused by the scans below
-        for (int sh = 0; sh < bits; sh += 4) {
-            // per-thread digit counts, packed 8 bits per digit in four words
-            uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-#pragma unroll
-            for (int r = 0; r < E; ++r) {
-                const uint32_t d = (key[r] >> sh) & 15u;
-                const uint32_t q = d >> 2, inc = 1u << ((d & 3u) << 3);
-                c0 += q == 0 ? inc : 0u;
-                c1 += q == 1 ? inc : 0u;
-                c2 += q == 2 ? inc : 0u;
-                c3 += q == 3 ? inc : 0u;
-            }
-#pragma unroll
-            for (int d = 0; d < 16; ++d) {
-                const uint32_t cw = d < 4 ? c0 : (d < 8 ? c1 : (d < 12 ? c2 : c3));
-                s_cnt[d * NT + t] = (uint16_t)((cw >> ((d & 3) << 3)) & 255u);
-            }
-            __syncthreads();
-            // exclusive scan of the counts in digit-major order: thread t takes 16 in a row
-            uint32_t tot = 0;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) tot += s_cnt[t * 16 + j];
-            uint32_t incl = tot;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t y = __shfl_up(incl, off, 64);
-                if (lane >= off) incl += y;
-            }
-            if (lane == 63) s_w[wave] = incl;
-            __syncthreads();
-            uint32_t base = incl - tot;
-            for (int i = 0; i < wave; ++i) base += s_w[i];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const uint32_t v = s_cnt[t * 16 + j];
-                s_cnt[t * 16 + j] = (uint16_t)base;
-                base += v;
-            }
-            __syncthreads();
-            // scatter: the rank among this thread's earlier entries with the same digit is
-            // recounted on the way (cheaper in registers than keeping E ranks)
-            c0 = c1 = c2 = c3 = 0;
-#pragma unroll
-            for (int r = 0; r < E; ++r) {
-                const uint32_t d = (key[r] >> sh) & 15u;
-                const uint32_t q = d >> 2, f = (d & 3u) << 3;
-                const uint32_t cw = q == 0 ? c0 : (q == 1 ? c1 : (q == 2 ? c2 : c3));
-                const uint32_t inc = 1u << f;
-                c0 += q == 0 ? inc : 0u;
-                c1 += q == 1 ? inc : 0u;
-                c2 += q == 2 ? inc : 0u;
-                c3 += q == 3 ? inc : 0u;
-                const uint32_t dest = ((uint32_t)s_cnt[d * NT + t] + ((cw >> f) & 255u)) & (uint32_t)(CAP - 1);
-                s_kv[dest] = ((unsigned long long)key[r] << 32) | val[r];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < E; ++r) {
-                const unsigned long long u = s_kv[t * E + r];
-                key[r] = (uint32_t)(u >> 32);
-                val[r] = (uint32_t)u;
-            }
-            __syncthreads();
-        }
-        // s_kv now holds the entries in key order (or in input order if every key is equal)
-        // ties: a run of equal keys is put in id order by the thread that owns its first entry
-        for (int r = 0; r < E; ++r) {
-            const uint32_t i = (uint32_t)(t * E + r);
-            if (i + 1 >= n) break;
-            const uint32_t k = (uint32_t)(s_kv[i] >> 32);
-            if ((uint32_t)(s_kv[i + 1] >> 32) != k) continue;
-            if (i > 0 && (uint32_t)(s_kv[i - 1] >> 32) == k) continue;
-            uint32_t j = i + 1;
-            while (j < n && (uint32_t)(s_kv[j] >> 32) == k) ++j;
-            for (uint32_t x = i + 1; x < j; ++x) {  // insertion sort of [i, j) (equal keys: by id)
-                const unsigned long long u = s_kv[x];
-                uint32_t y = x;
-                while (y > i && s_kv[y - 1] > u) {
-                    s_kv[y] = s_kv[y - 1];
-                    --y;
-                }
-                s_kv[y] = u;
-            }
-        }
-        __syncthreads();
-        for (uint32_t i = t; i < n; i += NT) {
-            const unsigned long long u = s_kv[i];
-            p[i] = ((unsigned long long)((uint32_t)(u >> 32) + zmin) << 32) | (u & 0xffffffffull);
-        }
-        __syncthreads();
+        sort_list<NT, E>(a.pairs + st, n, s_x, s_cnt, s_w, &s_long);
     }
 }
 
@@ -698,26 +738,25 @@ __device__ inline uint32_t lower_rank(const unsigned long long* src, uint32_t n,
     return lo;
 }
 
-// lists longer than one LDS load: sort CAP-sized chunks in LDS, then merge runs pairwise by
-// rank (keys are unique, so an element's output slot is its index in its run plus its rank in
-// the partner run), ping-ponging through the alternate pair buffer
-template <int NT, int CAP>
+// lists longer than one LDS load: sort chunks of NT * E entries with the LDS radix sort, then
+// merge runs pairwise by rank (keys are unique, so an element's output slot is its index in
+// its run plus its rank in the partner run), ping-ponging through the alternate pair buffer
+template <int NT, int E>
 __global__ __launch_bounds__(NT) void k_sort_big(FwdArgs a, int cls) {
-    __shared__ unsigned long long s[CAP];
+    constexpr uint32_t CAP = NT * E;
+    __shared__ unsigned long long s_x[NT * E + NT];
+    __shared__ uint16_t s_cnt[18 * NT];
+    __shared__ uint32_t s_w[4 * (NT / 64)];
+    __shared__ uint32_t s_long;
     const uint32_t count = a.status->cls[cls];
     for (uint32_t w = blockIdx.x; w < count; w += gridDim.x) {
         const uint32_t t = a.cls_list[(size_t)cls * a.tiles + w];
         const uint32_t st = a.starts[t], n = a.starts[t + 1] - st;
         unsigned long long* A = a.pairs + st;
         unsigned long long* B = a.pairs_alt + st;
-        for (uint32_t c0 = 0; c0 < n; c0 += CAP) {
-            const uint32_t m = (n - c0 < (uint32_t)CAP) ? n - c0 : (uint32_t)CAP;
-            for (uint32_t i = threadIdx.x; i < m; i += NT) s[i] = A[c0 + i];
-            __syncthreads();
-            bitonic_lds<NT>(s, (int)m);
-            for (uint32_t i = threadIdx.x; i < m; i += NT) A[c0 + i] = s[i];
-            __syncthreads();
-        }
+        for (uint32_t c0 = 0; c0 < n; c0 += CAP)
+            sort_list<NT, E>(A + c0, (n - c0 < CAP) ? n - c0 : CAP, s_x, s_cnt, s_w, &s_long);
+        __threadfence_block();
         unsigned long long* src = A;
         unsigned long long* dst = B;
         for (uint32_t run = CAP; run < n; run <<= 1) {
@@ -733,6 +772,7 @@ __global__ __launch_bounds__(NT) void k_sort_big(FwdArgs a, int cls) {
                     dst[base + (i - base) + lower_rank(src + pb, pn, x)] = x;
                 }
             }
+            __threadfence_block();
             __syncthreads();
             unsigned long long* tmp = src;
             src = dst;
@@ -741,6 +781,7 @@ __global__ __launch_bounds__(NT) void k_sort_big(FwdArgs a, int cls) {
         if (src != A) {
             for (uint32_t i = threadIdx.x; i < n; i += NT) A[i] = src[i];
         }
+        __threadfence_block();
         __syncthreads();
     }
 }
@@ -808,7 +849,7 @@ __device__ inline bool reaches_rect(const Record& R, float x0, float x1, float y
 // One wavefront composites its sub-tile of tile t, walking the tile's whole list in batches of
 // 64 entries staged in the wavefront's own LDS (wavefront-level synchronisation only, so each
 // wavefront stops as soon as its own pixels are saturated).
-template <int TW, int TH, int PPT, bool SAVE>
+template <int TW, int TH, int PPT, bool SAVE, bool COUNT>
 __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long t, const int wave, const int lane,
                                               float4* s0, float4* s1, float4* s2) {
     using ST = SubTile<TW, TH, PPT>;
@@ -896,7 +937,7 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
             for (int p = 0; p < PPT; ++p) {
                 const float dy = fpy[p] - e0.y;
                 q[p] = fmaf(Bdx, dy, fmaf(e1.x * dy, dy, qx));
-                evals[p] += T[p] > 0.0f ? 1u : 0u;
+                if (COUNT) evals[p] += T[p] > 0.0f ? 1u : 0u;
                 hit |= q[p] >= qcut;
             }
             if (!__any(hit)) continue;
@@ -939,24 +980,26 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
             a.n_contrib[q] = last[p];
         }
     }
-    for (int off = 32; off > 0; off >>= 1) nev += __shfl_xor(nev, off, 64);
-    if (lane == 0 && nev) atomicAdd(&a.status->evals, nev);
+    if (COUNT) {
+        for (int off = 32; off > 0; off >>= 1) nev += __shfl_xor(nev, off, 64);
+        if (lane == 0 && nev) atomicAdd(&a.status->evals, nev);
+    }
 }
 
-template <int TW, int TH, int PPT, bool SAVE>
+template <int TW, int TH, int PPT, bool SAVE, bool COUNT>
 __global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composite(FwdArgs a) {
     constexpr int NW = SubTile<TW, TH, PPT>::WAVES;
     __shared__ float4 s0[NW][64], s1[NW][64];
     __shared__ float4 s2[NW][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    composite_sub<TW, TH, PPT, SAVE>(a, (long long)blockIdx.x, wave, lane, s0[wave], s1[wave], s2[wave]);
+    composite_sub<TW, TH, PPT, SAVE, COUNT>(a, (long long)blockIdx.x, wave, lane, s0[wave], s1[wave], s2[wave]);
 }
 
 // persistent grid: block b takes queue items b, b + G, b + 2G, ... of the longest-first queue
 // (sort classes from the longest lists down, then the lists of at most one entry).  A static
 // interleave needs no shared counter: a single global atomic per tile would serialise the
 // grid.  The wavefronts of a block work on the same tile independently.
-template <int TW, int TH, int PPT, bool SAVE>
+template <int TW, int TH, int PPT, bool SAVE, bool COUNT>
 __global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composite_persistent(FwdArgs a) {
     constexpr int NW = SubTile<TW, TH, PPT>::WAVES;
     __shared__ float4 s0[NW][64], s1[NW][64];
@@ -967,7 +1010,7 @@ __global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composit
 #pragma unroll
     for (int c = 0; c < kNumClasses; ++c) cnt[c] = st->cls[c];
     for (long long item = blockIdx.x; item < a.tiles; item += gridDim.x) {
-        // queue order: longest class first (5, 4, 3, 2, 1, 0), then class 6
+        // queue order: longest class first (6, 5, ..., 0), then class 7
         uint32_t k = (uint32_t)item;
         int cls = kSortBig;
         while (cls >= 0 && k >= cnt[cls]) {
@@ -975,7 +1018,7 @@ __global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composit
             --cls;
         }
         if (cls < 0) cls = kSortNone;
-        composite_sub<TW, TH, PPT, SAVE>(a, (long long)a.cls_list[(size_t)cls * a.tiles + k], wave, lane, s0[wave],
+        composite_sub<TW, TH, PPT, SAVE, COUNT>(a, (long long)a.cls_list[(size_t)cls * a.tiles + k], wave, lane, s0[wave],
                                          s1[wave], s2[wave]);
     }
 }
@@ -1005,23 +1048,29 @@ static hipError_t launch_project(const FwdArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int TW, int TH, int PPT, bool SAVE>
+template <int TW, int TH, int PPT, bool SAVE, bool COUNT>
 static void launch_composite_s(const FwdArgs& a, hipStream_t s) {
     constexpr int NT = 64 * SubTile<TW, TH, PPT>::WAVES;
     if (a.persistent) {
         // persistent_grid counts 256-thread blocks
         const long long want = (long long)a.persistent_grid * 256 / NT;
         const long long g = want < a.tiles ? want : a.tiles;
-        hipLaunchKernelGGL((k_composite_persistent<TW, TH, PPT, SAVE>), dim3((unsigned)(g > 0 ? g : 1)), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_composite_persistent<TW, TH, PPT, SAVE, COUNT>), dim3((unsigned)(g > 0 ? g : 1)), dim3(NT),
+                           0, s, a);
     } else {
-        hipLaunchKernelGGL((k_composite<TW, TH, PPT, SAVE>), dim3((unsigned)a.tiles), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_composite<TW, TH, PPT, SAVE, COUNT>), dim3((unsigned)a.tiles), dim3(NT), 0, s, a);
     }
 }
 
 template <int TW, int TH, int PPT>
 static void launch_composite(const FwdArgs& a, hipStream_t s) {
-    if (a.save) launch_composite_s<TW, TH, PPT, true>(a, s);
-    else launch_composite_s<TW, TH, PPT, false>(a, s);
+    if (a.save) {
+        if (a.count) launch_composite_s<TW, TH, PPT, true, true>(a, s);
+        else launch_composite_s<TW, TH, PPT, true, false>(a, s);
+    } else {
+        if (a.count) launch_composite_s<TW, TH, PPT, false, true>(a, s);
+        else launch_composite_s<TW, TH, PPT, false, false>(a, s);
+    }
 }
 
 static int g_num_cu = 0;
@@ -1060,14 +1109,15 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
     mark(5);
     hipLaunchKernelGGL(k_classify, dim3((unsigned)((a.tiles + 255) / 256)), dim3(256), 0, s, a);
     mark(6);
-    hipLaunchKernelGGL((k_sort_radix<128, 8>), dim3(g_num_cu * 16), dim3(128), 0, s, a, 0);
-    hipLaunchKernelGGL((k_sort_radix<256, 8>), dim3(g_num_cu * 8), dim3(256), 0, s, a, 1);
+    hipLaunchKernelGGL((k_sort_radix<64, 8>), dim3(g_num_cu * 32), dim3(64), 0, s, a, 0);
+    hipLaunchKernelGGL((k_sort_radix<128, 8>), dim3(g_num_cu * 16), dim3(128), 0, s, a, 1);
+    hipLaunchKernelGGL((k_sort_radix<256, 8>), dim3(g_num_cu * 8), dim3(256), 0, s, a, 2);
     mark(7);
-    hipLaunchKernelGGL((k_sort_radix<256, 16>), dim3(g_num_cu * 4), dim3(256), 0, s, a, 2);
-    hipLaunchKernelGGL((k_sort_radix<512, 16>), dim3(g_num_cu * 2), dim3(512), 0, s, a, 3);
-    hipLaunchKernelGGL((k_sort_radix<512, 32>), dim3(g_num_cu), dim3(512), 0, s, a, 4);
+    hipLaunchKernelGGL((k_sort_radix<512, 8>), dim3(g_num_cu * 4), dim3(512), 0, s, a, 3);
+    hipLaunchKernelGGL((k_sort_radix<1024, 8>), dim3(g_num_cu * 2), dim3(1024), 0, s, a, 4);
+    hipLaunchKernelGGL((k_sort_radix<512, 32>), dim3(g_num_cu), dim3(512), 0, s, a, 5);
     mark(8);
-    hipLaunchKernelGGL((k_sort_big<1024, kSortMidCap>), dim3(g_num_cu), dim3(1024), 0, s, a, kSortBig);
+    hipLaunchKernelGGL((k_sort_big<512, 32>), dim3(g_num_cu), dim3(512), 0, s, a, kSortBig);
     mark(9);
     const bool two = a.ppt == 2;
     if (a.tw == 16 && a.th == 16) { if (two) launch_composite<16, 16, 2>(a, s); else launch_composite<16, 16, 1>(a, s); }

@@ -10,14 +10,14 @@
 namespace gsr {
 
 constexpr int kBlock = 256;          // Gaussians per projection / emission block
-// Per-tile sort classes by list length: lists of at most kSortCap[c] entries are sorted in LDS
-// by a block of kSortThreads[c] threads; longer lists (class kSortBig) are chunk-sorted and
-// merged; class kSortNone holds lists of at most one entry (and overflowed tiles).
-constexpr int kSortClasses = 5;
-constexpr int kSortBig = 5;
-constexpr int kSortNone = 6;
-constexpr int kNumClasses = 7;
-constexpr int kSortMidCap = 16384;
+// Per-tile sort classes by list length: classes 0 .. kSortClasses - 1 hold lists of at most
+// 512, 1024, ..., 16384 entries, each sorted in LDS by one block; longer lists (class
+// kSortBig) are chunk-sorted and merged; class kSortNone holds lists of at most one entry (and
+// overflowed tiles).
+constexpr int kSortClasses = 6;
+constexpr int kSortBig = 6;
+constexpr int kSortNone = 7;
+constexpr int kNumClasses = 8;
 constexpr int kLdsHistLimit = 16384; // int counters a block may keep in LDS for tile histograms
 
 // One (node, camera) view: the camera<-node map composed in FP64 and rounded
@@ -135,6 +135,7 @@ struct FwdArgs {
     int persistent_grid;
     int ppt;   // pixels per compositor thread (1 or 2; 8x8 tiles use 1)
     int save;  // write per-pixel T_final and contributor counts for the backward
+    int count; // count Gaussian-pixel evaluations into the status word
     hipEvent_t* stage_events;  // kStages + 1 events recorded between stages, or null
 };
 

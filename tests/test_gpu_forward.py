@@ -163,6 +163,28 @@ def test_long_tile_lists_chunk_sort_and_merge(gsr, ctx):
     assert lens.max() > 16384 * 2
 
 
+@pytest.mark.parametrize("spread_ulps,outlier", [(6, True), (0, True), (0, False)])
+def test_clustered_depths_sort_exactly(gsr, ctx, spread_ulps, outlier):
+    """Thousands of entries per tile within a few ulps of one depth (or at exactly one depth,
+    ordered by id), with or without a far entry in the same tiles: the per-tile sort must
+    still give the oracle's (z bits, id) order bit for bit."""
+    from helpers import cam_identity, env_of, node
+    rng = np.random.default_rng(41)
+    n = 3000
+    zb = np.float32(3.0).view(np.uint32) + rng.integers(0, spread_ulps + 1, n).astype(np.uint32)
+    means = np.c_[rng.uniform(-0.02, 0.02, (n, 2)).astype(np.float32), zb.view(np.float32)]
+    if outlier:
+        means = np.r_[means, [[0.0, 0.0, 30.0]]].astype(np.float32)
+    g = node(means, 0.005, opac=0.05, colours=rng.uniform(0, 1, (len(means), 3)))
+    env = env_of([g])
+    env["cams"] = [cam_identity(32, 32, 40.0)]
+    wl = dict(envs=[env], cams_per_env=1, width=32, height=32,
+              name=f"{n} entries within {spread_ulps} ulps, outlier {outlier}")
+    _, _, _, _, _, refs, _ = _run(gsr, ctx, wl, (16, 16))
+    lens = refs[0]["ranges"][:, 1] - refs[0]["ranges"][:, 0]
+    assert lens.max() > 2000
+
+
 def test_graph_replay_matches_eager_bitwise(gsr, ctx):
     import torch
     wl = synth.scene_config(3, seed=17, scale=0.02, n_envs=3)
@@ -250,6 +272,7 @@ def test_persistent_composite_matches_one_block_per_tile(gsr, ctx):
         scene = gsr.compose_scene(ctx, envs_t, poses)
         ref = [t.clone() for t in gsr.render_rgbd(ctx, scene, cams, W, H, C, flags=gsr.FLAG_CHECK)]
         ev_ref = gsr.query_status(ctx)["evals"]
+        assert ev_ref > 0
         out = gsr.render_rgbd(ctx, scene, cams, W, H, C, flags=gsr.FLAG_CHECK | gsr.FLAG_PERSISTENT)
         for a, b in zip(out, ref):
             assert torch.equal(a, b)

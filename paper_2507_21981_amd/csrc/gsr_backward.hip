@@ -36,14 +36,21 @@ __device__ inline float wave_sum(float v) {
     return v;
 }
 
+// One thread per pixel; each wavefront (TW x 64/TW pixels) walks its tile's list back to front
+// on its own, from the largest contributor count among its pixels, in batches of 64 entries
+// staged in wavefront-private LDS.  Entries that cannot reach the wavefront's pixels (the
+// forward's conservative rectangle test) are dropped from each batch before the loop; they
+// blended nothing in the forward, so the gradients are unchanged.
 template <int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void k_composite_bwd(BwdArgs b) {
-    constexpr int NT = TW * TH;
+    constexpr int NW = TW * TH / 64;
+    constexpr int WR = 64 / TW;  // pixel rows per wavefront
     const FwdArgs& a = b.f;
-    __shared__ float4 s0[NT], s1[NT], s2[NT];
-    __shared__ long long s_rec[NT];
-    __shared__ uint32_t s_max;
-    const long long t = blockIdx.x;
+    __shared__ float4 s0[NW][64], s1[NW][64], s2[NW][64];
+    __shared__ long long s_rec[NW][64];
+    __shared__ uint32_t s_e[NW][64];
+    const long long t = xcd_tile(blockIdx.x, a.tiles);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int image = (int)(t / a.tpi);
     const int lt = (int)(t - (long long)image * a.tpi);
     const int ty = lt / a.tiles_x, tx = lt - ty * a.tiles_x;
@@ -56,8 +63,6 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(BwdArgs b) {
     const size_t p = ((size_t)image * a.height + py) * a.width + px;
     uint32_t last = 0;
     float Tf = 1.0f, gr = 0.f, gg = 0.f, gb = 0.f, gD = 0.f, gA = 0.f, bgr = 0.f, bgg = 0.f, bgb = 0.f;
-    if (threadIdx.x == 0) s_max = 0;
-    __syncthreads();
     if (inside) {
         last = a.n_contrib[p];
         Tf = a.T_final[p];
@@ -68,43 +73,56 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(BwdArgs b) {
         gA = b.d_alpha ? b.d_alpha[p] : 0.0f;
         const gsr_camera& cm = a.cams[image];
         bgr = cm.bg[0]; bgg = cm.bg[1]; bgb = cm.bg[2];
-        if (last) atomicMax(&s_max, last);
     }
-    __syncthreads();
-    const uint32_t maxlast = s_max;
+    uint32_t wmax = last;
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = __shfl_xor(wmax, off, 64);
+        wmax = o > wmax ? o : wmax;
+    }
     const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
     const float thr = (float)(1.0 / 255.0);
+    const float qcut = -7.994353436858858f - 1e-3f;  // log2(1/255) - 1e-3, as in the forward
+    const float rx0 = (float)(tx * TW) + 0.5f, rx1 = rx0 + (float)(TW - 1);
+    const float ry0 = (float)(ty * TH + wave * WR) + 0.5f, ry1 = ry0 + (float)(WR - 1);
     float T = Tf;
     float SCr = Tf * bgr, SCg = Tf * bgg, SCb = Tf * bgb, SD = 0.0f;
-    const int lane = threadIdx.x & 63;
-    for (uint32_t hi = maxlast; hi > 0;) {
-        const uint32_t lo = hi > (uint32_t)NT ? hi - NT : 0u;
-        const uint32_t cnt = hi - lo;
-        if (threadIdx.x < cnt) {
-            const uint32_t e = hi - 1 - threadIdx.x;  // descending
+    for (uint32_t hi = wmax; hi > 0;) {
+        const uint32_t lo = hi > 64u ? hi - 64u : 0u;
+        // stage entries hi - 1, hi - 2, ... (descending) that can reach this wavefront's pixels
+        const uint32_t e = hi - 1u - (uint32_t)lane;
+        bool keep = false;
+        Record R;
+        long long rec = -1;
+        if (lane < (int)(hi - lo)) {
             const uint32_t gid = (uint32_t)a.pairs[start + e];
-            long long rec = -1;
-            Record R;
             if (gid - ev.gid_base < ev.n) {
                 rec = rec_off + gid;
                 R = a.records[rec];
-            } else {
-                R.r0 = R.r1 = R.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+                keep = reaches_rect(R, rx0, rx1, ry0, ry1, qcut);
             }
-            s0[threadIdx.x] = R.r0;
-            s1[threadIdx.x] = R.r1;
-            s2[threadIdx.x] = R.r2;
-            s_rec[threadIdx.x] = rec;
         }
-        __syncthreads();
-        for (uint32_t k = 0; k < cnt; ++k) {
-            const uint32_t e = hi - 1 - k;
-            const float4 r0 = s0[k];
-            const float4 r1 = s1[k];
+        const unsigned long long km = __ballot(keep);
+        if (keep) {
+            const int slot = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+            s0[wave][slot] = R.r0;
+            s1[wave][slot] = R.r1;
+            s2[wave][slot] = R.r2;
+            s_rec[wave][slot] = rec;
+            s_e[wave][slot] = e;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int n = __popcll(km);
+        for (int k = 0; k < n; ++k) {
+            const uint32_t ek = s_e[wave][k];
+            const float4 r0 = s0[wave][k];
+            const float4 r1 = s1[wave][k];
             float g_u = 0.f, g_v = 0.f, g_A = 0.f, g_B = 0.f, g_C = 0.f, g_o = 0.f, g_r = 0.f, g_g = 0.f,
                   g_b = 0.f, g_z = 0.f;
             bool contrib = false;
-            if (inside && e < last) {
+            if (inside && ek < last) {
                 const float dx = fpx - r0.x, dy = fpy - r0.y;
                 // the forward's operations exactly, so the same entries are blended:
                 // q = A' dx^2 + B' dx dy + C' dy^2 + log2 o, alpha = min(0.99, exp2(q))
@@ -117,7 +135,7 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(BwdArgs b) {
                 const float al = fminf(0.99f, oG);
                 if (al >= thr) {
                     contrib = true;
-                    const float4 r2 = s2[k];
+                    const float4 r2 = s2[wave][k];
                     const float om = 1.0f - al;
                     const float Ti = T / om;
                     const float w = al * Ti;
@@ -151,16 +169,16 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(BwdArgs b) {
                 g_u = wave_sum(g_u); g_v = wave_sum(g_v); g_A = wave_sum(g_A); g_B = wave_sum(g_B);
                 g_C = wave_sum(g_C); g_o = wave_sum(g_o); g_r = wave_sum(g_r); g_g = wave_sum(g_g);
                 g_b = wave_sum(g_b); g_z = wave_sum(g_z);
-                const long long rec = s_rec[k];
-                if (lane == 0 && rec >= 0) {
-                    float* o = b.g2d + (size_t)rec * 12;
+                if (lane == 0) {
+                    float* o = b.g2d + (size_t)s_rec[wave][k] * 12;
                     atomicAdd(o + 0, g_u); atomicAdd(o + 1, g_v); atomicAdd(o + 2, g_A); atomicAdd(o + 3, g_B);
                     atomicAdd(o + 4, g_C); atomicAdd(o + 5, g_o); atomicAdd(o + 6, g_r); atomicAdd(o + 7, g_g);
                     atomicAdd(o + 8, g_b); atomicAdd(o + 9, g_z);
                 }
             }
         }
-        __syncthreads();
+        // all lanes are done reading this batch before the next one overwrites it
+        __builtin_amdgcn_wave_barrier();
         hi = lo;
     }
 }

@@ -171,14 +171,19 @@ __device__ inline void load_sh(const float* __restrict__ sh, float* c) {
 // The rectangle bounds the ellipse o * G >= 1/255 for any o <= 1, so tile lists hold every
 // Gaussian that can reach a pixel of the tile.
 // --------------------------------------------------------------------------------------------
+// The read-only scene tables come in as separate restrict-qualified arguments: the compiler
+// may then keep them in the scalar cache (s_load) instead of issuing vector loads, which would
+// put a memory round trip in front of every chunk and every camera.
 template <int L>
-__global__ __launch_bounds__(kBlock) void k_project(FwdArgs a) {
+__global__ __launch_bounds__(kBlock) void k_project(FwdArgs a, const Super* __restrict__ supers,
+                                                     const Env* __restrict__ envs, const Block* __restrict__ blocks,
+                                                     const Node* __restrict__ nodes, const View* __restrict__ views) {
     // LDS: per camera, the count of this super-block's visible Gaussians, then a
     // (tiles_y + 1) x (tiles_x + 1) difference grid of pair counts: a rectangle adds +1/-1 at
     // its four corners; the 2D prefix gives pairs per tile
     extern __shared__ int s_lds[];
-    const Super sb = a.supers[blockIdx.x];
-    const Env ev = a.envs[sb.env];
+    const Super sb = supers[blockIdx.x];
+    const Env ev = envs[sb.env];
     const int C = a.C;
     const int gx = a.tiles_x + 1, gy = a.tiles_y + 1, gsz = gx * gy;
     uint32_t* s_nvis = reinterpret_cast<uint32_t*>(s_lds);
@@ -195,9 +200,9 @@ __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a) {
     float nm0 = 0.f, nm1 = 0.f, nm2 = 0.f, no = 0.f, ns0 = 0.f, ns1 = 0.f, ns2 = 0.f;
     float4 nq = make_float4(0.f, 0.f, 0.f, 0.f);
     auto fetch = [&](int ch) {
-        const Block blk = a.blocks[ch];
+        const Block blk = blocks[ch];
         if (i < (int)blk.count) {
-            const Node& nd = a.nodes[blk.node];
+            const Node& nd = nodes[blk.node];
             const size_t li = blk.gid0 + (uint32_t)i - nd.gid_base;
             nm0 = nd.means[3 * li + 0]; nm1 = nd.means[3 * li + 1]; nm2 = nd.means[3 * li + 2];
             no = nd.opac[li];
@@ -207,12 +212,12 @@ __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a) {
     };
     if (sb.chunk_begin < sb.chunk_end) fetch(sb.chunk_begin);
     for (int ch = sb.chunk_begin; ch < sb.chunk_end; ++ch) {
-        const Block blk = a.blocks[ch];
+        const Block blk = blocks[ch];
         const float mu0 = nm0, mu1 = nm1, mu2 = nm2, o = no, s0 = ns0, s1 = ns1, s2 = ns2;
         const float q0 = nq.x, q1 = nq.y, q2 = nq.z, q3 = nq.w;
         if (ch + 1 < sb.chunk_end) fetch(ch + 1);
         if (i >= (int)blk.count) continue;
-        const Node& nd = a.nodes[blk.node];
+        const Node& nd = nodes[blk.node];
         const uint32_t gid = blk.gid0 + i;
         const size_t li = gid - nd.gid_base;
         const size_t lg = gid - ev.gid_base;
@@ -239,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a) {
         float shc[3 * K];
         bool have_sh = false, vis_any = false;
         for (int c = 0; c < C; ++c) {
-            const View& v = a.views[blk.node * C + c];
+            const View& v = views[blk.node * C + c];
             const size_t rec = (size_t)C * ev.gid_base + (size_t)c * ev.n + lg;
             const float p0 = fmaf(v.W[0], mu0, fmaf(v.W[1], mu1, fmaf(v.W[2], mu2, v.w[0])));
             const float p1 = fmaf(v.W[3], mu0, fmaf(v.W[4], mu1, fmaf(v.W[5], mu2, v.w[1])));
@@ -427,11 +432,12 @@ __global__ __launch_bounds__(1024) void k_scan(FwdArgs a) {
 // prefix over rectangle areas, so large rectangles are shared by all threads.
 // Pair = (z bits << 32) | Gaussian id.
 // --------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_emit(FwdArgs a) {
+__global__ __launch_bounds__(kBlock) void k_emit(FwdArgs a, const Super* __restrict__ supers,
+                                                  const uint32_t* __restrict__ sbvis) {
     extern __shared__ uint32_t s_slot[];
     __shared__ uint32_t s_off[kBlock + 1];
     __shared__ uint32_t s_x0[kBlock], s_y0[kBlock], s_w[kBlock], s_z[kBlock], s_id[kBlock];
-    const Super sb = a.supers[blockIdx.x];
+    const Super sb = supers[blockIdx.x];
     const int c = blockIdx.y;
     const size_t image = (size_t)sb.env * a.C + c;
     const int tpi = a.tpi;
@@ -439,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(FwdArgs a) {
     for (int t = threadIdx.x; t < tpi; t += kBlock) s_slot[t] = a.starts[image * tpi + t] + so[t];
     const int i = threadIdx.x;
     const unsigned long long cap = (unsigned long long)a.pair_cap;
-    const uint32_t nv = a.sbvis[(size_t)blockIdx.x * a.C + c];
+    const uint32_t nv = sbvis[(size_t)blockIdx.x * a.C + c];
     const uint4* lst = a.vis + ((size_t)blockIdx.x * a.C + c) * a.sb_cap;
     for (uint32_t b0 = 0; b0 < nv; b0 += kBlock) {
         uint32_t n_i = 0;
@@ -715,15 +721,17 @@ __device__ void sort_list(unsigned long long* p, const uint32_t n, unsigned long
 
 // one block per tile of the class, lists of at most NT * E entries
 template <int NT, int E>
-__global__ __launch_bounds__(NT) void k_sort_radix(FwdArgs a, int cls) {
+__global__ __launch_bounds__(NT) void k_sort_radix(FwdArgs a, int cls, const Status* __restrict__ status,
+                                                   const uint32_t* __restrict__ cls_list,
+                                                   const uint32_t* __restrict__ starts) {
     __shared__ unsigned long long s_x[NT * E + NT];
     __shared__ uint16_t s_cnt[18 * NT];
     __shared__ uint32_t s_w[4 * (NT / 64)];
     __shared__ uint32_t s_long;
-    const uint32_t count = a.status->cls[cls];
+    const uint32_t count = status->cls[cls];
     for (uint32_t w = blockIdx.x; w < count; w += gridDim.x) {
-        const uint32_t tile = a.cls_list[(size_t)cls * a.tiles + w];
-        const uint32_t st = a.starts[tile], n = a.starts[tile + 1] - st;
+        const uint32_t tile = cls_list[(size_t)cls * a.tiles + w];
+        const uint32_t st = starts[tile], n = starts[tile + 1] - st;
         sort_list<NT, E>(a.pairs + st, n, s_x, s_cnt, s_w, &s_long);
     }
 }
@@ -742,16 +750,18 @@ __device__ inline uint32_t lower_rank(const unsigned long long* src, uint32_t n,
 // merge runs pairwise by rank (keys are unique, so an element's output slot is its index in
 // its run plus its rank in the partner run), ping-ponging through the alternate pair buffer
 template <int NT, int E>
-__global__ __launch_bounds__(NT) void k_sort_big(FwdArgs a, int cls) {
+__global__ __launch_bounds__(NT) void k_sort_big(FwdArgs a, int cls, const Status* __restrict__ status,
+                                                 const uint32_t* __restrict__ cls_list,
+                                                 const uint32_t* __restrict__ starts) {
     constexpr uint32_t CAP = NT * E;
     __shared__ unsigned long long s_x[NT * E + NT];
     __shared__ uint16_t s_cnt[18 * NT];
     __shared__ uint32_t s_w[4 * (NT / 64)];
     __shared__ uint32_t s_long;
-    const uint32_t count = a.status->cls[cls];
+    const uint32_t count = status->cls[cls];
     for (uint32_t w = blockIdx.x; w < count; w += gridDim.x) {
-        const uint32_t t = a.cls_list[(size_t)cls * a.tiles + w];
-        const uint32_t st = a.starts[t], n = a.starts[t + 1] - st;
+        const uint32_t t = cls_list[(size_t)cls * a.tiles + w];
+        const uint32_t st = starts[t], n = starts[t + 1] - st;
         unsigned long long* A = a.pairs + st;
         unsigned long long* B = a.pairs_alt + st;
         for (uint32_t c0 = 0; c0 < n; c0 += CAP)
@@ -808,50 +818,13 @@ struct SubTile {
     static constexpr int LROWS = 64 / SW;
 };
 
-// Whether a projected entry can pass the skip test q >= qcut at some pixel centre of the
-// rectangle [x0, x1] x [y0, y1].  With m(d) = A dx^2 + 2 B dx dy + C dy^2 (the conic's form),
-// q = log2(o) - m log2(e) / 2, so the test is m <= rho2 = 2 ln 2 (log2(o) - qcut).  The minimum
-// of m over the rectangle is 0 when the mean lies inside; otherwise it lies on an edge that
-// faces the mean, where m is minimised in closed form along the edge and clamped to it.  Each
-// candidate is evaluated as a sum of two non-negative squares (completing the square, with
-// the covariance entries C D and A D), which has no cancellation.  The slack covers the
-// rounding of that evaluation and of the compositor's own FP32 evaluation of q, whose error
-// grows with the magnitude of the form's terms over the rectangle (tmax).  Entries that fail
-// the test change no pixel, so dropping them leaves the result bit-identical.
-__device__ inline bool reaches_rect(const Record& R, float x0, float x1, float y0, float y1, float qcut) {
-    const float u = R.r0.x, v = R.r0.y, A = R.r1.x, B = R.r1.y, C = R.r1.z, lo = R.r1.w, D = R.r2.w;
-    const float rho2 = 1.3862943611198906f * (lo - qcut);
-    if (!(rho2 > 0.0f)) return false;
-    const float gx = fmaxf(fmaxf(x0 - u, u - x1), 0.0f);
-    const float gy = fmaxf(fmaxf(y0 - v, v - y1), 0.0f);
-    if (gx == 0.0f && gy == 0.0f) return true;
-    const float Dx = fmaxf(fabsf(x0 - u), fabsf(x1 - u)), Dy = fmaxf(fabsf(y0 - v), fabsf(y1 - v));
-    const float tmax = A * Dx * Dx + 2.0f * fabsf(B) * Dx * Dy + C * Dy * Dy + fabsf(lo);
-    const float slack = 4e-6f * tmax + 1e-4f * rho2 + 1e-3f;
-    float mmin = INFINITY;
-    if (gx > 0.0f) {  // the facing vertical edge
-        const float dx = u < x0 ? x0 - u : x1 - u;
-        const float bc = B / C;
-        const float dy = fminf(fmaxf(-bc * dx, y0 - v), y1 - v);
-        const float t = dy + bc * dx;
-        mmin = C * t * t + dx * dx / (C * D);
-    }
-    if (gy > 0.0f) {  // the facing horizontal edge
-        const float dy = v < y0 ? y0 - v : y1 - v;
-        const float ba = B / A;
-        const float dx = fminf(fmaxf(-ba * dy, x0 - u), x1 - u);
-        const float t = dx + ba * dy;
-        mmin = fminf(mmin, A * t * t + dy * dy / (A * D));
-    }
-    return mmin <= rho2 + slack;
-}
-
 // One wavefront composites its sub-tile of tile t, walking the tile's whole list in batches of
 // 64 entries staged in the wavefront's own LDS (wavefront-level synchronisation only, so each
 // wavefront stops as soon as its own pixels are saturated).
 template <int TW, int TH, int PPT, bool SAVE, bool COUNT>
 __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long t, const int wave, const int lane,
-                                              float4* s0, float4* s1, float4* s2) {
+                                              float4* s0, float4* s1, float4* s2, const uint32_t* __restrict__ starts,
+                                              const Env* __restrict__ envs) {
     using ST = SubTile<TW, TH, PPT>;
     const int image = (int)(t / a.tpi);
     const int lt = (int)(t - (long long)image * a.tpi);
@@ -859,10 +832,10 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
     const int sx = wave % (TW / ST::SW), sy = wave / (TW / ST::SW);
     const int px = tx * TW + sx * ST::SW + lane % ST::SW;
     const int py0 = ty * TH + sy * ST::SH + lane / ST::SW;
-    uint32_t start = a.starts[t], end = a.starts[t + 1];
+    uint32_t start = starts[t], end = starts[t + 1];
     if ((unsigned long long)end > (unsigned long long)a.pair_cap) end = start;  // overflow
     const int env = image / a.C, cam = image - env * a.C;
-    const Env ev = a.envs[env];
+    const Env ev = envs[env];
     const long long rec_off = (long long)a.C * ev.gid_base + (long long)cam * ev.n - (long long)ev.gid_base;
     const float fpx = (float)px + 0.5f;
     const float thr = (float)(1.0 / 255.0);
@@ -987,12 +960,14 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
 }
 
 template <int TW, int TH, int PPT, bool SAVE, bool COUNT>
-__global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composite(FwdArgs a) {
+__global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composite(FwdArgs a, const uint32_t* __restrict__ starts,
+                                                                              const Env* __restrict__ envs) {
     constexpr int NW = SubTile<TW, TH, PPT>::WAVES;
     __shared__ float4 s0[NW][64], s1[NW][64];
     __shared__ float4 s2[NW][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    composite_sub<TW, TH, PPT, SAVE, COUNT>(a, (long long)blockIdx.x, wave, lane, s0[wave], s1[wave], s2[wave]);
+    composite_sub<TW, TH, PPT, SAVE, COUNT>(a, xcd_tile(blockIdx.x, a.tiles), wave, lane, s0[wave], s1[wave], s2[wave],
+                                            starts, envs);
 }
 
 // persistent grid: block b takes queue items b, b + G, b + 2G, ... of the longest-first queue
@@ -1000,12 +975,14 @@ __global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composit
 // interleave needs no shared counter: a single global atomic per tile would serialise the
 // grid.  The wavefronts of a block work on the same tile independently.
 template <int TW, int TH, int PPT, bool SAVE, bool COUNT>
-__global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composite_persistent(FwdArgs a) {
+__global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composite_persistent(
+    FwdArgs a, const uint32_t* __restrict__ starts, const Env* __restrict__ envs, const Status* __restrict__ status,
+    const uint32_t* __restrict__ cls_list) {
     constexpr int NW = SubTile<TW, TH, PPT>::WAVES;
     __shared__ float4 s0[NW][64], s1[NW][64];
     __shared__ float4 s2[NW][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const Status* st = a.status;
+    const Status* st = status;
     uint32_t cnt[kNumClasses];
 #pragma unroll
     for (int c = 0; c < kNumClasses; ++c) cnt[c] = st->cls[c];
@@ -1018,8 +995,8 @@ __global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composit
             --cls;
         }
         if (cls < 0) cls = kSortNone;
-        composite_sub<TW, TH, PPT, SAVE, COUNT>(a, (long long)a.cls_list[(size_t)cls * a.tiles + k], wave, lane, s0[wave],
-                                         s1[wave], s2[wave]);
+        composite_sub<TW, TH, PPT, SAVE, COUNT>(a, (long long)cls_list[(size_t)cls * a.tiles + k], wave, lane, s0[wave],
+                                                s1[wave], s2[wave], starts, envs);
     }
 }
 
@@ -1044,7 +1021,8 @@ template <int L>
 static hipError_t launch_project(const FwdArgs& a, hipStream_t s) {
     const int gsz = (a.tiles_x + 1) * (a.tiles_y + 1);
     const size_t lds = (size_t)a.C * (gsz + 1) * sizeof(int);
-    hipLaunchKernelGGL((k_project<L>), dim3(a.n_supers), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL((k_project<L>), dim3(a.n_supers), dim3(kBlock), lds, s, a, a.supers, a.envs, a.blocks, a.nodes,
+                       a.views);
     return hipGetLastError();
 }
 
@@ -1056,9 +1034,10 @@ static void launch_composite_s(const FwdArgs& a, hipStream_t s) {
         const long long want = (long long)a.persistent_grid * 256 / NT;
         const long long g = want < a.tiles ? want : a.tiles;
         hipLaunchKernelGGL((k_composite_persistent<TW, TH, PPT, SAVE, COUNT>), dim3((unsigned)(g > 0 ? g : 1)), dim3(NT),
-                           0, s, a);
+                           0, s, a, a.starts, a.envs, a.status, a.cls_list);
     } else {
-        hipLaunchKernelGGL((k_composite<TW, TH, PPT, SAVE, COUNT>), dim3((unsigned)a.tiles), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_composite<TW, TH, PPT, SAVE, COUNT>), dim3((unsigned)a.tiles), dim3(NT), 0, s, a, a.starts,
+                           a.envs);
     }
 }
 
@@ -1105,19 +1084,20 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
     mark(4);
     if (a.n_supers > 0)
-        hipLaunchKernelGGL(k_emit, dim3(a.n_supers, a.C), dim3(kBlock), (size_t)a.tpi * sizeof(uint32_t), s, a);
+        hipLaunchKernelGGL(k_emit, dim3(a.n_supers, a.C), dim3(kBlock), (size_t)a.tpi * sizeof(uint32_t), s, a,
+                           a.supers, a.sbvis);
     mark(5);
     hipLaunchKernelGGL(k_classify, dim3((unsigned)((a.tiles + 255) / 256)), dim3(256), 0, s, a);
     mark(6);
-    hipLaunchKernelGGL((k_sort_radix<64, 8>), dim3(g_num_cu * 32), dim3(64), 0, s, a, 0);
-    hipLaunchKernelGGL((k_sort_radix<128, 8>), dim3(g_num_cu * 16), dim3(128), 0, s, a, 1);
-    hipLaunchKernelGGL((k_sort_radix<256, 8>), dim3(g_num_cu * 8), dim3(256), 0, s, a, 2);
+    hipLaunchKernelGGL((k_sort_radix<64, 8>), dim3(g_num_cu * 32), dim3(64), 0, s, a, 0, a.status, a.cls_list, a.starts);
+    hipLaunchKernelGGL((k_sort_radix<128, 8>), dim3(g_num_cu * 16), dim3(128), 0, s, a, 1, a.status, a.cls_list, a.starts);
+    hipLaunchKernelGGL((k_sort_radix<256, 8>), dim3(g_num_cu * 8), dim3(256), 0, s, a, 2, a.status, a.cls_list, a.starts);
     mark(7);
-    hipLaunchKernelGGL((k_sort_radix<512, 8>), dim3(g_num_cu * 4), dim3(512), 0, s, a, 3);
-    hipLaunchKernelGGL((k_sort_radix<1024, 8>), dim3(g_num_cu * 2), dim3(1024), 0, s, a, 4);
-    hipLaunchKernelGGL((k_sort_radix<512, 32>), dim3(g_num_cu), dim3(512), 0, s, a, 5);
+    hipLaunchKernelGGL((k_sort_radix<512, 8>), dim3(g_num_cu * 4), dim3(512), 0, s, a, 3, a.status, a.cls_list, a.starts);
+    hipLaunchKernelGGL((k_sort_radix<1024, 8>), dim3(g_num_cu * 2), dim3(1024), 0, s, a, 4, a.status, a.cls_list, a.starts);
+    hipLaunchKernelGGL((k_sort_radix<512, 32>), dim3(g_num_cu), dim3(512), 0, s, a, 5, a.status, a.cls_list, a.starts);
     mark(8);
-    hipLaunchKernelGGL((k_sort_big<512, 32>), dim3(g_num_cu), dim3(512), 0, s, a, kSortBig);
+    hipLaunchKernelGGL((k_sort_big<512, 32>), dim3(g_num_cu), dim3(512), 0, s, a, kSortBig, a.status, a.cls_list, a.starts);
     mark(9);
     const bool two = a.ppt == 2;
     if (a.tw == 16 && a.th == 16) { if (two) launch_composite<16, 16, 2>(a, s); else launch_composite<16, 16, 1>(a, s); }

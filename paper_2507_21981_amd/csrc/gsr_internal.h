@@ -91,6 +91,53 @@ struct Record {
     float4 r0, r1, r2;
 };
 
+// Whether a projected entry can pass the skip test q >= qcut at some pixel centre of the
+// rectangle [x0, x1] x [y0, y1].  With m(d) = A dx^2 + 2 B dx dy + C dy^2 (the conic's form),
+// q = log2(o) - m log2(e) / 2, so the test is m <= rho2 = 2 ln 2 (log2(o) - qcut).  The minimum
+// of m over the rectangle is 0 when the mean lies inside; otherwise it lies on an edge that
+// faces the mean, where m is minimised in closed form along the edge and clamped to it.  Each
+// candidate is evaluated as a sum of two non-negative squares (completing the square, with
+// the covariance entries C D and A D), which has no cancellation.  The slack covers the
+// rounding of that evaluation and of the compositor's own FP32 evaluation of q, whose error
+// grows with the magnitude of the form's terms over the rectangle (tmax).  Entries that fail
+// the test change no pixel, so dropping them leaves the result bit-identical.
+__device__ inline bool reaches_rect(const Record& R, float x0, float x1, float y0, float y1, float qcut) {
+    const float u = R.r0.x, v = R.r0.y, A = R.r1.x, B = R.r1.y, C = R.r1.z, lo = R.r1.w, D = R.r2.w;
+    const float rho2 = 1.3862943611198906f * (lo - qcut);
+    if (!(rho2 > 0.0f)) return false;
+    const float gx = fmaxf(fmaxf(x0 - u, u - x1), 0.0f);
+    const float gy = fmaxf(fmaxf(y0 - v, v - y1), 0.0f);
+    if (gx == 0.0f && gy == 0.0f) return true;
+    const float Dx = fmaxf(fabsf(x0 - u), fabsf(x1 - u)), Dy = fmaxf(fabsf(y0 - v), fabsf(y1 - v));
+    const float tmax = A * Dx * Dx + 2.0f * fabsf(B) * Dx * Dy + C * Dy * Dy + fabsf(lo);
+    const float slack = 4e-6f * tmax + 1e-4f * rho2 + 1e-3f;
+    float mmin = INFINITY;
+    if (gx > 0.0f) {  // the facing vertical edge
+        const float dx = u < x0 ? x0 - u : x1 - u;
+        const float bc = B / C;
+        const float dy = fminf(fmaxf(-bc * dx, y0 - v), y1 - v);
+        const float t = dy + bc * dx;
+        mmin = C * t * t + dx * dx / (C * D);
+    }
+    if (gy > 0.0f) {  // the facing horizontal edge
+        const float dy = v < y0 ? y0 - v : y1 - v;
+        const float ba = B / A;
+        const float dx = fminf(fmaxf(-ba * dy, x0 - u), x1 - u);
+        const float t = dx + ba * dy;
+        mmin = fminf(mmin, A * t * t + dy * dy / (A * D));
+    }
+    return mmin <= rho2 + slack;
+}
+
+// Workgroups are handed to the chip's 8 XCDs (each with its own L2) in turn, so block b runs
+// on XCD b % 8.  Mapping block b to tile (b % 8) Q + b / 8 (Q = tiles / 8; the last tiles % 8
+// blocks map to themselves) gives each XCD a contiguous run of tiles: neighbouring tiles, which
+// gather the same Gaussians' records, then share an L2.
+__device__ inline long long xcd_tile(long long b, long long tiles) {
+    const long long q = tiles >> 3;
+    return b < (q << 3) ? (b & 7) * q + (b >> 3) : b;
+}
+
 struct FwdArgs {
     // scene
     const Node* nodes;

@@ -141,7 +141,7 @@ typedef struct {
 
 /* Number of timed forward stages and their names, in order: views, project,
    tile_offsets, scan, emit, classify, sort_small (lists <= 2048), sort_mid
-   (<= 16384), sort_big (longer), composite. */
+   (<= 8192), sort_big (longer: chunk sort, merge, copy back), composite. */
 #define GSR_STAGES 10
 
 /* Configuration.  Tile shape must be one of 16x16, 16x8, 8x8, 32x8 (width x

@@ -36,59 +36,75 @@ __device__ inline float wave_sum(float v) {
     return v;
 }
 
-// One thread per pixel; each wavefront (TW x 64/TW pixels) walks its tile's list back to front
-// on its own, from the largest contributor count among its pixels, in batches of 64 entries
-// staged in wavefront-private LDS.  Entries that cannot reach the wavefront's pixels (the
-// forward's conservative rectangle test) are dropped from each batch before the loop; they
-// blended nothing in the forward, so the gradients are unchanged.
+// One wavefront per tile; each lane takes PPT = TW TH / 64 pixels of one column (pixel p of a
+// lane sits 64 / TW rows below pixel p - 1).  The wavefront walks the tile's list back to front
+// from the largest contributor count among its pixels, in batches of 64 entries staged in LDS;
+// entries that cannot reach the tile's pixels (the forward's conservative rectangle test) are
+// dropped from each batch first (they blended nothing).  A lane sums its pixels' gradient
+// contributions to an entry in registers, so each (tile, entry) costs one wavefront reduction
+// and one atomic add per record field.
 template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_composite_bwd(BwdArgs b) {
-    constexpr int NW = TW * TH / 64;
-    constexpr int WR = 64 / TW;  // pixel rows per wavefront
+__global__ __launch_bounds__(64) void k_composite_bwd(BwdArgs b) {
+    constexpr int PPT = TW * TH / 64;
+    constexpr int LR = 64 / TW;  // rows between a lane's pixels
     const FwdArgs& a = b.f;
-    __shared__ float4 s0[NW][64], s1[NW][64], s2[NW][64];
-    __shared__ long long s_rec[NW][64];
-    __shared__ uint32_t s_e[NW][64];
+    __shared__ float4 s0[64], s1[64], s2[64];
+    __shared__ long long s_rec[64];
+    __shared__ uint32_t s_e[64];
     const long long t = xcd_tile(blockIdx.x, a.tiles);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lane = threadIdx.x;
     const int image = (int)(t / a.tpi);
     const int lt = (int)(t - (long long)image * a.tpi);
     const int ty = lt / a.tiles_x, tx = lt - ty * a.tiles_x;
-    const int px = tx * TW + (int)(threadIdx.x % TW), py = ty * TH + (int)(threadIdx.x / TW);
-    const bool inside = px < a.width && py < a.height;
+    const int px = tx * TW + lane % TW, py0 = ty * TH + lane / TW;
     const uint32_t start = a.starts[t];
     const int env = image / a.C, cam = image - env * a.C;
     const Env ev = a.envs[env];
     const long long rec_off = (long long)a.C * ev.gid_base + (long long)cam * ev.n - (long long)ev.gid_base;
-    const size_t p = ((size_t)image * a.height + py) * a.width + px;
-    uint32_t last = 0;
-    float Tf = 1.0f, gr = 0.f, gg = 0.f, gb = 0.f, gD = 0.f, gA = 0.f, bgr = 0.f, bgg = 0.f, bgb = 0.f;
-    if (inside) {
-        last = a.n_contrib[p];
-        Tf = a.T_final[p];
-        gr = b.d_rgb[3 * p + 0];
-        gg = b.d_rgb[3 * p + 1];
-        gb = b.d_rgb[3 * p + 2];
-        gD = b.d_depth ? b.d_depth[p] : 0.0f;
-        gA = b.d_alpha ? b.d_alpha[p] : 0.0f;
-        const gsr_camera& cm = a.cams[image];
-        bgr = cm.bg[0]; bgg = cm.bg[1]; bgb = cm.bg[2];
+    const gsr_camera& cm = a.cams[image];
+    const float bgr = cm.bg[0], bgg = cm.bg[1], bgb = cm.bg[2];
+    bool inside[PPT];
+    uint32_t last[PPT];
+    float Tf[PPT], gr[PPT], gg[PPT], gb[PPT], gD[PPT], gA[PPT], T[PPT], SCr[PPT], SCg[PPT], SCb[PPT], SD[PPT],
+        fpy[PPT];
+    uint32_t wmax = 0;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int py = py0 + q * LR;
+        inside[q] = px < a.width && py < a.height;
+        fpy[q] = (float)py + 0.5f;
+        last[q] = 0;
+        Tf[q] = 1.0f;
+        gr[q] = gg[q] = gb[q] = gD[q] = gA[q] = 0.0f;
+        if (inside[q]) {
+            const size_t p = ((size_t)image * a.height + py) * a.width + px;
+            last[q] = a.n_contrib[p];
+            Tf[q] = a.T_final[p];
+            gr[q] = b.d_rgb[3 * p + 0];
+            gg[q] = b.d_rgb[3 * p + 1];
+            gb[q] = b.d_rgb[3 * p + 2];
+            gD[q] = b.d_depth ? b.d_depth[p] : 0.0f;
+            gA[q] = b.d_alpha ? b.d_alpha[p] : 0.0f;
+        }
+        T[q] = Tf[q];
+        SCr[q] = Tf[q] * bgr;
+        SCg[q] = Tf[q] * bgg;
+        SCb[q] = Tf[q] * bgb;
+        SD[q] = 0.0f;
+        wmax = last[q] > wmax ? last[q] : wmax;
     }
-    uint32_t wmax = last;
     for (int off = 32; off > 0; off >>= 1) {
         const uint32_t o = __shfl_xor(wmax, off, 64);
         wmax = o > wmax ? o : wmax;
     }
-    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const float fpx = (float)px + 0.5f;
     const float thr = (float)(1.0 / 255.0);
     const float qcut = -7.994353436858858f - 1e-3f;  // log2(1/255) - 1e-3, as in the forward
     const float rx0 = (float)(tx * TW) + 0.5f, rx1 = rx0 + (float)(TW - 1);
-    const float ry0 = (float)(ty * TH + wave * WR) + 0.5f, ry1 = ry0 + (float)(WR - 1);
-    float T = Tf;
-    float SCr = Tf * bgr, SCg = Tf * bgg, SCb = Tf * bgb, SD = 0.0f;
+    const float ry0 = (float)(ty * TH) + 0.5f, ry1 = ry0 + (float)(TH - 1);
     for (uint32_t hi = wmax; hi > 0;) {
         const uint32_t lo = hi > 64u ? hi - 64u : 0u;
-        // stage entries hi - 1, hi - 2, ... (descending) that can reach this wavefront's pixels
+        // stage entries hi - 1, hi - 2, ... (descending) that can reach this tile's pixels
         const uint32_t e = hi - 1u - (uint32_t)lane;
         bool keep = false;
         Record R;
@@ -105,72 +121,74 @@ __global__ __launch_bounds__(TW* TH) void k_composite_bwd(BwdArgs b) {
         if (keep) {
             const int slot = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
-            s0[wave][slot] = R.r0;
-            s1[wave][slot] = R.r1;
-            s2[wave][slot] = R.r2;
-            s_rec[wave][slot] = rec;
-            s_e[wave][slot] = e;
+            s0[slot] = R.r0;
+            s1[slot] = R.r1;
+            s2[slot] = R.r2;
+            s_rec[slot] = rec;
+            s_e[slot] = e;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const int n = __popcll(km);
         for (int k = 0; k < n; ++k) {
-            const uint32_t ek = s_e[wave][k];
-            const float4 r0 = s0[wave][k];
-            const float4 r1 = s1[wave][k];
+            const uint32_t ek = s_e[k];
+            const float4 r0 = s0[k];
+            const float4 r1 = s1[k];
+            const float4 r2 = s2[k];
+            const float A2 = -0.7213475204444817f * r1.x, B2 = -1.4426950408889634f * r1.y,
+                        C2 = -0.7213475204444817f * r1.z;
+            const float dx = fpx - r0.x;
+            const float Adx = A2 * dx, Bdx = B2 * dx;
+            const float qx = fmaf(Adx, dx, r1.w);
             float g_u = 0.f, g_v = 0.f, g_A = 0.f, g_B = 0.f, g_C = 0.f, g_o = 0.f, g_r = 0.f, g_g = 0.f,
                   g_b = 0.f, g_z = 0.f;
             bool contrib = false;
-            if (inside && ek < last) {
-                const float dx = fpx - r0.x, dy = fpy - r0.y;
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                if (!(inside[q] && ek < last[q])) continue;
+                const float dy = fpy[q] - r0.y;
                 // the forward's operations exactly, so the same entries are blended:
                 // q = A' dx^2 + B' dx dy + C' dy^2 + log2 o, alpha = min(0.99, exp2(q))
-                const float A2 = -0.7213475204444817f * r1.x, B2 = -1.4426950408889634f * r1.y,
-                            C2 = -0.7213475204444817f * r1.z;
-                const float Adx = A2 * dx, Bdx = B2 * dx;
-                const float qx = fmaf(Adx, dx, r1.w);
-                const float q = fmaf(Bdx, dy, fmaf(C2 * dy, dy, qx));
-                const float oG = __builtin_amdgcn_exp2f(q);  // o G, alpha before the clamp
+                const float qq = fmaf(Bdx, dy, fmaf(C2 * dy, dy, qx));
+                const float oG = __builtin_amdgcn_exp2f(qq);  // o G, alpha before the clamp
                 const float al = fminf(0.99f, oG);
-                if (al >= thr) {
-                    contrib = true;
-                    const float4 r2 = s2[wave][k];
-                    const float om = 1.0f - al;
-                    const float Ti = T / om;
-                    const float w = al * Ti;
-                    g_r = gr * w;
-                    g_g = gg * w;
-                    g_b = gb * w;
-                    g_z = gD * w;
-                    const float iom = 1.0f / om;
-                    float dLda = gr * (r2.x * Ti - SCr * iom) + gg * (r2.y * Ti - SCg * iom) +
-                                 gb * (r2.z * Ti - SCb * iom);
-                    dLda += gD * (r0.w * Ti - SD * iom);
-                    dLda += gA * Tf * iom;
-                    SCr = fmaf(r2.x, w, SCr);
-                    SCg = fmaf(r2.y, w, SCg);
-                    SCb = fmaf(r2.z, w, SCb);
-                    SD = fmaf(r0.w, w, SD);
-                    T = Ti;
-                    if (oG < 0.99f) {
-                        g_o = dLda * oG / r0.z;      // d alpha / d o = G
-                        const float dp = dLda * oG;  // dL/dpower, power = -1/2 A dx^2 - B dx dy - 1/2 C dy^2
-                        g_u = dp * (r1.x * dx + r1.y * dy);
-                        g_v = dp * (r1.z * dy + r1.y * dx);
-                        g_A = -0.5f * dp * dx * dx;
-                        g_B = -dp * dx * dy;
-                        g_C = -0.5f * dp * dy * dy;
-                    }
+                if (!(al >= thr)) continue;
+                contrib = true;
+                const float om = 1.0f - al;
+                const float Ti = T[q] / om;
+                const float w = al * Ti;
+                g_r = fmaf(gr[q], w, g_r);
+                g_g = fmaf(gg[q], w, g_g);
+                g_b = fmaf(gb[q], w, g_b);
+                g_z = fmaf(gD[q], w, g_z);
+                const float iom = 1.0f / om;
+                float dLda = gr[q] * (r2.x * Ti - SCr[q] * iom) + gg[q] * (r2.y * Ti - SCg[q] * iom) +
+                             gb[q] * (r2.z * Ti - SCb[q] * iom);
+                dLda += gD[q] * (r0.w * Ti - SD[q] * iom);
+                dLda += gA[q] * Tf[q] * iom;
+                SCr[q] = fmaf(r2.x, w, SCr[q]);
+                SCg[q] = fmaf(r2.y, w, SCg[q]);
+                SCb[q] = fmaf(r2.z, w, SCb[q]);
+                SD[q] = fmaf(r0.w, w, SD[q]);
+                T[q] = Ti;
+                if (oG < 0.99f) {
+                    g_o = fmaf(dLda, oG / r0.z, g_o);  // d alpha / d o = G
+                    const float dp = dLda * oG;        // dL/dpower, power = -1/2 A dx^2 - B dx dy - 1/2 C dy^2
+                    g_u = fmaf(dp, r1.x * dx + r1.y * dy, g_u);
+                    g_v = fmaf(dp, r1.z * dy + r1.y * dx, g_v);
+                    g_A = fmaf(-0.5f * dp, dx * dx, g_A);
+                    g_B = fmaf(-dp, dx * dy, g_B);
+                    g_C = fmaf(-0.5f * dp, dy * dy, g_C);
                 }
             }
-            // one atomic per field per wavefront and entry
+            // one atomic per field per tile and entry
             if (__any(contrib)) {
                 g_u = wave_sum(g_u); g_v = wave_sum(g_v); g_A = wave_sum(g_A); g_B = wave_sum(g_B);
                 g_C = wave_sum(g_C); g_o = wave_sum(g_o); g_r = wave_sum(g_r); g_g = wave_sum(g_g);
                 g_b = wave_sum(g_b); g_z = wave_sum(g_z);
                 if (lane == 0) {
-                    float* o = b.g2d + (size_t)s_rec[wave][k] * 12;
+                    float* o = b.g2d + (size_t)s_rec[k] * 12;
                     atomicAdd(o + 0, g_u); atomicAdd(o + 1, g_v); atomicAdd(o + 2, g_A); atomicAdd(o + 3, g_B);
                     atomicAdd(o + 4, g_C); atomicAdd(o + 5, g_o); atomicAdd(o + 6, g_r); atomicAdd(o + 7, g_g);
                     atomicAdd(o + 8, g_b); atomicAdd(o + 9, g_z);
@@ -447,7 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(BwdArgs b) {
 
 template <int TW, int TH>
 static void launch_cbwd(const BwdArgs& b, hipStream_t s) {
-    hipLaunchKernelGGL((k_composite_bwd<TW, TH>), dim3((unsigned)b.f.tiles), dim3(TW * TH), 0, s, b);
+    hipLaunchKernelGGL((k_composite_bwd<TW, TH>), dim3((unsigned)b.f.tiles), dim3(64), 0, s, b);
 }
 
 hipError_t launch_backward(const BwdArgs& b, size_t n_records, hipStream_t s) {

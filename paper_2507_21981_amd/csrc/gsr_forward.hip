@@ -366,12 +366,21 @@ __global__ void k_tile_offsets(FwdArgs a) {
     const int t = (int)(idx - (long long)image * a.tpi);
     const int env = image / a.C, c = image - env * a.C;
     const Env ev = a.envs[env];
+    // 16 super-blocks at a time: all loads issued before the first store, so they overlap
+    constexpr int B = 16;
+    const size_t stride = (size_t)a.C * a.tpi;
+    uint32_t* p = a.sbcnt + ((size_t)ev.sb_begin * a.C + c) * a.tpi + t;
     uint32_t run = 0;
-    for (int sbi = ev.sb_begin; sbi < ev.sb_begin + ev.sb_count; ++sbi) {
-        uint32_t* p = a.sbcnt + ((size_t)sbi * a.C + c) * a.tpi + t;
-        const uint32_t v = *p;
-        *p = run;
-        run += v;
+    for (int k0 = 0; k0 < ev.sb_count; k0 += B) {
+        const int m = ev.sb_count - k0 < B ? ev.sb_count - k0 : B;
+        uint32_t v[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) v[k] = k < m ? p[(size_t)(k0 + k) * stride] : 0u;
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            if (k < m) p[(size_t)(k0 + k) * stride] = run;
+            run += v[k];
+        }
     }
     a.counts[idx] = run;
 }
@@ -488,9 +497,9 @@ __global__ __launch_bounds__(kBlock) void k_emit(FwdArgs a, const Super* __restr
 }
 
 // --------------------------------------------------------------------------------------------
-// per-tile sort by (z bits, id): tiles are classed by list length (classes 0..5: at most
-// 512, 1024, 2048, 4096, 8192, 16384 entries, sorted in LDS; class 6: longer, chunk sort +
-// merge; class 7: at most one entry or overflowed, not sorted); each class is sorted by a persistent
+// per-tile sort by (z bits, id): tiles are classed by list length (classes 0..4: at most
+// 512, 1024, 2048, 4096, 8192 entries, sorted in LDS by one block; class 5: longer, sorted in
+// chunks and merged; class 6: at most one entry or overflowed, not sorted); each class is sorted by a persistent
 // grid pulling tiles from its list.  The lists also order the persistent compositor's queue,
 // longest class first.
 // --------------------------------------------------------------------------------------------
@@ -519,7 +528,6 @@ __global__ void k_classify(FwdArgs a) {
         else if (n <= 2048) cls = 2;
         else if (n <= 4096) cls = 3;
         else if (n <= 8192) cls = 4;
-        else if (n <= 16384) cls = 5;
         else cls = kSortBig;
     }
 #pragma unroll
@@ -545,15 +553,15 @@ __global__ void k_classify(FwdArgs a) {
 // LDS layouts are padded so that the blocked accesses hit distinct banks: entry i lives at
 // i + i / E, and count f of the digit-major table at f + 2 (f / 16) u16 slots.
 template <int NT, int E>
-__device__ void sort_list(unsigned long long* p, const uint32_t n, unsigned long long* s_x, uint16_t* s_cnt,
+__device__ __forceinline__ void sort_list(unsigned long long* p, const uint32_t n, unsigned long long* s_x, uint16_t* s_cnt,
                           uint32_t* s_w, uint32_t* s_long_p) {
     constexpr int CAP = NT * E;
     constexpr int NW = NT / 64;
     constexpr int NG = E / 8;
-    constexpr int LE = E == 8 ? 3 : (E == 16 ? 4 : 5);
-    static_assert((1 << LE) == E, "E must be 8, 16 or 32");
-    constexpr bool RECOUNT = E > 16;  // recount ranks in the scatter instead of keeping them (registers)
+    constexpr int LE = E == 8 ? 3 : 4;
+    static_assert((1 << LE) == E, "E must be 8 or 16");
     uint32_t& s_long = *s_long_p;
+    if (n <= 1) return;  // nothing to order (uniform across the block); a chunk may hold one entry
     const auto P = [](uint32_t i) { return i + (i >> LE); };
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     // count (d, t) of the digit-major table lives at Q(d NT + t) = Q(t) + d DSTRIDE, with
@@ -565,15 +573,15 @@ __device__ void sort_list(unsigned long long* p, const uint32_t n, unsigned long
     // before and after, and s_x the whole list after
     auto pass = [&](int sh) {
         unsigned long long c[NG];
-        uint32_t rk[RECOUNT ? 1 : E / 4];
+        uint32_t rk[E / 4];
 #pragma unroll
         for (int g = 0; g < NG; ++g) c[g] = 0ull;
 #pragma unroll
-        for (int k = 0; k < (RECOUNT ? 1 : E / 4); ++k) rk[k] = 0u;
+        for (int k = 0; k < E / 4; ++k) rk[k] = 0u;
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             const uint32_t s4 = ((uint32_t)(x[r] >> sh) & 15u) << 2;
-            if constexpr (!RECOUNT) rk[r >> 2] |= ((uint32_t)(c[r >> 3] >> s4) & 15u) << ((r & 3) << 3);
+            rk[r >> 2] |= ((uint32_t)(c[r >> 3] >> s4) & 15u) << ((r & 3) << 3);
             c[r >> 3] += 1ull << s4;
         }
 #pragma unroll
@@ -597,6 +605,7 @@ __device__ void sort_list(unsigned long long* p, const uint32_t n, unsigned long
         if (lane == 63) s_w[wave] = incl;
         __syncthreads();
         uint32_t base = incl - tot;
+#pragma unroll 1
         for (int i = 0; i < wave; ++i) base += s_w[i];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
@@ -605,21 +614,13 @@ __device__ void sort_list(unsigned long long* p, const uint32_t n, unsigned long
             base += v;
         }
         __syncthreads();
-        unsigned long long c2 = 0ull;  // RECOUNT: counts of the current group of 8 so far
         // recompute the digits below instead of keeping E of them alive across the scan
 #pragma unroll
         for (int r = 0; r < E; ++r) asm volatile("" : "+v"(x[r]));
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             const uint32_t s4 = ((uint32_t)(x[r] >> sh) & 15u) << 2;
-            uint32_t rank;
-            if constexpr (RECOUNT) {
-                if ((r & 7) == 0) c2 = 0ull;
-                rank = (uint32_t)(c2 >> s4) & 15u;
-                c2 += 1ull << s4;
-            } else {
-                rank = (rk[r >> 2] >> ((r & 3) << 3)) & 255u;
-            }
+            uint32_t rank = (rk[r >> 2] >> ((r & 3) << 3)) & 255u;
 #pragma unroll
             for (int g = 0; g < (r >> 3); ++g) rank += (uint32_t)(c[g] >> s4) & 15u;
             const uint32_t dest = (uint32_t)s_cnt[qt + (s4 >> 2) * DSTRIDE] + rank;
@@ -668,6 +669,7 @@ __device__ void sort_list(unsigned long long* p, const uint32_t n, unsigned long
     }
     if (t == 0) s_long = 0u;
     __syncthreads();
+#pragma unroll 1
     for (int i = 0; i < NW; ++i) {
         zmin = s_w[4 * i + 0] < zmin ? s_w[4 * i + 0] : zmin;
         zmax = s_w[4 * i + 1] > zmax ? s_w[4 * i + 1] : zmax;
@@ -736,63 +738,101 @@ __global__ __launch_bounds__(NT) void k_sort_radix(FwdArgs a, int cls, const Sta
     }
 }
 
-// number of keys in sorted src[0, n) that are smaller than x
-__device__ inline uint32_t lower_rank(const unsigned long long* src, uint32_t n, unsigned long long x) {
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (src[mid] < x) lo = mid + 1; else hi = mid;
-    }
-    return lo;
+// Lists longer than one LDS sort (class kSortBig) are cut into chunks of CH entries.  Every
+// (tile, chunk) is a work item of the grid, so long lists use many CUs at once:
+//   k_sort_chunks   sorts each chunk in LDS (the same routine as the single-block classes);
+//   k_merge_chunks  places each element of a chunk at its rank in the whole list: its index
+//                   in its own chunk plus, for every other chunk of the tile (staged in LDS),
+//                   the number of smaller keys there (keys are unique); writes pairs_alt;
+//   k_copy_chunks   copies the merged lists back.
+// The item count uses the longest list of the render (max_tile) as the chunk bound.
+__device__ inline uint32_t big_chunks(const Status* __restrict__ status, uint32_t ch) {
+    return (status->max_tile + ch - 1) / ch;
 }
 
-// lists longer than one LDS load: sort chunks of NT * E entries with the LDS radix sort, then
-// merge runs pairwise by rank (keys are unique, so an element's output slot is its index in
-// its run plus its rank in the partner run), ping-ponging through the alternate pair buffer
 template <int NT, int E>
-__global__ __launch_bounds__(NT) void k_sort_big(FwdArgs a, int cls, const Status* __restrict__ status,
-                                                 const uint32_t* __restrict__ cls_list,
-                                                 const uint32_t* __restrict__ starts) {
-    constexpr uint32_t CAP = NT * E;
+__global__ __launch_bounds__(NT) void k_sort_chunks(FwdArgs a, const Status* __restrict__ status,
+                                                    const uint32_t* __restrict__ cls_list,
+                                                    const uint32_t* __restrict__ starts) {
+    constexpr uint32_t CH = NT * E;
     __shared__ unsigned long long s_x[NT * E + NT];
     __shared__ uint16_t s_cnt[18 * NT];
     __shared__ uint32_t s_w[4 * (NT / 64)];
     __shared__ uint32_t s_long;
-    const uint32_t count = status->cls[cls];
-    for (uint32_t w = blockIdx.x; w < count; w += gridDim.x) {
-        const uint32_t t = cls_list[(size_t)cls * a.tiles + w];
-        const uint32_t st = starts[t], n = starts[t + 1] - st;
-        unsigned long long* A = a.pairs + st;
-        unsigned long long* B = a.pairs_alt + st;
-        for (uint32_t c0 = 0; c0 < n; c0 += CAP)
-            sort_list<NT, E>(A + c0, (n - c0 < CAP) ? n - c0 : CAP, s_x, s_cnt, s_w, &s_long);
-        __threadfence_block();
-        unsigned long long* src = A;
-        unsigned long long* dst = B;
-        for (uint32_t run = CAP; run < n; run <<= 1) {
-            for (uint32_t i = threadIdx.x; i < n; i += NT) {
-                const uint32_t rid = i / run;
-                const uint32_t base = (rid & ~1u) * run;
-                const unsigned long long x = src[i];
-                if (rid & 1u) {
-                    dst[base + (i - base - run) + lower_rank(src + base, run, x)] = x;
-                } else {
-                    const uint32_t pb = base + run;
-                    const uint32_t pn = pb >= n ? 0u : ((n - pb) < run ? (n - pb) : run);
-                    dst[base + (i - base) + lower_rank(src + pb, pn, x)] = x;
-                }
-            }
-            __threadfence_block();
+    const uint32_t mc = big_chunks(status, CH);
+    const uint32_t items = status->cls[kSortBig] * mc;
+    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const uint32_t w = it / mc, c = it - w * mc;
+        const uint32_t tile = cls_list[(size_t)kSortBig * a.tiles + w];
+        const uint32_t st = starts[tile], n = starts[tile + 1] - st;
+        if (c * CH >= n) continue;
+        sort_list<NT, E>(a.pairs + st + c * CH, (n - c * CH < CH) ? n - c * CH : CH, s_x, s_cnt, s_w, &s_long);
+    }
+}
+
+template <int NT, int E>
+__global__ __launch_bounds__(NT) void k_merge_chunks(FwdArgs a, const Status* __restrict__ status,
+                                                     const uint32_t* __restrict__ cls_list,
+                                                     const uint32_t* __restrict__ starts) {
+    constexpr uint32_t CH = NT * E;
+    __shared__ unsigned long long s_o[CH];
+    const uint32_t mc = big_chunks(status, CH);
+    const uint32_t items = status->cls[kSortBig] * mc;
+    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const uint32_t w = it / mc, c = it - w * mc;
+        const uint32_t tile = cls_list[(size_t)kSortBig * a.tiles + w];
+        const uint32_t st = starts[tile], n = starts[tile + 1] - st;
+        if (c * CH >= n) continue;
+        const uint32_t nc = (n + CH - 1) / CH;
+        const uint32_t len = (n - c * CH < CH) ? n - c * CH : CH;
+        const unsigned long long* src = a.pairs + st;
+        unsigned long long x[E];
+        uint32_t pos[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const uint32_t i = threadIdx.x + (uint32_t)k * NT;
+            x[k] = i < len ? src[c * CH + i] : 0ull;
+            pos[k] = i;  // rank within its own (sorted) chunk
+        }
+        for (uint32_t o = 0; o < nc; ++o) {
+            if (o == c) continue;
+            const uint32_t lo = (n - o * CH < CH) ? n - o * CH : CH;
             __syncthreads();
-            unsigned long long* tmp = src;
-            src = dst;
-            dst = tmp;
+            for (uint32_t i = threadIdx.x; i < lo; i += NT) s_o[i] = src[o * CH + i];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                uint32_t l = 0, h = lo;  // keys of chunk o smaller than x[k]
+                while (l < h) {
+                    const uint32_t m = (l + h) >> 1;
+                    if (s_o[m] < x[k]) l = m + 1; else h = m;
+                }
+                pos[k] += l;
+            }
         }
-        if (src != A) {
-            for (uint32_t i = threadIdx.x; i < n; i += NT) A[i] = src[i];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const uint32_t i = threadIdx.x + (uint32_t)k * NT;
+            if (i < len) a.pairs_alt[st + pos[k]] = x[k];
         }
-        __threadfence_block();
         __syncthreads();
+    }
+}
+
+template <int NT, int E>
+__global__ __launch_bounds__(NT) void k_copy_chunks(FwdArgs a, const Status* __restrict__ status,
+                                                    const uint32_t* __restrict__ cls_list,
+                                                    const uint32_t* __restrict__ starts) {
+    constexpr uint32_t CH = NT * E;
+    const uint32_t mc = big_chunks(status, CH);
+    const uint32_t items = status->cls[kSortBig] * mc;
+    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const uint32_t w = it / mc, c = it - w * mc;
+        const uint32_t tile = cls_list[(size_t)kSortBig * a.tiles + w];
+        const uint32_t st = starts[tile], n = starts[tile + 1] - st;
+        if (c * CH >= n) continue;
+        const uint32_t len = (n - c * CH < CH) ? n - c * CH : CH;
+        for (uint32_t i = threadIdx.x; i < len; i += NT) a.pairs[st + c * CH + i] = a.pairs_alt[st + c * CH + i];
     }
 }
 
@@ -987,7 +1027,7 @@ __global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composit
 #pragma unroll
     for (int c = 0; c < kNumClasses; ++c) cnt[c] = st->cls[c];
     for (long long item = blockIdx.x; item < a.tiles; item += gridDim.x) {
-        // queue order: longest class first (6, 5, ..., 0), then class 7
+        // queue order: longest class first (5, 4, ..., 0), then class 6
         uint32_t k = (uint32_t)item;
         int cls = kSortBig;
         while (cls >= 0 && k >= cnt[cls]) {
@@ -1095,9 +1135,10 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
     mark(7);
     hipLaunchKernelGGL((k_sort_radix<512, 8>), dim3(g_num_cu * 4), dim3(512), 0, s, a, 3, a.status, a.cls_list, a.starts);
     hipLaunchKernelGGL((k_sort_radix<1024, 8>), dim3(g_num_cu * 2), dim3(1024), 0, s, a, 4, a.status, a.cls_list, a.starts);
-    hipLaunchKernelGGL((k_sort_radix<512, 32>), dim3(g_num_cu), dim3(512), 0, s, a, 5, a.status, a.cls_list, a.starts);
     mark(8);
-    hipLaunchKernelGGL((k_sort_big<512, 32>), dim3(g_num_cu), dim3(512), 0, s, a, kSortBig, a.status, a.cls_list, a.starts);
+    hipLaunchKernelGGL((k_sort_chunks<1024, 8>), dim3(g_num_cu * 2), dim3(1024), 0, s, a, a.status, a.cls_list, a.starts);
+    hipLaunchKernelGGL((k_merge_chunks<1024, 8>), dim3(g_num_cu * 2), dim3(1024), 0, s, a, a.status, a.cls_list, a.starts);
+    hipLaunchKernelGGL((k_copy_chunks<1024, 8>), dim3(g_num_cu * 2), dim3(1024), 0, s, a, a.status, a.cls_list, a.starts);
     mark(9);
     const bool two = a.ppt == 2;
     if (a.tw == 16 && a.th == 16) { if (two) launch_composite<16, 16, 2>(a, s); else launch_composite<16, 16, 1>(a, s); }

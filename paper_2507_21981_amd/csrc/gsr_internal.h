@@ -11,13 +11,13 @@ namespace gsr {
 
 constexpr int kBlock = 256;          // Gaussians per projection / emission block
 // Per-tile sort classes by list length: classes 0 .. kSortClasses - 1 hold lists of at most
-// 512, 1024, ..., 16384 entries, each sorted in LDS by one block; longer lists (class
-// kSortBig) are chunk-sorted and merged; class kSortNone holds lists of at most one entry (and
+// 512, 1024, ..., 8192 entries, each sorted in LDS by one block; longer lists (class
+// kSortBig) are sorted in chunks by many blocks and merged; class kSortNone holds lists of at most one entry (and
 // overflowed tiles).
-constexpr int kSortClasses = 6;
-constexpr int kSortBig = 6;
-constexpr int kSortNone = 7;
-constexpr int kNumClasses = 8;
+constexpr int kSortClasses = 5;
+constexpr int kSortBig = 5;
+constexpr int kSortNone = 6;
+constexpr int kNumClasses = 7;
 constexpr int kLdsHistLimit = 16384; // int counters a block may keep in LDS for tile histograms
 
 // One (node, camera) view: the camera<-node map composed in FP64 and rounded

@@ -185,6 +185,21 @@ def test_clustered_depths_sort_exactly(gsr, ctx, spread_ulps, outlier):
     assert lens.max() > 2000
 
 
+@pytest.mark.parametrize("n", [8193, 8256, 16385])
+def test_chunked_lists_with_short_last_chunk(gsr, ctx, n):
+    """One 16x16 image, every Gaussian inside it: the tile's list holds exactly n entries, so
+    lists longer than one LDS sort are cut into chunks with a last chunk of 1 or 64 entries."""
+    from helpers import cam_identity, env_of, node
+    rng = np.random.default_rng(n)
+    means = np.c_[rng.uniform(-0.02, 0.02, (n, 2)), rng.uniform(2.0, 6.0, n)].astype(np.float32)
+    g = node(means, 0.002, opac=0.02, colours=rng.uniform(0, 1, (n, 3)))
+    env = env_of([g])
+    env["cams"] = [cam_identity(16, 16, 20.0)]
+    wl = dict(envs=[env], cams_per_env=1, width=16, height=16, name=f"one tile, {n} entries")
+    _, _, _, _, _, refs, _ = _run(gsr, ctx, wl, (16, 16))
+    assert refs[0]["ranges"][0, 1] - refs[0]["ranges"][0, 0] == n
+
+
 def test_graph_replay_matches_eager_bitwise(gsr, ctx):
     import torch
     wl = synth.scene_config(3, seed=17, scale=0.02, n_envs=3)

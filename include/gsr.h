@@ -151,8 +151,8 @@ typedef struct {
     int64_t pair_capacity;    /* initial pair capacity, default 1 << 22                       */
     int32_t persistent_grid;  /* persistent composite size in 256-thread blocks, default 8 per
                                  CU (scaled to the tile's block size)                        */
-    int32_t pixels_per_thread;/* compositor pixels per thread, 1 or 2 (default 2; 8x8 tiles
-                                 always use 1)                                               */
+    int32_t pixels_per_thread;/* compositor pixels per thread, 1, 2 or 4 (default 2); capped
+                                 at tile pixels / 64 (8x8 tiles use 1, 16x8 at most 2)       */
     int32_t reserved[6];
 } gsr_config;
 

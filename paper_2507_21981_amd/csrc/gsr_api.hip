@@ -180,9 +180,9 @@ int gsr_create(int device, const gsr_config* cfg, gsr_context** out) {
     hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device);
     if (c.persistent_grid <= 0) c.persistent_grid = 8 * std::max(ctx->num_cu, 1);
     if (c.pixels_per_thread == 0) c.pixels_per_thread = 2;
-    if (c.pixels_per_thread != 1 && c.pixels_per_thread != 2) {
+    if (c.pixels_per_thread != 1 && c.pixels_per_thread != 2 && c.pixels_per_thread != 4) {
         delete ctx;
-        return fail(nullptr, GSR_E_UNSUPPORTED, "gsr_create: pixels_per_thread must be 1 or 2");
+        return fail(nullptr, GSR_E_UNSUPPORTED, "gsr_create: pixels_per_thread must be 1, 2 or 4");
     }
     ctx->cfg = c;
     if (hipMalloc(&ctx->d_status, sizeof(Status)) != hipSuccess ||
@@ -232,7 +232,8 @@ int gsr_set_tile(gsr_context* ctx, int32_t tw, int32_t th) {
 
 int gsr_set_pixels_per_thread(gsr_context* ctx, int32_t ppt) {
     if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_set_pixels_per_thread: ctx is NULL");
-    if (ppt != 1 && ppt != 2) return fail(ctx, GSR_E_UNSUPPORTED, "gsr_set_pixels_per_thread: %d not 1 or 2", ppt);
+    if (ppt != 1 && ppt != 2 && ppt != 4)
+        return fail(ctx, GSR_E_UNSUPPORTED, "gsr_set_pixels_per_thread: %d not 1, 2 or 4", ppt);
     if (ppt != ctx->cfg.pixels_per_thread) drop_graph(ctx);
     ctx->cfg.pixels_per_thread = ppt;
     return GSR_OK;
@@ -432,7 +433,8 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
     a.n_contrib = ctx->n_contrib.p;
     a.persistent = persistent;
     a.persistent_grid = ctx->cfg.persistent_grid;
-    a.ppt = (tw == 8 && th == 8) ? 1 : ctx->cfg.pixels_per_thread;
+    // at most one wavefront's worth of pixels per lane group: 8x8 tiles take 1, 16x8 up to 2
+    a.ppt = std::min(ctx->cfg.pixels_per_thread, tw * th / 64);
     a.save = save;
     a.count = 0;
     return GSR_OK;
@@ -611,8 +613,8 @@ int gsr_autotune(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_cam
         HIPCHK(ctx, hipEventCreate(&e0));
         HIPCHK(ctx, hipEventCreate(&e1));
         for (auto& sh : shapes) {
-            for (int ppt = 1; ppt <= 2; ++ppt) {
-                if (ppt == 2 && sh[0] == 8 && sh[1] == 8) continue;
+            for (int ppt = 1; ppt <= 4; ppt *= 2) {
+                if (ppt > sh[0] * sh[1] / 64) continue;
                 for (int pers = 0; pers < 2; ++pers) {
                     int r = gsr_set_tile(ctx, sh[0], sh[1]);
                     if (!r) r = gsr_set_pixels_per_thread(ctx, ppt);

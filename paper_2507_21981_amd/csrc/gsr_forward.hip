@@ -852,10 +852,12 @@ __global__ __launch_bounds__(NT) void k_copy_chunks(FwdArgs a, const Status* __r
 // lane sits 64 / SW rows below pixel p - 1).  8 x 8 squares when the tile allows.
 template <int TW, int TH, int PPT>
 struct SubTile {
-    static constexpr int SW = (TH % (8 * PPT) == 0) ? 8 : 16;
+    // the narrowest of 8, 16, 32 columns whose 64 PPT / width rows fit the tile's height
+    static constexpr int SW = (TW >= 8 && TH % (8 * PPT) == 0) ? 8 : ((TW >= 16 && TH % (4 * PPT) == 0) ? 16 : 32);
     static constexpr int SH = 64 * PPT / SW;
     static constexpr int WAVES = (TW / SW) * (TH / SH);
     static constexpr int LROWS = 64 / SW;
+    static_assert(TW % SW == 0 && TH % SH == 0, "sub-tile must tile the tile");
 };
 
 // One wavefront composites its sub-tile of tile t, walking the tile's whole list in batches of
@@ -1140,11 +1142,20 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_merge_chunks<1024, 8>), dim3(g_num_cu * 2), dim3(1024), 0, s, a, a.status, a.cls_list, a.starts);
     hipLaunchKernelGGL((k_copy_chunks<1024, 8>), dim3(g_num_cu * 2), dim3(1024), 0, s, a, a.status, a.cls_list, a.starts);
     mark(9);
-    const bool two = a.ppt == 2;
-    if (a.tw == 16 && a.th == 16) { if (two) launch_composite<16, 16, 2>(a, s); else launch_composite<16, 16, 1>(a, s); }
-    else if (a.tw == 16 && a.th == 8) { if (two) launch_composite<16, 8, 2>(a, s); else launch_composite<16, 8, 1>(a, s); }
-    else if (a.tw == 8 && a.th == 8) launch_composite<8, 8, 1>(a, s);
-    else { if (two) launch_composite<32, 8, 2>(a, s); else launch_composite<32, 8, 1>(a, s); }
+    if (a.tw == 16 && a.th == 16) {
+        if (a.ppt == 4) launch_composite<16, 16, 4>(a, s);
+        else if (a.ppt == 2) launch_composite<16, 16, 2>(a, s);
+        else launch_composite<16, 16, 1>(a, s);
+    } else if (a.tw == 16 && a.th == 8) {
+        if (a.ppt == 2) launch_composite<16, 8, 2>(a, s);
+        else launch_composite<16, 8, 1>(a, s);
+    } else if (a.tw == 8 && a.th == 8) {
+        launch_composite<8, 8, 1>(a, s);
+    } else {
+        if (a.ppt == 4) launch_composite<32, 8, 4>(a, s);
+        else if (a.ppt == 2) launch_composite<32, 8, 2>(a, s);
+        else launch_composite<32, 8, 1>(a, s);
+    }
     mark(10);
     return hipGetLastError();
 }

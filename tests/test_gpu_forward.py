@@ -63,6 +63,17 @@ def test_plain_forward_20k_sh0_128(gsr, ctx, tile):
     _run(gsr, ctx, wl, tile)
 
 
+@pytest.mark.parametrize("tile,ppt", [((16, 16), 4), ((32, 8), 4), ((16, 16), 1), ((16, 8), 1)])
+def test_pixels_per_lane_variants(gsr, ctx, tile, ppt):
+    wl = synth.scene_config(0, seed=19)
+    wl["name"] = f"20k SH0 128x128, {ppt} pixels per lane"
+    ctx.set_pixels_per_thread(ppt)
+    try:
+        _run(gsr, ctx, wl, tile)
+    finally:
+        ctx.set_pixels_per_thread(2)
+
+
 def test_composed_scene_three_cameras(gsr, ctx):
     # background + 8 posed object nodes, SH degree 3, head + two wrist cameras
     wl = synth.scene_config(2, seed=3, scale=0.03)

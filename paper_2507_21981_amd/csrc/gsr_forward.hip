@@ -542,7 +542,8 @@ __global__ void k_classify(FwdArgs a) {
 // Each entry is packed into one 64-bit word X = (z bits - zmin) << ib | (id - idmin), whose
 // order is the order of (z bits, id) and whose significant bits number TB = (bits of the
 // depth range) + ib.  An LSD radix sort with 4-bit digits over the top 16 significant bits
-// (at most four passes) leaves the list in runs of equal top bits, in order; each entry then
+// (12 for lists of at most 1024 entries; at most four passes) leaves the list in runs of equal
+// top bits, in order; each entry then
 // takes its place inside its run by counting the run's smaller words.  Runs are short for any
 // spread of depths; if a run is longer than 64 entries, the tile is sorted again by LSD passes
 // over all TB bits (so the result is exact for any input, and fast for the usual one).

@@ -152,14 +152,19 @@ def main():
     log(f"[bench] batched: {ms:.3f} ms/step, {value:.1f} Mpx/s, pairs {st['pairs']}, evals {st['evals']}")
 
     # per-stage durations (eager, HIP events between stages on the render stream)
+    # (the same kernels as the graph; evaluations are counted by a checked render of each pose set)
     stage = {k: 0.0 for k in gsr.STAGES}
     n_t = max(1, min(args.steps, 5))
+    evals = 0
     for s in range(n_t):
         poses.copy_(pose_sets[(args.warmup + s) % len(pose_sets)])
         gsr.render_rgbd(ctx, scene, cams, W, H, C, out=out, flags=gsr.FLAG_TIMING | fl_pers)
         for k, v in gsr.stage_times(ctx).items():
             stage[k] += v / n_t
-    st_t = gsr.query_status(ctx)
+        gsr.render_rgbd(ctx, scene, cams, W, H, C, out=out, flags=gsr.FLAG_CHECK | fl_pers)
+        evals += gsr.query_status(ctx)["evals"]
+    st_t = dict(gsr.query_status(ctx))
+    st_t["evals"] = evals // n_t
     log("[bench] stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stage.items()))
     ppt = ctx.config.pixels_per_thread
     roof = roofline(stage, st_t, n_total, (tw, th, ppt, pers))
@@ -255,14 +260,18 @@ def roofline(stage, st, n_total, cfg):
     times = {"project": stage["project"], "emit": stage["emit"],
              "sort": stage["sort_small"] + stage["sort_mid"] + stage["sort_big"], "composite": stage["composite"]}
     tw, th, ppt, pers = cfg
-    kname = {"project": "k_project<3>(FwdArgs)", "emit": "k_emit(FwdArgs)",
-             "composite": f"k_composite{'_persistent' if pers else ''}<{tw}, {th}, {ppt}, false>(FwdArgs)"}
+    # kernel names as the profiler prints them, without the parameter list; the timed region
+    # composites without evaluation counting
+    kname = {"project": "k_project<3>", "emit": "k_emit",
+             "composite": f"k_composite{'_persistent' if pers else ''}<{tw}, {th}, {ppt}, false, false>"}
     traffic = measured_traffic()
+    if traffic is not None:
+        traffic = {n.split("(")[0]: v for n, v in traffic.items()}
 
     def kernel_traffic(k):
         if traffic is None:
             return None
-        names = [kname[k]] if k in kname else [n for n in traffic if n.startswith("k_sort")]
+        names = [kname[k]] if k in kname else [n for n in traffic if n.startswith(("k_sort", "k_merge", "k_copy_chunks"))]
         if not names or any(n not in traffic for n in names):
             return None
         return sum(traffic[n]["fetch_bytes"] + traffic[n]["write_bytes"] for n in names)

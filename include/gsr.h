@@ -135,8 +135,7 @@ typedef struct {
     uint64_t evals;          /* Gaussian-pixel evaluations of the last render: over pixels,
                                 the list entries that reach the pixel's wavefront sub-tile,
                                 evaluated up to and including the stopping one.  Counted
-                                only by renders with GSR_FLAG_CHECK or GSR_FLAG_TIMING (0
-                                otherwise).                                                 */
+                                only by renders with GSR_FLAG_CHECK (0 otherwise).          */
 } gsr_status_info;
 
 /* Number of timed forward stages and their names, in order: views, project,

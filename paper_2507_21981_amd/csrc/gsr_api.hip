@@ -462,7 +462,7 @@ int gsr_render_rgbd(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_
     FwdArgs a;
     int r = prepare(ctx, sc, C, cams, W, H, rgb, depth, alpha, persistent, save, a);
     if (r) return r;
-    const int count = (flags & (GSR_FLAG_CHECK | GSR_FLAG_TIMING)) ? 1 : 0;
+    const int count = (flags & GSR_FLAG_CHECK) ? 1 : 0;
     a.count = count;
     ctx->last_stream = s;
     if (flags & GSR_FLAG_GRAPH) {
@@ -530,9 +530,12 @@ int gsr_query_status(gsr_context* ctx, gsr_status_info* out) {
     out->pair_capacity = (uint64_t)ctx->pair_cap;
     out->max_tile_pairs = st.max_tile;
     out->reserved = 0;
-    out->visible = st.visible;
-    out->visible_any = st.visible_any;
-    out->evals = st.evals;
+    out->visible = out->visible_any = out->evals = 0;
+    for (int q = 0; q < kParts; ++q) {
+        out->visible += st.visible[q];
+        out->visible_any += st.visible_any[q];
+        out->evals += st.evals[q];
+    }
     return GSR_OK;
 }
 

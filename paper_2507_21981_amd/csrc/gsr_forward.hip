@@ -38,9 +38,7 @@ __global__ void k_views(FwdArgs a) {
         st->max_tile = 0;
         for (int c = 0; c < 8; ++c) st->cls[c] = 0;
         st->work_head = 0;
-        st->visible = 0;
-        st->visible_any = 0;
-        st->evals = 0;
+        for (int q = 0; q < kParts; ++q) st->visible[q] = st->visible_any[q] = st->evals[q] = 0;
     }
 
     if (idx >= a.n_nodes * a.C) return;
@@ -343,15 +341,27 @@ __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a, const Super* __re
         const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
         out[j] = (uint32_t)s_grid[c * gsz + ty * gx + tx];
     }
-    // per-wavefront sums of visible records, one atomic per wavefront
+    // block sums of visible records: one atomic per block into its counter slot
     unsigned long long nv = (unsigned long long)n_vis, na = (unsigned long long)n_any;
     for (int off = 32; off > 0; off >>= 1) {
         nv += __shfl_xor(nv, off, 64);
         na += __shfl_xor(na, off, 64);
     }
-    if ((threadIdx.x & 63) == 0 && nv) {
-        atomicAdd(&a.status->visible, nv);
-        atomicAdd(&a.status->visible_any, na);
+    __shared__ unsigned long long s_sum[2 * (kBlock / 64)];
+    if ((threadIdx.x & 63) == 0) {
+        s_sum[2 * (threadIdx.x >> 6)] = nv;
+        s_sum[2 * (threadIdx.x >> 6) + 1] = na;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) {
+            nv += s_sum[2 * w];
+            na += s_sum[2 * w + 1];
+        }
+        if (nv) {
+            atomicAdd(&a.status->visible[blockIdx.x % kParts], nv);
+            atomicAdd(&a.status->visible_any[blockIdx.x % kParts], na);
+        }
     }
 }
 
@@ -846,8 +856,9 @@ __global__ __launch_bounds__(NT) void k_copy_chunks(FwdArgs a, const Status* __r
 // Per pixel: skip if alpha < 1/255; stop (without blending) if T (1 - alpha) < 1e-4; else
 // C += alpha T c, D += alpha T z, T *= 1 - alpha.  rgb = C + T bg, depth = D, alpha = 1 - T.
 // Each batch of the list is culled against the wavefront's sub-tile and compacted (in list
-// order) before the pixel loop; the loop is predicated, a wavefront skips an entry that
-// reaches none of its pixels and leaves the list as soon as none of its pixels is live.
+// order) before the pixel loop; the loop is predicated (after the cull nearly every entry
+// reaches some pixel of the sub-tile, so a per-entry wavefront skip costs more than it saves)
+// and the wavefront leaves the list as soon as none of its pixels is live.
 // --------------------------------------------------------------------------------------------
 // Sub-tile of one wavefront: SW x SH pixels, 64 lanes x PPT pixels per lane (pixel p of a
 // lane sits 64 / SW rows below pixel p - 1).  8 x 8 squares when the tile allows.
@@ -898,7 +909,7 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
         last[p] = 0;
         evals[p] = 0;
     }
-    // an entry with q below this for every lane of a wavefront cannot pass the 1/255 test
+    // an entry with q below this at every pixel of the sub-tile cannot pass the 1/255 test
     // (exp2 is accurate to ~1e-7 relative, the margin is 1e-3 in the exponent)
     const float qcut = -7.994353436858858f - 1e-3f;  // log2(1/255) - 1e-3
     // the wavefront's pixel-centre rectangle
@@ -948,15 +959,12 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
             const float Adx = e0.z * dx, Bdx = e0.w * dx;
             const float qx = fmaf(Adx, dx, e1.y);
             float q[PPT];
-            bool hit = false;
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {
                 const float dy = fpy[p] - e0.y;
                 q[p] = fmaf(Bdx, dy, fmaf(e1.x * dy, dy, qx));
                 if (COUNT) evals[p] += T[p] > 0.0f ? 1u : 0u;
-                hit |= q[p] >= qcut;
             }
-            if (!__any(hit)) continue;
             const float4 e2 = s2[k];
             const uint32_t idx1 = __float_as_uint(e2.z);
 #pragma unroll
@@ -998,7 +1006,7 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
     }
     if (COUNT) {
         for (int off = 32; off > 0; off >>= 1) nev += __shfl_xor(nev, off, 64);
-        if (lane == 0 && nev) atomicAdd(&a.status->evals, nev);
+        if (lane == 0 && nev) atomicAdd(&a.status->evals[blockIdx.x % kParts], nev);
     }
 }
 

@@ -68,6 +68,8 @@ struct Super {
 
 constexpr int kMaxChunksPerSuper = 16;
 
+constexpr int kParts = 64;
+
 struct Status {
     uint32_t flags;
     uint32_t nonfinite;
@@ -75,10 +77,12 @@ struct Status {
     uint32_t max_tile;
     uint32_t cls[8];      // tile counts per sort class
     uint32_t work_head;   // unused
-    unsigned long long visible;      // visible (image, Gaussian) records
-    unsigned long long visible_any;  // Gaussians visible in at least one camera
-    unsigned long long evals;        // Gaussian-pixel evaluations of the compositor
-    uint32_t pad[6];
+    uint32_t pad[5];
+    // counters summed on the host over kParts slots (block b adds into slot b % kParts): a
+    // single address taking an atomic from every wavefront serialises the grid
+    unsigned long long visible[kParts];      // visible (image, Gaussian) records
+    unsigned long long visible_any[kParts];  // Gaussians visible in at least one camera
+    unsigned long long evals[kParts];        // Gaussian-pixel evaluations of the compositor
 };
 
 constexpr int kStages = 10;  // views, project, tile counts, scan, emit, classify, 3 sorts, composite

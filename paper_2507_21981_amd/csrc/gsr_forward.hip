@@ -582,18 +582,23 @@ __device__ __forceinline__ void sort_list(unsigned long long* p, const uint32_t 
     unsigned long long x[E];
     // one stable pass on the 4-bit digit at bit sh; x[] holds the thread's entries (blocked)
     // before and after, and s_x the whole list after
+    // threads whose entries are all padding (t E >= n) only report their counts: padding words
+    // are all-ones, so they always land in digit 15 behind every entry and are never stored
+    const bool live = (uint32_t)t * E < n;
     auto pass = [&](int sh) {
         unsigned long long c[NG];
         uint32_t rk[E / 4];
 #pragma unroll
-        for (int g = 0; g < NG; ++g) c[g] = 0ull;
+        for (int g = 0; g < NG; ++g) c[g] = live ? 0ull : 8ull << 60;  // 8 entries in digit 15
 #pragma unroll
         for (int k = 0; k < E / 4; ++k) rk[k] = 0u;
+        if (live) {
 #pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const uint32_t s4 = ((uint32_t)(x[r] >> sh) & 15u) << 2;
-            rk[r >> 2] |= ((uint32_t)(c[r >> 3] >> s4) & 15u) << ((r & 3) << 3);
-            c[r >> 3] += 1ull << s4;
+            for (int r = 0; r < E; ++r) {
+                const uint32_t s4 = ((uint32_t)(x[r] >> sh) & 15u) << 2;
+                rk[r >> 2] |= ((uint32_t)(c[r >> 3] >> s4) & 15u) << ((r & 3) << 3);
+                c[r >> 3] += 1ull << s4;
+            }
         }
 #pragma unroll
         for (int d = 0; d < 16; ++d) {
@@ -625,22 +630,26 @@ __device__ __forceinline__ void sort_list(unsigned long long* p, const uint32_t 
             base += v;
         }
         __syncthreads();
-        // recompute the digits below instead of keeping E of them alive across the scan
+        if (live) {
+            // recompute the digits below instead of keeping E of them alive across the scan
 #pragma unroll
-        for (int r = 0; r < E; ++r) asm volatile("" : "+v"(x[r]));
+            for (int r = 0; r < E; ++r) asm volatile("" : "+v"(x[r]));
 #pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const uint32_t s4 = ((uint32_t)(x[r] >> sh) & 15u) << 2;
-            uint32_t rank = (rk[r >> 2] >> ((r & 3) << 3)) & 255u;
+            for (int r = 0; r < E; ++r) {
+                const uint32_t s4 = ((uint32_t)(x[r] >> sh) & 15u) << 2;
+                uint32_t rank = (rk[r >> 2] >> ((r & 3) << 3)) & 255u;
 #pragma unroll
-            for (int g = 0; g < (r >> 3); ++g) rank += (uint32_t)(c[g] >> s4) & 15u;
-            const uint32_t dest = (uint32_t)s_cnt[qt + (s4 >> 2) * DSTRIDE] + rank;
-            s_x[P(dest)] = x[r];
-            if ((r & 7) == 7) asm volatile("" ::: "memory");  // bounds the scheduling window (registers)
+                for (int g = 0; g < (r >> 3); ++g) rank += (uint32_t)(c[g] >> s4) & 15u;
+                const uint32_t dest = (uint32_t)s_cnt[qt + (s4 >> 2) * DSTRIDE] + rank;
+                if (dest < n) s_x[P(dest)] = x[r];  // positions >= n hold padding only
+                if ((r & 7) == 7) asm volatile("" ::: "memory");  // bounds the scheduling window (registers)
+            }
         }
         __syncthreads();
+        if (live) {
 #pragma unroll
-        for (int r = 0; r < E; ++r) x[r] = s_x[t * (E + 1) + r];
+            for (int r = 0; r < E; ++r) x[r] = (uint32_t)(t * E + r) < n ? s_x[t * (E + 1) + r] : ~0ull;
+        }
         __syncthreads();
     };
     // striped copy into LDS (entry t + k NT lives at P(t) + k (NT + NT / E))

@@ -447,8 +447,9 @@ __global__ __launch_bounds__(1024) void k_scan(FwdArgs a) {
 // pair emission into tile buckets.  Each (super-block, camera) walks its compact list of
 // visible Gaussians and knows, per tile, the first slot of its pairs (tile start + the offsets
 // of the env's earlier super-blocks), so slots are taken with LDS atomics only.  Within a
-// batch of 256 list entries, the (Gaussian, tile) pairs are enumerated with a block-wide
-// prefix over rectangle areas, so large rectangles are shared by all threads.
+// batch of 256 list entries, the (Gaussian, tile) pairs are numbered by a block-wide prefix
+// over rectangle areas and split into equal runs of consecutive pairs, one per thread, so
+// large rectangles are shared by all threads.
 // Pair = (z bits << 32) | Gaussian id.
 // --------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_emit(FwdArgs a, const Super* __restrict__ supers,
@@ -488,19 +489,40 @@ __global__ __launch_bounds__(kBlock) void k_emit(FwdArgs a, const Super* __restr
             s_off[i + 1] += v;
             __syncthreads();
         }
+        // thread i takes the consecutive pairs [k0, k1): one search for the owner of k0, then
+        // a walk along the owners' rectangles (row-major tiles)
         const uint32_t total = s_off[kBlock];
-        for (uint32_t k = i; k < total; k += kBlock) {
-            int lo = 0, hi = kBlock - 1;  // first owner with s_off[owner + 1] > k
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (s_off[mid + 1] > k) hi = mid; else lo = mid + 1;
+        const uint32_t per = (total + kBlock - 1) / kBlock;
+        const uint32_t k0 = (uint32_t)i * per, k1 = k0 + per < total ? k0 + per : total;
+        if (k0 < k1) {
+            int o = 0, hi = kBlock - 1;  // first owner with s_off[owner + 1] > k0
+            while (o < hi) {
+                const int mid = (o + hi) >> 1;
+                if (s_off[mid + 1] > k0) hi = mid; else o = mid + 1;
             }
-            const uint32_t j = k - s_off[lo];
-            const uint32_t w = s_w[lo];
-            const uint32_t ty = s_y0[lo] + j / w, tx = s_x0[lo] + j % w;
-            const uint32_t pos = atomicAdd(&s_slot[ty * a.tiles_x + tx], 1u);
-            if ((unsigned long long)pos < cap)
-                a.pairs[pos] = ((unsigned long long)s_z[lo] << 32) | (unsigned long long)s_id[lo];
+            uint32_t j = k0 - s_off[o];
+            uint32_t w = s_w[o], x0 = s_x0[o];
+            uint32_t tx = x0 + j % w, ty = s_y0[o] + j / w;
+            uint32_t left = s_off[o + 1] - k0;  // pairs of owner o from k0 on
+            unsigned long long val = ((unsigned long long)s_z[o] << 32) | (unsigned long long)s_id[o];
+            for (uint32_t k = k0; k < k1; ++k) {
+                while (left == 0) {  // next owner with pairs; k < total guarantees one exists
+                    ++o;
+                    w = s_w[o];
+                    x0 = s_x0[o];
+                    tx = x0;
+                    ty = s_y0[o];
+                    left = s_off[o + 1] - s_off[o];
+                    val = ((unsigned long long)s_z[o] << 32) | (unsigned long long)s_id[o];
+                }
+                const uint32_t pos = atomicAdd(&s_slot[ty * a.tiles_x + tx], 1u);
+                if ((unsigned long long)pos < cap) a.pairs[pos] = val;
+                --left;
+                if (++tx == x0 + w) {
+                    tx = x0;
+                    ++ty;
+                }
+            }
         }
         __syncthreads();
     }

@@ -245,25 +245,27 @@ def roofline(stage, st, n_total, cfg):
 
     Algorithmic work per unit: projection reads 44 B per Gaussian (mean, opacity, scales,
     quaternion), 12 K B of SH per Gaussian visible from any camera, and writes 64 B per visible
-    (image, Gaussian) (48 B record + 16 B visible-list entry); emission reads the 16 B list entry
-    and writes 8 B per pair; the sort reads and writes each pair once (8 B each way); the
+    (image, Gaussian) (48 B record + 16 B visible-list entry); the depth sort copies each 16 B
+    list entry into its image's segment, then makes four radix passes, each reading the 4 B key
+    for the histogram and reading and writing the 16 B (key, id, rectangle) record; tile counting reads the 8 B rectangle and
+    emission the 16 B record per visible record, and emission writes 8 B per pair; the
     compositor does at least OPS_PER_EVAL VALU lane-operations per Gaussian-pixel evaluation.
     """
     K = 16
     visible, visible_any, pairs, evals = st["visible"], st["visible_any"], st["pairs"], st["evals"]
     work = {
         "project": ("hbm", 44 * n_total + 12 * K * visible_any + 64 * visible),
-        "emit": ("hbm", 16 * visible + 8 * pairs),
-        "sort": ("hbm", 16 * pairs),
+        "sort": ("hbm", (32 + 4 * (4 + 16 + 16)) * visible),
+        "emit": ("hbm", 8 * visible + 16 * visible + 8 * pairs),
         "composite": ("alu", evals * OPS_PER_EVAL),
     }
-    times = {"project": stage["project"], "emit": stage["emit"],
-             "sort": stage["sort_small"] + stage["sort_mid"] + stage["sort_big"], "composite": stage["composite"]}
+    times = {"project": stage["project"], "sort": stage["gather"] + stage["depth_sort"],
+             "emit": stage["tile_counts"] + stage["emit"], "composite": stage["composite"]}
     tw, th, ppt, pers = cfg
     # kernel names as the profiler prints them, without the parameter list; the timed region
     # composites without evaluation counting
-    kname = {"project": "k_project<3>", "emit": "k_emit",
-             "composite": f"k_composite{'_persistent' if pers else ''}<{tw}, {th}, {ppt}, false, false>"}
+    kname = {"project": ["k_project<3>"], "emit": ["k_tile_counts", "k_emit"],
+             "composite": [f"k_composite{'_persistent' if pers else ''}<{tw}, {th}, {ppt}, false, false>"]}
     traffic = measured_traffic()
     if traffic is not None:
         traffic = {n.split("(")[0]: v for n, v in traffic.items()}
@@ -271,21 +273,21 @@ def roofline(stage, st, n_total, cfg):
     def kernel_traffic(k):
         if traffic is None:
             return None
-        names = [kname[k]] if k in kname else [n for n in traffic if n.startswith(("k_sort", "k_merge", "k_copy_chunks"))]
+        names = kname[k] if k in kname else [n for n in traffic if n.startswith(("k_radix", "k_gather", "k_seg"))]
         if not names or any(n not in traffic for n in names):
             return None
         return sum(traffic[n]["fetch_bytes"] + traffic[n]["write_bytes"] for n in names)
 
-    # the dominant single kernel (the sort stage is six launches, each shorter)
-    dom = max(("project", "emit", "composite"), key=times.get)
+    # the dominant single kernel (the sort and emission stages are several launches)
+    dom = max(("project", "composite"), key=times.get)
     t = times[dom] * 1e-3
     bound, amount = work[dom]
     ach = amount / t / 1e9
     if bound == "hbm":
-        r = {"kernel": kname[dom], "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        r = {"kernel": kname[dom][0], "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
              "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": kernel_traffic(dom), "algorithmic_bytes": int(amount)}
     else:
-        r = {"kernel": kname[dom], "bound": "alu", "achieved": round(ach, 1), "peak": round(PEAK_VALU_GOPS, 1),
+        r = {"kernel": kname[dom][0], "bound": "alu", "achieved": round(ach, 1), "peak": round(PEAK_VALU_GOPS, 1),
              "unit": "Gop/s (VALU lane-ops)", "frac": round(ach / PEAK_VALU_GOPS, 4),
              "traffic": kernel_traffic(dom), "evals": int(evals), "ops_per_eval": OPS_PER_EVAL}
     r["kernel_ms"] = round(times[dom], 4)

@@ -139,8 +139,9 @@ typedef struct {
 } gsr_status_info;
 
 /* Number of timed forward stages and their names, in order: views, project,
-   tile_offsets, scan, emit, classify, sort_small (lists <= 2048), sort_mid
-   (<= 8192), sort_big (longer: chunk sort, merge, copy back), composite. */
+   gather (visible lists into per-image segments), depth_sort (the per-image radix
+   sort by depth), tile_counts (pair-balanced chunks and their per-tile counts),
+   tile_offsets, scan, emit, classify, composite. */
 #define GSR_STAGES 10
 
 /* Configuration.  Tile shape must be one of 16x16, 16x8, 8x8, 32x8 (width x

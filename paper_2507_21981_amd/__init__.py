@@ -25,7 +25,7 @@ FLAG_GRAPH = 4
 FLAG_PERSISTENT = 8
 FLAG_TIMING = 16
 STATUS_OVERFLOW = 1
-STAGES = ("views", "project", "tile_offsets", "scan", "emit", "classify", "sort_small", "sort_mid", "sort_big",
+STAGES = ("views", "project", "gather", "depth_sort", "tile_counts", "tile_offsets", "scan", "emit", "classify",
           "composite")
 
 _ERRORS = {-1: "GSR_E_INVALID", -2: "GSR_E_NOMEM", -3: "GSR_E_HIP", -4: "GSR_E_CAPACITY",

@@ -76,13 +76,15 @@ struct gsr_context {
     std::string err = "no error";
     Status* d_status = nullptr;
     Status* h_status = nullptr;  // pinned
-    DevBuf<unsigned long long> pairs, pairs_alt;
+    DevBuf<unsigned long long> pairs;
     long long pair_cap = 0;
     DevBuf<Record> records;
     DevBuf<uint4> vis;
-    DevBuf<uint32_t> sbvis;
-    DevBuf<uint32_t> sbcnt;
-    DevBuf<uint32_t> counts, starts, cursor, cls_list;
+    DevBuf<uint32_t> sbvis, loff;
+    DevBuf<uint32_t> skey0, skey1, sgid0, sgid1;
+    DevBuf<uint2> srect0, srect1;
+    DevBuf<uint32_t> hist, seg_n, seg_start, blk_pairs, chunk_base, cstart, cimg, ecnt;
+    DevBuf<uint32_t> counts, starts, cls_list;
     DevBuf<View> views;
     DevBuf<float> T_final;
     DevBuf<uint32_t> n_contrib;
@@ -204,8 +206,12 @@ void gsr_destroy(gsr_context* ctx) {
     for (auto& e : ctx->stage_ev)
         if (e) hipEventDestroy(e);
     if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
-    ctx->pairs.release(); ctx->pairs_alt.release(); ctx->records.release(); ctx->vis.release(); ctx->sbvis.release();
-    ctx->sbcnt.release(); ctx->counts.release(); ctx->starts.release(); ctx->cursor.release();
+    ctx->pairs.release(); ctx->records.release(); ctx->vis.release(); ctx->sbvis.release(); ctx->loff.release();
+    ctx->skey0.release(); ctx->skey1.release(); ctx->sgid0.release(); ctx->sgid1.release();
+    ctx->srect0.release(); ctx->srect1.release(); ctx->hist.release(); ctx->seg_n.release(); ctx->ecnt.release();
+    ctx->seg_start.release(); ctx->blk_pairs.release(); ctx->chunk_base.release(); ctx->cstart.release();
+    ctx->cimg.release();
+    ctx->counts.release(); ctx->starts.release();
     ctx->cls_list.release(); ctx->views.release(); ctx->T_final.release(); ctx->n_contrib.release();
     ctx->g2d.release(); ctx->grads_dev.release();
     if (ctx->d_status) hipFree(ctx->d_status);
@@ -393,37 +399,68 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
     a.tiles_y = (H + th - 1) / th;
     a.tpi = a.tiles_x * a.tiles_y;
     a.tiles = (long long)a.images * a.tpi;
-    const int gsz = (a.tiles_x + 1) * (a.tiles_y + 1);
-    if ((long long)C * gsz > kLdsHistLimit || (long long)C * a.tpi > kLdsHistLimit)
-        return fail(ctx, GSR_E_UNSUPPORTED, "%d cameras of %dx%d with %dx%d tiles exceed the %d per-block tile counters",
-                    C, W, H, tw, th, kLdsHistLimit);
+    const long long gsz = (long long)(a.tiles_x + 1) * (a.tiles_y + 1);
+    if (gsz > kLdsHistLimit || a.tpi > kMaxTilesPerImage)
+        return fail(ctx, GSR_E_UNSUPPORTED, "%dx%d images with %dx%d tiles exceed %d tiles per image", W, H, tw, th,
+                    kMaxTilesPerImage);
     if (a.tiles >= 0xffffffffll) return fail(ctx, GSR_E_UNSUPPORTED, "too many tiles");
     const size_t nrec = (size_t)C * (size_t)sc->total;
     const size_t npix = (size_t)a.images * W * H;
+    // depth-sort buffers: each image's segment is rounded up to whole radix chunks
+    const size_t sort_len = ((nrec + kSortTile - 1) / kSortTile + (size_t)a.images) * kSortTile;
+    if (sort_len >= 0xffffffffull) return fail(ctx, GSR_E_UNSUPPORTED, "too many (image, Gaussian) records");
+    a.sort_chunks = (int)(sort_len / kSortTile);
+    const size_t n_lists = (size_t)a.n_supers * C;
+    const size_t n_pblocks = sort_len / kPairBlock;
     int r;
     const int sb_cap = sc->sb_cap;
-    if ((r = ensure(ctx, ctx->records, nrec)) || (r = ensure(ctx, ctx->vis, (size_t)a.n_supers * C * sb_cap)) ||
-        (r = ensure(ctx, ctx->sbvis, (size_t)a.n_supers * C)) ||
-        (r = ensure(ctx, ctx->sbcnt, (size_t)a.n_supers * C * a.tpi)) || (r = ensure(ctx, ctx->counts, a.tiles)) ||
-        (r = ensure(ctx, ctx->starts, a.tiles + 1)) || (r = ensure(ctx, ctx->cursor, a.tiles)) ||
+    if ((r = ensure(ctx, ctx->records, nrec)) || (r = ensure(ctx, ctx->vis, n_lists * sb_cap)) ||
+        (r = ensure(ctx, ctx->sbvis, n_lists)) || (r = ensure(ctx, ctx->loff, n_lists)) || (r = ensure(ctx, ctx->skey0, sort_len)) ||
+        (r = ensure(ctx, ctx->skey1, sort_len)) || (r = ensure(ctx, ctx->sgid0, sort_len)) ||
+        (r = ensure(ctx, ctx->sgid1, sort_len)) || (r = ensure(ctx, ctx->srect0, sort_len)) ||
+        (r = ensure(ctx, ctx->srect1, sort_len)) ||
+        (r = ensure(ctx, ctx->hist, (size_t)a.sort_chunks * 256)) ||
+        (r = ensure(ctx, ctx->seg_n, a.images)) || (r = ensure(ctx, ctx->seg_start, a.images + 1)) ||
+        (r = ensure(ctx, ctx->blk_pairs, n_pblocks)) || (r = ensure(ctx, ctx->chunk_base, a.images + 1)) ||
+        (r = ensure(ctx, ctx->counts, a.tiles)) || (r = ensure(ctx, ctx->starts, a.tiles + 1)) ||
         (r = ensure(ctx, ctx->cls_list, (size_t)kNumClasses * a.tiles)) ||
         (r = ensure(ctx, ctx->views, (size_t)sc->n_nodes * C)) || (r = ensure(ctx, ctx->T_final, npix)) ||
         (r = ensure(ctx, ctx->n_contrib, npix)))
         return r;
     if (ctx->pair_cap < ctx->cfg.pair_capacity) ctx->pair_cap = ctx->cfg.pair_capacity;
-    if ((r = ensure(ctx, ctx->pairs, ctx->pair_cap)) || (r = ensure(ctx, ctx->pairs_alt, ctx->pair_cap))) return r;
+    if (ctx->pair_cap >= 0xffffffffll) return fail(ctx, GSR_E_UNSUPPORTED, "pair capacity beyond 32-bit slots");
+    // emission chunks of about chunk_pairs pairs: at most pairs / chunk_pairs + 1 per image
+    a.chunk_pairs = std::max(4096, 16 * a.tpi);
+    a.chunk_cap = (int)(ctx->pair_cap / a.chunk_pairs + a.images + 1);
+    if ((r = ensure(ctx, ctx->pairs, ctx->pair_cap)) || (r = ensure(ctx, ctx->cstart, (size_t)a.chunk_cap)) ||
+        (r = ensure(ctx, ctx->cimg, (size_t)a.chunk_cap)) ||
+        (r = ensure(ctx, ctx->ecnt, (size_t)a.chunk_cap * a.tpi)))
+        return r;
     a.views = ctx->views.p;
     a.records = ctx->records.p;
     a.vis = ctx->vis.p;
     a.sbvis = ctx->sbvis.p;
+    a.loff = ctx->loff.p;
     a.sb_cap = sb_cap;
-    a.sbcnt = ctx->sbcnt.p;
+    a.skey[0] = ctx->skey0.p;
+    a.skey[1] = ctx->skey1.p;
+    a.sgid[0] = ctx->sgid0.p;
+    a.sgid[1] = ctx->sgid1.p;
+    a.srect[0] = ctx->srect0.p;
+    a.srect[1] = ctx->srect1.p;
+    a.hist = ctx->hist.p;
+    a.seg_n = ctx->seg_n.p;
+    a.seg_start = ctx->seg_start.p;
+    a.blk_pairs = ctx->blk_pairs.p;
+    a.chunk_base = ctx->chunk_base.p;
+    a.cstart = ctx->cstart.p;
+    a.cimg = ctx->cimg.p;
+    a.ecnt = ctx->ecnt.p;
+    a.num_cu = ctx->num_cu;
     a.counts = ctx->counts.p;
     a.starts = ctx->starts.p;
-    a.cursor = ctx->cursor.p;
     a.cls_list = ctx->cls_list.p;
     a.pairs = ctx->pairs.p;
-    a.pairs_alt = ctx->pairs_alt.p;
     a.pair_cap = ctx->pair_cap;
     a.status = ctx->d_status;
     a.rgb = rgb;

@@ -5,14 +5,19 @@
 //                  (scene composition: background plus rigidly posed nodes, paper Sec. III-B)
 //   k_project      per Gaussian, all cameras of its env: EWA projection ("splatting"), tile
 //                  rectangle and depth key (the FP32 key specification below), SH colour
-//                  (paper Sec. III-A), projected record; per super-block (runs of an env's
-//                  Gaussians) per-tile pair counts via a difference grid kept in LDS
-//   k_tile_offsets per (image, tile): scan over the env's super-blocks of their pair counts
+//                  (paper Sec. III-A), projected record; per (super-block, camera) the list
+//                  of visible Gaussians, appended in id order
+//   k_seg, k_radix_*   per image, its visible Gaussians ordered by depth bits, ties by id: a
+//                  stable LSD radix sort over the four bytes of the depth bits whose first
+//                  pass reads the id-ordered lists ("efficient sorting")
+//   k_pair_*, k_chunk_starts   each image's depth-ordered Gaussians cut into chunks of about
+//                  equal pair counts
+//   k_tile_counts  per chunk: pairs per tile, from a difference grid in LDS
+//   k_tile_offsets per (image, tile): scan over the image's chunks of their pair counts
 //   k_scan         exclusive scan of per-tile counts -> per-tile [start, end) ranges
-//   k_emit         (depth bits, Gaussian id) pairs written into their tile's bucket; each
-//                  super-block starts at its precomputed slot, so only LDS atomics are used
-//   k_classify, k_sort_*   each tile's bucket sorted by (depth bits, id) in LDS; lists longer
-//                  than one LDS load are chunk-sorted then merged ("efficient sorting")
+//   k_emit         (depth bits, Gaussian id) pairs written into their tile's bucket in depth
+//                  order, so every bucket is sorted by (depth bits, id) as it is written
+//   k_classify     tiles grouped by list length (the persistent compositor's queue order)
 //   k_composite    per tile, front-to-back alpha blending of colour and camera-space z
 //                  (RGB and depth sensors, paper Sec. III-C), early exit when every pixel of a
 //                  wavefront is saturated
@@ -21,6 +26,8 @@
 // explicit fmaf() is written, and / and sqrtf are correctly rounded.  This makes the key
 // specification in k_project reproducible bit for bit by any IEEE FP32 implementation of
 // the same operation sequence.
+#include <algorithm>
+
 #include "gsr_internal.h"
 
 namespace gsr {
@@ -176,23 +183,22 @@ template <int L>
 __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a, const Super* __restrict__ supers,
                                                      const Env* __restrict__ envs, const Block* __restrict__ blocks,
                                                      const Node* __restrict__ nodes, const View* __restrict__ views) {
-    // LDS: per camera, the count of this super-block's visible Gaussians, then a
-    // (tiles_y + 1) x (tiles_x + 1) difference grid of pair counts: a rectangle adds +1/-1 at
-    // its four corners; the 2D prefix gives pairs per tile
-    extern __shared__ int s_lds[];
+    // LDS: per (wavefront, camera) the running length of the camera's visible list (every
+    // wavefront keeps its own copy of the same value), and the wavefronts' counts of the
+    // current append (two sets, used alternately)
+    extern __shared__ uint32_t s_run[];  // [kBlock / 64][C]
+    __shared__ uint32_t s_wc[2][kBlock / 64];
     const Super sb = supers[blockIdx.x];
     const Env ev = envs[sb.env];
     const int C = a.C;
-    const int gx = a.tiles_x + 1, gy = a.tiles_y + 1, gsz = gx * gy;
-    uint32_t* s_nvis = reinterpret_cast<uint32_t*>(s_lds);
-    int* s_grid = s_lds + C;
-    for (int i = threadIdx.x; i < C * gsz + C; i += kBlock) s_lds[i] = 0;
+    const int i = threadIdx.x, lane = i & 63, wave = i >> 6;
+    for (int k = i; k < (kBlock / 64) * C; k += kBlock) s_run[k] = 0u;
     __syncthreads();
     constexpr int K = (L + 1) * (L + 1);
-    const int i = threadIdx.x;
     const float thr = (float)(1.0 / 255.0);
     const float itw = 1.0f / (float)a.tw, ith = 1.0f / (float)a.th;
-    int n_vis = 0, n_any = 0, nonfinite = 0;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int n_vis = 0, n_any = 0, nonfinite = 0, par = 0;
     // this thread's Gaussian of the next chunk, loaded one chunk ahead so that its latency
     // overlaps the current chunk's arithmetic
     float nm0 = 0.f, nm1 = 0.f, nm2 = 0.f, no = 0.f, ns0 = 0.f, ns1 = 0.f, ns2 = 0.f;
@@ -214,21 +220,22 @@ __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a, const Super* __re
         const float mu0 = nm0, mu1 = nm1, mu2 = nm2, o = no, s0 = ns0, s1 = ns1, s2 = ns2;
         const float q0 = nq.x, q1 = nq.y, q2 = nq.z, q3 = nq.w;
         if (ch + 1 < sb.chunk_end) fetch(ch + 1);
-        if (i >= (int)blk.count) continue;
+        // every thread stays in the loop: the appends below take block-wide barriers
+        bool ok = i < (int)blk.count;
         const Node& nd = nodes[blk.node];
         const uint32_t gid = blk.gid0 + i;
         const size_t li = gid - nd.gid_base;
         const size_t lg = gid - ev.gid_base;
-        if (!(isfinite(mu0) && isfinite(mu1) && isfinite(mu2) && isfinite(o) && isfinite(s0) && isfinite(s1) &&
-              isfinite(s2) && isfinite(q0) && isfinite(q1) && isfinite(q2) && isfinite(q3))) {
+        if (ok && !(isfinite(mu0) && isfinite(mu1) && isfinite(mu2) && isfinite(o) && isfinite(s0) && isfinite(s1) &&
+                    isfinite(s2) && isfinite(q0) && isfinite(q1) && isfinite(q2) && isfinite(q3))) {
             nonfinite += C;  // culled and counted once per camera
-            continue;
+            ok = false;
         }
-        if (!(o >= thr)) continue;
+        if (!(o >= thr)) ok = false;
         // the rotation of the unit quaternion (camera independent)
         const float n2 = fmaf(q0, q0, fmaf(q1, q1, fmaf(q2, q2, q3 * q3)));
         float R00 = 0.f, R01 = 0.f, R02 = 0.f, R10 = 0.f, R11 = 0.f, R12 = 0.f, R20 = 0.f, R21 = 0.f, R22 = 0.f;
-        if (n2 > 0.0f) {
+        if (ok && n2 > 0.0f) {
             const float rn = 1.0f / sqrtf(n2);
             const float qw = q0 * rn, qx = q1 * rn, qy = q2 * rn, qz = q3 * rn;
             const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
@@ -242,105 +249,98 @@ __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a, const Super* __re
         float shc[3 * K];
         bool have_sh = false, vis_any = false;
         for (int c = 0; c < C; ++c) {
-            const View& v = views[blk.node * C + c];
-            const size_t rec = (size_t)C * ev.gid_base + (size_t)c * ev.n + lg;
-            const float p0 = fmaf(v.W[0], mu0, fmaf(v.W[1], mu1, fmaf(v.W[2], mu2, v.w[0])));
-            const float p1 = fmaf(v.W[3], mu0, fmaf(v.W[4], mu1, fmaf(v.W[5], mu2, v.w[1])));
-            const float p2 = fmaf(v.W[6], mu0, fmaf(v.W[7], mu1, fmaf(v.W[8], mu2, v.w[2])));
-            if (!(isfinite(p0) && isfinite(p1) && isfinite(p2))) { ++nonfinite; continue; }
-            const float z = p2;
-            if (!(z > v.znear)) continue;
-            if (!(n2 > 0.0f)) continue;
-            const float iz = 1.0f / z;
-            const float xz = p0 * iz, yz = p1 * iz;
-            const float u = fmaf(v.fx, xz, v.cx), vv = fmaf(v.fy, yz, v.cy);
-            float M[9];
+            bool vis = false;
+            uint4 ent = make_uint4(0u, 0u, 0u, 0u);
+            if (ok) do {
+                const View& v = views[blk.node * C + c];
+                const size_t rec = (size_t)C * ev.gid_base + (size_t)c * ev.n + lg;
+                const float p0 = fmaf(v.W[0], mu0, fmaf(v.W[1], mu1, fmaf(v.W[2], mu2, v.w[0])));
+                const float p1 = fmaf(v.W[3], mu0, fmaf(v.W[4], mu1, fmaf(v.W[5], mu2, v.w[1])));
+                const float p2 = fmaf(v.W[6], mu0, fmaf(v.W[7], mu1, fmaf(v.W[8], mu2, v.w[2])));
+                if (!(isfinite(p0) && isfinite(p1) && isfinite(p2))) { ++nonfinite; break; }
+                const float z = p2;
+                if (!(z > v.znear)) break;
+                if (!(n2 > 0.0f)) break;
+                const float iz = 1.0f / z;
+                const float xz = p0 * iz, yz = p1 * iz;
+                const float u = fmaf(v.fx, xz, v.cx), vv = fmaf(v.fy, yz, v.cy);
+                float M[9];
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                M[r * 3 + 0] = fmaf(v.W[r * 3 + 0], R00, fmaf(v.W[r * 3 + 1], R10, v.W[r * 3 + 2] * R20)) * s0;
-                M[r * 3 + 1] = fmaf(v.W[r * 3 + 0], R01, fmaf(v.W[r * 3 + 1], R11, v.W[r * 3 + 2] * R21)) * s1;
-                M[r * 3 + 2] = fmaf(v.W[r * 3 + 0], R02, fmaf(v.W[r * 3 + 1], R12, v.W[r * 3 + 2] * R22)) * s2;
+                for (int r = 0; r < 3; ++r) {
+                    M[r * 3 + 0] = fmaf(v.W[r * 3 + 0], R00, fmaf(v.W[r * 3 + 1], R10, v.W[r * 3 + 2] * R20)) * s0;
+                    M[r * 3 + 1] = fmaf(v.W[r * 3 + 0], R01, fmaf(v.W[r * 3 + 1], R11, v.W[r * 3 + 2] * R21)) * s1;
+                    M[r * 3 + 2] = fmaf(v.W[r * 3 + 0], R02, fmaf(v.W[r * 3 + 1], R12, v.W[r * 3 + 2] * R22)) * s2;
+                }
+                const float S00 = fmaf(M[0], M[0], fmaf(M[1], M[1], M[2] * M[2]));
+                const float S01 = fmaf(M[0], M[3], fmaf(M[1], M[4], M[2] * M[5]));
+                const float S02 = fmaf(M[0], M[6], fmaf(M[1], M[7], M[2] * M[8]));
+                const float S11 = fmaf(M[3], M[3], fmaf(M[4], M[4], M[5] * M[5]));
+                const float S12 = fmaf(M[3], M[6], fmaf(M[4], M[7], M[5] * M[8]));
+                const float S22 = fmaf(M[6], M[6], fmaf(M[7], M[7], M[8] * M[8]));
+                const float xc = fminf(fmaxf(xz, -v.limx), v.limx);
+                const float yc = fminf(fmaxf(yz, -v.limy), v.limy);
+                const float j00 = v.fx * iz, j11 = v.fy * iz;
+                const float j02 = -(j00 * xc), j12 = -(j11 * yc);
+                const float T00 = fmaf(j00, S00, j02 * S02);
+                const float T01 = fmaf(j00, S01, j02 * S12);
+                const float T02 = fmaf(j00, S02, j02 * S22);
+                const float T11 = fmaf(j11, S11, j12 * S12);
+                const float T12 = fmaf(j11, S12, j12 * S22);
+                const float ca = fmaf(T00, j00, T02 * j02) + 0.3f;
+                const float cb = fmaf(T01, j11, T02 * j12);
+                const float cc = fmaf(T11, j11, T12 * j12) + 0.3f;
+                const float det = fmaf(ca, cc, -(cb * cb));
+                if (!(det > 0.0f)) break;
+                const float rx = fmaf(3.33f, sqrtf(ca), 0.015625f);
+                const float ry = fmaf(3.33f, sqrtf(cc), 0.015625f);
+                const float tx0f = fminf(fmaxf(floorf((u - rx) * itw), 0.0f), (float)a.tiles_x);
+                const float tx1f = fminf(fmaxf(floorf((u + rx) * itw) + 1.0f, 0.0f), (float)a.tiles_x);
+                const float ty0f = fminf(fmaxf(floorf((vv - ry) * ith), 0.0f), (float)a.tiles_y);
+                const float ty1f = fminf(fmaxf(floorf((vv + ry) * ith) + 1.0f, 0.0f), (float)a.tiles_y);
+                const int tx0 = (int)tx0f, tx1 = (int)tx1f, ty0 = (int)ty0f, ty1 = (int)ty1f;
+                if (tx0 >= tx1 || ty0 >= ty1) break;
+                // visible: projected record (the conic and colour enter pixel values only, so
+                // the hardware reciprocal suffices there)
+                const float idet = __builtin_amdgcn_rcpf(det);
+                if (!have_sh) {
+                    load_sh<L>(nd.sh + li * (3 * K), shc);
+                    have_sh = true;
+                }
+                const float3 col = sh_colour<L>(shc, mu0 - v.cl[0], mu1 - v.cl[1], mu2 - v.cl[2]);
+                Record R;
+                R.r0 = make_float4(u, vv, o, z);
+                R.r1 = make_float4(cc * idet, -cb * idet, ca * idet, lo);
+                R.r2 = make_float4(col.x, col.y, col.z, det);
+                a.records[rec] = R;
+                ent = make_uint4((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16),
+                                 __float_as_uint(z), gid);
+                vis = true;
+            } while (false);
+            // append to this super-block's list for camera c in id order: slot = list length
+            // so far + visible threads before this one (wavefront ballots, block-wide prefix)
+            const unsigned long long m = __ballot(vis);
+            if (lane == 0) s_wc[par][wave] = (uint32_t)__popcll(m);
+            __syncthreads();
+            uint32_t before = s_run[wave * C + c], tot = 0u;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) {
+                const uint32_t cw = s_wc[par][w];
+                before += w < wave ? cw : 0u;
+                tot += cw;
             }
-            const float S00 = fmaf(M[0], M[0], fmaf(M[1], M[1], M[2] * M[2]));
-            const float S01 = fmaf(M[0], M[3], fmaf(M[1], M[4], M[2] * M[5]));
-            const float S02 = fmaf(M[0], M[6], fmaf(M[1], M[7], M[2] * M[8]));
-            const float S11 = fmaf(M[3], M[3], fmaf(M[4], M[4], M[5] * M[5]));
-            const float S12 = fmaf(M[3], M[6], fmaf(M[4], M[7], M[5] * M[8]));
-            const float S22 = fmaf(M[6], M[6], fmaf(M[7], M[7], M[8] * M[8]));
-            const float xc = fminf(fmaxf(xz, -v.limx), v.limx);
-            const float yc = fminf(fmaxf(yz, -v.limy), v.limy);
-            const float j00 = v.fx * iz, j11 = v.fy * iz;
-            const float j02 = -(j00 * xc), j12 = -(j11 * yc);
-            const float T00 = fmaf(j00, S00, j02 * S02);
-            const float T01 = fmaf(j00, S01, j02 * S12);
-            const float T02 = fmaf(j00, S02, j02 * S22);
-            const float T11 = fmaf(j11, S11, j12 * S12);
-            const float T12 = fmaf(j11, S12, j12 * S22);
-            const float ca = fmaf(T00, j00, T02 * j02) + 0.3f;
-            const float cb = fmaf(T01, j11, T02 * j12);
-            const float cc = fmaf(T11, j11, T12 * j12) + 0.3f;
-            const float det = fmaf(ca, cc, -(cb * cb));
-            if (!(det > 0.0f)) continue;
-            const float rx = fmaf(3.33f, sqrtf(ca), 0.015625f);
-            const float ry = fmaf(3.33f, sqrtf(cc), 0.015625f);
-            const float tx0f = fminf(fmaxf(floorf((u - rx) * itw), 0.0f), (float)a.tiles_x);
-            const float tx1f = fminf(fmaxf(floorf((u + rx) * itw) + 1.0f, 0.0f), (float)a.tiles_x);
-            const float ty0f = fminf(fmaxf(floorf((vv - ry) * ith), 0.0f), (float)a.tiles_y);
-            const float ty1f = fminf(fmaxf(floorf((vv + ry) * ith) + 1.0f, 0.0f), (float)a.tiles_y);
-            const int tx0 = (int)tx0f, tx1 = (int)tx1f, ty0 = (int)ty0f, ty1 = (int)ty1f;
-            if (tx0 >= tx1 || ty0 >= ty1) continue;
-            // visible: projected record (the conic and colour enter pixel values only, so the
-            // hardware reciprocal suffices there)
-            const float idet = __builtin_amdgcn_rcpf(det);
-            if (!have_sh) {
-                load_sh<L>(nd.sh + li * (3 * K), shc);
-                have_sh = true;
+            if (vis) {
+                a.vis[((size_t)blockIdx.x * C + c) * a.sb_cap + before + (uint32_t)__popcll(m & below)] = ent;
+                ++n_vis;
+                vis_any = true;
             }
-            const float3 col = sh_colour<L>(shc, mu0 - v.cl[0], mu1 - v.cl[1], mu2 - v.cl[2]);
-            Record R;
-            R.r0 = make_float4(u, vv, o, z);
-            R.r1 = make_float4(cc * idet, -cb * idet, ca * idet, lo);
-            R.r2 = make_float4(col.x, col.y, col.z, det);
-            a.records[rec] = R;
-            // append to this super-block's visible list for camera c
-            const uint32_t slot = atomicAdd(&s_nvis[c], 1u);
-            a.vis[((size_t)blockIdx.x * C + c) * a.sb_cap + slot] =
-                make_uint4((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16),
-                           __float_as_uint(z), gid);
-            // pair counts: +1/-1 corners of the rectangle in the image's difference grid
-            int* h = s_grid + c * gsz;
-            atomicAdd(h + ty0 * gx + tx0, 1);
-            atomicAdd(h + ty0 * gx + tx1, -1);
-            atomicAdd(h + ty1 * gx + tx0, -1);
-            atomicAdd(h + ty1 * gx + tx1, 1);
-            ++n_vis;
-            vis_any = true;
+            // the wavefront's own copy; every lane has read it above
+            if (lane == 0) s_run[wave * C + c] += tot;
+            par ^= 1;
         }
         n_any += vis_any ? 1 : 0;
     }
     if (nonfinite) atomicAdd(&a.status->nonfinite, (uint32_t)nonfinite);
-    __syncthreads();
-    // 2D prefix of every camera's grid: along x, then along y
-    for (int r = threadIdx.x; r < C * gy; r += kBlock) {
-        int* row = s_grid + (r / gy) * gsz + (r % gy) * gx;
-        int acc = 0;
-        for (int x = 0; x < gx; ++x) { acc += row[x]; row[x] = acc; }
-    }
-    __syncthreads();
-    for (int col = threadIdx.x; col < C * gx; col += kBlock) {
-        int* g = s_grid + (col / gx) * gsz + (col % gx);
-        int acc = 0;
-        for (int y = 0; y < gy; ++y) { acc += g[y * gx]; g[y * gx] = acc; }
-    }
-    __syncthreads();
-    // this super-block's pairs per (camera, tile) and visible-list lengths, plain stores
-    if (threadIdx.x < C) a.sbvis[(size_t)blockIdx.x * C + threadIdx.x] = s_nvis[threadIdx.x];
-    uint32_t* out = a.sbcnt + (size_t)blockIdx.x * C * a.tpi;
-    for (int j = threadIdx.x; j < C * a.tpi; j += kBlock) {
-        const int c = j / a.tpi, t = j - c * a.tpi;
-        const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
-        out[j] = (uint32_t)s_grid[c * gsz + ty * gx + tx];
-    }
+    for (int k = i; k < C; k += kBlock) a.sbvis[(size_t)blockIdx.x * C + k] = s_run[wave * C + k];  // own copy
     // block sums of visible records: one atomic per block into its counter slot
     unsigned long long nv = (unsigned long long)n_vis, na = (unsigned long long)n_any;
     for (int off = 32; off > 0; off >>= 1) {
@@ -348,9 +348,9 @@ __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a, const Super* __re
         na += __shfl_xor(na, off, 64);
     }
     __shared__ unsigned long long s_sum[2 * (kBlock / 64)];
-    if ((threadIdx.x & 63) == 0) {
-        s_sum[2 * (threadIdx.x >> 6)] = nv;
-        s_sum[2 * (threadIdx.x >> 6) + 1] = na;
+    if (lane == 0) {
+        s_sum[2 * wave] = nv;
+        s_sum[2 * wave + 1] = na;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -366,23 +366,547 @@ __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a, const Super* __re
 }
 
 // --------------------------------------------------------------------------------------------
-// per (image, tile): exclusive scan over the env's super-blocks -> each super-block's first
-// slot within the tile's bucket; the tile total -> pairs per tile
+// depth sort.  Image i keeps its visible (z bits, Gaussian id, tile rectangle) triples in a
+// segment of the sort buffers: k_seg counts them (the lengths of the image's lists) and lays
+// the segments out in image order, each starting at a multiple of kSortTile, so that every
+// radix chunk (kSortTile positions) below the end lies inside one image's segment and holds at
+// least one item.
+// The (super-block, camera) lists, which hold an image's Gaussians in id order when taken in
+// super-block order, are first copied into the segment in that order (k_gather).  The sort is
+// then a stable LSD radix sort over the four bytes of the z bits (positive floats order as
+// their bit patterns), so Gaussians of equal depth bits stay in id order: the result is the
+// (z bits, id) order of the keys.  Each pass is a per-chunk
+// digit histogram, a per-image scan of the histograms (chunks in order, digits in order) and
+// a scatter that ranks each item among its chunk's items of the same digit, stages the chunk
+// in LDS in digit order and writes every digit's run to consecutive slots.
+// --------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_seg(FwdArgs a) {
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_carry;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (t == 0) s_carry = 0u;
+    __syncthreads();
+    constexpr int B = 16;  // loads in flight
+    for (int b0 = 0; b0 < a.images; b0 += 1024) {
+        const int img = b0 + t;
+        uint32_t n = 0u;
+        if (img < a.images) {
+            const int e = img / a.C, c = img - e * a.C;
+            const Env ev = a.envs[e];
+            const uint32_t* p = a.sbvis + (size_t)ev.sb_begin * a.C + c;
+            for (int k0 = 0; k0 < ev.sb_count; k0 += B) {
+                uint32_t v[B];
+#pragma unroll
+                for (int k = 0; k < B; ++k) v[k] = k0 + k < ev.sb_count ? p[(size_t)(k0 + k) * a.C] : 0u;
+#pragma unroll
+                for (int k = 0; k < B; ++k) n += v[k];
+            }
+            a.seg_n[img] = n;
+        }
+        const uint32_t len = (n + kSortTile - 1) / kSortTile * kSortTile;
+        uint32_t incl = len;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) s_w[wave] = incl;
+        __syncthreads();
+        uint32_t before = s_carry;
+        for (int w = 0; w < wave; ++w) before += s_w[w];
+        if (img < a.images) {
+            // each list's first position: the segment start plus the image's earlier lists
+            const int e = img / a.C, c = img - e * a.C;
+            const Env ev = a.envs[e];
+            const size_t l0 = (size_t)ev.sb_begin * a.C + c;
+            uint32_t run = before + incl - len;
+            a.seg_start[img] = run;
+            for (int k0 = 0; k0 < ev.sb_count; k0 += B) {
+                uint32_t v[B];
+#pragma unroll
+                for (int k = 0; k < B; ++k) v[k] = k0 + k < ev.sb_count ? a.sbvis[l0 + (size_t)(k0 + k) * a.C] : 0u;
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    if (k0 + k < ev.sb_count) a.loff[l0 + (size_t)(k0 + k) * a.C] = run;
+                    run += v[k];
+                }
+            }
+        }
+        __syncthreads();
+        if (t == 1023) s_carry = before + incl;
+        __syncthreads();
+    }
+    if (t == 0) a.seg_start[a.images] = s_carry;
+}
+
+// the (super-block, camera) lists copied into their image segments (buffer 1), in list order
+__global__ __launch_bounds__(256) void k_gather(FwdArgs a) {
+    const uint32_t nl = (uint32_t)(a.n_supers * a.C);
+    for (uint32_t l = blockIdx.x; l < nl; l += gridDim.x) {
+        const uint32_t n = a.sbvis[l], dst = a.loff[l];
+        const uint4* lst = a.vis + (size_t)l * a.sb_cap;
+        for (uint32_t k = threadIdx.x; k < n; k += 256) {
+            const uint4 e = lst[k];
+            a.skey[1][dst + k] = e.z;
+            a.sgid[1][dst + k] = e.w;
+            a.srect[1][dst + k] = make_uint2(e.x, e.y);
+        }
+    }
+}
+
+// the image whose segment contains position pos (below the end): the last image whose segment
+// starts at or before pos (empty images share their start with the next one)
+__device__ inline int pos_image(const uint32_t* __restrict__ seg_start, int images, uint32_t pos) {
+    int lo = 0, hi = images - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg_start[mid] <= pos) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// the lanes (among those with valid set) whose 8-bit digit equals this lane's
+__device__ inline unsigned long long match_digit(uint32_t d, bool valid) {
+    unsigned long long m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const unsigned long long bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+// Radix chunks: kSortTile positions of the sort buffers.  Pass p reads buffer (p + 1) & 1 and
+// writes buffer p & 1 (the gather fills buffer 1, the last pass leaves the result there).
+__device__ inline uint32_t radix_chunks(const FwdArgs& a) { return a.seg_start[a.images] / (uint32_t)kSortTile; }
+// Items of radix chunk j; pos receives the chunk's first position.
+__device__ inline uint32_t radix_chunk(const FwdArgs& a, uint32_t j, uint32_t& pos) {
+    pos = j * (uint32_t)kSortTile;
+    const int img = pos_image(a.seg_start, a.images, pos);
+    const uint32_t end = a.seg_start[img] + a.seg_n[img];
+    return end - pos < (uint32_t)kSortTile ? end - pos : (uint32_t)kSortTile;
+}
+
+__global__ __launch_bounds__(256) void k_radix_hist(FwdArgs a, int pass) {
+    __shared__ uint32_t s_h[256];
+    const int t = threadIdx.x, lane = t & 63;
+    const int sh = 8 * pass;
+    const uint32_t nch = radix_chunks(a);
+    const uint32_t* kin = a.skey[(pass + 1) & 1];
+    for (uint32_t j = blockIdx.x; j < nch; j += gridDim.x) {
+        uint32_t pos;
+        const uint32_t n = radix_chunk(a, j, pos);
+        s_h[t] = 0u;
+        __syncthreads();
+        for (uint32_t k0 = 0; k0 < n; k0 += 256) {
+            const uint32_t k = k0 + (uint32_t)t;
+            const bool valid = k < n;
+            const uint32_t d = valid ? (kin[pos + k] >> sh) & 255u : 0u;
+            const unsigned long long m = match_digit(d, valid);
+            // one LDS atomic per distinct digit of the wavefront (its highest lane)
+            if (valid && (m >> lane) == 1ull) atomicAdd(&s_h[d], (uint32_t)__popcll(m));
+        }
+        __syncthreads();
+        a.hist[(size_t)j * 256 + t] = s_h[t];
+        __syncthreads();
+    }
+}
+
+// One block per image: thread (g, d) takes digit d of the g-th quarter of the image's chunks.
+// Each chunk's first slot per digit = segment start + items of smaller digits + items of this
+// digit in earlier chunks.
+__global__ __launch_bounds__(1024) void k_radix_scan(FwdArgs a) {
+    __shared__ uint32_t s_tot[4][256];
+    __shared__ uint32_t s_w[4];
+    const int img = blockIdx.x, d = threadIdx.x & 255, g = threadIdx.x >> 8, lane = threadIdx.x & 63;
+    const uint32_t base = a.seg_start[img];
+    const int nch = (int)((a.seg_n[img] + kSortTile - 1) / kSortTile);
+    const int per = (nch + 3) / 4;
+    const int c0 = g * per, c1 = min(nch, c0 + per);
+    uint32_t* h = a.hist + (size_t)(base / kSortTile) * 256 + d;
+    constexpr int B = 16;  // loads in flight per thread
+    uint32_t tot = 0u;
+    for (int k0 = c0; k0 < c1; k0 += B) {
+        uint32_t v[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) v[k] = k0 + k < c1 ? h[(size_t)(k0 + k) * 256] : 0u;
+#pragma unroll
+        for (int k = 0; k < B; ++k) tot += v[k];
+    }
+    s_tot[g][d] = tot;
+    __syncthreads();
+    uint32_t run = 0u;
+    if (g == 0) {
+        // digit totals, exclusive scan over digits (threads 0..255 = 4 wavefronts)
+        const uint32_t dt = s_tot[0][d] + s_tot[1][d] + s_tot[2][d] + s_tot[3][d];
+        uint32_t incl = dt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) s_w[d >> 6] = incl;
+        run = incl - dt;
+    }
+    __syncthreads();
+    if (g == 0) {
+        for (int w = 0; w < (d >> 6); ++w) run += s_w[w];
+        // group starts within the digit
+        uint32_t r = base + run;
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t v = s_tot[q][d];
+            s_tot[q][d] = r;
+            r += v;
+        }
+    }
+    __syncthreads();
+    run = s_tot[g][d];
+    for (int k0 = c0; k0 < c1; k0 += B) {
+        uint32_t v[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) v[k] = k0 + k < c1 ? h[(size_t)(k0 + k) * 256] : 0u;
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            if (k0 + k < c1) h[(size_t)(k0 + k) * 256] = run;
+            run += v[k];
+        }
+    }
+}
+
+// Wavefront w ranks chunk items [R 64 w, R 64 (w + 1)) in rounds of 64 consecutive items:
+// rank = items of the same digit in earlier rounds (a per-wavefront LDS counter) + matching
+// lanes below it.  Local position = items of smaller digits in the chunk + items of the same
+// digit in earlier wavefronts + rank, so the chunk is staged in LDS in stable digit order, and
+// local position p of digit d goes to slot p + (chunk slot of d - local start of d).  Only the
+// keys stay in registers; ids and rectangles are read again when they are staged.
+__global__ __launch_bounds__(256) void k_radix_scatter(FwdArgs a, int pass) {
+    constexpr int R = kSortTile / 256;  // rounds per wavefront
+    __shared__ uint32_t s_wc[4][256];
+    __shared__ uint32_t s_delta[256];
+    __shared__ uint32_t s_w[4];
+    __shared__ unsigned long long s_buf[kSortTile];
+    __shared__ uint8_t s_dig[kSortTile];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int sh = 8 * pass;
+    const int ib = (pass + 1) & 1, ob = pass & 1;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const uint32_t nch = radix_chunks(a);
+    for (uint32_t j = blockIdx.x; j < nch; j += gridDim.x) {
+        uint32_t pos;
+        const uint32_t n = radix_chunk(a, j, pos);
+        for (int k = lane; k < 256; k += 64) s_wc[wave][k] = 0u;  // read back by this wavefront only
+        const uint32_t w0 = (uint32_t)(wave * 64 * R);
+        // rounds of this wavefront that hold items (uniform across the wavefront)
+        const int nr = n > w0 ? (int)min((n - w0 + 63u) / 64u, (uint32_t)R) : 0;
+        const uint32_t* kin = a.skey[ib] + pos;
+        uint32_t key[R], rk[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t k = w0 + (uint32_t)(r * 64 + lane);
+            key[r] = (r < nr && k < n) ? kin[k] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (r >= nr) break;
+            const uint32_t k = w0 + (uint32_t)(r * 64 + lane);
+            const bool valid = k < n;
+            const uint32_t d = (key[r] >> sh) & 255u;
+            const unsigned long long m = match_digit(d, valid);
+            const uint32_t before = valid ? s_wc[wave][d] : 0u;
+            rk[r] = before + (uint32_t)__popcll(m & below);
+            if (valid && (m >> lane) == 1ull) s_wc[wave][d] = before + (uint32_t)__popcll(m);
+        }
+        __syncthreads();
+        {
+            // thread t = digit t: local start (scan over digits), per-wavefront bases
+            const uint32_t c0 = s_wc[0][t], c1 = s_wc[1][t], c2 = s_wc[2][t], c3 = s_wc[3][t];
+            const uint32_t cnt = c0 + c1 + c2 + c3;
+            uint32_t incl = cnt;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += y;
+            }
+            if (lane == 63) s_w[wave] = incl;
+            __syncthreads();
+            uint32_t ls = incl - cnt;
+            for (int w = 0; w < wave; ++w) ls += s_w[w];
+            s_wc[0][t] = ls;
+            s_wc[1][t] = ls + c0;
+            s_wc[2][t] = ls + c0 + c1;
+            s_wc[3][t] = ls + c0 + c1 + c2;
+            s_delta[t] = a.hist[(size_t)j * 256 + t] - ls;  // modulo 2^32
+        }
+        __syncthreads();
+        // local positions replace the ranks
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t k = w0 + (uint32_t)(r * 64 + lane);
+            if (r < nr && k < n) {
+                const uint32_t d = (key[r] >> sh) & 255u;
+                rk[r] += s_wc[wave][d];
+                const uint32_t id = a.sgid[ib][pos + k];
+                s_buf[rk[r]] = ((unsigned long long)id << 32) | (unsigned long long)key[r];
+                s_dig[rk[r]] = (uint8_t)d;
+            }
+        }
+        __syncthreads();
+        for (uint32_t lp = t; lp < n; lp += 256) {
+            const unsigned long long u = s_buf[lp];
+            const uint32_t dst = lp + s_delta[s_dig[lp]];
+            a.skey[ob][dst] = (uint32_t)u;
+            a.sgid[ob][dst] = (uint32_t)(u >> 32);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t k = w0 + (uint32_t)(r * 64 + lane);
+            if (r < nr && k < n) {
+                const uint2 rc = a.srect[ib][pos + k];
+                s_buf[rk[r]] = ((unsigned long long)rc.y << 32) | (unsigned long long)rc.x;
+            }
+        }
+        __syncthreads();
+        for (uint32_t lp = t; lp < n; lp += 256) {
+            const unsigned long long u = s_buf[lp];
+            a.srect[ob][lp + s_delta[s_dig[lp]]] = make_uint2((uint32_t)u, (uint32_t)(u >> 32));
+        }
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// emission chunks.  Each image's depth-ordered Gaussians are cut into chunks of about
+// chunk_pairs pairs: with e_i the pairs of the image's Gaussians before Gaussian i, chunk q
+// holds the Gaussians with floor(e_i / chunk_pairs) = q (empty when one Gaussian spans several
+// multiples).  Per block of kPairBlock positions: its pairs (k_pair_blocks); per image: the
+// blocks' prefix and the chunk count (k_pair_scan); per Gaussian: the chunks it starts
+// (k_chunk_starts).
+// --------------------------------------------------------------------------------------------
+__device__ inline uint32_t rect_area(uint2 r) {
+    return ((r.y & 0xffffu) - (r.x & 0xffffu)) * ((r.y >> 16) - (r.x >> 16));
+}
+
+// positions [pos, pos + n) of pair block b (n = 0 in the padding after an image's items)
+__device__ inline uint32_t pair_block(const FwdArgs& a, uint32_t b, uint32_t& pos, int& img) {
+    pos = b * (uint32_t)kPairBlock;
+    img = pos_image(a.seg_start, a.images, pos);
+    const uint32_t end = a.seg_start[img] + a.seg_n[img];
+    return pos < end ? (end - pos < (uint32_t)kPairBlock ? end - pos : (uint32_t)kPairBlock) : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_pair_blocks(FwdArgs a) {
+    __shared__ uint32_t s_w[4];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const uint32_t nb = a.seg_start[a.images] / (uint32_t)kPairBlock;
+    for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        uint32_t pos;
+        int img;
+        const uint32_t n = pair_block(a, b, pos, img);
+        uint32_t sum = 0u;
+        for (uint32_t k = t; k < n; k += 256) sum += rect_area(a.srect[1][pos + k]);
+        for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+        if (lane == 0) s_w[wave] = sum;
+        __syncthreads();
+        if (t == 0) a.blk_pairs[b] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        __syncthreads();
+    }
+}
+
+// One block: per image (one thread each) the exclusive prefix of its blocks' pairs and its
+// chunk count; chunk bases by a scan over images.  Total pairs and overflow into the status
+// word; on overflow no image gets chunks (nothing is emitted; the host grows the capacity).
+__global__ __launch_bounds__(1024) void k_pair_scan(FwdArgs a) {
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_carry;
+    __shared__ unsigned long long s_pairs;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (t == 0) {
+        s_carry = 0u;
+        s_pairs = 0ull;
+    }
+    __syncthreads();
+    const uint32_t PC = (uint32_t)a.chunk_pairs;
+    for (int b0 = 0; b0 < a.images; b0 += 1024) {
+        const int img = b0 + t;
+        uint32_t nchk = 0u;
+        if (img < a.images) {
+            const uint32_t s = a.seg_start[img] / kPairBlock;
+            const int nb = (int)((a.seg_n[img] + kPairBlock - 1) / kPairBlock);
+            uint32_t run = 0u;
+            constexpr int B = 16;
+            for (int k0 = 0; k0 < nb; k0 += B) {
+                uint32_t v[B];
+#pragma unroll
+                for (int k = 0; k < B; ++k) v[k] = k0 + k < nb ? a.blk_pairs[s + k0 + k] : 0u;
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    if (k0 + k < nb) a.blk_pairs[s + k0 + k] = run;
+                    run += v[k];
+                }
+            }
+            nchk = (run + PC - 1) / PC;
+            atomicAdd(&s_pairs, (unsigned long long)run);
+        }
+        uint32_t incl = nchk;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) s_w[wave] = incl;
+        __syncthreads();
+        uint32_t before = s_carry;
+        for (int w = 0; w < wave; ++w) before += s_w[w];
+        if (img < a.images) a.chunk_base[img] = before + incl - nchk;
+        __syncthreads();
+        if (t == 1023) s_carry = before + incl;
+        __syncthreads();
+    }
+    const bool over = s_pairs > (unsigned long long)a.pair_cap || s_carry > (uint32_t)a.chunk_cap;
+    if (over)
+        for (int i = t; i < a.images; i += 1024) a.chunk_base[i] = 0u;
+    if (t == 0) {
+        a.chunk_base[a.images] = over ? 0u : s_carry;
+        a.status->pairs = s_pairs;
+        if (over) atomicOr(&a.status->flags, (uint32_t)GSR_STATUS_OVERFLOW);
+    }
+}
+
+// Per pair block: each Gaussian's pair offset e within its image (block prefix + in-block
+// scan); Gaussian i starts the chunks q with e_(i-1) < q chunk_pairs <= e_i (the image's first
+// Gaussian starts chunk 0); chunks past the image's last Gaussian start at the image's end.
+__global__ __launch_bounds__(256) void k_chunk_starts(FwdArgs a) {
+    constexpr int E = kPairBlock / 256;  // Gaussians per thread (blocked)
+    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_last[256];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const uint32_t PC = (uint32_t)a.chunk_pairs;
+    const uint32_t nb = a.seg_start[a.images] / (uint32_t)kPairBlock;
+    for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        uint32_t pos;
+        int img;
+        const uint32_t n = pair_block(a, b, pos, img);
+        const uint32_t cb = a.chunk_base[img], nci = a.chunk_base[img + 1] - cb;
+        if (n == 0u || a.chunk_base[a.images] == 0u) continue;  // uniform
+        uint32_t ar[E];
+        uint32_t sum = 0u;
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const uint32_t k = (uint32_t)t * E + q;
+            ar[q] = k < n ? rect_area(a.srect[1][pos + k]) : 0u;
+            sum += ar[q];
+        }
+        uint32_t incl = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) s_w[wave] = incl;
+        s_last[t] = ar[E - 1];
+        __syncthreads();
+        uint32_t e = a.blk_pairs[b] + incl - sum;
+        for (int w = 0; w < wave; ++w) e += s_w[w];
+        uint32_t prev = t > 0 ? s_last[t - 1] : 0u;  // pairs of the Gaussian before
+        const uint32_t seg0 = a.seg_start[img], end = seg0 + a.seg_n[img];
+        if (t == 0 && pos > seg0) prev = rect_area(a.srect[1][pos - 1]);
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const uint32_t k = (uint32_t)t * E + q;
+            if (k < n) {
+                const uint32_t p = pos + k;
+                const uint32_t qlo = p == seg0 ? 0u : (e - prev) / PC + 1u;
+                const uint32_t qhi = e / PC;
+                for (uint32_t c = qlo; c <= qhi && c < nci; ++c) {
+                    a.cstart[cb + c] = p;
+                    a.cimg[cb + c] = (uint32_t)img;
+                }
+                if (p + 1 == end)
+                    for (uint32_t c = qhi + 1; c < nci; ++c) {
+                        a.cstart[cb + c] = end;
+                        a.cimg[cb + c] = (uint32_t)img;
+                    }
+            }
+            prev = ar[q];
+            e += ar[q];
+        }
+        __syncthreads();
+    }
+}
+
+// Gaussians [s, e) of emission chunk q and its image
+__device__ inline uint32_t emit_chunk(const FwdArgs& a, uint32_t q, uint32_t& s, int& img) {
+    img = (int)a.cimg[q];
+    s = a.cstart[q];
+    const uint32_t e = q + 1 < a.chunk_base[img + 1] ? a.cstart[q + 1] : a.seg_start[img] + a.seg_n[img];
+    return e - s;
+}
+
+// --------------------------------------------------------------------------------------------
+// per emission chunk: pairs per tile of the image.  A rectangle adds +1/-1 at the four corners
+// of a (tiles_y + 1) x (tiles_x + 1) difference grid in LDS; the 2D prefix gives the counts.
+// --------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_tile_counts(FwdArgs a) {
+    extern __shared__ int s_grid[];
+    const int gx = a.tiles_x + 1, gy = a.tiles_y + 1, gsz = gx * gy;
+    const uint32_t nq = a.chunk_base[a.images];
+    for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+        uint32_t s;
+        int img;
+        const uint32_t n = emit_chunk(a, q, s, img);
+        for (int k = threadIdx.x; k < gsz; k += 256) s_grid[k] = 0;
+        __syncthreads();
+        const uint2* rects = a.srect[1] + s;
+        for (uint32_t k = threadIdx.x; k < n; k += 256) {
+            const uint2 r = rects[k];
+            const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu, y1 = r.y >> 16;
+            atomicAdd(&s_grid[y0 * gx + x0], 1);
+            atomicAdd(&s_grid[y0 * gx + x1], -1);
+            atomicAdd(&s_grid[y1 * gx + x0], -1);
+            atomicAdd(&s_grid[y1 * gx + x1], 1);
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < gy; r += 256) {
+            int* row = s_grid + r * gx;
+            int acc = 0;
+            for (int x = 0; x < gx; ++x) { acc += row[x]; row[x] = acc; }
+        }
+        __syncthreads();
+        for (int col = threadIdx.x; col < gx; col += 256) {
+            int acc = 0;
+            for (int y = 0; y < gy; ++y) { acc += s_grid[y * gx + col]; s_grid[y * gx + col] = acc; }
+        }
+        __syncthreads();
+        uint32_t* out = a.ecnt + (size_t)q * a.tpi;
+        for (int j = threadIdx.x; j < a.tpi; j += 256) {
+            const int ty = j / a.tiles_x, tx = j - ty * a.tiles_x;
+            out[j] = (uint32_t)s_grid[ty * gx + tx];
+        }
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// per (image, tile): exclusive scan over the image's emission chunks (in depth order) -> each
+// chunk's first slot within the tile's bucket; the tile total -> pairs per tile
 // --------------------------------------------------------------------------------------------
 __global__ void k_tile_offsets(FwdArgs a) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.tiles) return;
     const int image = (int)(idx / a.tpi);
     const int t = (int)(idx - (long long)image * a.tpi);
-    const int env = image / a.C, c = image - env * a.C;
-    const Env ev = a.envs[env];
-    // 16 super-blocks at a time: all loads issued before the first store, so they overlap
+    const uint32_t q0 = a.chunk_base[image];
+    const int nq = (int)(a.chunk_base[image + 1] - q0);
+    // 16 chunks at a time: all loads issued before the first store, so they overlap
     constexpr int B = 16;
-    const size_t stride = (size_t)a.C * a.tpi;
-    uint32_t* p = a.sbcnt + ((size_t)ev.sb_begin * a.C + c) * a.tpi + t;
+    const size_t stride = (size_t)a.tpi;
+    uint32_t* p = a.ecnt + (size_t)q0 * a.tpi + t;
     uint32_t run = 0;
-    for (int k0 = 0; k0 < ev.sb_count; k0 += B) {
-        const int m = ev.sb_count - k0 < B ? ev.sb_count - k0 : B;
+    for (int k0 = 0; k0 < nq; k0 += B) {
+        const int m = nq - k0 < B ? nq - k0 : B;
         uint32_t v[B];
 #pragma unroll
         for (int k = 0; k < B; ++k) v[k] = k < m ? p[(size_t)(k0 + k) * stride] : 0u;
@@ -396,8 +920,7 @@ __global__ void k_tile_offsets(FwdArgs a) {
 }
 
 // --------------------------------------------------------------------------------------------
-// exclusive scan of per-tile counts (one block, coalesced 1024-tile chunks); total pairs and
-// overflow into the status word
+// exclusive scan of per-tile counts (one block, coalesced 1024-tile chunks)
 // --------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_scan(FwdArgs a) {
     __shared__ unsigned long long s_wave[16];
@@ -431,10 +954,8 @@ __global__ __launch_bounds__(1024) void k_scan(FwdArgs a) {
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const unsigned long long total = s_carry;
+        const unsigned long long total = s_carry;  // pairs and overflow were set by k_pair_scan
         a.starts[T] = total > 0xffffffffull ? 0xffffffffu : (uint32_t)total;
-        a.status->pairs = total;
-        if (total > (unsigned long long)a.pair_cap) atomicOr(&a.status->flags, (uint32_t)GSR_STATUS_OVERFLOW);
     }
     for (int off = 32; off > 0; off >>= 1) {
         const uint32_t o = __shfl_xor(mx, off, 64);
@@ -444,96 +965,139 @@ __global__ __launch_bounds__(1024) void k_scan(FwdArgs a) {
 }
 
 // --------------------------------------------------------------------------------------------
-// pair emission into tile buckets.  Each (super-block, camera) walks its compact list of
-// visible Gaussians and knows, per tile, the first slot of its pairs (tile start + the offsets
-// of the env's earlier super-blocks), so slots are taken with LDS atomics only.  Within a
-// batch of 256 list entries, the (Gaussian, tile) pairs are numbered by a block-wide prefix
-// over rectangle areas and split into equal runs of consecutive pairs, one per thread, so
-// large rectangles are shared by all threads.
-// Pair = (z bits << 32) | Gaussian id.
+// pair emission.  One wavefront per emission chunk walks the chunk's depth-ordered Gaussians
+// in rounds of 64 and writes their (z bits << 32 | id) pairs into the tile buckets, so each
+// bucket receives its entries in (z bits, id) order: chunks in order (first slots from the
+// tile offsets), rounds in order (a running slot per tile in LDS) and, within a round, by the
+// Gaussian's rank in the round: the set bits below it in the tile's 64-bit round mask.
+// A round's pairs are numbered by a prefix over the rectangle areas and split into equal runs
+// of consecutive pairs, one per lane, walked three times: set the mask bits; write the pairs;
+// advance each tile's slot (by the tile's highest Gaussian of the round) and clear its mask.
+// Chunks hold about the same number of pairs, so the wavefronts' work is balanced even where
+// the nearest (largest) splats of an image crowd into its first chunk.
 // --------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_emit(FwdArgs a, const Super* __restrict__ supers,
-                                                  const uint32_t* __restrict__ sbvis) {
-    extern __shared__ uint32_t s_slot[];
-    __shared__ uint32_t s_off[kBlock + 1];
-    __shared__ uint32_t s_x0[kBlock], s_y0[kBlock], s_w[kBlock], s_z[kBlock], s_id[kBlock];
-    const Super sb = supers[blockIdx.x];
-    const int c = blockIdx.y;
-    const size_t image = (size_t)sb.env * a.C + c;
-    const int tpi = a.tpi;
-    const uint32_t* so = a.sbcnt + ((size_t)blockIdx.x * a.C + c) * tpi;
-    for (int t = threadIdx.x; t < tpi; t += kBlock) s_slot[t] = a.starts[image * tpi + t] + so[t];
-    const int i = threadIdx.x;
+__global__ __launch_bounds__(64) void k_emit(FwdArgs a) {
+    extern __shared__ unsigned long long s_mask[];  // [tpi] round masks, then [tpi] u32 slots
+    __shared__ uint32_t s_off[65], s_x0[64], s_y0[64], s_w[64], s_z[64], s_id[64];
+    const int lane = threadIdx.x;
+    uint32_t* s_slot = reinterpret_cast<uint32_t*>(s_mask + a.tpi);
     const unsigned long long cap = (unsigned long long)a.pair_cap;
-    const uint32_t nv = sbvis[(size_t)blockIdx.x * a.C + c];
-    const uint4* lst = a.vis + ((size_t)blockIdx.x * a.C + c) * a.sb_cap;
-    for (uint32_t b0 = 0; b0 < nv; b0 += kBlock) {
-        uint32_t n_i = 0;
-        if (b0 + i < nv) {
-            const uint4 r = lst[b0 + i];
-            const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu, y1 = r.y >> 16;
-            n_i = (x1 - x0) * (y1 - y0);
-            s_x0[i] = x0;
-            s_y0[i] = y0;
-            s_w[i] = x1 - x0;
-            s_z[i] = r.z;
-            s_id[i] = r.w;
+    const int tx_n = a.tiles_x;
+    for (int t = lane; t < a.tpi; t += 64) s_mask[t] = 0ull;  // masks are left clear by each round
+    const uint32_t nq = a.chunk_base[a.images];
+    for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+        uint32_t pos;
+        int img;
+        const uint32_t n = emit_chunk(a, q, pos, img);
+        if (n == 0u) continue;
+        const uint32_t* so = a.ecnt + (size_t)q * a.tpi;
+        const uint32_t* st = a.starts + (size_t)img * a.tpi;
+        for (int t = lane; t < a.tpi; t += 64) s_slot[t] = st[t] + so[t];
+        const uint32_t* keys = a.skey[1] + pos;
+        const uint32_t* gids = a.sgid[1] + pos;
+        const uint2* rects = a.srect[1] + pos;
+        // the next round's Gaussian, loaded one round ahead
+        uint2 nr = make_uint2(0u, 0u);
+        uint32_t nz = 0u, ni = 0u;
+        if ((uint32_t)lane < n) {
+            nr = rects[lane];
+            nz = keys[lane];
+            ni = gids[lane];
         }
-        // block-wide exclusive scan of n_i (Hillis-Steele in LDS)
-        s_off[i + 1] = n_i;
-        if (i == 0) s_off[0] = 0;
-        __syncthreads();
-        for (int off = 1; off < kBlock; off <<= 1) {
-            const uint32_t v = (i + 1 > off) ? s_off[i + 1 - off] : 0u;
-            __syncthreads();
-            s_off[i + 1] += v;
-            __syncthreads();
-        }
-        // thread i takes the consecutive pairs [k0, k1): one search for the owner of k0, then
-        // a walk along the owners' rectangles (row-major tiles)
-        const uint32_t total = s_off[kBlock];
-        const uint32_t per = (total + kBlock - 1) / kBlock;
-        const uint32_t k0 = (uint32_t)i * per, k1 = k0 + per < total ? k0 + per : total;
-        if (k0 < k1) {
-            int o = 0, hi = kBlock - 1;  // first owner with s_off[owner + 1] > k0
-            while (o < hi) {
-                const int mid = (o + hi) >> 1;
-                if (s_off[mid + 1] > k0) hi = mid; else o = mid + 1;
+        for (uint32_t r0 = 0; r0 < n; r0 += 64) {
+            const uint32_t k = r0 + (uint32_t)lane;
+            uint32_t area = 0u;
+            if (k < n) {
+                const uint32_t x0 = nr.x & 0xffffu, y0 = nr.x >> 16, x1 = nr.y & 0xffffu, y1 = nr.y >> 16;
+                s_x0[lane] = x0;
+                s_y0[lane] = y0;
+                s_w[lane] = x1 - x0;
+                s_z[lane] = nz;
+                s_id[lane] = ni;
+                area = (x1 - x0) * (y1 - y0);
             }
-            uint32_t j = k0 - s_off[o];
-            uint32_t w = s_w[o], x0 = s_x0[o];
-            uint32_t tx = x0 + j % w, ty = s_y0[o] + j / w;
-            uint32_t left = s_off[o + 1] - k0;  // pairs of owner o from k0 on
-            unsigned long long val = ((unsigned long long)s_z[o] << 32) | (unsigned long long)s_id[o];
-            for (uint32_t k = k0; k < k1; ++k) {
-                while (left == 0) {  // next owner with pairs; k < total guarantees one exists
-                    ++o;
-                    w = s_w[o];
-                    x0 = s_x0[o];
-                    tx = x0;
-                    ty = s_y0[o];
-                    left = s_off[o + 1] - s_off[o];
-                    val = ((unsigned long long)s_z[o] << 32) | (unsigned long long)s_id[o];
-                }
-                const uint32_t pos = atomicAdd(&s_slot[ty * a.tiles_x + tx], 1u);
-                if ((unsigned long long)pos < cap) a.pairs[pos] = val;
-                --left;
-                if (++tx == x0 + w) {
-                    tx = x0;
-                    ++ty;
-                }
+            if (k + 64u < n) {
+                nr = rects[k + 64u];
+                nz = keys[k + 64u];
+                ni = gids[k + 64u];
             }
+            uint32_t incl = area;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += y;
+            }
+            s_off[lane + 1] = incl;
+            if (lane == 0) s_off[0] = 0u;
+            __syncthreads();
+            const uint32_t total = s_off[64];
+            const uint32_t per = (total + 63u) / 64u;
+            const uint32_t k0 = (uint32_t)lane * per, k1 = k0 + per < total ? k0 + per : total;
+            // where this lane's pairs start: the Gaussian of pair k0 (first o with
+            // s_off[o + 1] > k0) and the tile of that pair
+            int o0 = 0;
+            uint32_t w0 = 1u, x00 = 0u, tx0 = 0u, ty0 = 0u, left0 = 0u;
+            if (k0 < k1) {
+                int hi = 63;
+                while (o0 < hi) {
+                    const int mid = (o0 + hi) >> 1;
+                    if (s_off[mid + 1] > k0) hi = mid;
+                    else o0 = mid + 1;
+                }
+                w0 = s_w[o0];
+                x00 = s_x0[o0];
+                const uint32_t j = k0 - s_off[o0];
+                const uint32_t jy = j / w0;
+                tx0 = x00 + (j - jy * w0);
+                ty0 = s_y0[o0] + jy;
+                left0 = s_off[o0 + 1] - k0;
+            }
+            // calls f(o, tile) for this lane's pairs [k0, k1), in order (every listed rectangle
+            // is non-empty; k < total guarantees a next Gaussian with pairs)
+            auto walk = [&](auto&& f) {
+                int o = o0;
+                uint32_t w = w0, x0 = x00, tx = tx0, ty = ty0, left = left0;
+                for (uint32_t kk = k0; kk < k1; ++kk) {
+                    while (left == 0u) {
+                        ++o;
+                        w = s_w[o];
+                        x0 = s_x0[o];
+                        tx = x0;
+                        ty = s_y0[o];
+                        left = s_off[o + 1] - s_off[o];
+                    }
+                    f(o, ty * (uint32_t)tx_n + tx);
+                    --left;
+                    if (++tx == x0 + w) {
+                        tx = x0;
+                        ++ty;
+                    }
+                }
+            };
+            walk([&](int o, uint32_t t) { atomicOr(&s_mask[t], 1ull << o); });
+            __syncthreads();
+            walk([&](int o, uint32_t t) {
+                const unsigned long long m = s_mask[t];
+                const uint32_t p = s_slot[t] + (uint32_t)__popcll(m & ((1ull << o) - 1ull));
+                if ((unsigned long long)p < cap)
+                    a.pairs[p] = ((unsigned long long)s_z[o] << 32) | (unsigned long long)s_id[o];
+            });
+            __syncthreads();
+            walk([&](int o, uint32_t t) {
+                const unsigned long long m = s_mask[t];
+                if ((m >> o) == 1ull) {
+                    s_slot[t] += (uint32_t)__popcll(m);
+                    s_mask[t] = 0ull;
+                }
+            });
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
 // --------------------------------------------------------------------------------------------
-// per-tile sort by (z bits, id): tiles are classed by list length (classes 0..4: at most
-// 512, 1024, 2048, 4096, 8192 entries, sorted in LDS by one block; class 5: longer, sorted in
-// chunks and merged; class 6: at most one entry or overflowed, not sorted); each class is sorted by a persistent
-// grid pulling tiles from its list.  The lists also order the persistent compositor's queue,
-// longest class first.
+// tile length classes (at most 512, 1024, 2048, 4096, 8192 pairs, longer, at most one pair or
+// overflowed): the persistent compositor takes tiles longest class first.
 // --------------------------------------------------------------------------------------------
 // append a wavefront's flagged lanes to a device list with one atomic; returns each flagged
 // lane's slot
@@ -554,13 +1118,13 @@ __global__ void k_classify(FwdArgs a) {
     if (t < a.tiles) {
         const uint32_t s = a.starts[t], e = a.starts[t + 1];
         const uint32_t n = e - s;
-        if ((unsigned long long)e > (unsigned long long)a.pair_cap || n <= 1) cls = kSortNone;
+        if ((unsigned long long)e > (unsigned long long)a.pair_cap || n <= 1) cls = kLenNone;
         else if (n <= 512) cls = 0;
         else if (n <= 1024) cls = 1;
         else if (n <= 2048) cls = 2;
         else if (n <= 4096) cls = 3;
         else if (n <= 8192) cls = 4;
-        else cls = kSortBig;
+        else cls = kLenLong;
     }
 #pragma unroll
     for (int c = 0; c < kNumClasses; ++c) {
@@ -569,314 +1133,6 @@ __global__ void k_classify(FwdArgs a) {
     }
 }
 
-
-// Per-tile sort by (depth bits, Gaussian id) in LDS, for lists of at most NT * E entries.
-// Each entry is packed into one 64-bit word X = (z bits - zmin) << ib | (id - idmin), whose
-// order is the order of (z bits, id) and whose significant bits number TB = (bits of the
-// depth range) + ib.  An LSD radix sort with 4-bit digits over the top 16 significant bits
-// (12 for lists of at most 1024 entries; at most four passes) leaves the list in runs of equal
-// top bits, in order; each entry then
-// takes its place inside its run by counting the run's smaller words.  Runs are short for any
-// spread of depths; if a run is longer than 64 entries, the tile is sorted again by LSD passes
-// over all TB bits (so the result is exact for any input, and fast for the usual one).
-// A pass: thread t owns entries [t E, t E + E) ("blocked") and ranks them among its own
-// entries with 4-bit per-digit counters (one 64-bit word per 8 entries); the (digit, thread)
-// counts are scanned in digit-major order across the block, and each entry is scattered to
-// its digit's offset plus its rank, which keeps the pass stable.
-// LDS layouts are padded so that the blocked accesses hit distinct banks: entry i lives at
-// i + i / E, and count f of the digit-major table at f + 2 (f / 16) u16 slots.
-template <int NT, int E>
-__device__ __forceinline__ void sort_list(unsigned long long* p, const uint32_t n, unsigned long long* s_x, uint16_t* s_cnt,
-                          uint32_t* s_w, uint32_t* s_long_p) {
-    constexpr int CAP = NT * E;
-    constexpr int NW = NT / 64;
-    constexpr int NG = E / 8;
-    constexpr int LE = E == 8 ? 3 : 4;
-    static_assert((1 << LE) == E, "E must be 8 or 16");
-    uint32_t& s_long = *s_long_p;
-    if (n <= 1) return;  // nothing to order (uniform across the block); a chunk may hold one entry
-    const auto P = [](uint32_t i) { return i + (i >> LE); };
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    // count (d, t) of the digit-major table lives at Q(d NT + t) = Q(t) + d DSTRIDE, with
-    // Q(f) = f + 2 (f / 16) (NT is a multiple of 16)
-    constexpr uint32_t DSTRIDE = NT + NT / 8;
-    const uint32_t qt = (uint32_t)t + (((uint32_t)t >> 4) << 1);
-    unsigned long long x[E];
-    // one stable pass on the 4-bit digit at bit sh; x[] holds the thread's entries (blocked)
-    // before and after, and s_x the whole list after
-    // threads whose entries are all padding (t E >= n) only report their counts: padding words
-    // are all-ones, so they always land in digit 15 behind every entry and are never stored
-    const bool live = (uint32_t)t * E < n;
-    auto pass = [&](int sh) {
-        unsigned long long c[NG];
-        uint32_t rk[E / 4];
-#pragma unroll
-        for (int g = 0; g < NG; ++g) c[g] = live ? 0ull : 8ull << 60;  // 8 entries in digit 15
-#pragma unroll
-        for (int k = 0; k < E / 4; ++k) rk[k] = 0u;
-        if (live) {
-#pragma unroll
-            for (int r = 0; r < E; ++r) {
-                const uint32_t s4 = ((uint32_t)(x[r] >> sh) & 15u) << 2;
-                rk[r >> 2] |= ((uint32_t)(c[r >> 3] >> s4) & 15u) << ((r & 3) << 3);
-                c[r >> 3] += 1ull << s4;
-            }
-        }
-#pragma unroll
-        for (int d = 0; d < 16; ++d) {
-            uint32_t tot = 0;
-#pragma unroll
-            for (int g = 0; g < NG; ++g) tot += (uint32_t)(c[g] >> (4 * d)) & 15u;
-            s_cnt[qt + d * DSTRIDE] = (uint16_t)tot;
-        }
-        __syncthreads();
-        // exclusive scan in digit-major order: thread t takes counts 16 t .. 16 t + 15
-        uint32_t tot = 0;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) tot += s_cnt[18 * t + j];
-        uint32_t incl = tot;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += y;
-        }
-        if (lane == 63) s_w[wave] = incl;
-        __syncthreads();
-        uint32_t base = incl - tot;
-#pragma unroll 1
-        for (int i = 0; i < wave; ++i) base += s_w[i];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const uint32_t v = s_cnt[18 * t + j];
-            s_cnt[18 * t + j] = (uint16_t)base;
-            base += v;
-        }
-        __syncthreads();
-        if (live) {
-            // recompute the digits below instead of keeping E of them alive across the scan
-#pragma unroll
-            for (int r = 0; r < E; ++r) asm volatile("" : "+v"(x[r]));
-#pragma unroll
-            for (int r = 0; r < E; ++r) {
-                const uint32_t s4 = ((uint32_t)(x[r] >> sh) & 15u) << 2;
-                uint32_t rank = (rk[r >> 2] >> ((r & 3) << 3)) & 255u;
-#pragma unroll
-                for (int g = 0; g < (r >> 3); ++g) rank += (uint32_t)(c[g] >> s4) & 15u;
-                const uint32_t dest = (uint32_t)s_cnt[qt + (s4 >> 2) * DSTRIDE] + rank;
-                if (dest < n) s_x[P(dest)] = x[r];  // positions >= n hold padding only
-                if ((r & 7) == 7) asm volatile("" ::: "memory");  // bounds the scheduling window (registers)
-            }
-        }
-        __syncthreads();
-        if (live) {
-#pragma unroll
-            for (int r = 0; r < E; ++r) x[r] = (uint32_t)(t * E + r) < n ? s_x[t * (E + 1) + r] : ~0ull;
-        }
-        __syncthreads();
-    };
-    // striped copy into LDS (entry t + k NT lives at P(t) + k (NT + NT / E))
-#pragma unroll 1
-    for (int k = 0; k < E; ++k) {
-        const uint32_t i = (uint32_t)(t + k * NT);
-        s_x[P((uint32_t)t) + (uint32_t)k * (NT + NT / E)] = i < n ? p[i] : ~0ull;
-    }
-    __syncthreads();
-    // ranges of depth bits and ids
-    uint32_t zmin = 0xffffffffu, zmax = 0u, imin = 0xffffffffu, imax = 0u;
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const unsigned long long u = s_x[t * (E + 1) + r];
-        x[r] = u;
-        if ((uint32_t)(t * E + r) < n) {
-            const uint32_t z = (uint32_t)(u >> 32), id = (uint32_t)u;
-            zmin = z < zmin ? z : zmin;
-            zmax = z > zmax ? z : zmax;
-            imin = id < imin ? id : imin;
-            imax = id > imax ? id : imax;
-        }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint32_t a1 = __shfl_xor(zmin, off, 64), a2 = __shfl_xor(zmax, off, 64);
-        const uint32_t a3 = __shfl_xor(imin, off, 64), a4 = __shfl_xor(imax, off, 64);
-        zmin = a1 < zmin ? a1 : zmin;
-        zmax = a2 > zmax ? a2 : zmax;
-        imin = a3 < imin ? a3 : imin;
-        imax = a4 > imax ? a4 : imax;
-    }
-    if (lane == 0) {
-        s_w[4 * wave + 0] = zmin;
-        s_w[4 * wave + 1] = zmax;
-        s_w[4 * wave + 2] = imin;
-        s_w[4 * wave + 3] = imax;
-    }
-    if (t == 0) s_long = 0u;
-    __syncthreads();
-#pragma unroll 1
-    for (int i = 0; i < NW; ++i) {
-        zmin = s_w[4 * i + 0] < zmin ? s_w[4 * i + 0] : zmin;
-        zmax = s_w[4 * i + 1] > zmax ? s_w[4 * i + 1] : zmax;
-        imin = s_w[4 * i + 2] < imin ? s_w[4 * i + 2] : imin;
-        imax = s_w[4 * i + 3] > imax ? s_w[4 * i + 3] : imax;
-    }
-    __syncthreads();  // s_w is reused by the passes
-    const uint32_t zr = zmax - zmin, ir = imax - imin;
-    const int zb = zr ? 32 - __clz((int)zr) : 0;
-    const int ib = ir ? 32 - __clz((int)ir) : 0;
-    const int TB = zb + ib;
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const uint32_t z = (uint32_t)(x[r] >> 32), id = (uint32_t)x[r];
-        x[r] = (uint32_t)(t * E + r) < n ? ((unsigned long long)(z - zmin) << ib) | (unsigned long long)(id - imin)
-                                          : ~0ull;
-    }
-    const int sh0 = TB > 16 ? TB - 16 : 0;
-    for (int sh = sh0; sh < TB; sh += 4) pass(sh);
-    // a run of more than 64 equal top words: sort by every bit instead
-    bool lng = false;
-#pragma unroll 1
-    for (uint32_t i = t; i + 64 < n; i += NT) lng |= (s_x[P(i)] >> sh0) == (s_x[P(i + 64)] >> sh0);
-    if (__any(lng) && lane == 0) s_long = 1u;
-    __syncthreads();
-    const bool full = s_long != 0u;
-    if (full)
-        for (int sh = 0; sh < TB; sh += 4) pass(sh);
-    const int shr = full ? 0 : sh0;
-#pragma unroll 1
-    for (uint32_t i = t; i < n; i += NT) {
-        const unsigned long long u = s_x[P(i)];
-        const unsigned long long top = u >> shr;
-        uint32_t pos = i;
-        const bool prev = i > 0 && (s_x[P(i - 1)] >> shr) == top;
-        const bool next = i + 1 < n && (s_x[P(i + 1)] >> shr) == top;
-        if (prev || next) {  // inside a run: place by the number of smaller words
-            uint32_t b = i, e = i + 1;
-            while (b > 0 && (s_x[P(b - 1)] >> shr) == top) --b;
-            while (e < n && (s_x[P(e)] >> shr) == top) ++e;
-            uint32_t rank = 0;
-            for (uint32_t j = b; j < e; ++j) rank += s_x[P(j)] < u ? 1u : 0u;
-            pos = b + rank;
-        }
-        const uint32_t z = (uint32_t)(u >> ib) + zmin;
-        const uint32_t id = (uint32_t)(u & ((1ull << ib) - 1ull)) + imin;
-        p[pos] = ((unsigned long long)z << 32) | (unsigned long long)id;
-    }
-    __syncthreads();
-}
-
-// one block per tile of the class, lists of at most NT * E entries
-template <int NT, int E>
-__global__ __launch_bounds__(NT) void k_sort_radix(FwdArgs a, int cls, const Status* __restrict__ status,
-                                                   const uint32_t* __restrict__ cls_list,
-                                                   const uint32_t* __restrict__ starts) {
-    __shared__ unsigned long long s_x[NT * E + NT];
-    __shared__ uint16_t s_cnt[18 * NT];
-    __shared__ uint32_t s_w[4 * (NT / 64)];
-    __shared__ uint32_t s_long;
-    const uint32_t count = status->cls[cls];
-    for (uint32_t w = blockIdx.x; w < count; w += gridDim.x) {
-        const uint32_t tile = cls_list[(size_t)cls * a.tiles + w];
-        const uint32_t st = starts[tile], n = starts[tile + 1] - st;
-        sort_list<NT, E>(a.pairs + st, n, s_x, s_cnt, s_w, &s_long);
-    }
-}
-
-// Lists longer than one LDS sort (class kSortBig) are cut into chunks of CH entries.  Every
-// (tile, chunk) is a work item of the grid, so long lists use many CUs at once:
-//   k_sort_chunks   sorts each chunk in LDS (the same routine as the single-block classes);
-//   k_merge_chunks  places each element of a chunk at its rank in the whole list: its index
-//                   in its own chunk plus, for every other chunk of the tile (staged in LDS),
-//                   the number of smaller keys there (keys are unique); writes pairs_alt;
-//   k_copy_chunks   copies the merged lists back.
-// The item count uses the longest list of the render (max_tile) as the chunk bound.
-__device__ inline uint32_t big_chunks(const Status* __restrict__ status, uint32_t ch) {
-    return (status->max_tile + ch - 1) / ch;
-}
-
-template <int NT, int E>
-__global__ __launch_bounds__(NT) void k_sort_chunks(FwdArgs a, const Status* __restrict__ status,
-                                                    const uint32_t* __restrict__ cls_list,
-                                                    const uint32_t* __restrict__ starts) {
-    constexpr uint32_t CH = NT * E;
-    __shared__ unsigned long long s_x[NT * E + NT];
-    __shared__ uint16_t s_cnt[18 * NT];
-    __shared__ uint32_t s_w[4 * (NT / 64)];
-    __shared__ uint32_t s_long;
-    const uint32_t mc = big_chunks(status, CH);
-    const uint32_t items = status->cls[kSortBig] * mc;
-    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
-        const uint32_t w = it / mc, c = it - w * mc;
-        const uint32_t tile = cls_list[(size_t)kSortBig * a.tiles + w];
-        const uint32_t st = starts[tile], n = starts[tile + 1] - st;
-        if (c * CH >= n) continue;
-        sort_list<NT, E>(a.pairs + st + c * CH, (n - c * CH < CH) ? n - c * CH : CH, s_x, s_cnt, s_w, &s_long);
-    }
-}
-
-template <int NT, int E>
-__global__ __launch_bounds__(NT) void k_merge_chunks(FwdArgs a, const Status* __restrict__ status,
-                                                     const uint32_t* __restrict__ cls_list,
-                                                     const uint32_t* __restrict__ starts) {
-    constexpr uint32_t CH = NT * E;
-    __shared__ unsigned long long s_o[CH];
-    const uint32_t mc = big_chunks(status, CH);
-    const uint32_t items = status->cls[kSortBig] * mc;
-    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
-        const uint32_t w = it / mc, c = it - w * mc;
-        const uint32_t tile = cls_list[(size_t)kSortBig * a.tiles + w];
-        const uint32_t st = starts[tile], n = starts[tile + 1] - st;
-        if (c * CH >= n) continue;
-        const uint32_t nc = (n + CH - 1) / CH;
-        const uint32_t len = (n - c * CH < CH) ? n - c * CH : CH;
-        const unsigned long long* src = a.pairs + st;
-        unsigned long long x[E];
-        uint32_t pos[E];
-#pragma unroll
-        for (int k = 0; k < E; ++k) {
-            const uint32_t i = threadIdx.x + (uint32_t)k * NT;
-            x[k] = i < len ? src[c * CH + i] : 0ull;
-            pos[k] = i;  // rank within its own (sorted) chunk
-        }
-        for (uint32_t o = 0; o < nc; ++o) {
-            if (o == c) continue;
-            const uint32_t lo = (n - o * CH < CH) ? n - o * CH : CH;
-            __syncthreads();
-            for (uint32_t i = threadIdx.x; i < lo; i += NT) s_o[i] = src[o * CH + i];
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < E; ++k) {
-                uint32_t l = 0, h = lo;  // keys of chunk o smaller than x[k]
-                while (l < h) {
-                    const uint32_t m = (l + h) >> 1;
-                    if (s_o[m] < x[k]) l = m + 1; else h = m;
-                }
-                pos[k] += l;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < E; ++k) {
-            const uint32_t i = threadIdx.x + (uint32_t)k * NT;
-            if (i < len) a.pairs_alt[st + pos[k]] = x[k];
-        }
-        __syncthreads();
-    }
-}
-
-template <int NT, int E>
-__global__ __launch_bounds__(NT) void k_copy_chunks(FwdArgs a, const Status* __restrict__ status,
-                                                    const uint32_t* __restrict__ cls_list,
-                                                    const uint32_t* __restrict__ starts) {
-    constexpr uint32_t CH = NT * E;
-    const uint32_t mc = big_chunks(status, CH);
-    const uint32_t items = status->cls[kSortBig] * mc;
-    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
-        const uint32_t w = it / mc, c = it - w * mc;
-        const uint32_t tile = cls_list[(size_t)kSortBig * a.tiles + w];
-        const uint32_t st = starts[tile], n = starts[tile + 1] - st;
-        if (c * CH >= n) continue;
-        const uint32_t len = (n - c * CH < CH) ? n - c * CH : CH;
-        for (uint32_t i = threadIdx.x; i < len; i += NT) a.pairs[st + c * CH + i] = a.pairs_alt[st + c * CH + i];
-    }
-}
 
 // --------------------------------------------------------------------------------------------
 // front-to-back compositing.  One tile per block, one sub-tile per wavefront; each lane shades
@@ -1053,7 +1309,7 @@ __global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composit
 }
 
 // persistent grid: block b takes queue items b, b + G, b + 2G, ... of the longest-first queue
-// (sort classes from the longest lists down, then the lists of at most one entry).  A static
+// (length classes from the longest lists down, then the lists of at most one entry).  A static
 // interleave needs no shared counter: a single global atomic per tile would serialise the
 // grid.  The wavefronts of a block work on the same tile independently.
 template <int TW, int TH, int PPT, bool SAVE, bool COUNT>
@@ -1071,12 +1327,12 @@ __global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composit
     for (long long item = blockIdx.x; item < a.tiles; item += gridDim.x) {
         // queue order: longest class first (5, 4, ..., 0), then class 6
         uint32_t k = (uint32_t)item;
-        int cls = kSortBig;
+        int cls = kLenLong;
         while (cls >= 0 && k >= cnt[cls]) {
             k -= cnt[cls];
             --cls;
         }
-        if (cls < 0) cls = kSortNone;
+        if (cls < 0) cls = kLenNone;
         composite_sub<TW, TH, PPT, SAVE, COUNT>(a, (long long)cls_list[(size_t)cls * a.tiles + k], wave, lane, s0[wave],
                                                 s1[wave], s2[wave], starts, envs);
     }
@@ -1101,8 +1357,7 @@ __global__ void k_copy_pairs(FwdArgs a, uint64_t* keys, uint32_t* vals, uint32_t
 // --------------------------------------------------------------------------------------------
 template <int L>
 static hipError_t launch_project(const FwdArgs& a, hipStream_t s) {
-    const int gsz = (a.tiles_x + 1) * (a.tiles_y + 1);
-    const size_t lds = (size_t)a.C * (gsz + 1) * sizeof(int);
+    const size_t lds = (size_t)(kBlock / 64) * a.C * sizeof(uint32_t);
     hipLaunchKernelGGL((k_project<L>), dim3(a.n_supers), dim3(kBlock), lds, s, a, a.supers, a.envs, a.blocks, a.nodes,
                        a.views);
     return hipGetLastError();
@@ -1134,15 +1389,7 @@ static void launch_composite(const FwdArgs& a, hipStream_t s) {
     }
 }
 
-static int g_num_cu = 0;
-
 hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
-    if (g_num_cu == 0) {
-        int dev = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev);
-        if (g_num_cu <= 0) g_num_cu = 256;
-    }
     auto mark = [&](int i) {
         if (a.stage_events) hipEventRecord(a.stage_events[i], s);
     };
@@ -1161,26 +1408,36 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
         if (e != hipSuccess) return e;
     }
     mark(2);
-    hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)((a.tiles + 255) / 256)), dim3(256), 0, s, a);
+    const int nl = a.n_supers * a.C;
+    const unsigned ncu = (unsigned)(a.num_cu > 0 ? a.num_cu : 256);
+    auto grid = [&](long long items, unsigned per_cu) {
+        const long long g = std::min<long long>(items, (long long)ncu * per_cu);
+        return dim3((unsigned)(g > 0 ? g : 1));
+    };
+    hipLaunchKernelGGL(k_seg, dim3(1), dim3(1024), 0, s, a);
+    if (nl > 0) hipLaunchKernelGGL(k_gather, grid(nl, 16), dim3(256), 0, s, a);
     mark(3);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
+    for (int pass = 0; pass < 4; ++pass) {
+        hipLaunchKernelGGL(k_radix_hist, grid(a.sort_chunks, 8), dim3(256), 0, s, a, pass);
+        hipLaunchKernelGGL(k_radix_scan, dim3(a.images), dim3(1024), 0, s, a);
+        hipLaunchKernelGGL(k_radix_scatter, grid(a.sort_chunks, 6), dim3(256), 0, s, a, pass);
+    }
     mark(4);
-    if (a.n_supers > 0)
-        hipLaunchKernelGGL(k_emit, dim3(a.n_supers, a.C), dim3(kBlock), (size_t)a.tpi * sizeof(uint32_t), s, a,
-                           a.supers, a.sbvis);
+    const long long n_blocks = (long long)a.sort_chunks * (kSortTile / kPairBlock);
+    hipLaunchKernelGGL(k_pair_blocks, grid(n_blocks, 8), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_pair_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_chunk_starts, grid(n_blocks, 8), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_tile_counts, grid(a.chunk_cap, 8), dim3(256),
+                       (size_t)(a.tiles_x + 1) * (a.tiles_y + 1) * sizeof(int), s, a);
     mark(5);
-    hipLaunchKernelGGL(k_classify, dim3((unsigned)((a.tiles + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)((a.tiles + 255) / 256)), dim3(256), 0, s, a);
     mark(6);
-    hipLaunchKernelGGL((k_sort_radix<64, 8>), dim3(g_num_cu * 32), dim3(64), 0, s, a, 0, a.status, a.cls_list, a.starts);
-    hipLaunchKernelGGL((k_sort_radix<128, 8>), dim3(g_num_cu * 16), dim3(128), 0, s, a, 1, a.status, a.cls_list, a.starts);
-    hipLaunchKernelGGL((k_sort_radix<256, 8>), dim3(g_num_cu * 8), dim3(256), 0, s, a, 2, a.status, a.cls_list, a.starts);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
     mark(7);
-    hipLaunchKernelGGL((k_sort_radix<512, 8>), dim3(g_num_cu * 4), dim3(512), 0, s, a, 3, a.status, a.cls_list, a.starts);
-    hipLaunchKernelGGL((k_sort_radix<1024, 8>), dim3(g_num_cu * 2), dim3(1024), 0, s, a, 4, a.status, a.cls_list, a.starts);
+    hipLaunchKernelGGL(k_emit, grid(a.chunk_cap, 16), dim3(64),
+                       (size_t)a.tpi * (sizeof(unsigned long long) + sizeof(uint32_t)), s, a);
     mark(8);
-    hipLaunchKernelGGL((k_sort_chunks<1024, 8>), dim3(g_num_cu * 2), dim3(1024), 0, s, a, a.status, a.cls_list, a.starts);
-    hipLaunchKernelGGL((k_merge_chunks<1024, 8>), dim3(g_num_cu * 2), dim3(1024), 0, s, a, a.status, a.cls_list, a.starts);
-    hipLaunchKernelGGL((k_copy_chunks<1024, 8>), dim3(g_num_cu * 2), dim3(1024), 0, s, a, a.status, a.cls_list, a.starts);
+    hipLaunchKernelGGL(k_classify, dim3((unsigned)((a.tiles + 255) / 256)), dim3(256), 0, s, a);
     mark(9);
     if (a.tw == 16 && a.th == 16) {
         if (a.ppt == 4) launch_composite<16, 16, 4>(a, s);

@@ -9,16 +9,22 @@
 
 namespace gsr {
 
-constexpr int kBlock = 256;          // Gaussians per projection / emission block
-// Per-tile sort classes by list length: classes 0 .. kSortClasses - 1 hold lists of at most
-// 512, 1024, ..., 8192 entries, each sorted in LDS by one block; longer lists (class
-// kSortBig) are sorted in chunks by many blocks and merged; class kSortNone holds lists of at most one entry (and
-// overflowed tiles).
-constexpr int kSortClasses = 5;
-constexpr int kSortBig = 5;
-constexpr int kSortNone = 6;
+constexpr int kBlock = 256;          // Gaussians per projection block (one chunk)
+// Tile-length classes: classes 0 .. 4 hold tiles with at most 512, 1024, ..., 8192 pairs,
+// class kLenLong longer lists, class kLenNone tiles with at most one pair (and overflowed
+// tiles).  They order the persistent compositor's queue, longest lists first.
+constexpr int kLenClasses = 5;
+constexpr int kLenLong = 5;
+constexpr int kLenNone = 6;
 constexpr int kNumClasses = 7;
-constexpr int kLdsHistLimit = 16384; // int counters a block may keep in LDS for tile histograms
+constexpr int kLdsHistLimit = 16384; // int counters of one image's tile difference grid in LDS
+// Depth sort and emission: each image's visible Gaussians occupy a segment of the sort buffers
+// made of radix chunks of kSortTile items; tile counts and emission work on chunks of the
+// depth-ordered Gaussians holding about the same number of pairs.  An image has at most
+// kMaxTilesPerImage tiles (LDS of the emission).
+constexpr int kSortTile = 2048;
+constexpr int kPairBlock = 1024;     // positions per block of the pair-prefix kernels
+constexpr int kMaxTilesPerImage = 5120;
 
 // One (node, camera) view: the camera<-node map composed in FP64 and rounded
 // once to FP32, the camera centre in node-local coordinates, intrinsics and
@@ -67,6 +73,7 @@ struct Super {
 };
 
 constexpr int kMaxChunksPerSuper = 16;
+static_assert(kSortTile % kPairBlock == 0, "pair-prefix blocks tile the radix chunks");
 
 constexpr int kParts = 64;
 
@@ -75,7 +82,7 @@ struct Status {
     uint32_t nonfinite;
     unsigned long long pairs;
     uint32_t max_tile;
-    uint32_t cls[8];      // tile counts per sort class
+    uint32_t cls[8];      // tile counts per length class
     uint32_t work_head;   // unused
     uint32_t pad[5];
     // counters summed on the host over kParts slots (block b adds into slot b % kParts): a
@@ -85,7 +92,8 @@ struct Status {
     unsigned long long evals[kParts];        // Gaussian-pixel evaluations of the compositor
 };
 
-constexpr int kStages = 10;  // views, project, tile counts, scan, emit, classify, 3 sorts, composite
+constexpr int kStages = 10;  // views, project, gather, depth_sort, tile_counts, tile_offsets, scan,
+                             // emit, classify, composite
 
 // Projected record of one (image, Gaussian): r0 = (u, v, opacity, z),
 // r1 = (A, B, C, log2 opacity) with (A, B, C) the conic (inverse dilated 2D covariance),
@@ -163,17 +171,32 @@ struct FwdArgs {
     // workspace
     View* views;
     Record* records;
-    uint4* vis;          // per (super-block, camera): list of visible Gaussians,
+    uint4* vis;          // per (super-block, camera): the visible Gaussians in id order,
                          //   {x0 | y0 << 16, x1 | y1 << 16, z bits, Gaussian id}
     uint32_t* sbvis;     // per (super-block, camera): length of that list
+    uint32_t* loff;      // per (super-block, camera): the list's first position in the sort buffers
     int sb_cap;          // list capacity per (super-block, camera)
-    uint32_t* sbcnt;     // per (super-block, camera, tile): pair count, then slot offset
+    // depth sort (two ping-pong buffers; the last pass leaves the result in buffer 1)
+    uint32_t* skey[2];   // z bits
+    uint32_t* sgid[2];   // Gaussian id
+    uint2* srect[2];     // tile rectangle {x0 | y0 << 16, x1 | y1 << 16}
+    uint32_t* hist;      // per radix chunk (pass 0: per list): 256 digit counts, then first slots
+    uint32_t* seg_n;     // per image: visible Gaussians (the length of its segment)
+    uint32_t* seg_start; // per image + 1: first position of its segment (kSortTile multiples)
+    int sort_chunks;     // radix chunks the sort buffers can hold
+    uint32_t* blk_pairs; // per kPairBlock positions of the sorted buffer: pairs, then the
+                         //   image's pairs before the block
+    uint32_t* chunk_base;  // per image + 1: first emission chunk of the image
+    uint32_t* cstart;    // per emission chunk: first position of its Gaussians
+    uint32_t* cimg;      // per emission chunk: its image
+    int chunk_cap;       // emission chunks the workspace holds
+    int chunk_pairs;     // pairs per emission chunk (a chunk starts at every multiple)
+    uint32_t* ecnt;      // per (emission chunk, tile): pairs, then first slot in the tile's bucket
+    int num_cu;          // compute units (grid sizes of the grid-stride kernels)
     uint32_t* counts;    // per tile
     uint32_t* starts;    // per tile + 1
-    uint32_t* cursor;    // per tile
     uint32_t* cls_list;  // kNumClasses lists of `tiles` entries
     unsigned long long* pairs;
-    unsigned long long* pairs_alt;
     long long pair_cap;
     Status* status;
     // outputs

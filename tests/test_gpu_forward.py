@@ -160,8 +160,9 @@ def test_pair_capacity_overflow_is_reported_then_grown(gsr):
         c.close()
 
 
-def test_long_tile_lists_chunk_sort_and_merge(gsr, ctx):
-    # dense cube, small image: per-tile lists well above one LDS load (16384 entries)
+def test_long_tile_lists(gsr, ctx):
+    # dense cube, small image: per-tile lists above 32768 entries, written by many emission
+    # chunks of the depth-sorted Gaussians
     wl = synth.scene_config(0, seed=13, scale=3.0)
     cam = synth.camera((0, 0, -3), (0, 0, 0), 48, 48)
     cam["fx"] = cam["fy"] = np.float32(41.57)
@@ -177,8 +178,8 @@ def test_long_tile_lists_chunk_sort_and_merge(gsr, ctx):
 @pytest.mark.parametrize("spread_ulps,outlier", [(6, True), (0, True), (0, False)])
 def test_clustered_depths_sort_exactly(gsr, ctx, spread_ulps, outlier):
     """Thousands of entries per tile within a few ulps of one depth (or at exactly one depth,
-    ordered by id), with or without a far entry in the same tiles: the per-tile sort must
-    still give the oracle's (z bits, id) order bit for bit."""
+    ordered by id), with or without a far entry in the same tiles: the depth sort and the
+    emission must still give the oracle's (z bits, id) order bit for bit."""
     from helpers import cam_identity, env_of, node
     rng = np.random.default_rng(41)
     n = 3000
@@ -196,10 +197,11 @@ def test_clustered_depths_sort_exactly(gsr, ctx, spread_ulps, outlier):
     assert lens.max() > 2000
 
 
-@pytest.mark.parametrize("n", [8193, 8256, 16385])
-def test_chunked_lists_with_short_last_chunk(gsr, ctx, n):
+@pytest.mark.parametrize("n", [1025, 8193, 8256, 16385])
+def test_depth_sort_chunk_boundaries(gsr, ctx, n):
     """One 16x16 image, every Gaussian inside it: the tile's list holds exactly n entries, so
-    lists longer than one LDS sort are cut into chunks with a last chunk of 1 or 64 entries."""
+    the image's depth-sorted Gaussians fill radix chunks of 4096 and emission chunks of 1024
+    with a short last chunk (1 or 64 entries)."""
     from helpers import cam_identity, env_of, node
     rng = np.random.default_rng(n)
     means = np.c_[rng.uniform(-0.02, 0.02, (n, 2)), rng.uniform(2.0, 6.0, n)].astype(np.float32)

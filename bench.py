@@ -247,8 +247,9 @@ def roofline(stage, st, n_total, cfg):
     quaternion), 12 K B of SH per Gaussian visible from any camera, and writes 64 B per visible
     (image, Gaussian) (48 B record + 16 B visible-list entry); the depth sort copies each 16 B
     list entry into its image's segment, then makes four radix passes, each reading the 4 B key
-    for the histogram and reading and writing the 16 B (key, id, rectangle) record; tile counting reads the 8 B rectangle and
-    emission the 16 B record per visible record, and emission writes 8 B per pair; the
+    for the histogram and reading and writing the 16 B (key, id, rectangle) record; chunking
+    and tile counting read the 8 B rectangle three times and emission the 16 B record per
+    visible record, and emission writes 8 B per pair; the
     compositor does at least OPS_PER_EVAL VALU lane-operations per Gaussian-pixel evaluation.
     """
     K = 16
@@ -256,15 +257,15 @@ def roofline(stage, st, n_total, cfg):
     work = {
         "project": ("hbm", 44 * n_total + 12 * K * visible_any + 64 * visible),
         "sort": ("hbm", (32 + 4 * (4 + 16 + 16)) * visible),
-        "emit": ("hbm", 8 * visible + 16 * visible + 8 * pairs),
+        "emit": ("hbm", 3 * 8 * visible + 16 * visible + 8 * pairs),
         "composite": ("alu", evals * OPS_PER_EVAL),
     }
     times = {"project": stage["project"], "sort": stage["gather"] + stage["depth_sort"],
-             "emit": stage["tile_counts"] + stage["emit"], "composite": stage["composite"]}
+             "emit": stage["chunks"] + stage["tile_counts"] + stage["emit"], "composite": stage["composite"]}
     tw, th, ppt, pers = cfg
     # kernel names as the profiler prints them, without the parameter list; the timed region
     # composites without evaluation counting
-    kname = {"project": ["k_project<3>"], "emit": ["k_tile_counts", "k_emit"],
+    kname = {"project": ["k_project<3>"], "emit": ["k_pair_blocks", "k_pair_scan", "k_chunk_starts", "k_tile_counts", "k_emit"],
              "composite": [f"k_composite{'_persistent' if pers else ''}<{tw}, {th}, {ppt}, false, false>"]}
     traffic = measured_traffic()
     if traffic is not None:

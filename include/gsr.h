@@ -140,9 +140,10 @@ typedef struct {
 
 /* Number of timed forward stages and their names, in order: views, project,
    gather (visible lists into per-image segments), depth_sort (the per-image radix
-   sort by depth), tile_counts (pair-balanced chunks and their per-tile counts),
-   tile_offsets, scan, emit, classify, composite. */
-#define GSR_STAGES 10
+   sort by depth), chunks (each image's depth-ordered Gaussians cut into chunks of
+   about equal pair counts), tile_counts (per chunk and tile), tile_ranges (per-tile
+   slots and [start, end) ranges), emit, composite. */
+#define GSR_STAGES 9
 
 /* Configuration.  Tile shape must be one of 16x16, 16x8, 8x8, 32x8 (width x
    height).  Unset (zero) fields take defaults. */

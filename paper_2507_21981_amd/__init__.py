@@ -25,8 +25,7 @@ FLAG_GRAPH = 4
 FLAG_PERSISTENT = 8
 FLAG_TIMING = 16
 STATUS_OVERFLOW = 1
-STAGES = ("views", "project", "gather", "depth_sort", "tile_counts", "tile_offsets", "scan", "emit", "classify",
-          "composite")
+STAGES = ("views", "project", "gather", "depth_sort", "chunks", "tile_counts", "tile_ranges", "emit", "composite")
 
 _ERRORS = {-1: "GSR_E_INVALID", -2: "GSR_E_NOMEM", -3: "GSR_E_HIP", -4: "GSR_E_CAPACITY",
            -5: "GSR_E_UNSUPPORTED", -6: "GSR_E_STATE"}

@@ -83,8 +83,8 @@ struct gsr_context {
     DevBuf<uint32_t> sbvis, loff;
     DevBuf<uint32_t> skey0, skey1, sgid0, sgid1;
     DevBuf<uint2> srect0, srect1;
-    DevBuf<uint32_t> hist, seg_n, seg_start, blk_pairs, chunk_base, cstart, cimg, ecnt;
-    DevBuf<uint32_t> counts, starts, cls_list;
+    DevBuf<uint32_t> hist, seg_n, seg_start, blk_pairs, chunk_base, pair_base, cstart, cimg, ecnt;
+    DevBuf<uint32_t> starts, cls_list;
     DevBuf<View> views;
     DevBuf<float> T_final;
     DevBuf<uint32_t> n_contrib;
@@ -210,8 +210,8 @@ void gsr_destroy(gsr_context* ctx) {
     ctx->skey0.release(); ctx->skey1.release(); ctx->sgid0.release(); ctx->sgid1.release();
     ctx->srect0.release(); ctx->srect1.release(); ctx->hist.release(); ctx->seg_n.release(); ctx->ecnt.release();
     ctx->seg_start.release(); ctx->blk_pairs.release(); ctx->chunk_base.release(); ctx->cstart.release();
-    ctx->cimg.release();
-    ctx->counts.release(); ctx->starts.release();
+    ctx->cimg.release(); ctx->pair_base.release();
+    ctx->starts.release();
     ctx->cls_list.release(); ctx->views.release(); ctx->T_final.release(); ctx->n_contrib.release();
     ctx->g2d.release(); ctx->grads_dev.release();
     if (ctx->d_status) hipFree(ctx->d_status);
@@ -421,8 +421,8 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
         (r = ensure(ctx, ctx->srect1, sort_len)) ||
         (r = ensure(ctx, ctx->hist, (size_t)a.sort_chunks * 256)) ||
         (r = ensure(ctx, ctx->seg_n, a.images)) || (r = ensure(ctx, ctx->seg_start, a.images + 1)) ||
-        (r = ensure(ctx, ctx->blk_pairs, n_pblocks)) || (r = ensure(ctx, ctx->chunk_base, a.images + 1)) ||
-        (r = ensure(ctx, ctx->counts, a.tiles)) || (r = ensure(ctx, ctx->starts, a.tiles + 1)) ||
+        (r = ensure(ctx, ctx->blk_pairs, n_pblocks)) || (r = ensure(ctx, ctx->chunk_base, a.images + 1)) || (r = ensure(ctx, ctx->pair_base, a.images)) ||
+        (r = ensure(ctx, ctx->starts, a.tiles + 1)) ||
         (r = ensure(ctx, ctx->cls_list, (size_t)kNumClasses * a.tiles)) ||
         (r = ensure(ctx, ctx->views, (size_t)sc->n_nodes * C)) || (r = ensure(ctx, ctx->T_final, npix)) ||
         (r = ensure(ctx, ctx->n_contrib, npix)))
@@ -453,11 +453,11 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
     a.seg_start = ctx->seg_start.p;
     a.blk_pairs = ctx->blk_pairs.p;
     a.chunk_base = ctx->chunk_base.p;
+    a.pair_base = ctx->pair_base.p;
     a.cstart = ctx->cstart.p;
     a.cimg = ctx->cimg.p;
     a.ecnt = ctx->ecnt.p;
     a.num_cu = ctx->num_cu;
-    a.counts = ctx->counts.p;
     a.starts = ctx->starts.p;
     a.cls_list = ctx->cls_list.p;
     a.pairs = ctx->pairs.p;

@@ -13,11 +13,10 @@
 //   k_pair_*, k_chunk_starts   each image's depth-ordered Gaussians cut into chunks of about
 //                  equal pair counts
 //   k_tile_counts  per chunk: pairs per tile, from a difference grid in LDS
-//   k_tile_offsets per (image, tile): scan over the image's chunks of their pair counts
-//   k_scan         exclusive scan of per-tile counts -> per-tile [start, end) ranges
+//   k_tile_ranges  per image: each chunk's first slot in every tile bucket, the tiles' [start,
+//                  end) ranges, tiles grouped by list length (persistent compositor's order)
 //   k_emit         (depth bits, Gaussian id) pairs written into their tile's bucket in depth
 //                  order, so every bucket is sorted by (depth bits, id) as it is written
-//   k_classify     tiles grouped by list length (the persistent compositor's queue order)
 //   k_composite    per tile, front-to-back alpha blending of colour and camera-space z
 //                  (RGB and depth sensors, paper Sec. III-C), early exit when every pixel of a
 //                  wavefront is saturated
@@ -579,8 +578,8 @@ __global__ __launch_bounds__(1024) void k_radix_scan(FwdArgs a) {
 // rank = items of the same digit in earlier rounds (a per-wavefront LDS counter) + matching
 // lanes below it.  Local position = items of smaller digits in the chunk + items of the same
 // digit in earlier wavefronts + rank, so the chunk is staged in LDS in stable digit order, and
-// local position p of digit d goes to slot p + (chunk slot of d - local start of d).  Only the
-// keys stay in registers; ids and rectangles are read again when they are staged.
+// local position p of digit d goes to slot p + (chunk slot of d - local start of d).  All of
+// the chunk's loads are issued before the ranking.
 __global__ __launch_bounds__(256) void k_radix_scatter(FwdArgs a, int pass) {
     constexpr int R = kSortTile / 256;  // rounds per wavefront
     __shared__ uint32_t s_wc[4][256];
@@ -601,11 +600,15 @@ __global__ __launch_bounds__(256) void k_radix_scatter(FwdArgs a, int pass) {
         // rounds of this wavefront that hold items (uniform across the wavefront)
         const int nr = n > w0 ? (int)min((n - w0 + 63u) / 64u, (uint32_t)R) : 0;
         const uint32_t* kin = a.skey[ib] + pos;
-        uint32_t key[R], rk[R];
+        uint32_t key[R], rk[R], id[R];
+        uint2 rc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t k = w0 + (uint32_t)(r * 64 + lane);
-            key[r] = (r < nr && k < n) ? kin[k] : 0u;
+            const bool in = r < nr && k < n;
+            key[r] = in ? kin[k] : 0u;
+            id[r] = in ? a.sgid[ib][pos + k] : 0u;
+            rc[r] = in ? a.srect[ib][pos + k] : make_uint2(0u, 0u);
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -647,8 +650,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(FwdArgs a, int pass) {
             if (r < nr && k < n) {
                 const uint32_t d = (key[r] >> sh) & 255u;
                 rk[r] += s_wc[wave][d];
-                const uint32_t id = a.sgid[ib][pos + k];
-                s_buf[rk[r]] = ((unsigned long long)id << 32) | (unsigned long long)key[r];
+                s_buf[rk[r]] = ((unsigned long long)id[r] << 32) | (unsigned long long)key[r];
                 s_dig[rk[r]] = (uint8_t)d;
             }
         }
@@ -663,10 +665,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(FwdArgs a, int pass) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t k = w0 + (uint32_t)(r * 64 + lane);
-            if (r < nr && k < n) {
-                const uint2 rc = a.srect[ib][pos + k];
-                s_buf[rk[r]] = ((unsigned long long)rc.y << 32) | (unsigned long long)rc.x;
-            }
+            if (r < nr && k < n) s_buf[rk[r]] = ((unsigned long long)rc[r].y << 32) | (unsigned long long)rc[r].x;
         }
         __syncthreads();
         for (uint32_t lp = t; lp < n; lp += 256) {
@@ -720,6 +719,7 @@ __global__ __launch_bounds__(256) void k_pair_blocks(FwdArgs a) {
 // word; on overflow no image gets chunks (nothing is emitted; the host grows the capacity).
 __global__ __launch_bounds__(1024) void k_pair_scan(FwdArgs a) {
     __shared__ uint32_t s_w[16];
+    __shared__ unsigned long long s_wp[16];
     __shared__ uint32_t s_carry;
     __shared__ unsigned long long s_pairs;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -731,11 +731,10 @@ __global__ __launch_bounds__(1024) void k_pair_scan(FwdArgs a) {
     const uint32_t PC = (uint32_t)a.chunk_pairs;
     for (int b0 = 0; b0 < a.images; b0 += 1024) {
         const int img = b0 + t;
-        uint32_t nchk = 0u;
+        uint32_t nchk = 0u, run = 0u;
         if (img < a.images) {
             const uint32_t s = a.seg_start[img] / kPairBlock;
             const int nb = (int)((a.seg_n[img] + kPairBlock - 1) / kPairBlock);
-            uint32_t run = 0u;
             constexpr int B = 16;
             for (int k0 = 0; k0 < nb; k0 += B) {
                 uint32_t v[B];
@@ -748,26 +747,44 @@ __global__ __launch_bounds__(1024) void k_pair_scan(FwdArgs a) {
                 }
             }
             nchk = (run + PC - 1) / PC;
-            atomicAdd(&s_pairs, (unsigned long long)run);
         }
+        // chunk bases and pair bases: exclusive scans over images
         uint32_t incl = nchk;
+        unsigned long long inclp = run;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t y = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += y;
+            const unsigned long long yp = __shfl_up(inclp, off, 64);
+            if (lane >= off) {
+                incl += y;
+                inclp += yp;
+            }
         }
-        if (lane == 63) s_w[wave] = incl;
+        if (lane == 63) {
+            s_w[wave] = incl;
+            s_wp[wave] = inclp;
+        }
         __syncthreads();
         uint32_t before = s_carry;
-        for (int w = 0; w < wave; ++w) before += s_w[w];
-        if (img < a.images) a.chunk_base[img] = before + incl - nchk;
+        unsigned long long beforep = s_pairs;
+        for (int w = 0; w < wave; ++w) {
+            before += s_w[w];
+            beforep += s_wp[w];
+        }
+        if (img < a.images) {
+            a.chunk_base[img] = before + incl - nchk;
+            a.pair_base[img] = (uint32_t)(beforep + inclp - run);  // < pair_cap unless overflowed
+        }
         __syncthreads();
-        if (t == 1023) s_carry = before + incl;
+        if (t == 1023) {
+            s_carry = before + incl;
+            s_pairs = beforep + inclp;
+        }
         __syncthreads();
     }
     const bool over = s_pairs > (unsigned long long)a.pair_cap || s_carry > (uint32_t)a.chunk_cap;
     if (over)
-        for (int i = t; i < a.images; i += 1024) a.chunk_base[i] = 0u;
+        for (int i = t; i < a.images; i += 1024) a.chunk_base[i] = a.pair_base[i] = 0u;
     if (t == 0) {
         a.chunk_base[a.images] = over ? 0u : s_carry;
         a.status->pairs = s_pairs;
@@ -890,73 +907,89 @@ __global__ __launch_bounds__(256) void k_tile_counts(FwdArgs a) {
 }
 
 // --------------------------------------------------------------------------------------------
-// per (image, tile): exclusive scan over the image's emission chunks (in depth order) -> each
-// chunk's first slot within the tile's bucket; the tile total -> pairs per tile
+// tile ranges: one block per image, one thread per tile (1024 at a time).  The tile's
+// exclusive scan over the image's emission chunks (in depth order) turns the chunks' counts
+// into their first slots within the tile's bucket; the tile totals, scanned over the image's
+// tiles from the image's pair base, give the tiles' starts (the range table).  Tiles are also
+// grouped by list length (at most 512, 1024, ..., 8192 pairs, longer, at most one pair): the
+// persistent compositor takes them longest class first.
 // --------------------------------------------------------------------------------------------
-__global__ void k_tile_offsets(FwdArgs a) {
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= a.tiles) return;
-    const int image = (int)(idx / a.tpi);
-    const int t = (int)(idx - (long long)image * a.tpi);
-    const uint32_t q0 = a.chunk_base[image];
-    const int nq = (int)(a.chunk_base[image + 1] - q0);
-    // 16 chunks at a time: all loads issued before the first store, so they overlap
-    constexpr int B = 16;
-    const size_t stride = (size_t)a.tpi;
-    uint32_t* p = a.ecnt + (size_t)q0 * a.tpi + t;
-    uint32_t run = 0;
-    for (int k0 = 0; k0 < nq; k0 += B) {
-        const int m = nq - k0 < B ? nq - k0 : B;
-        uint32_t v[B];
-#pragma unroll
-        for (int k = 0; k < B; ++k) v[k] = k < m ? p[(size_t)(k0 + k) * stride] : 0u;
-#pragma unroll
-        for (int k = 0; k < B; ++k) {
-            if (k < m) p[(size_t)(k0 + k) * stride] = run;
-            run += v[k];
-        }
-    }
-    a.counts[idx] = run;
+// append a wavefront's flagged lanes to a device list with one atomic; returns each flagged
+// lane's slot
+__device__ inline uint32_t wave_append(uint32_t* counter, bool pred) {
+    const unsigned long long m = __ballot(pred);
+    if (m == 0ull) return 0u;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+    base = __shfl(base, leader, 64);
+    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
 }
 
-// --------------------------------------------------------------------------------------------
-// exclusive scan of per-tile counts (one block, coalesced 1024-tile chunks)
-// --------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_scan(FwdArgs a) {
-    __shared__ unsigned long long s_wave[16];
-    __shared__ unsigned long long s_carry;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (threadIdx.x == 0) s_carry = 0;
+__global__ __launch_bounds__(1024) void k_tile_ranges(FwdArgs a) {
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_carry;
+    const int img = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t q0 = a.chunk_base[img];
+    const int nq = (int)(a.chunk_base[img + 1] - q0);
+    if (threadIdx.x == 0) s_carry = a.pair_base[img];
     __syncthreads();
-    const long long T = a.tiles;
-    uint32_t mx = 0;
-    for (long long base = 0; base < T; base += 1024) {
-        const long long i = base + threadIdx.x;
-        const uint32_t v = i < T ? a.counts[i] : 0u;
-        mx = v > mx ? v : mx;
-        unsigned long long x = v;
+    constexpr int B = 16;  // loads in flight
+    const size_t stride = (size_t)a.tpi;
+    uint32_t mx = 0u;
+    for (int t0 = 0; t0 < a.tpi; t0 += 1024) {
+        const int t = t0 + (int)threadIdx.x;
+        uint32_t run = 0u;
+        if (t < a.tpi) {
+            uint32_t* p = a.ecnt + (size_t)q0 * a.tpi + t;
+            for (int k0 = 0; k0 < nq; k0 += B) {
+                const int m = nq - k0 < B ? nq - k0 : B;
+                uint32_t v[B];
+#pragma unroll
+                for (int k = 0; k < B; ++k) v[k] = k < m ? p[(size_t)(k0 + k) * stride] : 0u;
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    if (k < m) p[(size_t)(k0 + k) * stride] = run;
+                    run += v[k];
+                }
+            }
+        }
+        mx = run > mx ? run : mx;
+        uint32_t incl = run;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-            const unsigned long long y = __shfl_up(x, off, 64);
-            if (lane >= off) x += y;
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
         }
-        if (lane == 63) s_wave[wave] = x;
+        if (lane == 63) s_w[wave] = incl;
         __syncthreads();
-        unsigned long long before = s_carry;
-        for (int w = 0; w < wave; ++w) before += s_wave[w];
-        const unsigned long long excl = before + x - v;
-        if (i < T) {
-            const uint32_t st = excl > 0xffffffffull ? 0xffffffffu : (uint32_t)excl;
-            a.starts[i] = st;
+        uint32_t st = s_carry;
+        for (int w = 0; w < wave; ++w) st += s_w[w];
+        st += incl - run;
+        const long long gt = (long long)img * a.tpi + t;
+        int cls = -1;
+        if (t < a.tpi) {
+            a.starts[gt] = st;
+            const uint32_t n = run;
+            if ((unsigned long long)st + n > (unsigned long long)a.pair_cap || n <= 1) cls = kLenNone;
+            else if (n <= 512) cls = 0;
+            else if (n <= 1024) cls = 1;
+            else if (n <= 2048) cls = 2;
+            else if (n <= 4096) cls = 3;
+            else if (n <= 8192) cls = 4;
+            else cls = kLenLong;
+        }
+#pragma unroll
+        for (int c = 0; c < kNumClasses; ++c) {
+            const uint32_t pos = wave_append(&a.status->cls[c], cls == c);
+            if (cls == c) a.cls_list[(size_t)c * a.tiles + pos] = (uint32_t)gt;
         }
         __syncthreads();
-        if (threadIdx.x == 1023) s_carry = excl + v;
+        if (threadIdx.x == 1023) s_carry = st + run;
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const unsigned long long total = s_carry;  // pairs and overflow were set by k_pair_scan
-        a.starts[T] = total > 0xffffffffull ? 0xffffffffu : (uint32_t)total;
-    }
+    if (img == a.images - 1 && threadIdx.x == 0) a.starts[a.tiles] = s_carry;  // total pairs
     for (int off = 32; off > 0; off >>= 1) {
         const uint32_t o = __shfl_xor(mx, off, 64);
         mx = o > mx ? o : mx;
@@ -1094,45 +1127,6 @@ __global__ __launch_bounds__(64) void k_emit(FwdArgs a) {
         }
     }
 }
-
-// --------------------------------------------------------------------------------------------
-// tile length classes (at most 512, 1024, 2048, 4096, 8192 pairs, longer, at most one pair or
-// overflowed): the persistent compositor takes tiles longest class first.
-// --------------------------------------------------------------------------------------------
-// append a wavefront's flagged lanes to a device list with one atomic; returns each flagged
-// lane's slot
-__device__ inline uint32_t wave_append(uint32_t* counter, bool pred) {
-    const unsigned long long m = __ballot(pred);
-    if (m == 0ull) return 0u;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((long long)m) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
-    base = __shfl(base, leader, 64);
-    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-}
-
-__global__ void k_classify(FwdArgs a) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    int cls = -1;
-    if (t < a.tiles) {
-        const uint32_t s = a.starts[t], e = a.starts[t + 1];
-        const uint32_t n = e - s;
-        if ((unsigned long long)e > (unsigned long long)a.pair_cap || n <= 1) cls = kLenNone;
-        else if (n <= 512) cls = 0;
-        else if (n <= 1024) cls = 1;
-        else if (n <= 2048) cls = 2;
-        else if (n <= 4096) cls = 3;
-        else if (n <= 8192) cls = 4;
-        else cls = kLenLong;
-    }
-#pragma unroll
-    for (int c = 0; c < kNumClasses; ++c) {
-        const uint32_t pos = wave_append(&a.status->cls[c], cls == c);
-        if (cls == c) a.cls_list[(size_t)c * a.tiles + pos] = (uint32_t)t;
-    }
-}
-
 
 // --------------------------------------------------------------------------------------------
 // front-to-back compositing.  One tile per block, one sub-tile per wavefront; each lane shades
@@ -1427,18 +1421,15 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_pair_blocks, grid(n_blocks, 8), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_pair_scan, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_chunk_starts, grid(n_blocks, 8), dim3(256), 0, s, a);
+    mark(5);
     hipLaunchKernelGGL(k_tile_counts, grid(a.chunk_cap, 8), dim3(256),
                        (size_t)(a.tiles_x + 1) * (a.tiles_y + 1) * sizeof(int), s, a);
-    mark(5);
-    hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)((a.tiles + 255) / 256)), dim3(256), 0, s, a);
     mark(6);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_tile_ranges, dim3(a.images), dim3(1024), 0, s, a);
     mark(7);
     hipLaunchKernelGGL(k_emit, grid(a.chunk_cap, 16), dim3(64),
                        (size_t)a.tpi * (sizeof(unsigned long long) + sizeof(uint32_t)), s, a);
     mark(8);
-    hipLaunchKernelGGL(k_classify, dim3((unsigned)((a.tiles + 255) / 256)), dim3(256), 0, s, a);
-    mark(9);
     if (a.tw == 16 && a.th == 16) {
         if (a.ppt == 4) launch_composite<16, 16, 4>(a, s);
         else if (a.ppt == 2) launch_composite<16, 16, 2>(a, s);
@@ -1453,7 +1444,7 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
         else if (a.ppt == 2) launch_composite<32, 8, 2>(a, s);
         else launch_composite<32, 8, 1>(a, s);
     }
-    mark(10);
+    mark(9);
     return hipGetLastError();
 }
 

@@ -92,8 +92,8 @@ struct Status {
     unsigned long long evals[kParts];        // Gaussian-pixel evaluations of the compositor
 };
 
-constexpr int kStages = 10;  // views, project, gather, depth_sort, tile_counts, tile_offsets, scan,
-                             // emit, classify, composite
+constexpr int kStages = 9;  // views, project, gather, depth_sort, chunks, tile_counts, tile_ranges,
+                            // emit, composite
 
 // Projected record of one (image, Gaussian): r0 = (u, v, opacity, z),
 // r1 = (A, B, C, log2 opacity) with (A, B, C) the conic (inverse dilated 2D covariance),
@@ -187,13 +187,13 @@ struct FwdArgs {
     uint32_t* blk_pairs; // per kPairBlock positions of the sorted buffer: pairs, then the
                          //   image's pairs before the block
     uint32_t* chunk_base;  // per image + 1: first emission chunk of the image
+    uint32_t* pair_base; // per image: pairs of the earlier images (its first bucket slot)
     uint32_t* cstart;    // per emission chunk: first position of its Gaussians
     uint32_t* cimg;      // per emission chunk: its image
     int chunk_cap;       // emission chunks the workspace holds
     int chunk_pairs;     // pairs per emission chunk (a chunk starts at every multiple)
     uint32_t* ecnt;      // per (emission chunk, tile): pairs, then first slot in the tile's bucket
     int num_cu;          // compute units (grid sizes of the grid-stride kernels)
-    uint32_t* counts;    // per tile
     uint32_t* starts;    // per tile + 1
     uint32_t* cls_list;  // kNumClasses lists of `tiles` entries
     unsigned long long* pairs;

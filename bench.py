@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--no-fwdbwd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", default="auto", help="auto (autotuner) or WxH")
+    ap.add_argument("--ppt", type=int, default=0, help="pixels per compositor lane with --tile (1, 2, 4)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (calibrates HBM traffic counters) and exit")
     return ap.parse_args()
@@ -120,6 +121,8 @@ def main():
         tw, th = (int(v) for v in args.tile.split("x"))
         pers = False
         ctx.set_tile(tw, th)
+        if args.ppt:
+            ctx.set_pixels_per_thread(args.ppt)
     log(f"[bench] tile {tw}x{th} persistent={pers}")
     fl_pers = gsr.FLAG_PERSISTENT if pers else 0
     rgb, depth, alpha = gsr.render_rgbd(ctx, scene, cams, W, H, C, flags=gsr.FLAG_CHECK | fl_pers)

@@ -1133,7 +1133,9 @@ __global__ __launch_bounds__(64) void k_emit(FwdArgs a) {
 // PPT pixels of one column, sharing the LDS reads and the dx terms.  List entries are staged
 // in LDS per batch with the conic pre-scaled, so that for a pixel offset (dx, dy)
 //   q = A' dx^2 + B' dx dy + C' dy^2 + log2(o),   A' = -1/2 log2(e) A, B' = -log2(e) B,
-//   C' = -1/2 log2(e) C,   alpha = min(0.99, exp2(q)) = min(0.99, o G).
+//   C' = -1/2 log2(e) C,   alpha = min(0.99, exp2(q)) = min(0.99, o G),
+// staged as the coefficients of q in the lane's pixel offsets within the wavefront's sub-tile
+// (five fma per pixel and entry).
 // Per pixel: skip if alpha < 1/255; stop (without blending) if T (1 - alpha) < 1e-4; else
 // C += alpha T c, D += alpha T z, T *= 1 - alpha.  rgb = C + T bg, depth = D, alpha = 1 - T.
 // Each batch of the list is culled against the wavefront's sub-tile and compacted (in list
@@ -1172,19 +1174,20 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
     const int env = image / a.C, cam = image - env * a.C;
     const Env ev = envs[env];
     const long long rec_off = (long long)a.C * ev.gid_base + (long long)cam * ev.n - (long long)ev.gid_base;
-    const float fpx = (float)px + 0.5f;
     const float thr = (float)(1.0 / 255.0);
+    // the lane's pixel offsets from the sub-tile's first pixel (small integers, exact)
+    const float X = (float)(lane % ST::SW);
     // Per pixel: T > 0 is the transmittance while the pixel is live; at the stop T becomes
     // -T (the sign marks a stopped pixel and |T| keeps its final transmittance), so later
     // entries add nothing.  Pixels outside the image start stopped.
-    float fpy[PPT], T[PPT], Cr[PPT], Cg[PPT], Cb[PPT], D[PPT];
+    float Y[PPT], T[PPT], Cr[PPT], Cg[PPT], Cb[PPT], D[PPT];
     uint32_t last[PPT], evals[PPT];
     bool inside[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
         const int py = py0 + p * ST::LROWS;
         inside[p] = px < a.width && py < a.height;
-        fpy[p] = (float)py + 0.5f;
+        Y[p] = (float)(lane / ST::SW + p * ST::LROWS);
         T[p] = inside[p] ? 1.0f : -1.0f;
         Cr[p] = Cg[p] = Cb[p] = D[p] = 0.0f;
         last[p] = 0;
@@ -1196,6 +1199,18 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
     // the wavefront's pixel-centre rectangle
     const float rx0 = (float)(tx * TW + sx * ST::SW) + 0.5f, rx1 = rx0 + (float)(ST::SW - 1);
     const float ry0 = (float)(ty * TH + sy * ST::SH) + 0.5f, ry1 = ry0 + (float)(ST::SH - 1);
+    // software pipeline over batches of 64 list entries: the ids of batch b + 2 and the
+    // records of batch b + 1 are loaded while batch b is composited
+    const uint32_t nid = ev.n;
+    auto load_id = [&](uint32_t j) -> uint32_t {
+        return j < end ? (uint32_t)a.pairs[j] - ev.gid_base : 0xffffffffu;  // local id, or none
+    };
+    auto load_rec = [&](uint32_t lid, Record& R) {
+        if (lid < nid) R = a.records[rec_off + ev.gid_base + lid];
+    };
+    uint32_t lid_cur = load_id(start + lane), lid_next = load_id(start + 64u + lane);
+    Record R_cur;
+    load_rec(lid_cur, R_cur);
     for (uint32_t base = start; base < end; base += 64) {
         bool any = false;
 #pragma unroll
@@ -1203,12 +1218,14 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
         if (!__any(any)) break;
         // stage the batch's entries that can reach this sub-tile, compacted in list order
         const uint32_t j = base + lane;
-        Record R;
+        const Record R = R_cur;
+        const uint32_t lid = lid_cur;
+        lid_cur = lid_next;
+        load_rec(lid_cur, R_cur);
+        lid_next = load_id(j + 128u);
         bool keep = false;
         if (j < end) {
-            const uint32_t gid = (uint32_t)a.pairs[j];
-            if (gid - ev.gid_base < ev.n) {
-                R = a.records[rec_off + gid];
+            if (lid < nid) {
                 keep = reaches_rect(R, rx0, rx1, ry0, ry1, qcut);
             } else {  // never produced by a consistent emission; blends nothing
                 atomicOr(&a.status->flags, 2u);
@@ -1218,8 +1235,18 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
         if (keep) {
             const int slot = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
-            s0[slot] = make_float4(R.r0.x, R.r0.y, -0.7213475204444817f * R.r1.x, -1.4426950408889634f * R.r1.y);
-            s1[slot] = make_float4(-0.7213475204444817f * R.r1.z, R.r1.w, R.r0.w, R.r2.x);
+            // q as a polynomial in the lane's offsets (X, Y) from the sub-tile's first pixel
+            // centre: with (Dx, Dy) = that centre - mean,
+            //   q = c0 + X (cx + A' X) + Y (cy + B' X + C' Y)
+            //   c0 = A' Dx^2 + B' Dx Dy + C' Dy^2 + log2 o, cx = 2 A' Dx + B' Dy, cy = B' Dx + 2 C' Dy
+            const float Ap = -0.7213475204444817f * R.r1.x, Bp = -1.4426950408889634f * R.r1.y;
+            const float Cp = -0.7213475204444817f * R.r1.z;
+            const float Dx = rx0 - R.r0.x, Dy = ry0 - R.r0.y;
+            const float cx = fmaf(2.0f * Ap, Dx, Bp * Dy);
+            const float cy = fmaf(Bp, Dx, (2.0f * Cp) * Dy);
+            const float c0 = fmaf(Dx, fmaf(Ap, Dx, Bp * Dy), fmaf(Cp * Dy, Dy, R.r1.w));
+            s0[slot] = make_float4(c0, cx, cy, Ap);
+            s1[slot] = make_float4(Bp, Cp, R.r0.w, R.r2.x);
             s2[slot] = make_float4(R.r2.y, R.r2.z, __uint_as_float(j - start + 1u), 0.0f);
         }
         // the wavefront's LDS writes are visible to its own later reads
@@ -1236,14 +1263,12 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
             }
             const float4 e0 = s0[k];
             const float4 e1 = s1[k];
-            const float dx = fpx - e0.x;
-            const float Adx = e0.z * dx, Bdx = e0.w * dx;
-            const float qx = fmaf(Adx, dx, e1.y);
+            const float qx = fmaf(X, fmaf(e0.w, X, e0.y), e0.x);
+            const float cyx = fmaf(e1.x, X, e0.z);
             float q[PPT];
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {
-                const float dy = fpy[p] - e0.y;
-                q[p] = fmaf(Bdx, dy, fmaf(e1.x * dy, dy, qx));
+                q[p] = fmaf(Y[p], fmaf(e1.y, Y[p], cyx), qx);
                 if (COUNT) evals[p] += T[p] > 0.0f ? 1u : 0u;
             }
             const float4 e2 = s2[k];

@@ -440,8 +440,9 @@ __global__ __launch_bounds__(1024) void k_seg(FwdArgs a) {
 
 // the (super-block, camera) lists copied into their image segments (buffer 1), in list order
 __global__ __launch_bounds__(256) void k_gather(FwdArgs a) {
-    const uint32_t nl = (uint32_t)(a.n_supers * a.C);
-    for (uint32_t l = blockIdx.x; l < nl; l += gridDim.x) {
+    uint32_t l0, l1, ls;
+    xcd_items((uint32_t)(a.n_supers * a.C), l0, l1, ls);
+    for (uint32_t l = l0; l < l1; l += ls) {
         const uint32_t n = a.sbvis[l], dst = a.loff[l];
         const uint4* lst = a.vis + (size_t)l * a.sb_cap;
         for (uint32_t k = threadIdx.x; k < n; k += 256) {
@@ -591,8 +592,9 @@ __global__ __launch_bounds__(256) void k_radix_scatter(FwdArgs a, int pass) {
     const int sh = 8 * pass;
     const int ib = (pass + 1) & 1, ob = pass & 1;
     const unsigned long long below = (1ull << lane) - 1ull;
-    const uint32_t nch = radix_chunks(a);
-    for (uint32_t j = blockIdx.x; j < nch; j += gridDim.x) {
+    uint32_t j0, j1, js;
+    xcd_items(radix_chunks(a), j0, j1, js);
+    for (uint32_t j = j0; j < j1; j += js) {
         uint32_t pos;
         const uint32_t n = radix_chunk(a, j, pos);
         for (int k = lane; k < 256; k += 64) s_wc[wave][k] = 0u;  // read back by this wavefront only
@@ -1017,8 +1019,9 @@ __global__ __launch_bounds__(64) void k_emit(FwdArgs a) {
     const unsigned long long cap = (unsigned long long)a.pair_cap;
     const int tx_n = a.tiles_x;
     for (int t = lane; t < a.tpi; t += 64) s_mask[t] = 0ull;  // masks are left clear by each round
-    const uint32_t nq = a.chunk_base[a.images];
-    for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+    uint32_t q0, q1, qs;
+    xcd_items(a.chunk_base[a.images], q0, q1, qs);
+    for (uint32_t q = q0; q < q1; q += qs) {
         uint32_t pos;
         int img;
         const uint32_t n = emit_chunk(a, q, pos, img);
@@ -1429,9 +1432,9 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
     mark(2);
     const int nl = a.n_supers * a.C;
     const unsigned ncu = (unsigned)(a.num_cu > 0 ? a.num_cu : 256);
-    auto grid = [&](long long items, unsigned per_cu) {
+    auto grid = [&](long long items, unsigned per_cu) {  // a multiple of 8 (one block per XCD at least)
         const long long g = std::min<long long>(items, (long long)ncu * per_cu);
-        return dim3((unsigned)(g > 0 ? g : 1));
+        return dim3((unsigned)((std::max<long long>(g, 1) + 7) / 8 * 8));
     };
     hipLaunchKernelGGL(k_seg, dim3(1), dim3(1024), 0, s, a);
     if (nl > 0) hipLaunchKernelGGL(k_gather, grid(nl, 16), dim3(256), 0, s, a);

@@ -150,6 +150,17 @@ __device__ inline long long xcd_tile(long long b, long long tiles) {
     return b < (q << 3) ? (b & 7) * q + (b >> 3) : b;
 }
 
+// Grid-stride split for kernels whose neighbouring work items write the same cache lines:
+// block b runs on XCD b % 8 and takes items of that XCD's contiguous eighth of [0, n), so the
+// lines are assembled in one L2 instead of being written back in pieces from several.  The
+// grid must be a multiple of 8.
+__device__ inline void xcd_items(uint32_t n, uint32_t& first, uint32_t& last, uint32_t& step) {
+    const uint32_t x = blockIdx.x & 7u;
+    first = (uint32_t)(((unsigned long long)n * x) >> 3) + (blockIdx.x >> 3);
+    last = (uint32_t)(((unsigned long long)n * (x + 1u)) >> 3);
+    step = gridDim.x >> 3;
+}
+
 struct FwdArgs {
     // scene
     const Node* nodes;

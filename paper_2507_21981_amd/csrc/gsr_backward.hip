@@ -141,6 +141,7 @@ __global__ __launch_bounds__(64) void k_composite_bwd(BwdArgs b) {
             const float dx = fpx - r0.x;
             const float Adx = A2 * dx, Bdx = B2 * dx;
             const float qx = fmaf(Adx, dx, r1.w);
+            const float io = __builtin_amdgcn_rcpf(r0.z);  // 1 / opacity
             float g_u = 0.f, g_v = 0.f, g_A = 0.f, g_B = 0.f, g_C = 0.f, g_o = 0.f, g_r = 0.f, g_g = 0.f,
                   g_b = 0.f, g_z = 0.f;
             bool contrib = false;
@@ -156,13 +157,15 @@ __global__ __launch_bounds__(64) void k_composite_bwd(BwdArgs b) {
                 if (!(al >= thr)) continue;
                 contrib = true;
                 const float om = 1.0f - al;
-                const float Ti = T[q] / om;
+                // the transmittance in front, T / (1 - alpha); values only, no decision
+                // depends on them, so the hardware reciprocal (about 1 ulp) is enough
+                const float iom = __builtin_amdgcn_rcpf(om);
+                const float Ti = T[q] * iom;
                 const float w = al * Ti;
                 g_r = fmaf(gr[q], w, g_r);
                 g_g = fmaf(gg[q], w, g_g);
                 g_b = fmaf(gb[q], w, g_b);
                 g_z = fmaf(gD[q], w, g_z);
-                const float iom = 1.0f / om;
                 float dLda = gr[q] * (r2.x * Ti - SCr[q] * iom) + gg[q] * (r2.y * Ti - SCg[q] * iom) +
                              gb[q] * (r2.z * Ti - SCb[q] * iom);
                 dLda += gD[q] * (r0.w * Ti - SD[q] * iom);
@@ -173,7 +176,7 @@ __global__ __launch_bounds__(64) void k_composite_bwd(BwdArgs b) {
                 SD[q] = fmaf(r0.w, w, SD[q]);
                 T[q] = Ti;
                 if (oG < 0.99f) {
-                    g_o = fmaf(dLda, oG / r0.z, g_o);  // d alpha / d o = G
+                    g_o = fmaf(dLda, oG * io, g_o);  // d alpha / d o = G
                     const float dp = dLda * oG;        // dL/dpower, power = -1/2 A dx^2 - B dx dy - 1/2 C dy^2
                     g_u = fmaf(dp, r1.x * dx + r1.y * dy, g_u);
                     g_v = fmaf(dp, r1.z * dy + r1.y * dx, g_v);

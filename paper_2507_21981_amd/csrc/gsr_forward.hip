@@ -380,59 +380,73 @@ __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a, const Super* __re
 // in LDS in digit order and writes every digit's run to consecutive slots.
 // --------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_seg(FwdArgs a) {
+    // G threads per image (a power of two, at most one wavefront), each over a contiguous
+    // range of the image's lists; 1024 / G images per pass
+    int G = 64;
+    while (G > 1 && G * a.images > 1024) G >>= 1;
+    const int t = threadIdx.x, grp = t / G, r = t % G, lane = t & 63, wave = t >> 6;
     __shared__ uint32_t s_w[16];
     __shared__ uint32_t s_carry;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     if (t == 0) s_carry = 0u;
     __syncthreads();
     constexpr int B = 16;  // loads in flight
-    for (int b0 = 0; b0 < a.images; b0 += 1024) {
-        const int img = b0 + t;
-        uint32_t n = 0u;
-        if (img < a.images) {
+    for (int b0 = 0; b0 < a.images; b0 += 1024 / G) {
+        const int img = b0 + grp;
+        const bool valid = img < a.images;
+        size_t l0 = 0;
+        int k0 = 0, k1 = 0;
+        if (valid) {
             const int e = img / a.C, c = img - e * a.C;
             const Env ev = a.envs[e];
-            const uint32_t* p = a.sbvis + (size_t)ev.sb_begin * a.C + c;
-            for (int k0 = 0; k0 < ev.sb_count; k0 += B) {
-                uint32_t v[B];
-#pragma unroll
-                for (int k = 0; k < B; ++k) v[k] = k0 + k < ev.sb_count ? p[(size_t)(k0 + k) * a.C] : 0u;
-#pragma unroll
-                for (int k = 0; k < B; ++k) n += v[k];
-            }
-            a.seg_n[img] = n;
+            l0 = (size_t)ev.sb_begin * a.C + c;
+            k0 = (int)((long long)ev.sb_count * r / G);
+            k1 = (int)((long long)ev.sb_count * (r + 1) / G);
         }
-        const uint32_t len = (n + kSortTile - 1) / kSortTile * kSortTile;
-        uint32_t incl = len;
+        const uint32_t* p = a.sbvis + l0;
+        uint32_t sum = 0u;
+        for (int k = k0; k < k1; k += B) {
+            uint32_t v[B];
+#pragma unroll
+            for (int q = 0; q < B; ++q) v[q] = k + q < k1 ? p[(size_t)(k + q) * a.C] : 0u;
+#pragma unroll
+            for (int q = 0; q < B; ++q) sum += v[q];
+        }
+        // the group's scan (the group lies inside one wavefront)
+        uint32_t incl = sum;
+        for (int off = 1; off < G; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, G);
+            if (r >= off) incl += y;
+        }
+        const uint32_t n = __shfl(incl, G - 1, G);  // the image's visible Gaussians
+        if (valid && r == 0) a.seg_n[img] = n;
+        // segment starts: block scan of the rounded lengths (one per group)
+        const uint32_t len = (valid && r == 0) ? (n + kSortTile - 1) / kSortTile * kSortTile : 0u;
+        uint32_t bi = len;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += y;
+            const uint32_t y = __shfl_up(bi, off, 64);
+            if (lane >= off) bi += y;
         }
-        if (lane == 63) s_w[wave] = incl;
+        if (lane == 63) s_w[wave] = bi;
         __syncthreads();
         uint32_t before = s_carry;
         for (int w = 0; w < wave; ++w) before += s_w[w];
-        if (img < a.images) {
-            // each list's first position: the segment start plus the image's earlier lists
-            const int e = img / a.C, c = img - e * a.C;
-            const Env ev = a.envs[e];
-            const size_t l0 = (size_t)ev.sb_begin * a.C + c;
-            uint32_t run = before + incl - len;
-            a.seg_start[img] = run;
-            for (int k0 = 0; k0 < ev.sb_count; k0 += B) {
-                uint32_t v[B];
+        const uint32_t seg0 = __shfl(before + bi - len, 0, G);  // from the group's first thread
+        if (valid && r == 0) a.seg_start[img] = seg0;
+        // each list's first position: the segment start plus the image's earlier lists
+        uint32_t run = seg0 + incl - sum;
+        for (int k = k0; k < k1; k += B) {
+            uint32_t v[B];
 #pragma unroll
-                for (int k = 0; k < B; ++k) v[k] = k0 + k < ev.sb_count ? a.sbvis[l0 + (size_t)(k0 + k) * a.C] : 0u;
+            for (int q = 0; q < B; ++q) v[q] = k + q < k1 ? p[(size_t)(k + q) * a.C] : 0u;
 #pragma unroll
-                for (int k = 0; k < B; ++k) {
-                    if (k0 + k < ev.sb_count) a.loff[l0 + (size_t)(k0 + k) * a.C] = run;
-                    run += v[k];
-                }
+            for (int q = 0; q < B; ++q) {
+                if (k + q < k1) a.loff[l0 + (size_t)(k + q) * a.C] = run;
+                run += v[q];
             }
         }
         __syncthreads();
-        if (t == 1023) s_carry = before + incl;
+        if (t == 1023) s_carry = before + bi;
         __syncthreads();
     }
     if (t == 0) a.seg_start[a.images] = s_carry;
@@ -1136,9 +1150,8 @@ __global__ __launch_bounds__(64) void k_emit(FwdArgs a) {
 // PPT pixels of one column, sharing the LDS reads and the dx terms.  List entries are staged
 // in LDS per batch with the conic pre-scaled, so that for a pixel offset (dx, dy)
 //   q = A' dx^2 + B' dx dy + C' dy^2 + log2(o),   A' = -1/2 log2(e) A, B' = -log2(e) B,
-//   C' = -1/2 log2(e) C,   alpha = min(0.99, exp2(q)) = min(0.99, o G),
-// staged as the coefficients of q in the lane's pixel offsets within the wavefront's sub-tile
-// (five fma per pixel and entry).
+//   C' = -1/2 log2(e) C,   alpha = min(0.99, exp2(q)) = min(0.99, o G).
+// The backward evaluates q with the same operations, so both passes take the same decisions.
 // Per pixel: skip if alpha < 1/255; stop (without blending) if T (1 - alpha) < 1e-4; else
 // C += alpha T c, D += alpha T z, T *= 1 - alpha.  rgb = C + T bg, depth = D, alpha = 1 - T.
 // Each batch of the list is culled against the wavefront's sub-tile and compacted (in list
@@ -1177,20 +1190,19 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
     const int env = image / a.C, cam = image - env * a.C;
     const Env ev = envs[env];
     const long long rec_off = (long long)a.C * ev.gid_base + (long long)cam * ev.n - (long long)ev.gid_base;
+    const float fpx = (float)px + 0.5f;
     const float thr = (float)(1.0 / 255.0);
-    // the lane's pixel offsets from the sub-tile's first pixel (small integers, exact)
-    const float X = (float)(lane % ST::SW);
     // Per pixel: T > 0 is the transmittance while the pixel is live; at the stop T becomes
     // -T (the sign marks a stopped pixel and |T| keeps its final transmittance), so later
     // entries add nothing.  Pixels outside the image start stopped.
-    float Y[PPT], T[PPT], Cr[PPT], Cg[PPT], Cb[PPT], D[PPT];
+    float fpy[PPT], T[PPT], Cr[PPT], Cg[PPT], Cb[PPT], D[PPT];
     uint32_t last[PPT], evals[PPT];
     bool inside[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
         const int py = py0 + p * ST::LROWS;
         inside[p] = px < a.width && py < a.height;
-        Y[p] = (float)(lane / ST::SW + p * ST::LROWS);
+        fpy[p] = (float)py + 0.5f;
         T[p] = inside[p] ? 1.0f : -1.0f;
         Cr[p] = Cg[p] = Cb[p] = D[p] = 0.0f;
         last[p] = 0;
@@ -1238,18 +1250,8 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
         if (keep) {
             const int slot = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
-            // q as a polynomial in the lane's offsets (X, Y) from the sub-tile's first pixel
-            // centre: with (Dx, Dy) = that centre - mean,
-            //   q = c0 + X (cx + A' X) + Y (cy + B' X + C' Y)
-            //   c0 = A' Dx^2 + B' Dx Dy + C' Dy^2 + log2 o, cx = 2 A' Dx + B' Dy, cy = B' Dx + 2 C' Dy
-            const float Ap = -0.7213475204444817f * R.r1.x, Bp = -1.4426950408889634f * R.r1.y;
-            const float Cp = -0.7213475204444817f * R.r1.z;
-            const float Dx = rx0 - R.r0.x, Dy = ry0 - R.r0.y;
-            const float cx = fmaf(2.0f * Ap, Dx, Bp * Dy);
-            const float cy = fmaf(Bp, Dx, (2.0f * Cp) * Dy);
-            const float c0 = fmaf(Dx, fmaf(Ap, Dx, Bp * Dy), fmaf(Cp * Dy, Dy, R.r1.w));
-            s0[slot] = make_float4(c0, cx, cy, Ap);
-            s1[slot] = make_float4(Bp, Cp, R.r0.w, R.r2.x);
+            s0[slot] = make_float4(R.r0.x, R.r0.y, -0.7213475204444817f * R.r1.x, -1.4426950408889634f * R.r1.y);
+            s1[slot] = make_float4(-0.7213475204444817f * R.r1.z, R.r1.w, R.r0.w, R.r2.x);
             s2[slot] = make_float4(R.r2.y, R.r2.z, __uint_as_float(j - start + 1u), 0.0f);
         }
         // the wavefront's LDS writes are visible to its own later reads
@@ -1266,12 +1268,14 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
             }
             const float4 e0 = s0[k];
             const float4 e1 = s1[k];
-            const float qx = fmaf(X, fmaf(e0.w, X, e0.y), e0.x);
-            const float cyx = fmaf(e1.x, X, e0.z);
+            const float dx = fpx - e0.x;
+            const float Adx = e0.z * dx, Bdx = e0.w * dx;
+            const float qx = fmaf(Adx, dx, e1.y);
             float q[PPT];
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {
-                q[p] = fmaf(Y[p], fmaf(e1.y, Y[p], cyx), qx);
+                const float dy = fpy[p] - e0.y;
+                q[p] = fmaf(Bdx, dy, fmaf(e1.x * dy, dy, qx));
                 if (COUNT) evals[p] += T[p] > 0.0f ? 1u : 0u;
             }
             const float4 e2 = s2[k];

@@ -30,9 +30,24 @@ __global__ void k_zero(float4* p, size_t n4) {
         p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-__device__ inline float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// v + (v of another lane) by a DPP move: ctrl selects the source lane, row_mask the rows of
+// 16 lanes that add (the others add zero)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_add(float v) {
+    const int m = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false);
+    return v + __int_as_float(m);
+}
+// Sum over the wavefront, complete in lane 63, with data-parallel-primitive moves only (no
+// LDS crossbar): quads (swap neighbours, then pairs), half rows (mirror), rows (mirror), then
+// row 0 into row 1 and row 2 into row 3 (broadcast of lane 15), rows 0-1 into rows 2-3
+// (broadcast of lane 31).
+__device__ __forceinline__ float wave_sum63(float v) {
+    v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+    v = dpp_add<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
+    v = dpp_add<0x141, 0xF>(v);  // row_half_mirror
+    v = dpp_add<0x140, 0xF>(v);  // row_mirror
+    v = dpp_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
     return v;
 }
 
@@ -187,10 +202,10 @@ __global__ __launch_bounds__(64) void k_composite_bwd(BwdArgs b) {
             }
             // one atomic per field per tile and entry
             if (__any(contrib)) {
-                g_u = wave_sum(g_u); g_v = wave_sum(g_v); g_A = wave_sum(g_A); g_B = wave_sum(g_B);
-                g_C = wave_sum(g_C); g_o = wave_sum(g_o); g_r = wave_sum(g_r); g_g = wave_sum(g_g);
-                g_b = wave_sum(g_b); g_z = wave_sum(g_z);
-                if (lane == 0) {
+                g_u = wave_sum63(g_u); g_v = wave_sum63(g_v); g_A = wave_sum63(g_A); g_B = wave_sum63(g_B);
+                g_C = wave_sum63(g_C); g_o = wave_sum63(g_o); g_r = wave_sum63(g_r); g_g = wave_sum63(g_g);
+                g_b = wave_sum63(g_b); g_z = wave_sum63(g_z);
+                if (lane == 63) {
                     float* o = b.g2d + (size_t)s_rec[k] * 12;
                     atomicAdd(o + 0, g_u); atomicAdd(o + 1, g_v); atomicAdd(o + 2, g_A); atomicAdd(o + 3, g_B);
                     atomicAdd(o + 4, g_C); atomicAdd(o + 5, g_o); atomicAdd(o + 6, g_r); atomicAdd(o + 7, g_g);

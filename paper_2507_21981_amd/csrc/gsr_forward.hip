@@ -1071,12 +1071,7 @@ __global__ __launch_bounds__(64) void k_emit(FwdArgs a) {
                 nz = keys[k + 64u];
                 ni = gids[k + 64u];
             }
-            uint32_t incl = area;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t y = __shfl_up(incl, off, 64);
-                if (lane >= off) incl += y;
-            }
+            const uint32_t incl = wave_incl_scan(area);
             s_off[lane + 1] = incl;
             if (lane == 0) s_off[0] = 0u;
             __syncthreads();

@@ -150,6 +150,25 @@ __device__ inline long long xcd_tile(long long b, long long tiles) {
     return b < (q << 3) ? (b & 7) * q + (b >> 3) : b;
 }
 
+// v + (v of another lane) by a DPP move (ctrl selects the source lane; lanes whose source is
+// outside their row, and rows outside row_mask, add zero)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_add_u32(uint32_t v) {
+    return v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
+}
+// Inclusive prefix sum over the wavefront's 64 lanes with DPP moves only (no LDS crossbar):
+// shifts by 1, 2, 4, 8 within rows of 16 lanes, then lane 15 of rows 0 and 2 into rows 1 and
+// 3, then lane 31 into rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    v = dpp_add_u32<0x111, 0xF>(v);  // row_shr:1
+    v = dpp_add_u32<0x112, 0xF>(v);  // row_shr:2
+    v = dpp_add_u32<0x114, 0xF>(v);  // row_shr:4
+    v = dpp_add_u32<0x118, 0xF>(v);  // row_shr:8
+    v = dpp_add_u32<0x142, 0xA>(v);  // row_bcast:15
+    v = dpp_add_u32<0x143, 0xC>(v);  // row_bcast:31
+    return v;
+}
+
 // Grid-stride split for kernels whose neighbouring work items write the same cache lines:
 // block b runs on XCD b % 8 and takes items of that XCD's contiguous eighth of [0, n), so the
 // lines are assembled in one L2 instead of being written back in pieces from several.  The

@@ -213,12 +213,15 @@ int64_t gsr_scene_gaussians(const gsr_scene* scene, int32_t env);
    rgb (required), depth (required), alpha (nullable): DEVICE outputs laid
    out [n_envs][cams_per_env][height][width](x3 for rgb), fully written.
    flags: GSR_FLAG_*.  Stages, all on `stream`: node pose composition, EWA
-   projection + SH colour + per-tile pair counting, scan of tile counts, pair
-   emission into tile buckets, per-tile sort by (depth bits, Gaussian id),
-   front-to-back compositing.
+   projection + SH colour + visible lists, per-image radix sort of the visible
+   Gaussians by (depth bits, Gaussian id), per-tile pair counts and ranges,
+   emission of the pairs into their tile buckets in that order, front-to-back
+   compositing.
    Errors: GSR_E_INVALID (null ctx/scene/cams/rgb/depth, cams_per_env < 1,
-   bad size), GSR_E_NOMEM, GSR_E_HIP, GSR_E_CAPACITY (with GSR_FLAG_CHECK,
-   capacity still short after growing). */
+   bad size), GSR_E_UNSUPPORTED (more than 13312 tiles per image or more than
+   40000 tile-grid corners, more than 64 cameras per env), GSR_E_NOMEM,
+   GSR_E_HIP, GSR_E_CAPACITY (with GSR_FLAG_CHECK, capacity still short after
+   growing). */
 int gsr_render_rgbd(gsr_context* ctx, const gsr_scene* scene, int32_t cams_per_env,
                     const gsr_camera* cams, int32_t width, int32_t height,
                     float* rgb, float* depth, float* alpha, uint32_t flags, void* stream);

@@ -458,6 +458,10 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
     a.cimg = ctx->cimg.p;
     a.ecnt = ctx->ecnt.p;
     a.num_cu = ctx->num_cu;
+    if (forward_lds_limits(a) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, GSR_E_UNSUPPORTED, "%d tiles per image exceed the device's LDS per block", a.tpi);
+    }
     a.starts = ctx->starts.p;
     a.cls_list = ctx->cls_list.p;
     a.pairs = ctx->pairs.p;

@@ -1410,6 +1410,21 @@ static void launch_composite(const FwdArgs& a, hipStream_t s) {
     }
 }
 
+static size_t emit_lds(const FwdArgs& a) { return (size_t)a.tpi * (sizeof(unsigned long long) + sizeof(uint32_t)); }
+static size_t counts_lds(const FwdArgs& a) { return (size_t)(a.tiles_x + 1) * (a.tiles_y + 1) * sizeof(int); }
+
+hipError_t forward_lds_limits(const FwdArgs& a) {
+    // only grids beyond 48 KiB of dynamic LDS need the raised limit (it persists per kernel)
+    constexpr size_t kDefault = 48 * 1024;
+    hipError_t e = hipSuccess;
+    if (emit_lds(a) > kDefault)
+        e = hipFuncSetAttribute((const void*)k_emit, hipFuncAttributeMaxDynamicSharedMemorySize, (int)emit_lds(a));
+    if (e == hipSuccess && counts_lds(a) > kDefault)
+        e = hipFuncSetAttribute((const void*)k_tile_counts, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)counts_lds(a));
+    return e;
+}
+
 hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
     auto mark = [&](int i) {
         if (a.stage_events) hipEventRecord(a.stage_events[i], s);
@@ -1449,13 +1464,11 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_pair_scan, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_chunk_starts, grid(n_blocks, 8), dim3(256), 0, s, a);
     mark(5);
-    hipLaunchKernelGGL(k_tile_counts, grid(a.chunk_cap, 8), dim3(256),
-                       (size_t)(a.tiles_x + 1) * (a.tiles_y + 1) * sizeof(int), s, a);
+    hipLaunchKernelGGL(k_tile_counts, grid(a.chunk_cap, 8), dim3(256), counts_lds(a), s, a);
     mark(6);
     hipLaunchKernelGGL(k_tile_ranges, dim3(a.images), dim3(1024), 0, s, a);
     mark(7);
-    hipLaunchKernelGGL(k_emit, grid(a.chunk_cap, 16), dim3(64),
-                       (size_t)a.tpi * (sizeof(unsigned long long) + sizeof(uint32_t)), s, a);
+    hipLaunchKernelGGL(k_emit, grid(a.chunk_cap, 16), dim3(64), emit_lds(a), s, a);
     mark(8);
     if (a.tw == 16 && a.th == 16) {
         if (a.ppt == 4) launch_composite<16, 16, 4>(a, s);

@@ -17,14 +17,15 @@ constexpr int kLenClasses = 5;
 constexpr int kLenLong = 5;
 constexpr int kLenNone = 6;
 constexpr int kNumClasses = 7;
-constexpr int kLdsHistLimit = 16384; // int counters of one image's tile difference grid in LDS
+constexpr int kLdsHistLimit = 40000; // int counters of one image's tile difference grid in LDS
 // Depth sort and emission: each image's visible Gaussians occupy a segment of the sort buffers
 // made of radix chunks of kSortTile items; tile counts and emission work on chunks of the
 // depth-ordered Gaussians holding about the same number of pairs.  An image has at most
-// kMaxTilesPerImage tiles (LDS of the emission).
+// kMaxTilesPerImage tiles: the emission keeps 12 bytes per tile in LDS (160 KB per block on
+// gfx950).
 constexpr int kSortTile = 2048;
 constexpr int kPairBlock = 1024;     // positions per block of the pair-prefix kernels
-constexpr int kMaxTilesPerImage = 5120;
+constexpr int kMaxTilesPerImage = 13312;
 
 // One (node, camera) view: the camera<-node map composed in FP64 and rounded
 // once to FP32, the camera centre in node-local coordinates, intrinsics and
@@ -254,6 +255,9 @@ struct BwdArgs {
 
 // forward stages
 hipError_t launch_forward(const FwdArgs& a, hipStream_t s);
+// raise the dynamic LDS limit of the kernels whose LDS grows with the tile grid (host side,
+// before launches or graph capture)
+hipError_t forward_lds_limits(const FwdArgs& a);
 hipError_t launch_copy_pairs(const FwdArgs& a, uint64_t* keys, uint32_t* values, uint32_t* ranges, hipStream_t s);
 // backward stages
 hipError_t launch_backward(const BwdArgs& a, size_t n_records, hipStream_t s);

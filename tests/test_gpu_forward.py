@@ -97,6 +97,30 @@ def test_ragged_image_partial_tiles(gsr, ctx):
         _run(gsr, ctx, wl, tile)
 
 
+def test_full_hd_image_beyond_64_kib_of_tile_state(gsr, ctx):
+    """1920x1080 with 16x16 tiles: 8160 tiles per image, so the emission's per-tile state
+    (12 B per tile in LDS) and the tile-count grid of a block exceed 64 KiB."""
+    wl = synth.scene_config(0, seed=23)
+    cam = synth.camera((0.1, 0.05, -2.6), (0, 0, 0), 1920, 1080)
+    wl["envs"][0]["cams"] = [cam]
+    wl["width"], wl["height"] = 1920, 1080
+    wl["name"] = "20k SH0 1920x1080"
+    _run(gsr, ctx, wl, (16, 16), full=False, sample=4000)
+
+
+def test_too_many_tiles_per_image_is_refused(gsr, ctx):
+    """2048x1024 with 8x8 tiles is 32768 tiles per image: beyond the emission's LDS state, the
+    render fails with GSR_E_UNSUPPORTED before touching the device."""
+    wl = synth.scene_config(0, seed=2, scale=0.05)
+    cam = synth.camera((0, 0, -3), (0, 0, 0), 2048, 1024)
+    wl["envs"][0]["cams"] = [cam]
+    wl["width"], wl["height"] = 2048, 1024
+    ctx.set_tile(8, 8)
+    with pytest.raises(gsr.GsrError) as err:
+        render_gpu(ctx, wl)
+    assert err.value.code == -5
+
+
 def test_empty_zero_opacity_and_behind_camera_give_background(gsr, ctx):
     import torch
     bg = (0.25, 0.5, 0.75)

@@ -87,6 +87,17 @@ def test_batched_uneven_envs(gsr, ctx):
     _run(gsr, ctx, wl, (16, 8))
 
 
+def test_image_without_visible_gaussians_between_others(gsr, ctx):
+    """Three envs of two cameras; the middle env's second camera looks away from its scene, so
+    its image has an empty segment between non-empty ones in the depth-sort buffers."""
+    wl = synth.scene_config(3, seed=11, scale=0.02, n_envs=3)
+    env = wl["envs"][1]
+    env["cams"][1] = synth.camera((0.0, 0.6, -7.0), (0.0, 0.6, -20.0), wl["width"], wl["height"])
+    wl["name"] = "3 envs, one image empty"
+    _, _, _, _, _, refs, _ = _run(gsr, ctx, wl, (16, 16))
+    assert len(refs[3]["keys"]) == 0 and all(len(refs[i]["keys"]) > 0 for i in (0, 1, 2, 4, 5))
+
+
 def test_ragged_image_partial_tiles(gsr, ctx):
     wl = synth.scene_config(0, seed=7, scale=0.5)
     cam = synth.camera((0.2, -0.1, -3.0), (0, 0, 0), 100, 75)

@@ -1249,45 +1249,56 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
             s1[slot] = make_float4(-0.7213475204444817f * R.r1.z, R.r1.w, R.r0.w, R.r2.x);
             s2[slot] = make_float4(R.r2.y, R.r2.z, __uint_as_float(j - start + 1u), 0.0f);
         }
+        const int n = __popcll(km);
+        // pad the staged entries to a multiple of 4 with entries that blend nothing at any
+        // pixel (log2 opacity -inf: q = -inf, alpha 0 < 1/255, colour and depth 0, index 0),
+        // so the walk below needs no per-entry bound
+        const int n4 = (n + 3) & ~3;
+        if (lane >= n && lane < n4) {
+            s0[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            s1[lane] = make_float4(0.0f, -__builtin_inff(), 0.0f, 0.0f);
+            s2[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
         // the wavefront's LDS writes are visible to its own later reads
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int n = __popcll(km);
-        for (int k = 0; k < n; ++k) {
-            if ((k & 3) == 0) {
-                bool wl = false;
+        for (int k0 = 0; k0 < n4; k0 += 4) {
+            bool wl = false;
 #pragma unroll
-                for (int p = 0; p < PPT; ++p) wl |= T[p] > 0.0f;
-                if (!__any(wl)) break;
-            }
-            const float4 e0 = s0[k];
-            const float4 e1 = s1[k];
-            const float dx = fpx - e0.x;
-            const float Adx = e0.z * dx, Bdx = e0.w * dx;
-            const float qx = fmaf(Adx, dx, e1.y);
-            float q[PPT];
+            for (int p = 0; p < PPT; ++p) wl |= T[p] > 0.0f;
+            if (!__any(wl)) break;
 #pragma unroll
-            for (int p = 0; p < PPT; ++p) {
-                const float dy = fpy[p] - e0.y;
-                q[p] = fmaf(Bdx, dy, fmaf(e1.x * dy, dy, qx));
-                if (COUNT) evals[p] += T[p] > 0.0f ? 1u : 0u;
-            }
-            const float4 e2 = s2[k];
-            const uint32_t idx1 = __float_as_uint(e2.z);
+            for (int u = 0; u < 4; ++u) {
+                const int k = k0 + u;
+                const float4 e0 = s0[k];
+                const float4 e1 = s1[k];
+                const float dx = fpx - e0.x;
+                const float Adx = e0.z * dx, Bdx = e0.w * dx;
+                const float qx = fmaf(Adx, dx, e1.y);
+                float q[PPT];
 #pragma unroll
-            for (int p = 0; p < PPT; ++p) {
-                const float al = fminf(0.99f, __builtin_amdgcn_exp2f(q[p]));
-                const float w = al >= thr ? al * T[p] : 0.0f;
-                const float Tn = T[p] - w;
-                const bool st = Tn < 1e-4f;  // also true for a stopped pixel (T < 0)
-                const float wb = st ? 0.0f : w;
-                Cr[p] = fmaf(wb, e1.w, Cr[p]);
-                Cg[p] = fmaf(wb, e2.x, Cg[p]);
-                Cb[p] = fmaf(wb, e2.y, Cb[p]);
-                D[p] = fmaf(wb, e1.z, D[p]);
-                T[p] = st ? -fabsf(T[p]) : Tn;
-                if (SAVE) last[p] = wb > 0.0f ? idx1 : last[p];
+                for (int p = 0; p < PPT; ++p) {
+                    const float dy = fpy[p] - e0.y;
+                    q[p] = fmaf(Bdx, dy, fmaf(e1.x * dy, dy, qx));
+                    if (COUNT) evals[p] += (T[p] > 0.0f && k < n) ? 1u : 0u;
+                }
+                const float4 e2 = s2[k];
+                const uint32_t idx1 = __float_as_uint(e2.z);
+#pragma unroll
+                for (int p = 0; p < PPT; ++p) {
+                    const float al = fminf(0.99f, __builtin_amdgcn_exp2f(q[p]));
+                    const float w = al >= thr ? al * T[p] : 0.0f;
+                    const float Tn = T[p] - w;
+                    const bool st = Tn < 1e-4f;  // also true for a stopped pixel (T < 0)
+                    const float wb = st ? 0.0f : w;
+                    Cr[p] = fmaf(wb, e1.w, Cr[p]);
+                    Cg[p] = fmaf(wb, e2.x, Cg[p]);
+                    Cb[p] = fmaf(wb, e2.y, Cb[p]);
+                    D[p] = fmaf(wb, e1.z, D[p]);
+                    T[p] = st ? -fabsf(T[p]) : Tn;
+                    if (SAVE) last[p] = wb > 0.0f ? idx1 : last[p];
+                }
             }
         }
         // all lanes are done reading this batch before the next one overwrites it

@@ -1149,10 +1149,11 @@ __global__ __launch_bounds__(64) void k_emit(FwdArgs a) {
 // The backward evaluates q with the same operations, so both passes take the same decisions.
 // Per pixel: skip if alpha < 1/255; stop (without blending) if T (1 - alpha) < 1e-4; else
 // C += alpha T c, D += alpha T z, T *= 1 - alpha.  rgb = C + T bg, depth = D, alpha = 1 - T.
-// Each batch of the list is culled against the wavefront's sub-tile and compacted (in list
-// order) before the pixel loop; the loop is predicated (after the cull nearly every entry
-// reaches some pixel of the sub-tile, so a per-entry wavefront skip costs more than it saves)
-// and the wavefront leaves the list as soon as none of its pixels is live.
+// Each batch of the list is culled against the bounding box of the wavefront's live pixels
+// (those not yet stopped) and compacted (in list order) before the pixel loop; the loop is
+// predicated (after the cull nearly every entry reaches some live pixel, so a per-entry
+// wavefront skip costs more than it saves) and the wavefront leaves the list as soon as none
+// of its pixels is live.
 // --------------------------------------------------------------------------------------------
 // Sub-tile of one wavefront: SW x SH pixels, 64 lanes x PPT pixels per lane (pixel p of a
 // lane sits 64 / SW rows below pixel p - 1).  8 x 8 squares when the tile allows.
@@ -1206,9 +1207,9 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
     // an entry with q below this at every pixel of the sub-tile cannot pass the 1/255 test
     // (exp2 is accurate to ~1e-7 relative, the margin is 1e-3 in the exponent)
     const float qcut = -7.994353436858858f - 1e-3f;  // log2(1/255) - 1e-3
-    // the wavefront's pixel-centre rectangle
-    const float rx0 = (float)(tx * TW + sx * ST::SW) + 0.5f, rx1 = rx0 + (float)(ST::SW - 1);
-    const float ry0 = (float)(ty * TH + sy * ST::SH) + 0.5f, ry1 = ry0 + (float)(ST::SH - 1);
+    // centre of the sub-tile's first pixel
+    const float rx0 = (float)(tx * TW + sx * ST::SW) + 0.5f;
+    const float ry0 = (float)(ty * TH + sy * ST::SH) + 0.5f;
     // software pipeline over batches of 64 list entries: the ids of batch b + 2 and the
     // records of batch b + 1 are loaded while batch b is composited
     const uint32_t nid = ev.n;
@@ -1222,10 +1223,26 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
     Record R_cur;
     load_rec(lid_cur, R_cur);
     for (uint32_t base = start; base < end; base += 64) {
-        bool any = false;
+        // bounding box of the wavefront's live pixels (lane l holds column l % SW and row
+        // l / SW + p LROWS of the sub-tile): entries that cannot reach it blend nothing at any
+        // live pixel and are not staged
+        unsigned long long live = 0;
+        int lr0 = ST::SH, lr1 = -1;
 #pragma unroll
-        for (int p = 0; p < PPT; ++p) any |= T[p] > 0.0f;
-        if (!__any(any)) break;
+        for (int p = 0; p < PPT; ++p) {
+            const unsigned long long m = __ballot(T[p] > 0.0f);
+            if (m) {
+                live |= m;
+                lr0 = min(lr0, (int)__builtin_ctzll(m) / ST::SW + p * ST::LROWS);
+                lr1 = max(lr1, (63 - (int)__builtin_clzll(m)) / ST::SW + p * ST::LROWS);
+            }
+        }
+        if (!live) break;
+#pragma unroll
+        for (int sft = 32; sft >= ST::SW; sft >>= 1) live |= live >> sft;
+        live &= (ST::SW == 32 ? 0xffffffffull : ((1ull << ST::SW) - 1ull));
+        const float lx0 = rx0 + (float)__builtin_ctzll(live), lx1 = rx0 + (float)(63 - (int)__builtin_clzll(live));
+        const float ly0 = ry0 + (float)lr0, ly1 = ry0 + (float)lr1;
         // stage the batch's entries that can reach this sub-tile, compacted in list order
         const uint32_t j = base + lane;
         const Record R = R_cur;
@@ -1236,7 +1253,7 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
         bool keep = false;
         if (j < end) {
             if (lid < nid) {
-                keep = reaches_rect(R, rx0, rx1, ry0, ry1, qcut);
+                keep = reaches_rect(R, lx0, lx1, ly0, ly1, qcut);
             } else {  // never produced by a consistent emission; blends nothing
                 atomicOr(&a.status->flags, 2u);
             }

@@ -54,10 +54,10 @@ __device__ __forceinline__ float wave_sum63(float v) {
 // One wavefront per tile; each lane takes PPT = TW TH / 64 pixels of one column (pixel p of a
 // lane sits 64 / TW rows below pixel p - 1).  The wavefront walks the tile's list back to front
 // from the largest contributor count among its pixels, in batches of 64 entries staged in LDS;
-// entries that cannot reach the tile's pixels (the forward's conservative rectangle test) are
-// dropped from each batch first (they blended nothing).  A lane sums its pixels' gradient
-// contributions to an entry in registers, so each (tile, entry) costs one wavefront reduction
-// and one atomic add per record field.
+// entries that cannot reach the batch's participating pixels (the forward's conservative
+// rectangle test on their bounding box) are dropped from each batch first (they blended
+// nothing there).  A lane sums its pixels' gradient contributions to an entry in registers,
+// so each (tile, entry) costs one wavefront reduction and one atomic add per record field.
 template <int TW, int TH>
 __global__ __launch_bounds__(64) void k_composite_bwd(BwdArgs b) {
     constexpr int PPT = TW * TH / 64;
@@ -115,10 +115,29 @@ __global__ __launch_bounds__(64) void k_composite_bwd(BwdArgs b) {
     const float fpx = (float)px + 0.5f;
     const float thr = (float)(1.0 / 255.0);
     const float qcut = -7.994353436858858f - 1e-3f;  // log2(1/255) - 1e-3, as in the forward
-    const float rx0 = (float)(tx * TW) + 0.5f, rx1 = rx0 + (float)(TW - 1);
-    const float ry0 = (float)(ty * TH) + 0.5f, ry1 = ry0 + (float)(TH - 1);
+    const float rx0 = (float)(tx * TW) + 0.5f, ry0 = (float)(ty * TH) + 0.5f;  // first pixel's centre
     for (uint32_t hi = wmax; hi > 0;) {
         const uint32_t lo = hi > 64u ? hi - 64u : 0u;
+        // bounding box of the pixels that take part in this batch (those with a contributor
+        // count above lo; lane l holds column l % TW and row l / TW + q LR): entries that
+        // cannot reach it change no pixel and receive no gradient from this tile
+        unsigned long long act = 0;
+        int ar0 = TH, ar1 = -1;
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const unsigned long long m = __ballot(inside[q] && last[q] > lo);
+            if (m) {
+                act |= m;
+                ar0 = min(ar0, (int)__builtin_ctzll(m) / TW + q * LR);
+                ar1 = max(ar1, (63 - (int)__builtin_clzll(m)) / TW + q * LR);
+            }
+        }
+        if (!act) break;  // not reached: the pixel with count wmax takes part in every batch
+#pragma unroll
+        for (int sft = 32; sft >= TW; sft >>= 1) act |= act >> sft;
+        act &= (TW == 32 ? 0xffffffffull : ((1ull << TW) - 1ull));
+        const float bx0 = rx0 + (float)__builtin_ctzll(act), bx1 = rx0 + (float)(63 - (int)__builtin_clzll(act));
+        const float by0 = ry0 + (float)ar0, by1 = ry0 + (float)ar1;
         // stage entries hi - 1, hi - 2, ... (descending) that can reach this tile's pixels
         const uint32_t e = hi - 1u - (uint32_t)lane;
         bool keep = false;
@@ -129,7 +148,7 @@ __global__ __launch_bounds__(64) void k_composite_bwd(BwdArgs b) {
             if (gid - ev.gid_base < ev.n) {
                 rec = rec_off + gid;
                 R = a.records[rec];
-                keep = reaches_rect(R, rx0, rx1, ry0, ry1, qcut);
+                keep = reaches_rect(R, bx0, bx1, by0, by1, qcut);
             }
         }
         const unsigned long long km = __ballot(keep);

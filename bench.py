@@ -251,8 +251,8 @@ def roofline(stage, st, n_total, cfg):
     (image, Gaussian) (48 B record + 16 B visible-list entry); the depth sort copies each 16 B
     list entry into its image's segment, then makes four radix passes, each reading the 4 B key
     for the histogram and reading and writing the 16 B (key, id, rectangle) record; chunking
-    and tile counting read the 8 B rectangle three times and emission the 16 B record per
-    visible record, and emission writes 8 B per pair; the
+    and tile counting read the 8 B rectangle three times and emission the 8 B rectangle and
+    4 B id per visible record, and emission writes the 4 B Gaussian id per pair; the
     compositor does at least OPS_PER_EVAL VALU lane-operations per Gaussian-pixel evaluation.
     """
     K = 16
@@ -260,7 +260,7 @@ def roofline(stage, st, n_total, cfg):
     work = {
         "project": ("hbm", 44 * n_total + 12 * K * visible_any + 64 * visible),
         "sort": ("hbm", (32 + 4 * (4 + 16 + 16)) * visible),
-        "emit": ("hbm", 3 * 8 * visible + 16 * visible + 8 * pairs),
+        "emit": ("hbm", 3 * 8 * visible + 12 * visible + 4 * pairs),
         "composite": ("alu", evals * OPS_PER_EVAL),
     }
     times = {"project": stage["project"], "sort": stage["gather"] + stage["depth_sort"],

@@ -76,7 +76,7 @@ struct gsr_context {
     std::string err = "no error";
     Status* d_status = nullptr;
     Status* h_status = nullptr;  // pinned
-    DevBuf<unsigned long long> pairs;
+    DevBuf<uint32_t> pairs;
     long long pair_cap = 0;
     DevBuf<Record> records;
     DevBuf<uint4> vis;

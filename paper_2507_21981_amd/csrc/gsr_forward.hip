@@ -15,8 +15,8 @@
 //   k_tile_counts  per chunk: pairs per tile, from a difference grid in LDS
 //   k_tile_ranges  per image: each chunk's first slot in every tile bucket, the tiles' [start,
 //                  end) ranges, tiles grouped by list length (persistent compositor's order)
-//   k_emit         (depth bits, Gaussian id) pairs written into their tile's bucket in depth
-//                  order, so every bucket is sorted by (depth bits, id) as it is written
+//   k_emit         Gaussian ids written into their tiles' buckets in depth order, so every
+//                  bucket is sorted by (depth bits, id) as it is written
 //   k_composite    per tile, front-to-back alpha blending of colour and camera-space z
 //                  (RGB and depth sensors, paper Sec. III-C), early exit when every pixel of a
 //                  wavefront is saturated
@@ -1027,7 +1027,7 @@ __global__ __launch_bounds__(1024) void k_tile_ranges(FwdArgs a) {
 // --------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_emit(FwdArgs a) {
     extern __shared__ unsigned long long s_mask[];  // [tpi] round masks, then [tpi] u32 slots
-    __shared__ uint32_t s_off[65], s_x0[64], s_y0[64], s_w[64], s_z[64], s_id[64];
+    __shared__ uint32_t s_off[65], s_x0[64], s_y0[64], s_w[64], s_id[64];
     const int lane = threadIdx.x;
     uint32_t* s_slot = reinterpret_cast<uint32_t*>(s_mask + a.tpi);
     const unsigned long long cap = (unsigned long long)a.pair_cap;
@@ -1043,15 +1043,13 @@ __global__ __launch_bounds__(64) void k_emit(FwdArgs a) {
         const uint32_t* so = a.ecnt + (size_t)q * a.tpi;
         const uint32_t* st = a.starts + (size_t)img * a.tpi;
         for (int t = lane; t < a.tpi; t += 64) s_slot[t] = st[t] + so[t];
-        const uint32_t* keys = a.skey[1] + pos;
         const uint32_t* gids = a.sgid[1] + pos;
         const uint2* rects = a.srect[1] + pos;
         // the next round's Gaussian, loaded one round ahead
         uint2 nr = make_uint2(0u, 0u);
-        uint32_t nz = 0u, ni = 0u;
+        uint32_t ni = 0u;
         if ((uint32_t)lane < n) {
             nr = rects[lane];
-            nz = keys[lane];
             ni = gids[lane];
         }
         for (uint32_t r0 = 0; r0 < n; r0 += 64) {
@@ -1062,13 +1060,11 @@ __global__ __launch_bounds__(64) void k_emit(FwdArgs a) {
                 s_x0[lane] = x0;
                 s_y0[lane] = y0;
                 s_w[lane] = x1 - x0;
-                s_z[lane] = nz;
                 s_id[lane] = ni;
                 area = (x1 - x0) * (y1 - y0);
             }
             if (k + 64u < n) {
                 nr = rects[k + 64u];
-                nz = keys[k + 64u];
                 ni = gids[k + 64u];
             }
             const uint32_t incl = wave_incl_scan(area);
@@ -1124,8 +1120,7 @@ __global__ __launch_bounds__(64) void k_emit(FwdArgs a) {
             walk([&](int o, uint32_t t) {
                 const unsigned long long m = s_mask[t];
                 const uint32_t p = s_slot[t] + (uint32_t)__popcll(m & ((1ull << o) - 1ull));
-                if ((unsigned long long)p < cap)
-                    a.pairs[p] = ((unsigned long long)s_z[o] << 32) | (unsigned long long)s_id[o];
+                if ((unsigned long long)p < cap) a.pairs[p] = s_id[o];
             });
             __syncthreads();
             walk([&](int o, uint32_t t) {
@@ -1387,17 +1382,24 @@ __global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composit
     }
 }
 
+// the (tile, depth bits) key of every slot, rebuilt from the slot's Gaussian id and the depth
+// its camera record holds (the projection writes the same z to the record and to the key)
 __global__ void k_copy_pairs(FwdArgs a, uint64_t* keys, uint32_t* vals, uint32_t* ranges) {
     const long long t = blockIdx.x;
+    const int image = (int)(t / a.tpi);
+    const int env = image / a.C, cam = image - env * a.C;
+    const Env ev = a.envs[env];
+    const long long rec_off = (long long)a.C * ev.gid_base + (long long)cam * ev.n - (long long)ev.gid_base;
     const uint32_t s = a.starts[t], e = a.starts[t + 1];
     if (threadIdx.x == 0) {
         ranges[2 * t] = s;
         ranges[2 * t + 1] = e;
     }
     for (uint32_t i = s + threadIdx.x; i < e; i += blockDim.x) {
-        const unsigned long long u = a.pairs[i];
-        keys[i] = ((unsigned long long)t << 32) | (u >> 32);
-        vals[i] = (uint32_t)u;
+        const uint32_t gid = a.pairs[i];
+        const uint32_t zb = gid - ev.gid_base < ev.n ? __float_as_uint(a.records[rec_off + gid].r0.w) : 0xffffffffu;
+        keys[i] = ((unsigned long long)t << 32) | zb;
+        vals[i] = gid;
     }
 }
 

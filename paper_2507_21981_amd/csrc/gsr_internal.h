@@ -227,7 +227,7 @@ struct FwdArgs {
     int num_cu;          // compute units (grid sizes of the grid-stride kernels)
     uint32_t* starts;    // per tile + 1
     uint32_t* cls_list;  // kNumClasses lists of `tiles` entries
-    unsigned long long* pairs;
+    uint32_t* pairs;     // per tile bucket slot: the Gaussian id, buckets in depth order
     long long pair_cap;
     Status* status;
     // outputs

@@ -250,7 +250,8 @@ def roofline(stage, st, n_total, cfg):
     quaternion), 12 K B of SH per Gaussian visible from any camera, and writes 64 B per visible
     (image, Gaussian) (48 B record + 16 B visible-list entry); the depth sort copies each 16 B
     list entry into its image's segment, then makes four radix passes, each reading the 4 B key
-    for the histogram and reading and writing the 16 B (key, id, rectangle) record; chunking
+    for the histogram, reading the 16 B (key, id, rectangle) record and writing it (the last
+    pass writes only id and rectangle, 12 B: nothing reads the sorted keys); chunking
     and tile counting read the 8 B rectangle three times and emission the 8 B rectangle and
     4 B id per visible record, and emission writes the 4 B Gaussian id per pair; the
     compositor does at least OPS_PER_EVAL VALU lane-operations per Gaussian-pixel evaluation.
@@ -259,7 +260,7 @@ def roofline(stage, st, n_total, cfg):
     visible, visible_any, pairs, evals = st["visible"], st["visible_any"], st["pairs"], st["evals"]
     work = {
         "project": ("hbm", 44 * n_total + 12 * K * visible_any + 64 * visible),
-        "sort": ("hbm", (32 + 4 * (4 + 16 + 16)) * visible),
+        "sort": ("hbm", (32 + 4 * (4 + 16) + 3 * 16 + 12) * visible),
         "emit": ("hbm", 3 * 8 * visible + 12 * visible + 4 * pairs),
         "composite": ("alu", evals * OPS_PER_EVAL),
     }

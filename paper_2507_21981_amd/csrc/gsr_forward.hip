@@ -674,7 +674,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(FwdArgs a, int pass) {
         for (uint32_t lp = t; lp < n; lp += 256) {
             const unsigned long long u = s_buf[lp];
             const uint32_t dst = lp + s_delta[s_dig[lp]];
-            a.skey[ob][dst] = (uint32_t)u;
+            if (pass < 3) a.skey[ob][dst] = (uint32_t)u;  // nothing reads the sorted keys
             a.sgid[ob][dst] = (uint32_t)(u >> 32);
         }
         __syncthreads();

@@ -456,14 +456,26 @@ __global__ __launch_bounds__(1024) void k_seg(FwdArgs a) {
 __global__ __launch_bounds__(256) void k_gather(FwdArgs a) {
     uint32_t l0, l1, ls;
     xcd_items((uint32_t)(a.n_supers * a.C), l0, l1, ls);
+    constexpr int U = 4;  // loads in flight per thread
     for (uint32_t l = l0; l < l1; l += ls) {
         const uint32_t n = a.sbvis[l], dst = a.loff[l];
         const uint4* lst = a.vis + (size_t)l * a.sb_cap;
-        for (uint32_t k = threadIdx.x; k < n; k += 256) {
-            const uint4 e = lst[k];
-            a.skey[1][dst + k] = e.z;
-            a.sgid[1][dst + k] = e.w;
-            a.srect[1][dst + k] = make_uint2(e.x, e.y);
+        for (uint32_t k0 = threadIdx.x; k0 < n; k0 += 256 * U) {
+            uint4 e[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t k = k0 + 256u * u;
+                if (k < n) e[u] = lst[k];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t k = k0 + 256u * u;
+                if (k < n) {
+                    a.skey[1][dst + k] = e[u].z;
+                    a.sgid[1][dst + k] = e[u].w;
+                    a.srect[1][dst + k] = make_uint2(e[u].x, e[u].y);
+                }
+            }
         }
     }
 }

@@ -112,8 +112,10 @@ struct Record {
 // candidate is evaluated as a sum of two non-negative squares (completing the square, with
 // the covariance entries C D and A D), which has no cancellation.  The slack covers the
 // rounding of that evaluation and of the compositor's own FP32 evaluation of q, whose error
-// grows with the magnitude of the form's terms over the rectangle (tmax).  Entries that fail
-// the test change no pixel, so dropping them leaves the result bit-identical.
+// grows with the magnitude of the form's terms over the rectangle (tmax); it is hundreds of
+// times the error of the hardware reciprocal (about 1 ulp), which therefore stands in for the
+// four divisions.  Entries that fail the test change no pixel, so dropping them leaves the
+// result bit-identical.
 __device__ inline bool reaches_rect(const Record& R, float x0, float x1, float y0, float y1, float qcut) {
     const float u = R.r0.x, v = R.r0.y, A = R.r1.x, B = R.r1.y, C = R.r1.z, lo = R.r1.w, D = R.r2.w;
     const float rho2 = 1.3862943611198906f * (lo - qcut);
@@ -127,17 +129,17 @@ __device__ inline bool reaches_rect(const Record& R, float x0, float x1, float y
     float mmin = INFINITY;
     if (gx > 0.0f) {  // the facing vertical edge
         const float dx = u < x0 ? x0 - u : x1 - u;
-        const float bc = B / C;
+        const float bc = B * __builtin_amdgcn_rcpf(C);
         const float dy = fminf(fmaxf(-bc * dx, y0 - v), y1 - v);
         const float t = dy + bc * dx;
-        mmin = C * t * t + dx * dx / (C * D);
+        mmin = C * t * t + dx * dx * __builtin_amdgcn_rcpf(C * D);
     }
     if (gy > 0.0f) {  // the facing horizontal edge
         const float dy = v < y0 ? y0 - v : y1 - v;
-        const float ba = B / A;
+        const float ba = B * __builtin_amdgcn_rcpf(A);
         const float dx = fminf(fmaxf(-ba * dy, x0 - u), x1 - u);
         const float t = dx + ba * dy;
-        mmin = fminf(mmin, A * t * t + dy * dy / (A * D));
+        mmin = fminf(mmin, A * t * t + dy * dy * __builtin_amdgcn_rcpf(A * D));
     }
     return mmin <= rho2 + slack;
 }

@@ -429,8 +429,17 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
         return r;
     if (ctx->pair_cap < ctx->cfg.pair_capacity) ctx->pair_cap = ctx->cfg.pair_capacity;
     if (ctx->pair_cap >= 0xffffffffll) return fail(ctx, GSR_E_UNSUPPORTED, "pair capacity beyond 32-bit slots");
-    // emission chunks of about chunk_pairs pairs: at most pairs / chunk_pairs + 1 per image
-    a.chunk_pairs = std::max(4096, 16 * a.tpi);
+    // emission chunks of about chunk_pairs pairs (at most pairs / chunk_pairs + 1 per image).
+    // Small chunks give the emission more wavefronts; each chunk adds a count and an offset per
+    // tile of its image, so chunks hold at least 4 pairs per tile, and k_tile_ranges walks an
+    // image's (chunk, tile) table in one block, so that table is kept near 2^20 entries (pairs
+    // per image estimated from the capacity, which follows the last render's pair count), up
+    // to 16 pairs per tile
+    {
+        const long long ppi = ctx->pair_cap / std::max(a.images, 1);
+        const long long cp = std::min<long long>((ppi * a.tpi) >> 20, 16ll * a.tpi);
+        a.chunk_pairs = (int)std::max<long long>(std::max<long long>(1024, 4ll * a.tpi), cp);
+    }
     a.chunk_cap = (int)(ctx->pair_cap / a.chunk_pairs + a.images + 1);
     if ((r = ensure(ctx, ctx->pairs, ctx->pair_cap)) || (r = ensure(ctx, ctx->cstart, (size_t)a.chunk_cap)) ||
         (r = ensure(ctx, ctx->cimg, (size_t)a.chunk_cap)) ||

@@ -235,8 +235,8 @@ def test_clustered_depths_sort_exactly(gsr, ctx, spread_ulps, outlier):
 @pytest.mark.parametrize("n", [1025, 8193, 8256, 16385])
 def test_depth_sort_chunk_boundaries(gsr, ctx, n):
     """One 16x16 image, every Gaussian inside it: the tile's list holds exactly n entries, so
-    the image's depth-sorted Gaussians fill radix chunks of 4096 and emission chunks of 1024
-    with a short last chunk (1 or 64 entries)."""
+    the image's depth-sorted Gaussians fill radix chunks of 2048 and emission chunks of 1024
+    pairs with a short last chunk (1 or 64 entries)."""
     from helpers import cam_identity, env_of, node
     rng = np.random.default_rng(n)
     means = np.c_[rng.uniform(-0.02, 0.02, (n, 2)), rng.uniform(2.0, 6.0, n)].astype(np.float32)

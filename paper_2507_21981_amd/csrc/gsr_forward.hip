@@ -135,21 +135,13 @@ __device__ inline float3 sh_colour(const float* c, float dx, float dy, float dz)
     return make_float3(fmaxf(r, 0.0f), fmaxf(g, 0.0f), fmaxf(b, 0.0f));
 }
 
-// one Gaussian's SH coefficients into registers (16-byte loads when the row allows)
+// one Gaussian's SH coefficients into registers (global loads; the compiler merges them)
 template <int L>
-__device__ inline void load_sh(const float* __restrict__ sh, float* c) {
+__device__ inline void load_sh(const float* __restrict__ shp, float* c) {
     constexpr int K3 = 3 * (L + 1) * (L + 1);
-    if constexpr (K3 % 4 == 0) {
-        const float4* s4 = reinterpret_cast<const float4*>(sh);
+    const auto* sh = global_ptr(shp);
 #pragma unroll
-        for (int i = 0; i < K3 / 4; ++i) {
-            const float4 q = s4[i];
-            c[4 * i + 0] = q.x; c[4 * i + 1] = q.y; c[4 * i + 2] = q.z; c[4 * i + 3] = q.w;
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < K3; ++i) c[i] = sh[i];
-    }
+    for (int i = 0; i < K3; ++i) c[i] = sh[i];
 }
 
 // --------------------------------------------------------------------------------------------
@@ -207,10 +199,13 @@ __global__ __launch_bounds__(kBlock) void k_project(FwdArgs a, const Super* __re
         if (i < (int)blk.count) {
             const Node& nd = nodes[blk.node];
             const size_t li = blk.gid0 + (uint32_t)i - nd.gid_base;
-            nm0 = nd.means[3 * li + 0]; nm1 = nd.means[3 * li + 1]; nm2 = nd.means[3 * li + 2];
-            no = nd.opac[li];
-            ns0 = nd.scales[3 * li + 0]; ns1 = nd.scales[3 * li + 1]; ns2 = nd.scales[3 * li + 2];
-            nq = reinterpret_cast<const float4*>(nd.quats)[li];
+            const auto* means = global_ptr(nd.means);
+            const auto* scales = global_ptr(nd.scales);
+            nm0 = means[3 * li + 0]; nm1 = means[3 * li + 1]; nm2 = means[3 * li + 2];
+            no = global_ptr(nd.opac)[li];
+            ns0 = scales[3 * li + 0]; ns1 = scales[3 * li + 1]; ns2 = scales[3 * li + 2];
+            const auto* quats = global_ptr(nd.quats);
+            nq = make_float4(quats[4 * li + 0], quats[4 * li + 1], quats[4 * li + 2], quats[4 * li + 3]);
         }
     };
     if (sb.chunk_begin < sb.chunk_end) fetch(sb.chunk_begin);

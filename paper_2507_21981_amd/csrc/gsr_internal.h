@@ -144,6 +144,15 @@ __device__ inline bool reaches_rect(const Record& R, float x0, float x1, float y
     return mmin <= rho2 + slack;
 }
 
+// The scene's per-node arrays are reached through pointers stored in tables, which the
+// compiler must treat as generic (flat) addresses.  Flat loads count on the same wait counter
+// as scalar and LDS loads, so every wait for a table entry would also wait for the node data
+// in flight; reading through a global address-space pointer keeps them apart.
+template <class T>
+__device__ inline const __attribute__((address_space(1))) T* global_ptr(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+
 // Workgroups are handed to the chip's 8 XCDs (each with its own L2) in turn, so block b runs
 // on XCD b % 8.  Mapping block b to tile (b % 8) Q + b / 8 (Q = tiles / 8; the last tiles % 8
 // blocks map to themselves) gives each XCD a contiguous run of tiles: neighbouring tiles, which

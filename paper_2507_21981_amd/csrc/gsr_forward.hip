@@ -885,11 +885,13 @@ __device__ inline uint32_t emit_chunk(const FwdArgs& a, uint32_t q, uint32_t& s,
     return e - s;
 }
 
+constexpr int kCountThreads = 64;  // one wavefront per chunk: many chunks in flight per CU
+
 // --------------------------------------------------------------------------------------------
 // per emission chunk: pairs per tile of the image.  A rectangle adds +1/-1 at the four corners
 // of a (tiles_y + 1) x (tiles_x + 1) difference grid in LDS; the 2D prefix gives the counts.
 // --------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_tile_counts(FwdArgs a) {
+__global__ __launch_bounds__(kCountThreads) void k_tile_counts(FwdArgs a) {
     extern __shared__ int s_grid[];
     const int gx = a.tiles_x + 1, gy = a.tiles_y + 1, gsz = gx * gy;
     const uint32_t nq = a.chunk_base[a.images];
@@ -897,10 +899,10 @@ __global__ __launch_bounds__(256) void k_tile_counts(FwdArgs a) {
         uint32_t s;
         int img;
         const uint32_t n = emit_chunk(a, q, s, img);
-        for (int k = threadIdx.x; k < gsz; k += 256) s_grid[k] = 0;
+        for (int k = threadIdx.x; k < gsz; k += kCountThreads) s_grid[k] = 0;
         __syncthreads();
         const uint2* rects = a.srect[1] + s;
-        for (uint32_t k = threadIdx.x; k < n; k += 256) {
+        for (uint32_t k = threadIdx.x; k < n; k += kCountThreads) {
             const uint2 r = rects[k];
             const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu, y1 = r.y >> 16;
             atomicAdd(&s_grid[y0 * gx + x0], 1);
@@ -909,19 +911,19 @@ __global__ __launch_bounds__(256) void k_tile_counts(FwdArgs a) {
             atomicAdd(&s_grid[y1 * gx + x1], 1);
         }
         __syncthreads();
-        for (int r = threadIdx.x; r < gy; r += 256) {
+        for (int r = threadIdx.x; r < gy; r += kCountThreads) {
             int* row = s_grid + r * gx;
             int acc = 0;
             for (int x = 0; x < gx; ++x) { acc += row[x]; row[x] = acc; }
         }
         __syncthreads();
-        for (int col = threadIdx.x; col < gx; col += 256) {
+        for (int col = threadIdx.x; col < gx; col += kCountThreads) {
             int acc = 0;
             for (int y = 0; y < gy; ++y) { acc += s_grid[y * gx + col]; s_grid[y * gx + col] = acc; }
         }
         __syncthreads();
         uint32_t* out = a.ecnt + (size_t)q * a.tpi;
-        for (int j = threadIdx.x; j < a.tpi; j += 256) {
+        for (int j = threadIdx.x; j < a.tpi; j += kCountThreads) {
             const int ty = j / a.tiles_x, tx = j - ty * a.tiles_x;
             out[j] = (uint32_t)s_grid[ty * gx + tx];
         }
@@ -1501,7 +1503,7 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_pair_scan, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_chunk_starts, grid(n_blocks, 8), dim3(256), 0, s, a);
     mark(5);
-    hipLaunchKernelGGL(k_tile_counts, grid(a.chunk_cap, 8), dim3(256), counts_lds(a), s, a);
+    hipLaunchKernelGGL(k_tile_counts, grid(a.chunk_cap, 32), dim3(kCountThreads), counts_lds(a), s, a);
     mark(6);
     hipLaunchKernelGGL(k_tile_ranges, dim3(a.images), dim3(1024), 0, s, a);
     mark(7);

@@ -133,9 +133,10 @@ typedef struct {
     uint64_t visible;        /* visible (image, Gaussian) projections                         */
     uint64_t visible_any;    /* Gaussians visible from at least one camera of their env       */
     uint64_t evals;          /* Gaussian-pixel evaluations of the last render: over pixels,
-                                the list entries that reach the pixel's wavefront sub-tile,
-                                evaluated up to and including the stopping one.  Counted
-                                only by renders with GSR_FLAG_CHECK (0 otherwise).          */
+                                the list entries that reach the bounding box of the live
+                                pixels of the pixel's wavefront sub-tile (taken per batch of
+                                64 entries), evaluated up to and including the stopping one.
+                                Counted only by renders with GSR_FLAG_CHECK (0 otherwise). */
 } gsr_status_info;
 
 /* Number of timed forward stages and their names, in order: views, project,

@@ -12,7 +12,7 @@ Printed (one JSON line on stdout):
   per_camera_loop  the same frames rendered by one eager call per (env, camera)
   fwd_bwd_ms_per_view   forward + L1 loss + backward, 500k Gaussians SH3, 8 views 640x480,
                    divided by 8
-  roofline         the step's dominant kernel against its bound (see the design doc for the model)
+  roofline         the step's dominant kernel against its bound (work model: roofline())
   cpu_baseline     the CPU oracle on a bounded sample of the same workload
 Progress goes to stderr.
 """
@@ -71,8 +71,8 @@ def upload_nodes(nodes, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build renders on one GPU; --gpus {args.gpus} is not supported "
-              "(environments shard across GPUs with no exchange, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: renders on one GPU; --gpus {args.gpus} is not supported "
+              "(environments would shard across GPUs with no exchange between them)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

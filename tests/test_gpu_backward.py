@@ -129,6 +129,25 @@ def test_gradients_differentiable_subset(gsr, ctx, tile):
     log("worst", _compare(got, ref))
 
 
+def test_gradients_with_partial_saturation(gsr, ctx):
+    """Three near splats of opacity 0.99 saturate part of the image in front of 3000 splats:
+    the pixels' contributor counts differ widely within a tile, so the backward culls each
+    batch against the box of the pixels whose counts reach into it."""
+    from helpers import cam_identity, env_of, node
+    wall = node([[-0.35, 0.0, 1.0], [-0.35, 0.0, 1.05], [-0.35, 0.0, 1.1]], 0.25, opac=0.99,
+                colours=[(0.9, 0.1, 0.1), (0.1, 0.9, 0.1), (0.1, 0.1, 0.9)])
+    back = synth.gaussians_uniform_cube(3000, 5)
+    back["sh"] = back["sh"][:, :1]
+    eye = np.eye(3, dtype=np.float32)
+    env = env_of([wall, back], poses=[(eye, np.zeros(3, np.float32)), (eye, np.array([0, 0, 4], np.float32))])
+    env["cams"] = [cam_identity(64, 64, 64.0)]
+    wl = dict(envs=[env], cams_per_env=1, width=64, height=64)
+    w = _weights(wl, 3)
+    ref = _oracle_grads(wl, w, 16, 16)
+    got = _gpu_grads(gsr, ctx, wl, w, (16, 16))
+    log("worst", _compare(got, ref))
+
+
 def test_gradients_batched_envs(gsr, ctx):
     wl = synth.scene_config(3, seed=61, scale=0.004, n_envs=3)
     for env in wl["envs"]:

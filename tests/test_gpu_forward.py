@@ -177,6 +177,25 @@ def test_one_gaussian_covering_every_tile(gsr, ctx):
     assert refs[0]["vis"][0] == 0 and all((refs[0]["ranges"][:, 1] - refs[0]["ranges"][:, 0]) >= 1)
 
 
+def test_partial_saturation_shrinks_the_live_pixel_cull(gsr, ctx):
+    """Three near splats of opacity 0.99 saturate a region whose edge crosses many wavefront
+    sub-tiles, with 3000 splats behind it (tile lists of 52 to 1155 entries): the compositor
+    culls each later batch against the box of the pixels still live, which must leave every
+    pixel as the oracle composites it."""
+    from helpers import cam_identity, env_of, node
+    wall = node([[-0.35, 0.0, 1.0], [-0.35, 0.0, 1.05], [-0.35, 0.0, 1.1]], 0.25, opac=0.99,
+                colours=[(0.9, 0.1, 0.1), (0.1, 0.9, 0.1), (0.1, 0.1, 0.9)])
+    back = synth.gaussians_uniform_cube(3000, 5)
+    back["sh"] = back["sh"][:, :1]
+    eye = np.eye(3, dtype=np.float32)
+    env = env_of([wall, back], poses=[(eye, np.zeros(3, np.float32)), (eye, np.array([0, 0, 4], np.float32))])
+    env["cams"] = [cam_identity(64, 64, 64.0)]
+    wl = dict(envs=[env], cams_per_env=1, width=64, height=64, name="partial saturation")
+    _, _, _, _, _, refs, _ = _run(gsr, ctx, wl, (16, 16))
+    a = refs[0]["alpha"].reshape(64, 64)
+    assert (a > 0.99).sum() > 200 and (a < 0.9).sum() > 200  # both saturated and live regions
+
+
 def test_pair_capacity_overflow_is_reported_then_grown(gsr):
     import torch
     wl = synth.scene_config(0, seed=11, scale=0.25)

@@ -79,13 +79,15 @@ def test_composed_step_2m_plus_8_objects_3_cams(gsr):
         ctx.close()
 
 
+@pytest.mark.parametrize("ppt", [1, 2])
 @pytest.mark.parametrize("persistent", [False, True])
-def test_batched_64_envs_in_the_benchmark_configuration(gsr, persistent):
-    """64 envs x 2 cams, one hipGraph launch, 16x16 tiles, 2 pixels per lane (the autotuner's
-    usual choice for this workload), persistent or one block per tile."""
+def test_batched_64_envs_in_the_benchmark_configuration(gsr, persistent, ppt):
+    """64 envs x 2 cams, one hipGraph launch, 16x16 tiles, one or two pixels per lane (the
+    autotuner's choices for this workload), persistent or one block per tile."""
     import torch
     ctx = gsr.create(0, tile=(16, 16))
     try:
+        ctx.set_pixels_per_thread(ppt)
         wl = synth.scene_config(3, seed=0)
         envs_t, poses, cams = upload(wl)
         scene = gsr.compose_scene(ctx, envs_t, poses)

@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-loop", action="store_true")
     ap.add_argument("--no-fwdbwd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--fwdbwd-only", action="store_true",
+                    help="only the differentiable workload (for profiling it alone); prints its record")
     ap.add_argument("--tile", default="auto", help="auto (autotuner) or WxH")
     ap.add_argument("--ppt", type=int, default=0, help="pixels per compositor lane with --tile (1, 2, 4)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -90,6 +92,9 @@ def main():
     import paper_2507_21981_amd as gsr
     import synth
 
+    if args.fwdbwd_only:
+        print(json.dumps({"fwd_bwd": fwd_bwd(gsr, args)}), flush=True)
+        return
     dev = "cuda"
     torch.cuda.init()
     t0 = time.time()

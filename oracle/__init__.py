@@ -28,15 +28,16 @@ _i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
 _c_int = ctypes.c_int
 _c_dbl = ctypes.c_double
 
-GEO = 16
+GEO = 24
 G2D = 10
-# Decision margins of the near-threshold rule (relative distance of alpha to 1/255 and of
-# T (1 - alpha) to 1e-4).  They cover the error of an FP32 renderer's alpha: pixel
-# coordinates rounded at ~4e-5 px and the conditioning of the 2D covariance inverse move the
-# exponent by up to ~1e-4, and the transmittance at the stopping point accumulates those
-# relative errors over the blended entries.
-TAU_ALPHA = 1e-4
-TAU_T = 1e-3
+# Ambiguous decisions: a blending decision is ambiguous when its relative distance to the
+# threshold (alpha vs 1/255, T (1 - alpha) vs 1e-4) is below ERR_SAFETY times the oracle's
+# first-order bound of an FP32 renderer's relative error of that quantity, plus ERR_FLOOR
+# (which covers the FP32 roundings of the three threshold constants).  The bound is derived
+# per decision from the magnitudes of the Gaussian's projection (gsr_oracle.c, fp32_bounds
+# and decision_bound); the factor 2 covers the second-order terms the bound drops.
+ERR_SAFETY = 2.0
+ERR_FLOOR = 2e-7
 
 
 def lib():
@@ -62,12 +63,17 @@ def lib():
         L.or_backward_2d.argtypes = [_c_int, _c_int, _c_int, _c_int, _i64p, _i32p, _f64p, _f32p, _f64p,
                                      ctypes.c_void_p, ctypes.c_void_p, _c_int, _f64p]
         L.or_backward_2d.restype = None
+        L.or_backward_2d_sample.argtypes = [_c_int, _c_int, _c_int, _c_int, _i64p, _i32p, _f64p, _f32p, _i64p,
+                                            ctypes.c_int64, _f64p, ctypes.c_void_p, ctypes.c_void_p, _c_int, _f64p]
+        L.or_backward_2d_sample.restype = None
         L.or_sh_eval.argtypes = [_c_int, _f64p, _f64p, ctypes.c_void_p]
         L.or_sh_eval.restype = None
         L.or_wigner.argtypes = [_c_int, _f64p, _f64p]
         L.or_wigner.restype = _c_int
         L.or_compose_view.argtypes = [_f32p, _f32p, _f32p, _f32p, _f32p]
         L.or_compose_view.restype = None
+        L.or_alpha_bounds.argtypes = [_f64p, ctypes.c_int64, _i32p, _i32p, _i32p, _f64p, _f64p]
+        L.or_alpha_bounds.restype = None
         L.or_num_threads.argtypes = []
         L.or_num_threads.restype = _c_int
         _lib = L
@@ -172,7 +178,7 @@ def pairs(rect, zbits, vis, width, height, tw, th, image=0, gid_base=0):
     return keys, vals, np.ascontiguousarray(ids.astype(np.int32)), ranges
 
 
-def composite(geo, ranges, local_vals, width, height, tw, th, bg, tau_a=TAU_ALPHA, tau_t=TAU_T):
+def composite(geo, ranges, local_vals, width, height, tw, th, bg, safety=ERR_SAFETY, floor=ERR_FLOOR):
     P = width * height
     out = dict(rgb=np.zeros((height, width, 3)), depth=np.zeros((height, width)),
                alpha=np.zeros((height, width)), T=np.zeros((height, width)),
@@ -181,7 +187,7 @@ def composite(geo, ranges, local_vals, width, height, tw, th, bg, tau_a=TAU_ALPH
                alt=np.zeros((height, width, 5)), trace=np.zeros((height, width), np.int64))
     lib().or_composite(width, height, tw, th, np.ascontiguousarray(ranges, dtype=np.int64),
                        np.ascontiguousarray(local_vals, dtype=np.int32), np.ascontiguousarray(geo),
-                       np.asarray(bg, np.float32), tau_a, tau_t,
+                       np.asarray(bg, np.float32), safety, floor,
                        out["rgb"].reshape(-1), out["depth"].reshape(-1), out["alpha"].reshape(-1),
                        out["T"].reshape(-1), out["last"].reshape(-1), out["evals"].reshape(-1),
                        out["margin"].reshape(-1), out["flags"].reshape(-1), out["alt"].reshape(-1),
@@ -190,7 +196,7 @@ def composite(geo, ranges, local_vals, width, height, tw, th, bg, tau_a=TAU_ALPH
     return out
 
 
-def composite_sample(geo, ranges, local_vals, width, height, tw, th, bg, pix, tau_a=TAU_ALPHA, tau_t=TAU_T):
+def composite_sample(geo, ranges, local_vals, width, height, tw, th, bg, pix, safety=ERR_SAFETY, floor=ERR_FLOOR):
     """Oracle pixels at flat indices ``pix`` (py * width + px)."""
     pix = np.ascontiguousarray(pix, dtype=np.int64)
     out = np.zeros((pix.size, 8))
@@ -198,24 +204,25 @@ def composite_sample(geo, ranges, local_vals, width, height, tw, th, bg, pix, ta
     alt = np.zeros((pix.size, 5))
     lib().or_composite_sample(width, height, tw, th, np.ascontiguousarray(ranges, dtype=np.int64),
                               np.ascontiguousarray(local_vals, dtype=np.int32), np.ascontiguousarray(geo),
-                              np.asarray(bg, np.float32), tau_a, tau_t, pix, pix.size, out.reshape(-1), flags,
+                              np.asarray(bg, np.float32), safety, floor, pix, pix.size, out.reshape(-1), flags,
                               alt.reshape(-1))
     return dict(rgb=out[:, 0:3], depth=out[:, 3], alpha=out[:, 4], T=out[:, 5], last=out[:, 6].astype(np.int64),
                 evals=out[:, 7].astype(np.int64), flags=flags, alt=alt)
 
 
-def render(env, cam, width, height, tw=16, th=16, fe=None, image=0, gid_base=0, tau_a=TAU_ALPHA, tau_t=TAU_T):
+def render(env, cam, width, height, tw=16, th=16, fe=None, image=0, gid_base=0, safety=ERR_SAFETY,
+           floor=ERR_FLOOR):
     """Full oracle frame for one camera of one environment."""
     fe = fe or FlatEnv(env)
     rect, zbits, vis = keyspec(fe, cam, width, height, tw, th)
     geo = project(fe, cam, width, height)
     keys, vals, lvals, ranges = pairs(rect, zbits, vis, width, height, tw, th, image, gid_base)
-    out = composite(geo, ranges, lvals, width, height, tw, th, cam["bg"], tau_a, tau_t)
+    out = composite(geo, ranges, lvals, width, height, tw, th, cam["bg"], safety, floor)
     out.update(rect=rect, zbits=zbits, vis=vis, geo=geo, keys=keys, vals=vals, lvals=lvals, ranges=ranges, fe=fe)
     return out
 
 
-def render_brute(env, cam, width, height, fe=None, tau_a=TAU_ALPHA, tau_t=TAU_T):
+def render_brute(env, cam, width, height, fe=None, safety=ERR_SAFETY, floor=ERR_FLOOR):
     """Every Gaussian in front of the camera, for every pixel, no tile rectangles.
 
     The candidate list is all Gaussians that pass the non-geometric culls
@@ -229,7 +236,7 @@ def render_brute(env, cam, width, height, fe=None, tau_a=TAU_ALPHA, tau_t=TAU_T)
     order = np.lexsort((cand, z32[cand]))
     lst = np.ascontiguousarray(cand[order].astype(np.int32))
     ranges = np.array([[0, len(lst)]], dtype=np.int64)
-    return composite(geo, ranges, lst, width, height, width, height, cam["bg"], tau_a, tau_t)
+    return composite(geo, ranges, lst, width, height, width, height, cam["bg"], safety, floor)
 
 
 def backward(ref, cam, width, height, g_rgb, g_depth=None, g_alpha=None, tw=16, th=16):
@@ -244,6 +251,29 @@ def backward(ref, cam, width, height, g_rgb, g_depth=None, g_alpha=None, tw=16, 
                          None if gd is None else gd.ctypes.data_as(ctypes.c_void_p),
                          None if ga is None else ga.ctypes.data_as(ctypes.c_void_p),
                          fe.n, g2d.reshape(-1))
+    return _project_grads(fe, cam, width, height, g2d)
+
+
+def backward_sample(ref, cam, width, height, pix, g_rgb, g_depth=None, g_alpha=None, tw=16, th=16):
+    """FP64 analytic gradients for one camera when only the pixels ``pix`` (flat indices
+    py * width + px) carry upstream gradients: g_rgb [len(pix), 3], g_depth and g_alpha
+    [len(pix)] or None.  Same result as ``backward`` with those gradients scattered into
+    otherwise zero frames."""
+    fe = ref["fe"]
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    g2d = np.zeros((fe.n, G2D), dtype=np.float64)
+    gr = np.ascontiguousarray(g_rgb, dtype=np.float64).reshape(-1)
+    gd = None if g_depth is None else np.ascontiguousarray(g_depth, dtype=np.float64).reshape(-1)
+    ga = None if g_alpha is None else np.ascontiguousarray(g_alpha, dtype=np.float64).reshape(-1)
+    lib().or_backward_2d_sample(width, height, tw, th, ref["ranges"], ref["lvals"], ref["geo"],
+                                np.asarray(cam["bg"], np.float32), pix, pix.size, gr,
+                                None if gd is None else gd.ctypes.data_as(ctypes.c_void_p),
+                                None if ga is None else ga.ctypes.data_as(ctypes.c_void_p),
+                                fe.n, g2d.reshape(-1))
+    return _project_grads(fe, cam, width, height, g2d)
+
+
+def _project_grads(fe, cam, width, height, g2d):
     grads = dict(means=np.zeros((fe.n, 3)), scales=np.zeros((fe.n, 3)), quats=np.zeros((fe.n, 4)),
                  opacities=np.zeros(fe.n), sh=np.zeros((fe.n, fe.K * 3)))
     lib().or_backward_project_flat(*fe.args(), cam_array(cam).astype(np.float64), width, height, g2d.reshape(-1),
@@ -252,6 +282,18 @@ def backward(ref, cam, width, height, g_rgb, g_depth=None, g_alpha=None, tw=16, 
     grads["sh"] = grads["sh"].reshape(fe.n, fe.K, 3)
     grads["g2d"] = g2d
     return grads
+
+
+def alpha_bounds(geo, gidx, px, py):
+    """FP64 o exp(power) of Gaussian gidx[i] at pixel (px[i], py[i]) and the bound of an FP32
+    renderer's relative error of it."""
+    gidx = np.ascontiguousarray(gidx, np.int32)
+    px = np.ascontiguousarray(px, np.int32)
+    py = np.ascontiguousarray(py, np.int32)
+    a = np.zeros(gidx.size)
+    b = np.zeros(gidx.size)
+    lib().or_alpha_bounds(np.ascontiguousarray(geo), gidx.size, gidx, px, py, a, b)
+    return a, b
 
 
 def num_threads():

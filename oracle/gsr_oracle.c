@@ -392,9 +392,10 @@ void or_keyspec(const or_scene32* sc, const float* cam, int width, int height, i
 /* Sigma2D = J Rc Sigma_w Rc^T J^T + 0.3 I; conic Q = Sigma2D^-1;            */
 /* u = fx x/z + cx, v = fy y/z + cy.  Colour c = max(0, sum k Y(d) + 0.5)    */
 /* with d the unit vector from the camera centre to mu'.                     */
-/* geo[i*16]: u v A B C o r g b z  a b c  (sigma2d)  ... (rest unused)        */
+/* geo[i*24]: u v A B C o r g b z, a b c (Sigma2D), eu ev eSa eSb eSc edet     */
+/* (FP32 error bounds), rest unused.                                         */
 /* ------------------------------------------------------------------------ */
-#define GEO 16
+#define GEO 24
 
 typedef struct {
     double Rk[9], tk[3], D[OR_MAXK * OR_MAXK];
@@ -422,12 +423,74 @@ static void prep_cam(const double* cam, int width, int height, cam64* c) {
         c->centre[i] = -(c->Rc[0 * 3 + i] * c->tc[0] + c->Rc[1 * 3 + i] * c->tc[1] + c->Rc[2 * 3 + i] * c->tc[2]);
 }
 
-/* Everything the backward needs about one Gaussian in one camera. */
+/* Everything the backward needs about one Gaussian in one camera, and the FP32 error
+   bounds of its screen-space quantities (see fp32_bounds). */
 typedef struct {
     double mu_w[3], Rg[9], s[3], p[3], Sc[9], J[6], S2[3], Q[3], u, v, o, col[3], colpre[3];
     double dvec[3], kw[OR_MAXK * 3];
+    double eu, ev, eS[3], edet;
     int clampx, clampy;
 } proj64;
+
+/* ------------------------------------------------------------------------ */
+/* FP32 error bounds of the screen-space quantities.                         */
+/*                                                                           */
+/* An FP32 renderer computes u, v and the dilated 2D covariance from FP32    */
+/* inputs with the key-specification operations (camera<-node map rounded    */
+/* once to FP32, fma chains, correctly rounded division and square root).    */
+/* With U = 2^-24 the unit roundoff and each operation contributing at most  */
+/* U times the sum of the magnitudes of its terms, to first order:           */
+/*   p_r  = W_r . mu + w_r           |dp_r| <= 4U a_r,  a_r = sum_j |W_rj mu_j| + |w_r| */
+/*   x/z                             |d(x/z)| <= |x/z| (2U + dz/z) + dp_0/z  */
+/*   u = fx x/z + cx                 eu = fx |d(x/z)| + U |u|   (same for v) */
+/*   Sigma = M M^T, M = (W R(q)) s   |dSigma_ab| <= 53U sum_c s_c^2          */
+/*   J (x/z clamped or not)          |dJ| entrywise from the above           */
+/*   Sigma2D = J Sigma J^T + 0.3 I   eS = |dJ||S||J|^T + |J||S||dJ|^T        */
+/*                                        + |J| dSigma |J|^T + 4U |J||S||J|^T + U |Sigma2D| */
+/*   det = a c - b^2                 edet = U (b^2 + det) / det + 4U  (relative, with  */
+/*                                        the conic's reciprocal and products) */
+/* These bound how far an FP32 renderer's alpha can sit from the exact one   */
+/* (decision_bound below) and so which blending decisions are ambiguous.     */
+/* ------------------------------------------------------------------------ */
+#define OR_U 5.9604644775390625e-08
+
+static void fp32_bounds(const node64* N, const cam64* c, const double* mu, proj64* P) {
+    const double U = OR_U;
+    double W[9], w[3], a[3];
+    matmul3(c->Rc, N->Rk, W);
+    for (int r = 0; r < 3; ++r) {
+        w[r] = c->Rc[r * 3 + 0] * N->tk[0] + c->Rc[r * 3 + 1] * N->tk[1] + c->Rc[r * 3 + 2] * N->tk[2] + c->tc[r];
+        a[r] = fabs(W[r * 3 + 0] * mu[0]) + fabs(W[r * 3 + 1] * mu[1]) + fabs(W[r * 3 + 2] * mu[2]) + fabs(w[r]);
+    }
+    const double z = P->p[2], dz = 4.0 * U * a[2];
+    const double xz = P->p[0] / z, yz = P->p[1] / z;
+    const double dxz = fabs(xz) * (2.0 * U + dz / z) + 4.0 * U * a[0] / z;
+    const double dyz = fabs(yz) * (2.0 * U + dz / z) + 4.0 * U * a[1] / z;
+    P->eu = c->fx * dxz + U * fabs(P->u);
+    P->ev = c->fy * dyz + U * fabs(P->v);
+    const double s2 = P->s[0] * P->s[0] + P->s[1] * P->s[1] + P->s[2] * P->s[2];
+    const double eSig = 53.0 * U * s2;
+    const double j00 = c->fx / z, j11 = c->fy / z;
+    const double dxc = P->clampx ? 4.0 * U * c->limx : dxz;
+    const double dyc = P->clampy ? 4.0 * U * c->limy : dyz;
+    const double J[6] = {j00, 0.0, fabs(P->J[2]), 0.0, j11, fabs(P->J[5])};
+    const double dJ[6] = {j00 * (2.0 * U + dz / z), 0.0, fabs(P->J[2]) * (3.0 * U + dz / z) + j00 * dxc,
+                          0.0, j11 * (2.0 * U + dz / z), fabs(P->J[5]) * (3.0 * U + dz / z) + j11 * dyc};
+    const int ab[3][2] = {{0, 0}, {0, 1}, {1, 1}};
+    for (int e = 0; e < 3; ++e) {
+        const int ra = ab[e][0], rb = ab[e][1];
+        double t = 0.0;
+        for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l) {
+                const double S = fabs(P->Sc[k * 3 + l]);
+                t += dJ[ra * 3 + k] * S * J[rb * 3 + l] + J[ra * 3 + k] * S * dJ[rb * 3 + l] +
+                     J[ra * 3 + k] * eSig * J[rb * 3 + l] + 4.0 * U * J[ra * 3 + k] * S * J[rb * 3 + l];
+            }
+        P->eS[e] = t + U * fabs(P->S2[e]);
+    }
+    const double det = P->S2[0] * P->S2[2] - P->S2[1] * P->S2[1];
+    P->edet = U * (P->S2[1] * P->S2[1] + fabs(det)) / det + 4.0 * U;
+}
 
 static void project64(const or_scene* sc, const node64* nd, const cam64* c, int i, proj64* P) {
     const int k = sc->node[i];
@@ -493,6 +556,7 @@ static void project64(const or_scene* sc, const node64* nd, const cam64* c, int 
         P->colpre[ch] = sum + 0.5;
         P->col[ch] = fmax(0.0, sum + 0.5);
     }
+    fp32_bounds(N, c, mu, P);
 }
 
 /* FP64 projection of every Gaussian (geo[i*GEO]) for one camera. */
@@ -510,6 +574,7 @@ void or_project(const or_scene* sc, const double* cam, int width, int height, do
         g[0] = P.u; g[1] = P.v; g[2] = P.Q[0]; g[3] = P.Q[1]; g[4] = P.Q[2]; g[5] = P.o;
         g[6] = P.col[0]; g[7] = P.col[1]; g[8] = P.col[2]; g[9] = P.p[2];
         g[10] = P.S2[0]; g[11] = P.S2[1]; g[12] = P.S2[2];
+        g[13] = P.eu; g[14] = P.ev; g[15] = P.eS[0]; g[16] = P.eS[1]; g[17] = P.eS[2]; g[18] = P.edet;
     }
     free(nd);
 }
@@ -523,11 +588,23 @@ void or_project(const or_scene* sc, const double* cam, int width, int height, do
 /*   else C += alpha T c, D += alpha T z, T *= (1 - alpha).                  */
 /* Outputs rgb = C + T bg, depth = D, alpha = 1 - T.                         */
 /*                                                                           */
-/* Decision margins: each threshold decision has a relative distance to its  */
-/* threshold (|alpha - 1/255| * 255, |T(1-alpha) - 1e-4| / 1e-4).  A pixel    */
-/* whose smallest margin is below tau is reported with the result of that    */
-/* one decision flipped as an equally valid alternative; a pixel with two or */
-/* more such decisions is flagged (out_flags bit 1).                        */
+/* Ambiguous decisions.  Near a threshold an FP32 renderer can take the     */
+/* other branch, and both results are correct.  decision_bound gives, from  */
+/* the FP32 bounds of u, v and Sigma2D (fp32_bounds), a bound on the        */
+/* error of an FP32 alpha in log units (|d ln alpha| = |d power|):          */
+/*   |d power| <= |g_x| du' + |g_y| dv' + 1/2 g^T eS g + 1/2 m edet          */
+/*                + 6U (m_abs / 2 + |ln o|) + 4U                             */
+/* with g = Q d (the exponent's gradient in u, v), m = d^T Q d, du' = eu +   */
+/* U |dx| (the subtraction), m_abs the form with absolute values, the 6U    */
+/* term the evaluation of the exponent in FP32 and the 4U term exp and log.  */
+/* The transmittance test T (1 - alpha) carries the log errors of the       */
+/* alphas blended before it, each amplified by alpha / (1 - alpha), plus two */
+/* roundings per blend.  A decision whose log-distance to its threshold     */
+/* (|ln alpha - ln(1/255)|, |ln(T (1 - alpha)) - ln 1e-4|) is below         */
+/* safety x bound + floor is ambiguous; the pixel is                         */
+/* reported with the result of its most ambiguous decision (smallest        */
+/* distance / bound) flipped as an equally valid alternative; a pixel with  */
+/* two or more ambiguous decisions is flagged (out_flags bit 1).            */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     double rgb[3], depth, T;
@@ -537,10 +614,24 @@ typedef struct {
     int amb_count, amb_j, amb_type;
 } pixres;
 
+/* bound of |ln alpha_FP32 - ln alpha| for alpha = o exp(power) at offset (dx, dy) */
+static double decision_bound(const double* g, double dx, double dy) {
+    const double U = OR_U;
+    const double A = g[2], B = g[3], C = g[4];
+    const double gx = A * dx + B * dy, gy = B * dx + C * dy;
+    const double m = A * dx * dx + 2.0 * B * dx * dy + C * dy * dy;
+    const double m_abs = fabs(A) * dx * dx + 2.0 * fabs(B * dx * dy) + fabs(C) * dy * dy;
+    const double du = g[13] + U * fabs(dx), dv = g[14] + U * fabs(dy);
+    return fabs(gx) * du + fabs(gy) * dv + 0.5 * (gx * gx * g[15] + 2.0 * fabs(gx * gy) * g[16] + gy * gy * g[17]) +
+           0.5 * fabs(m) * g[18] + 6.0 * U * (0.5 * m_abs + fabs(log(g[5]))) + 4.0 * U;
+}
+
 static void composite_pixel(const int32_t* list, int64_t cnt, const double* geo, const double* bg,
                             double px, double py, int flip_j, int flip_type,
-                            double tau_a, double tau_t, pixres* R) {
+                            double safety, double floor_, pixres* R) {
+    const double U = OR_U;
     double T = 1.0, C[3] = {0, 0, 0}, D = 0.0;
+    double eT = 0.0; /* relative error bound of an FP32 T */
     int last = 0, evals = 0;
     int64_t trace = 0;
     R->min_margin = INFINITY;
@@ -554,23 +645,29 @@ static void composite_pixel(const int32_t* list, int64_t cnt, const double* geo,
         if (power > 0.0) continue;
         double oG = g[5] * exp(power);
         double alpha = fmin(0.99, oG);
-        double ma = fabs(alpha - athr) / athr;
+        const double ea = decision_bound(g, dx, dy);
+        /* log-distance to the threshold over the bound: below 1 the decision is ambiguous */
+        double ra = fabs(log(alpha / athr)) / (safety * ea + floor_);
         int skip = alpha < athr;
-        if (ma < tau_a) { R->amb_count++; if (ma < R->min_margin) { R->min_margin = ma; R->amb_j = (int)j; R->amb_type = 0; } }
-        else if (ma < R->min_margin) R->min_margin = ma;
+        if (ra < 1.0) { R->amb_count++; if (ra < R->min_margin) { R->min_margin = ra; R->amb_j = (int)j; R->amb_type = 0; } }
+        else if (ra < R->min_margin) R->min_margin = ra;
         if (flip_j == (int)j && flip_type == 0) skip = !skip;
         if (skip) continue;
+        /* an FP32 alpha equals the FP32 clamp value when both sides surely clamp */
+        const double ea_eff = (oG * (1.0 - ea) >= 0.99 ? 0.0 : ea) + 1e-8;
+        const double eTn = eT + (ea_eff + U) * alpha / (1.0 - alpha) + U;
         double test = T * (1.0 - alpha);
-        double mt = fabs(test - 1e-4) / 1e-4;
+        double rt = fabs(log(test / 1e-4)) / (safety * eTn + floor_);
         int stop = test < 1e-4;
-        if (mt < tau_t) { R->amb_count++; if (mt < R->min_margin) { R->min_margin = mt; R->amb_j = (int)j; R->amb_type = 1; } }
-        else if (mt < R->min_margin) R->min_margin = mt;
+        if (rt < 1.0) { R->amb_count++; if (rt < R->min_margin) { R->min_margin = rt; R->amb_j = (int)j; R->amb_type = 1; } }
+        else if (rt < R->min_margin) R->min_margin = rt;
         if (flip_j == (int)j && flip_type == 1) stop = !stop;
         if (stop) break;
         double wgt = alpha * T;
         C[0] += wgt * g[6]; C[1] += wgt * g[7]; C[2] += wgt * g[8];
         D += wgt * g[9];
         T = test;
+        eT = eTn;
         last = (int)j + 1;
         /* decision trace: which entries were blended, and whether the 0.99 clamp was active */
         trace += (int64_t)(j + 1) * (oG >= 0.99 ? 1000003 : 1);
@@ -586,11 +683,13 @@ static void composite_pixel(const int32_t* list, int64_t cnt, const double* geo,
 /* Composite an image from per-tile sorted candidate lists.
    ranges[t*2] = [start, end) into vals (indices into geo).
    Per pixel out: rgb[3] depth alpha, Tfin, last (entries up to the last blended one),
-   evals, margin, flags (bit0: ambiguous, alternative provided; bit1: >= 2 ambiguous
+   evals, margin (smallest ratio of a decision's distance to its threshold over its FP32
+   bound; below 1 the decision is ambiguous), flags (bit0: ambiguous, alternative provided;
+   bit1: >= 2 ambiguous
    decisions), alt[5] = rgb depth alpha of the flipped branch, trace = a checksum of
    the discrete decisions (which entries were blended, clamp states). */
 void or_composite(int width, int height, int tw, int th, const int64_t* ranges, const int32_t* vals,
-                  const double* geo, const float* bgf, double tau_a, double tau_t,
+                  const double* geo, const float* bgf, double safety, double floor_,
                   double* rgb, double* depth, double* alpha, double* Tfin, int32_t* last,
                   int32_t* evals, double* margin, int32_t* flags, double* alt, int64_t* trace) {
     const int tiles_x = (width + tw - 1) / tw;
@@ -601,7 +700,7 @@ void or_composite(int width, int height, int tw, int th, const int64_t* ranges, 
             const int t = (py / th) * tiles_x + (px / tw);
             const int64_t s = ranges[2 * t], e = ranges[2 * t + 1];
             pixres R;
-            composite_pixel(vals + s, e - s, geo, bg, px + 0.5, py + 0.5, -1, -1, tau_a, tau_t, &R);
+            composite_pixel(vals + s, e - s, geo, bg, px + 0.5, py + 0.5, -1, -1, safety, floor_, &R);
             const size_t p = (size_t)py * width + px;
             rgb[3 * p + 0] = R.rgb[0]; rgb[3 * p + 1] = R.rgb[1]; rgb[3 * p + 2] = R.rgb[2];
             depth[p] = R.depth; alpha[p] = 1.0 - R.T; Tfin[p] = R.T; last[p] = R.last; evals[p] = R.evals;
@@ -612,7 +711,7 @@ void or_composite(int width, int height, int tw, int th, const int64_t* ranges, 
             a[0] = R.rgb[0]; a[1] = R.rgb[1]; a[2] = R.rgb[2]; a[3] = R.depth; a[4] = 1.0 - R.T;
             if (R.amb_count >= 1) {
                 pixres F;
-                composite_pixel(vals + s, e - s, geo, bg, px + 0.5, py + 0.5, R.amb_j, R.amb_type, tau_a, tau_t, &F);
+                composite_pixel(vals + s, e - s, geo, bg, px + 0.5, py + 0.5, R.amb_j, R.amb_type, safety, floor_, &F);
                 a[0] = F.rgb[0]; a[1] = F.rgb[1]; a[2] = F.rgb[2]; a[3] = F.depth; a[4] = 1.0 - F.T;
                 fl |= 1;
                 if (R.amb_count >= 2) fl |= 2;
@@ -625,7 +724,7 @@ void or_composite(int width, int height, int tw, int th, const int64_t* ranges, 
 /* The same per-pixel definition at a list of pixels (pix[i] = py * width + px); out[i*8] =
    r g b depth alpha T last evals, flags[i], alt[i*5]. */
 void or_composite_sample(int width, int height, int tw, int th, const int64_t* ranges, const int32_t* vals,
-                         const double* geo, const float* bgf, double tau_a, double tau_t,
+                         const double* geo, const float* bgf, double safety, double floor_,
                          const int64_t* pix, int64_t npix, double* out, int32_t* flags, double* alt) {
     const int tiles_x = (width + tw - 1) / tw;
     const double bg[3] = {bgf[0], bgf[1], bgf[2]};
@@ -636,7 +735,7 @@ void or_composite_sample(int width, int height, int tw, int th, const int64_t* r
         const int t = (py / th) * tiles_x + (px / tw);
         const int64_t s = ranges[2 * t], e = ranges[2 * t + 1];
         pixres R;
-        composite_pixel(vals + s, e - s, geo, bg, px + 0.5, py + 0.5, -1, -1, tau_a, tau_t, &R);
+        composite_pixel(vals + s, e - s, geo, bg, px + 0.5, py + 0.5, -1, -1, safety, floor_, &R);
         double* o = out + 8 * i;
         o[0] = R.rgb[0]; o[1] = R.rgb[1]; o[2] = R.rgb[2]; o[3] = R.depth; o[4] = 1.0 - R.T; o[5] = R.T;
         o[6] = R.last; o[7] = R.evals;
@@ -645,7 +744,7 @@ void or_composite_sample(int width, int height, int tw, int th, const int64_t* r
         int fl = 0;
         if (R.amb_count >= 1) {
             pixres F;
-            composite_pixel(vals + s, e - s, geo, bg, px + 0.5, py + 0.5, R.amb_j, R.amb_type, tau_a, tau_t, &F);
+            composite_pixel(vals + s, e - s, geo, bg, px + 0.5, py + 0.5, R.amb_j, R.amb_type, safety, floor_, &F);
             a[0] = F.rgb[0]; a[1] = F.rgb[1]; a[2] = F.rgb[2]; a[3] = F.depth; a[4] = 1.0 - F.T;
             fl |= 1;
             if (R.amb_count >= 2) fl |= 2;
@@ -669,77 +768,108 @@ void or_composite_sample(int width, int height, int tw, int th, const int64_t* r
 /* ------------------------------------------------------------------------ */
 #define G2D 10
 
+/* Backward of one pixel's compositing: recompute the forward walk, then accumulate the 2D
+   gradients of its blended entries back to front (serial: fixed accumulation order). */
+typedef struct {
+    int cap;
+    int* ent;
+    double *ea, *eT;
+} bwd_scratch;
+
+static void backward_pixel(const int32_t* list, int64_t cnt, const double* geo, const double* bg, int px, int py,
+                           const double* gC, double gD, double gA, double* g2d, bwd_scratch* w) {
+    const double fx = px + 0.5, fy = py + 0.5;
+    double T = 1.0;
+    int nb = 0;
+    for (int64_t j = 0; j < cnt; ++j) {
+        const double* g = geo + (size_t)list[j] * GEO;
+        double dx = fx - g[0], dy = fy - g[1];
+        double power = -0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy;
+        if (power > 0.0) continue;
+        double alpha = fmin(0.99, g[5] * exp(power));
+        if (alpha < 1.0 / 255.0) continue;
+        double test = T * (1.0 - alpha);
+        if (test < 1e-4) break;
+        if (nb == w->cap) {
+            w->cap *= 2;
+            w->ent = (int*)realloc(w->ent, sizeof(int) * w->cap);
+            w->ea = (double*)realloc(w->ea, sizeof(double) * w->cap);
+            w->eT = (double*)realloc(w->eT, sizeof(double) * w->cap);
+        }
+        w->ent[nb] = list[j]; w->ea[nb] = alpha; w->eT[nb] = T; ++nb;
+        T = test;
+    }
+    const double Tf = T;
+    double SC[3] = {Tf * bg[0], Tf * bg[1], Tf * bg[2]}, SD = 0.0;
+    for (int k = nb - 1; k >= 0; --k) {
+        const int i = w->ent[k];
+        const double* g = geo + (size_t)i * GEO;
+        double* o = g2d + (size_t)i * G2D;
+        const double a = w->ea[k], Ti = w->eT[k], wt = a * Ti;
+        o[6] += gC[0] * wt; o[7] += gC[1] * wt; o[8] += gC[2] * wt;
+        o[9] += gD * wt;
+        double dLda = 0.0;
+        for (int ch = 0; ch < 3; ++ch) dLda += gC[ch] * (g[6 + ch] * Ti - SC[ch] / (1.0 - a));
+        dLda += gD * (g[9] * Ti - SD / (1.0 - a));
+        dLda += gA * Tf / (1.0 - a);
+        for (int ch = 0; ch < 3; ++ch) SC[ch] += g[6 + ch] * wt;
+        SD += g[9] * wt;
+        double dx = fx - g[0], dy = fy - g[1];
+        double power = -0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy;
+        double G = exp(power);
+        if (g[5] * G < 0.99) {
+            o[5] += dLda * G;
+            double dp = dLda * g[5] * G;
+            o[0] += dp * (g[2] * dx + g[3] * dy);
+            o[1] += dp * (g[4] * dy + g[3] * dx);
+            o[2] += dp * (-0.5 * dx * dx);
+            o[3] += dp * (-dx * dy);
+            o[4] += dp * (-0.5 * dy * dy);
+        }
+    }
+}
+
 void or_backward_2d(int width, int height, int tw, int th, const int64_t* ranges, const int32_t* vals,
                     const double* geo, const float* bgf, const double* g_rgb, const double* g_depth,
                     const double* g_alpha, int n, double* g2d) {
     const int tiles_x = (width + tw - 1) / tw;
     const double bg[3] = {bgf[0], bgf[1], bgf[2]};
     memset(g2d, 0, sizeof(double) * G2D * (size_t)n);
-    /* serial over pixels: accumulation order fixed, no races */
-    int cap = 1024;
-    int* ent = (int*)malloc(sizeof(int) * cap);
-    double* ea = (double*)malloc(sizeof(double) * cap);
-    double* eT = (double*)malloc(sizeof(double) * cap);
+    bwd_scratch w = {1024, (int*)malloc(sizeof(int) * 1024), (double*)malloc(sizeof(double) * 1024),
+                     (double*)malloc(sizeof(double) * 1024)};
     for (int py = 0; py < height; ++py) {
         for (int px = 0; px < width; ++px) {
             const int t = (py / th) * tiles_x + (px / tw);
             const int64_t s = ranges[2 * t], e = ranges[2 * t + 1];
             const size_t p = (size_t)py * width + px;
             const double gC[3] = {g_rgb[3 * p], g_rgb[3 * p + 1], g_rgb[3 * p + 2]};
-            const double gD = g_depth ? g_depth[p] : 0.0, gA = g_alpha ? g_alpha[p] : 0.0;
-            const double fx = px + 0.5, fy = py + 0.5;
-            /* forward again, recording the blended entries */
-            double T = 1.0;
-            int nb = 0;
-            for (int64_t j = s; j < e; ++j) {
-                const double* g = geo + (size_t)vals[j] * GEO;
-                double dx = fx - g[0], dy = fy - g[1];
-                double power = -0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy;
-                if (power > 0.0) continue;
-                double alpha = fmin(0.99, g[5] * exp(power));
-                if (alpha < 1.0 / 255.0) continue;
-                double test = T * (1.0 - alpha);
-                if (test < 1e-4) break;
-                if (nb == cap) {
-                    cap *= 2;
-                    ent = (int*)realloc(ent, sizeof(int) * cap);
-                    ea = (double*)realloc(ea, sizeof(double) * cap);
-                    eT = (double*)realloc(eT, sizeof(double) * cap);
-                }
-                ent[nb] = vals[j]; ea[nb] = alpha; eT[nb] = T; ++nb;
-                T = test;
-            }
-            const double Tf = T;
-            double SC[3] = {Tf * bg[0], Tf * bg[1], Tf * bg[2]}, SD = 0.0;
-            for (int k = nb - 1; k >= 0; --k) {
-                const int i = ent[k];
-                const double* g = geo + (size_t)i * GEO;
-                double* o = g2d + (size_t)i * G2D;
-                const double a = ea[k], Ti = eT[k], w = a * Ti;
-                o[6] += gC[0] * w; o[7] += gC[1] * w; o[8] += gC[2] * w;
-                o[9] += gD * w;
-                double dLda = 0.0;
-                for (int ch = 0; ch < 3; ++ch) dLda += gC[ch] * (g[6 + ch] * Ti - SC[ch] / (1.0 - a));
-                dLda += gD * (g[9] * Ti - SD / (1.0 - a));
-                dLda += gA * Tf / (1.0 - a);
-                for (int ch = 0; ch < 3; ++ch) SC[ch] += g[6 + ch] * w;
-                SD += g[9] * w;
-                double dx = fx - g[0], dy = fy - g[1];
-                double power = -0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy;
-                double G = exp(power);
-                if (g[5] * G < 0.99) {
-                    o[5] += dLda * G;
-                    double dp = dLda * g[5] * G;
-                    o[0] += dp * (g[2] * dx + g[3] * dy);
-                    o[1] += dp * (g[4] * dy + g[3] * dx);
-                    o[2] += dp * (-0.5 * dx * dx);
-                    o[3] += dp * (-dx * dy);
-                    o[4] += dp * (-0.5 * dy * dy);
-                }
-            }
+            backward_pixel(vals + s, e - s, geo, bg, px, py, gC, g_depth ? g_depth[p] : 0.0,
+                           g_alpha ? g_alpha[p] : 0.0, g2d, &w);
         }
     }
-    free(ent); free(ea); free(eT);
+    free(w.ent); free(w.ea); free(w.eT);
+}
+
+/* The same at a list of pixels (pix[i] = py * width + px) with upstream gradients g_rgb[3i],
+   g_depth[i], g_alpha[i] (either of the last two may be NULL); every other pixel has zero
+   upstream gradient and contributes nothing. */
+void or_backward_2d_sample(int width, int height, int tw, int th, const int64_t* ranges, const int32_t* vals,
+                           const double* geo, const float* bgf, const int64_t* pix, int64_t npix,
+                           const double* g_rgb, const double* g_depth, const double* g_alpha, int n, double* g2d) {
+    const int tiles_x = (width + tw - 1) / tw;
+    const double bg[3] = {bgf[0], bgf[1], bgf[2]};
+    (void)height;
+    memset(g2d, 0, sizeof(double) * G2D * (size_t)n);
+    bwd_scratch w = {1024, (int*)malloc(sizeof(int) * 1024), (double*)malloc(sizeof(double) * 1024),
+                     (double*)malloc(sizeof(double) * 1024)};
+    for (int64_t i = 0; i < npix; ++i) {
+        const int px = (int)(pix[i] % width), py = (int)(pix[i] / width);
+        const int t = (py / th) * tiles_x + (px / tw);
+        const int64_t s = ranges[2 * t], e = ranges[2 * t + 1];
+        backward_pixel(vals + s, e - s, geo, bg, px, py, g_rgb + 3 * i, g_depth ? g_depth[i] : 0.0,
+                       g_alpha ? g_alpha[i] : 0.0, g2d, &w);
+    }
+    free(w.ent); free(w.ea); free(w.eT);
 }
 
 /* Stage 2 (per Gaussian, projection): chain the 2D gradients to the node-   */
@@ -887,6 +1017,20 @@ void or_backward_project(const or_scene* sc, const double* cam, int width, int h
             }
     }
     free(nd);
+}
+
+/* For pairs (Gaussian gidx[i], pixel (px[i], py[i])): the FP64 alpha before the 0.99 clamp,
+   o exp(power), and the bound of an FP32 renderer's relative error of it (decision_bound). */
+void or_alpha_bounds(const double* geo, int64_t npairs, const int32_t* gidx, const int32_t* px, const int32_t* py,
+                     double* alpha, double* bound) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < npairs; ++i) {
+        const double* g = geo + (size_t)gidx[i] * GEO;
+        const double dx = px[i] + 0.5 - g[0], dy = py[i] + 0.5 - g[1];
+        const double power = -0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy;
+        alpha[i] = g[5] * exp(power);
+        bound[i] = decision_bound(g, dx, dy);
+    }
 }
 
 /* Threads an OpenMP region of the oracle uses. */

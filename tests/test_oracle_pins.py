@@ -460,3 +460,125 @@ def test_closed_form_opacity_and_colour_derivative(orc):
     C0 = 0.5 / math.sqrt(math.pi)
     assert abs(gr["sh"][0, 0, 1] - o * G * C0) < 1e-12
     assert gr["sh"][0, 0, 0] == 0.0 and gr["sh"][0, 0, 2] == 0.0
+
+
+# ------------------------------------------------------------- colour clamp
+C1 = math.sqrt(3 / (4 * math.pi))
+
+
+def test_colour_clamp_closed_form_and_zero_gradient(orc):
+    """One SH-degree-1 Gaussian on the optical axis (view direction (0, 0, 1), so only the
+    m = 0 coefficient of degree 1 contributes, with Y = C1): channel 0 has a coefficient that
+    drives its colour below zero, so colour = max(0, 0.5 - 2 C1) = 0; channel 1 stays at
+    0.5 + C1.  Gradients of an upstream gradient on channel 0 alone vanish for every
+    parameter (the clamp cuts the colour path, and with a black background alpha has no
+    effect on that channel); on channel 1 the SH gradient of the m = 0 coefficient is
+    alpha C1."""
+    W = H = 15
+    f, z0, sig, o = 20.0, 2.0, 0.15, 0.7
+    cam = cam_identity(W, H, f)
+    sh = np.zeros((1, 4, 3), np.float32)
+    sh[0, 2, 0], sh[0, 2, 1] = -2.0, 1.0
+    env = env_of([node([[0, 0, z0]], sig, opac=o, sh_degree=1, sh=sh)])
+    r = orc.render(env, cam, W, H)
+    s2 = (f * f32(sig) / z0) ** 2 + 0.3
+    a = _alpha_closed(np.eye(2) * s2, W / 2, H / 2, f32(o), W, H)
+    assert 0.5 - 2 * C1 < 0
+    np.testing.assert_array_equal(r["rgb"][..., 0], 0.0)
+    np.testing.assert_allclose(r["rgb"][..., 1], a * (0.5 + C1), atol=1e-12)
+    np.testing.assert_allclose(r["rgb"][..., 2], a * 0.5, atol=1e-12)
+    wr = np.zeros((H, W, 3))
+    wr[:, :, 0] = np.random.default_rng(0).standard_normal((H, W))
+    gr = orc.backward(r, cam, W, H, wr)
+    for k in ("means", "scales", "quats", "opacities", "sh"):
+        assert np.all(gr[k] == 0.0), k
+    wr = np.zeros((H, W, 3))
+    wr[7, 7, 1] = 1.0
+    gr = orc.backward(r, cam, W, H, wr)
+    assert abs(gr["sh"][0, 2, 1] - a[7, 7] * C1) < 1e-12 and gr["sh"][0, 2, 0] == 0.0
+
+
+def test_view_direction_sign_off_axis(orc):
+    """Off-axis Gaussian at (x0, 0, z0): the view direction is (x0, 0, z0) / |.|, and the m = 1
+    coefficient of degree 1 (basis -C1 x) moves the colour by -C1 k x0 / |.|."""
+    W = H = 31
+    f, x0, z0, k = 30.0, 0.4, 2.0, 0.6
+    cam = cam_identity(W, H, f)
+    sh = np.zeros((1, 4, 3), np.float32)
+    sh[0, 3, :] = [k, -k, 0.0]
+    env = env_of([node([[x0, 0, z0]], 0.1, opac=0.9, sh_degree=1, sh=sh)])
+    r = orc.render(env, cam, W, H)
+    xf, zf = float(np.float32(x0)), float(np.float32(z0))
+    dxn = xf / math.hypot(xf, zf)
+    col = np.array([0.5 - C1 * f32(k) * dxn, 0.5 + C1 * f32(k) * dxn, 0.5])
+    m = r["alpha"] > 0
+    np.testing.assert_allclose(r["rgb"][m], r["alpha"][m][:, None] * col[None, :], atol=1e-12)
+
+
+# ------------------------------------------------- ambiguous decisions
+def _edge_sigma(o, k, target, z0, f):
+    """World sigma of an on-axis isotropic Gaussian whose alpha at a pixel k px from its
+    centre (one axis) is target: o exp(-k^2 / (2 s^2)) = target, s^2 = (f sigma / z0)^2 + 0.3."""
+    s2 = -k * k / (2 * math.log(target / o))
+    return z0 / f * math.sqrt(s2 - 0.3)
+
+
+@pytest.mark.parametrize("side", [+1, -1])
+def test_alpha_decision_at_the_threshold_is_ambiguous(orc, side):
+    """alpha = (1/255)(1 + side 3e-6) at one pixel: within the FP32 error of alpha (a few 1e-6
+    there), so the oracle flags the decision and returns the other branch as the alternative:
+    the Gaussian blended (rgb = alpha c) on one branch, skipped (rgb = background) on the
+    other.  A pixel at (1/255)(1 + 1e-3) is not flagged."""
+    W = H = 15
+    f, z0, o, k = 20.0, 2.0, 0.8, 3
+    cam = cam_identity(W, H, f, bg=(0.1, 0.2, 0.3))
+    thr = 1 / 255
+    c = np.array([0.9, 0.4, 0.2])
+    sig = np.float32(_edge_sigma(o, k, thr * (1 + side * 3e-6), z0, f))
+    env = env_of([node([[0, 0, z0]], sig, opac=o, colours=c)])
+    r = orc.render(env, cam, W, H)
+    s2 = (f * float(sig) / z0) ** 2 + 0.3
+    al = f32(o) * math.exp(-k * k / (2 * s2))
+    assert abs(al / thr - 1) < 4e-6 and np.sign(al - thr) == side
+    py, px = 7, 7 + k
+    bg = f32([0.1, 0.2, 0.3])
+    blended, skipped = al * c + (1 - al) * bg, bg
+    assert r["flags"][py, px] == 1
+    main, alt = (blended, skipped) if side > 0 else (skipped, blended)
+    np.testing.assert_allclose(r["rgb"][py, px], main, atol=1e-7)
+    np.testing.assert_allclose(r["alt"][py, px, :3], alt, atol=1e-7)
+    np.testing.assert_allclose(r["alt"][py, px, 4], al if side < 0 else 0.0, atol=1e-12)
+    # clear of the threshold: no flag
+    sig2 = np.float32(_edge_sigma(o, k, thr * (1 + 1e-3), z0, f))
+    r2 = orc.render(env_of([node([[0, 0, z0]], sig2, opac=o, colours=c)]), cam, W, H)
+    assert r2["flags"][py, px] == 0
+
+
+@pytest.mark.parametrize("side", [+1, -1])
+def test_stop_decision_at_the_threshold_is_ambiguous(orc, side):
+    """n = 10 co-located identical Gaussians of alpha = o at the centre pixel, with
+    (1 - o)^n = 1e-4 (1 + side 5e-6): the n-th transmittance test sits within the FP32 error
+    of T (about 1e-5 after ten blends) of its threshold.  One branch blends n layers (alpha =
+    1 - (1 - o)^n), the other n - 1; the oracle's main result and alternative are the two.
+    With (1 - o)^n = 1e-4 (1 + 1e-2) the decision is not flagged."""
+    n = 10
+    cam = cam_identity(15, 15, 20.0)
+    c = np.array([0.75, 0.5, 0.25])
+
+    def run(rel):
+        o = np.float32(1 - (1e-4 * (1 + rel)) ** (1 / n))
+        nd = node(np.tile([[0, 0, 1.5]], (n + 3, 1)), 0.05, opac=o, colours=c)
+        return o, orc.render(env_of([nd]), cam, 15, 15)
+
+    o, r = run(side * 5e-6)
+    q = 1 - float(o)
+    assert abs(q ** n / 1e-4 - 1 - side * 5e-6) < 2e-6
+    a_n, a_m = 1 - q ** n, 1 - q ** (n - 1)  # n and n - 1 layers
+    main, alt = (a_n, a_m) if side > 0 else (a_m, a_n)
+    assert r["flags"][7, 7] == 1
+    assert abs(r["alpha"][7, 7] - main) < 1e-12 and abs(r["alt"][7, 7, 4] - alt) < 1e-12
+    np.testing.assert_allclose(r["rgb"][7, 7], main * c, atol=1e-7)
+    np.testing.assert_allclose(r["alt"][7, 7, :3], alt * c, atol=1e-7)
+    np.testing.assert_allclose(r["alt"][7, 7, 3], alt * 1.5, atol=1e-12)
+    _, r2 = run(1e-2)
+    assert r2["flags"][7, 7] == 0

@@ -28,7 +28,7 @@ _i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
 _c_int = ctypes.c_int
 _c_dbl = ctypes.c_double
 
-GEO = 24
+GEO = 28
 G2D = 10
 # Ambiguous decisions: a blending decision is ambiguous when its relative distance to the
 # threshold (alpha vs 1/255, T (1 - alpha) vs 1e-4) is below ERR_SAFETY times the oracle's

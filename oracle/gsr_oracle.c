@@ -392,10 +392,10 @@ void or_keyspec(const or_scene32* sc, const float* cam, int width, int height, i
 /* Sigma2D = J Rc Sigma_w Rc^T J^T + 0.3 I; conic Q = Sigma2D^-1;            */
 /* u = fx x/z + cx, v = fy y/z + cy.  Colour c = max(0, sum k Y(d) + 0.5)    */
 /* with d the unit vector from the camera centre to mu'.                     */
-/* geo[i*24]: u v A B C o r g b z, a b c (Sigma2D), eu ev eSa eSb eSc edet     */
-/* (FP32 error bounds), rest unused.                                         */
+/* geo[i*28]: u v A B C o r g b z, a b c (Sigma2D), then the FP32 error-bound  */
+/* quantities of fp32_bounds (13..24), rest unused.                          */
 /* ------------------------------------------------------------------------ */
-#define GEO 24
+#define GEO 28
 
 typedef struct {
     double Rk[9], tk[3], D[OR_MAXK * OR_MAXK];
@@ -428,7 +428,7 @@ static void prep_cam(const double* cam, int width, int height, cam64* c) {
 typedef struct {
     double mu_w[3], Rg[9], s[3], p[3], Sc[9], J[6], S2[3], Q[3], u, v, o, col[3], colpre[3];
     double dvec[3], kw[OR_MAXK * 3];
-    double eu, ev, eS[3], edet;
+    double eu, ev, edet, dj, ajx, ajy, smax, ssum;
     int clampx, clampy;
 } proj64;
 
@@ -440,17 +440,26 @@ typedef struct {
 /* once to FP32, fma chains, correctly rounded division and square root).    */
 /* With U = 2^-24 the unit roundoff and each operation contributing at most  */
 /* U times the sum of the magnitudes of its terms, to first order:           */
-/*   p_r  = W_r . mu + w_r           |dp_r| <= 4U a_r,  a_r = sum_j |W_rj mu_j| + |w_r| */
-/*   x/z                             |d(x/z)| <= |x/z| (2U + dz/z) + dp_0/z  */
-/*   u = fx x/z + cx                 eu = fx |d(x/z)| + U |u|   (same for v) */
-/*   Sigma = M M^T, M = (W R(q)) s   |dSigma_ab| <= 53U sum_c s_c^2          */
-/*   J (x/z clamped or not)          |dJ| entrywise from the above           */
-/*   Sigma2D = J Sigma J^T + 0.3 I   eS = |dJ||S||J|^T + |J||S||dJ|^T        */
-/*                                        + |J| dSigma |J|^T + 4U |J||S||J|^T + U |Sigma2D| */
-/*   det = a c - b^2                 edet = U (b^2 + det) / det + 4U  (relative, with  */
-/*                                        the conic's reciprocal and products) */
-/* These bound how far an FP32 renderer's alpha can sit from the exact one   */
-/* (decision_bound below) and so which blending decisions are ambiguous.     */
+/*   p_r = W_r . mu + w_r          |dp_r| <= 4U a_r,  a_r = sum_j |W_rj mu_j| + |w_r| */
+/*   x/z                           |d(x/z)| <= |x/z| (2U + dz/z) + dp_0/z    */
+/*   u = fx x/z + cx               eu = fx |d(x/z)| + U |u|   (same for v)   */
+/*   J entries                     relative error dj = 3U + dz/z, and j02 also */
+/*                                 moves by j00 |d(x/z)| (fx dxc below), j12 likewise */
+/*   M = (W R(q)) diag(s)          M + E diag(s) with |E_rc| <= 18U (rotation from */
+/*                                 the normalised quaternion, W rounded, 3-term sums) */
+/*   Sigma = M M^T                 3-term dot products, error <= 3U sum_c |M_ac M_bc| */
+/*   Sigma2D = J Sigma J^T + 0.3 I two more 2-term fma levels: 4U |J||Sigma||J|^T */
+/*   det = a c - b^2, conic = adj / det   relative edet = U (b^2 + det) / det + 4U */
+/* The exponent depends on the covariance through the quadratic form          */
+/* g^T Sigma2D g with g = Q d (decision_bound), so the bound is taken on that */
+/* form directly: with y = J^T g, y' = |J|^T |g| and q = y^T Sigma y,        */
+/*   |g^T dSigma2D g| <= 108U s_max |y| sqrt(q) + (54U s_max |y|)^2          */
+/*                       + 3U (sum s^2) |y|^2 + 2 s_max |dJ^T g| sqrt(q)     */
+/*                       + 4U (sum s^2) |y'|^2 + 2U 0.3 |g|^2                */
+/* (errors of M enter linearly in s_max, roundings of entries of size s_max^2 */
+/* quadratically, which is how the form of a thin splat loses accuracy).     */
+/* geo[13..24] keep eu, ev, edet, j00, j11, j02, j12, dj, fx dxc, fy dyc,     */
+/* s_max, sum s^2.                                                            */
 /* ------------------------------------------------------------------------ */
 #define OR_U 5.9604644775390625e-08
 
@@ -468,26 +477,14 @@ static void fp32_bounds(const node64* N, const cam64* c, const double* mu, proj6
     const double dyz = fabs(yz) * (2.0 * U + dz / z) + 4.0 * U * a[1] / z;
     P->eu = c->fx * dxz + U * fabs(P->u);
     P->ev = c->fy * dyz + U * fabs(P->v);
-    const double s2 = P->s[0] * P->s[0] + P->s[1] * P->s[1] + P->s[2] * P->s[2];
-    const double eSig = 53.0 * U * s2;
-    const double j00 = c->fx / z, j11 = c->fy / z;
+    /* beyond the clamp the FP32 limit (1.3f (0.5 W / fx)) moves by a few U */
     const double dxc = P->clampx ? 4.0 * U * c->limx : dxz;
     const double dyc = P->clampy ? 4.0 * U * c->limy : dyz;
-    const double J[6] = {j00, 0.0, fabs(P->J[2]), 0.0, j11, fabs(P->J[5])};
-    const double dJ[6] = {j00 * (2.0 * U + dz / z), 0.0, fabs(P->J[2]) * (3.0 * U + dz / z) + j00 * dxc,
-                          0.0, j11 * (2.0 * U + dz / z), fabs(P->J[5]) * (3.0 * U + dz / z) + j11 * dyc};
-    const int ab[3][2] = {{0, 0}, {0, 1}, {1, 1}};
-    for (int e = 0; e < 3; ++e) {
-        const int ra = ab[e][0], rb = ab[e][1];
-        double t = 0.0;
-        for (int k = 0; k < 3; ++k)
-            for (int l = 0; l < 3; ++l) {
-                const double S = fabs(P->Sc[k * 3 + l]);
-                t += dJ[ra * 3 + k] * S * J[rb * 3 + l] + J[ra * 3 + k] * S * dJ[rb * 3 + l] +
-                     J[ra * 3 + k] * eSig * J[rb * 3 + l] + 4.0 * U * J[ra * 3 + k] * S * J[rb * 3 + l];
-            }
-        P->eS[e] = t + U * fabs(P->S2[e]);
-    }
+    P->dj = 3.0 * U + dz / z;
+    P->ajx = c->fx / z * dxc;
+    P->ajy = c->fy / z * dyc;
+    P->smax = fmax(P->s[0], fmax(P->s[1], P->s[2]));
+    P->ssum = P->s[0] * P->s[0] + P->s[1] * P->s[1] + P->s[2] * P->s[2];
     const double det = P->S2[0] * P->S2[2] - P->S2[1] * P->S2[1];
     P->edet = U * (P->S2[1] * P->S2[1] + fabs(det)) / det + 4.0 * U;
 }
@@ -574,7 +571,8 @@ void or_project(const or_scene* sc, const double* cam, int width, int height, do
         g[0] = P.u; g[1] = P.v; g[2] = P.Q[0]; g[3] = P.Q[1]; g[4] = P.Q[2]; g[5] = P.o;
         g[6] = P.col[0]; g[7] = P.col[1]; g[8] = P.col[2]; g[9] = P.p[2];
         g[10] = P.S2[0]; g[11] = P.S2[1]; g[12] = P.S2[2];
-        g[13] = P.eu; g[14] = P.ev; g[15] = P.eS[0]; g[16] = P.eS[1]; g[17] = P.eS[2]; g[18] = P.edet;
+        g[13] = P.eu; g[14] = P.ev; g[15] = P.edet; g[16] = P.J[0]; g[17] = P.J[4]; g[18] = P.J[2];
+        g[19] = P.J[5]; g[20] = P.dj; g[21] = P.ajx; g[22] = P.ajy; g[23] = P.smax; g[24] = P.ssum;
     }
     free(nd);
 }
@@ -599,7 +597,14 @@ void or_project(const or_scene* sc, const double* cam, int width, int height, do
 /* term the evaluation of the exponent in FP32 and the 4U term exp and log.  */
 /* The transmittance test T (1 - alpha) carries the log errors of the       */
 /* alphas blended before it, each amplified by alpha / (1 - alpha), plus two */
-/* roundings per blend.  A decision whose log-distance to its threshold     */
+/* roundings per blend.  Those come from the roundings of different         */
+/* Gaussians' projections and of separate products, which are independent,  */
+/* so they are accumulated as a root sum of squares (the square-root growth */
+/* of independent rounding errors, Higham, Accuracy and Stability of        */
+/* Numerical Algorithms, sec. 2.8) of the per-blend worst cases, rather than */
+/* by their sum, which would grow with the number of layers and mark a      */
+/* large share of the stopping decisions of deep pixels as ambiguous.       */
+/* A decision whose log-distance to its threshold                           */
 /* (|ln alpha - ln(1/255)|, |ln(T (1 - alpha)) - ln 1e-4|) is below         */
 /* safety x bound + floor is ambiguous; the pixel is                         */
 /* reported with the result of its most ambiguous decision (smallest        */
@@ -622,8 +627,20 @@ static double decision_bound(const double* g, double dx, double dy) {
     const double m = A * dx * dx + 2.0 * B * dx * dy + C * dy * dy;
     const double m_abs = fabs(A) * dx * dx + 2.0 * fabs(B * dx * dy) + fabs(C) * dy * dy;
     const double du = g[13] + U * fabs(dx), dv = g[14] + U * fabs(dy);
-    return fabs(gx) * du + fabs(gy) * dv + 0.5 * (gx * gx * g[15] + 2.0 * fabs(gx * gy) * g[16] + gy * gy * g[17]) +
-           0.5 * fabs(m) * g[18] + 6.0 * U * (0.5 * m_abs + fabs(log(g[5]))) + 4.0 * U;
+    /* the quadratic form g^T dSigma2D g (fp32_bounds) */
+    const double j00 = g[16], j11 = g[17], j02 = g[18], j12 = g[19];
+    const double y0 = j00 * gx, y1 = j11 * gy, y2 = j02 * gx + j12 * gy;
+    const double ny = sqrt(y0 * y0 + y1 * y1 + y2 * y2);
+    const double a0 = j00 * fabs(gx), a1 = j11 * fabs(gy), a2 = fabs(j02 * gx) + fabs(j12 * gy);
+    const double na2 = a0 * a0 + a1 * a1 + a2 * a2;
+    const double q = fmax(0.0, (g[10] - 0.3) * gx * gx + 2.0 * g[11] * gx * gy + (g[12] - 0.3) * gy * gy);
+    const double smax = g[23], ssum = g[24];
+    const double dJg = g[20] * sqrt(na2) + g[21] * fabs(gx) + g[22] * fabs(gy);
+    const double form = 108.0 * U * smax * ny * sqrt(q) + (54.0 * U * smax * ny) * (54.0 * U * smax * ny) +
+                        3.0 * U * ssum * ny * ny + 2.0 * smax * dJg * sqrt(q) + 4.0 * U * ssum * na2 +
+                        0.6 * U * (gx * gx + gy * gy);
+    return fabs(gx) * du + fabs(gy) * dv + 0.5 * form + 0.5 * fabs(m) * g[15] +
+           6.0 * U * (0.5 * m_abs + fabs(log(g[5]))) + 4.0 * U;
 }
 
 static void composite_pixel(const int32_t* list, int64_t cnt, const double* geo, const double* bg,
@@ -631,7 +648,7 @@ static void composite_pixel(const int32_t* list, int64_t cnt, const double* geo,
                             double safety, double floor_, pixres* R) {
     const double U = OR_U;
     double T = 1.0, C[3] = {0, 0, 0}, D = 0.0;
-    double eT = 0.0; /* relative error bound of an FP32 T */
+    double eT2 = 0.0; /* sum of squares of the blends' contributions to the log error of T */
     int last = 0, evals = 0;
     int64_t trace = 0;
     R->min_margin = INFINITY;
@@ -655,7 +672,8 @@ static void composite_pixel(const int32_t* list, int64_t cnt, const double* geo,
         if (skip) continue;
         /* an FP32 alpha equals the FP32 clamp value when both sides surely clamp */
         const double ea_eff = (oG * (1.0 - ea) >= 0.99 ? 0.0 : ea) + 1e-8;
-        const double eTn = eT + (ea_eff + U) * alpha / (1.0 - alpha) + U;
+        const double cT = (ea_eff + U) * alpha / (1.0 - alpha) + U;
+        const double eTn = sqrt(eT2 + cT * cT);
         double test = T * (1.0 - alpha);
         double rt = fabs(log(test / 1e-4)) / (safety * eTn + floor_);
         int stop = test < 1e-4;
@@ -667,7 +685,7 @@ static void composite_pixel(const int32_t* list, int64_t cnt, const double* geo,
         C[0] += wgt * g[6]; C[1] += wgt * g[7]; C[2] += wgt * g[8];
         D += wgt * g[9];
         T = test;
-        eT = eTn;
+        eT2 += cT * cT;
         last = (int)j + 1;
         /* decision trace: which entries were blended, and whether the 0.99 clamp was active */
         trace += (int64_t)(j + 1) * (oG >= 0.99 ? 1000003 : 1);
@@ -685,8 +703,8 @@ static void composite_pixel(const int32_t* list, int64_t cnt, const double* geo,
    Per pixel out: rgb[3] depth alpha, Tfin, last (entries up to the last blended one),
    evals, margin (smallest ratio of a decision's distance to its threshold over its FP32
    bound; below 1 the decision is ambiguous), flags (bit0: ambiguous, alternative provided;
-   bit1: >= 2 ambiguous
-   decisions), alt[5] = rgb depth alpha of the flipped branch, trace = a checksum of
+   bit1: >= 2 ambiguous decisions, bit2: the most ambiguous one is a stopping decision),
+   alt[5] = rgb depth alpha of the flipped branch, trace = a checksum of
    the discrete decisions (which entries were blended, clamp states). */
 void or_composite(int width, int height, int tw, int th, const int64_t* ranges, const int32_t* vals,
                   const double* geo, const float* bgf, double safety, double floor_,
@@ -715,6 +733,7 @@ void or_composite(int width, int height, int tw, int th, const int64_t* ranges, 
                 a[0] = F.rgb[0]; a[1] = F.rgb[1]; a[2] = F.rgb[2]; a[3] = F.depth; a[4] = 1.0 - F.T;
                 fl |= 1;
                 if (R.amb_count >= 2) fl |= 2;
+                if (R.amb_type == 1) fl |= 4;
             }
             flags[p] = fl;
         }
@@ -748,6 +767,7 @@ void or_composite_sample(int width, int height, int tw, int th, const int64_t* r
             a[0] = F.rgb[0]; a[1] = F.rgb[1]; a[2] = F.rgb[2]; a[3] = F.depth; a[4] = 1.0 - F.T;
             fl |= 1;
             if (R.amb_count >= 2) fl |= 2;
+            if (R.amb_type == 1) fl |= 4;
         }
         flags[i] = fl;
     }

@@ -173,6 +173,13 @@ def _scenes():
     near = _sh0(synth.gaussians_uniform_cube(1200, 7, half=1.5, log_scale=(-2.8, 0.5)))
     out["near camera, J clamp"] = (dict(nodes=[near], poses=[(eye, z3)], cams=[]),
                                    synth.camera((0.0, 0.0, -1.6), (0, 0, 0), 64, 48, znear=0.05), (8, 8), 0.01)
+    # a background whose means lie 300 m from the world origin, seen from 1.5 m: the camera map
+    # cancels terms of 300 m in FP32 (a posed node's offset would cancel in the FP64 composition)
+    far = _sh0(synth.gaussians_uniform_cube(1500, 9, half=0.5, log_scale=(-4.0, 0.4)))
+    off = np.array([300.0, -40.0, 250.0], np.float32)
+    far["means"] = (far["means"] + off).astype(np.float32)
+    cam = synth.camera(off + np.array([0.2, 0.3, -1.5]), off, 64, 64, znear=0.05)
+    out["means 300 m from the origin"] = (dict(nodes=[far], poses=[(eye, z3)], cams=[]), cam, (16, 16), None)
     # a dense stack of opaque splats: most pixels stop on the transmittance test
     g = np.random.default_rng(8)
     dense = _sh0(synth.gaussians_uniform_cube(900, 8, half=0.25, log_scale=(-2.3, 0.3)))
@@ -211,6 +218,8 @@ def test_fp32_alpha_within_the_oracle_bound(orc, name):
 @pytest.mark.parametrize("name", list(SCENES))
 def test_fp32_renderer_matches_oracle_under_the_ambiguity_rule(orc, name):
     env, cam, (tw, th), cap = SCENES[name]
+    if cap is None:
+        pytest.skip("FP32 pixel values of this scene carry errors beyond 1e-4 (300 m coordinates): bound pin only")
     W, H = cam["width"], cam["height"]
     r = orc.render(env, cam, W, H, tw, th)
     pr = emulate_projection(r["fe"], cam, W, H)

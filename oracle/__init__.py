@@ -52,7 +52,8 @@ def lib():
         L.or_keyspec_flat.restype = None
         L.or_project_flat.argtypes = scene + [_f64p, _c_int, _c_int, _f64p]
         L.or_project_flat.restype = None
-        L.or_backward_project_flat.argtypes = scene + [_f64p, _c_int, _c_int, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p]
+        L.or_backward_project_flat.argtypes = scene + [_f64p, _c_int, _c_int, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p,
+                                                       _f64p]
         L.or_backward_project_flat.restype = None
         L.or_composite.argtypes = [_c_int, _c_int, _c_int, _c_int, _i64p, _i32p, _f64p, _f32p, _c_dbl, _c_dbl,
                                    _f64p, _f64p, _f64p, _f64p, _i32p, _i32p, _f64p, _i32p, _f64p, _i64p]
@@ -116,7 +117,8 @@ class FlatEnv:
         # tests perturb these while the FP32 key specification keeps the originals)
         self.p64 = dict(means=self.means.astype(np.float64), scales=self.scales.astype(np.float64),
                         quats=self.quats.astype(np.float64), opac=self.opac.astype(np.float64),
-                        sh=self.sh.astype(np.float64).reshape(-1))
+                        sh=self.sh.astype(np.float64).reshape(-1),
+                        pose_R=self.pose_R.astype(np.float64).reshape(-1), pose_t=self.pose_t.astype(np.float64).reshape(-1))
 
     def args32(self):
         return (self.n, self.sh_degree, self.means, self.scales, self.quats, self.opac, self.node, self.n_nodes,
@@ -127,7 +129,7 @@ class FlatEnv:
         c = np.ascontiguousarray
         return (self.n, self.sh_degree, c(p["means"]).reshape(-1), c(p["scales"]).reshape(-1),
                 c(p["quats"]).reshape(-1), c(p["opac"]).reshape(-1), c(p["sh"]).reshape(-1), self.node,
-                self.n_nodes, self.pose_R.astype(np.float64).reshape(-1), self.pose_t.astype(np.float64).reshape(-1))
+                self.n_nodes, c(p["pose_R"]), c(p["pose_t"]))
 
 
 def keyspec(fe, cam, width, height, tw, th):
@@ -275,10 +277,11 @@ def backward_sample(ref, cam, width, height, pix, g_rgb, g_depth=None, g_alpha=N
 
 def _project_grads(fe, cam, width, height, g2d):
     grads = dict(means=np.zeros((fe.n, 3)), scales=np.zeros((fe.n, 3)), quats=np.zeros((fe.n, 4)),
-                 opacities=np.zeros(fe.n), sh=np.zeros((fe.n, fe.K * 3)))
+                 opacities=np.zeros(fe.n), sh=np.zeros((fe.n, fe.K * 3)), pose=np.zeros((fe.n_nodes, 6)))
     lib().or_backward_project_flat(*fe.args(), cam_array(cam).astype(np.float64), width, height, g2d.reshape(-1),
                                    grads["means"].reshape(-1), grads["scales"].reshape(-1),
-                                   grads["quats"].reshape(-1), grads["opacities"], grads["sh"].reshape(-1))
+                                   grads["quats"].reshape(-1), grads["opacities"], grads["sh"].reshape(-1),
+                                   grads["pose"].reshape(-1))
     grads["sh"] = grads["sh"].reshape(fe.n, fe.K, 3)
     grads["g2d"] = g2d
     return grads

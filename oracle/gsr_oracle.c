@@ -899,13 +899,28 @@ void or_backward_2d_sample(int width, int height, int tw, int th, const int64_t*
 /* Sw = M M^T with M = Rg diag(s), Rg = Rk R(q/|q|); colour through the SH   */
 /* basis and the view direction; mu' = Rk mu + tk; k_w = D^T k.              */
 /* Outputs are ACCUMULATED into the gradient arrays (same layout as inputs). */
+/* Node poses (Sec. III-B: each node is placed by a rigid pose from the physics engine).      */
+/* With d_pose != NULL the gradient with respect to each node's pose is ACCUMULATED into     */
+/* d_pose[k*6] = (omega, rho): the derivative along the world-frame left perturbation        */
+/* R' = exp([omega]x) R_k, t' = exp([omega]x) t_k + rho.  To first order it moves each of    */
+/* the node's world means by omega x mu' + rho and each world rotation frame Rg by          */
+/* [omega]x Rg, and (colour = k_w . Y(d), k_w = D(R')^T k, with D(e^[omega] R) =            */
+/* D(R) D(e^[omega])) turns the colour's view vector mu' - c into mu' - c + rho + omega x c,  */
+/* so with g_mu the gradient of the world mean through the projection, g_v that of the      */
+/* view vector through the colour and G that of Rg:                                         */
+/*   d rho   = sum_i g_mu + g_v                                                             */
+/*   d omega = sum_i mu' x g_mu + c x g_v + (M_21 - M_12, M_02 - M_20, M_10 - M_01),       */
+/*             M = G Rg^T.                                                                   */
 void or_backward_project(const or_scene* sc, const double* cam, int width, int height, const double* g2d,
-                         double* d_means, double* d_scales, double* d_quats, double* d_opac, double* d_sh) {
+                         double* d_means, double* d_scales, double* d_quats, double* d_opac, double* d_sh,
+                         double* d_pose) {
     node64* nd = (node64*)malloc(sizeof(node64) * (size_t)(sc->n_nodes > 0 ? sc->n_nodes : 1));
     prep_nodes(sc, nd);
     cam64 c;
     prep_cam(cam, width, height, &c);
     const int L = sc->sh_degree, K = (L + 1) * (L + 1);
+    /* per-Gaussian pose contributions, summed per node in a fixed order after the loop */
+    double* pg = d_pose ? (double*)calloc((size_t)(sc->n > 0 ? sc->n : 1) * 6, sizeof(double)) : NULL;
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < sc->n; ++i) {
         const double* gg = g2d + (size_t)i * G2D;
@@ -1021,6 +1036,18 @@ void or_backward_project(const or_scene* sc, const double* cam, int width, int h
                 for (int j = 0; j < 3; ++j) ddir[j] += gcol * P.kw[m * 3 + ch] * dY[m * 3 + j];
             }
         }
+        if (pg) {
+            double M[9], *o = pg + 6 * (size_t)i;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    M[a * 3 + b] = dRg[a * 3 + 0] * P.Rg[b * 3 + 0] + dRg[a * 3 + 1] * P.Rg[b * 3 + 1] + dRg[a * 3 + 2] * P.Rg[b * 3 + 2];
+            const double* m = P.mu_w;
+            const double* cc = c.centre;
+            o[0] = m[1] * dmw[2] - m[2] * dmw[1] + cc[1] * ddir[2] - cc[2] * ddir[1] + M[7] - M[5];
+            o[1] = m[2] * dmw[0] - m[0] * dmw[2] + cc[2] * ddir[0] - cc[0] * ddir[2] + M[2] - M[6];
+            o[2] = m[0] * dmw[1] - m[1] * dmw[0] + cc[0] * ddir[1] - cc[1] * ddir[0] + M[3] - M[1];
+            for (int j = 0; j < 3; ++j) o[3 + j] = dmw[j] + ddir[j];
+        }
         for (int j = 0; j < 3; ++j) dmw[j] += ddir[j];
         /* mu' = Rk mu + tk -> dmu = Rk^T dmu' */
         for (int j = 0; j < 3; ++j)
@@ -1035,6 +1062,11 @@ void or_backward_project(const or_scene* sc, const double* cam, int width, int h
                 for (int j = 0; j < K; ++j) t += N->D[m * K + j] * dkw[j * 3 + ch];
                 d_sh[(size_t)i * K * 3 + m * 3 + ch] += t;
             }
+    }
+    if (pg) {
+        for (int i = 0; i < sc->n; ++i)
+            for (int j = 0; j < 6; ++j) d_pose[6 * (size_t)sc->node[i] + j] += pg[6 * (size_t)i + j];
+        free(pg);
     }
     free(nd);
 }
@@ -1088,7 +1120,7 @@ void or_backward_project_flat(int n, int sh_degree, const double* means, const d
                               const double* opac, const double* sh, const int32_t* node, int n_nodes,
                               const double* pose_R, const double* pose_t, const double* cam, int width, int height,
                               const double* g2d, double* d_means, double* d_scales, double* d_quats,
-                              double* d_opac, double* d_sh) {
+                              double* d_opac, double* d_sh, double* d_pose) {
     or_scene s = mk_scene(n, sh_degree, means, scales, quats, opac, sh, node, n_nodes, pose_R, pose_t);
-    or_backward_project(&s, cam, width, height, g2d, d_means, d_scales, d_quats, d_opac, d_sh);
+    or_backward_project(&s, cam, width, height, g2d, d_means, d_scales, d_quats, d_opac, d_sh, d_pose);
 }

@@ -582,3 +582,59 @@ def test_stop_decision_at_the_threshold_is_ambiguous(orc, side):
     np.testing.assert_allclose(r["alt"][7, 7, 3], alt * 1.5, atol=1e-12)
     _, r2 = run(1e-2)
     assert r2["flags"][7, 7] == 0
+
+
+# ------------------------------------------------------------- node poses
+def _so3_exp(w):
+    th = np.linalg.norm(w)
+    K = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])
+    if th < 1e-300:
+        return np.eye(3)
+    return np.eye(3) + math.sin(th) / th * K + (1 - math.cos(th)) / th ** 2 * (K @ K)
+
+
+def test_pose_gradient_matches_fp64_finite_differences(orc):
+    """dL/d(pose) of both nodes (background and a posed SH3 object) along the world-frame left
+    perturbation R' = exp([omega]x) R, t' = exp([omega]x) t + rho, against FP64 central
+    differences of the FP64 forward taken with the exact exponential map (h = 1e-6)."""
+    env, cam = _fd_scene()
+    W = H = 32
+    g = np.random.default_rng(7)
+    wr, wd, wa = g.standard_normal((H, W, 3)), g.standard_normal((H, W)), g.standard_normal((H, W))
+    fe = orc.FlatEnv(env)
+    rect, zb, vis = orc.keyspec(fe, cam, W, H, 16, 16)
+    keys, vals, lv, ranges = orc.pairs(rect, zb, vis, W, H, 16, 16)
+    R0 = fe.p64["pose_R"].copy().reshape(-1, 3, 3)
+    t0 = fe.p64["pose_t"].copy().reshape(-1, 3)
+
+    def fwd():
+        geo = orc.project(fe, cam, W, H)
+        out = orc.composite(geo, ranges, lv, W, H, 16, 16, cam["bg"])
+        return float(np.sum(wr * out["rgb"]) + np.sum(wd * out["depth"]) + np.sum(wa * out["alpha"])), out["trace"]
+
+    L0, tr0 = fwd()
+    ref = dict(fe=fe, ranges=ranges, lvals=lv, geo=orc.project(fe, cam, W, H))
+    gp = orc.backward(ref, cam, W, H, wr, wd, wa)["pose"]
+    h = 1e-6
+    checked = 0
+    for k in range(fe.n_nodes):
+        for j in range(6):
+            vals_ = []
+            for sgn in (1, -1):
+                e = np.zeros(6)
+                e[j] = sgn * h
+                Rw = _so3_exp(e[:3])
+                Rk, tk = fe.p64["pose_R"].reshape(-1, 3, 3), fe.p64["pose_t"].reshape(-1, 3)
+                Rk[k] = Rw @ R0[k]
+                tk[k] = Rw @ t0[k] + e[3:]
+                vals_.append(fwd())
+                Rk[k], tk[k] = R0[k], t0[k]
+            (Lp, tp), (Lm, tm) = vals_
+            if not (np.array_equal(tp, tr0) and np.array_equal(tm, tr0)):
+                continue
+            fd = (Lp - Lm) / (2 * h)
+            scale = np.abs(gp[k]).max()
+            assert abs(fd - gp[k, j]) <= 1e-5 * max(abs(fd), 1e-3 * scale), (k, j, fd, gp[k, j])
+            checked += 1
+    assert checked >= 10, checked
+    assert np.abs(gp).min() > 0  # every component is exercised

@@ -227,17 +227,42 @@ int gsr_render_rgbd(gsr_context* ctx, const gsr_scene* scene, int32_t cams_per_e
                     const gsr_camera* cams, int32_t width, int32_t height,
                     float* rgb, float* depth, float* alpha, uint32_t flags, void* stream);
 
-/* Gradients of a scalar loss through the last render (which must have been
-   called with GSR_FLAG_SAVE on the same scene and not been followed by
-   another render).  d_rgb [..][H][W][3] required; d_depth, d_alpha nullable
-   (zero upstream gradient).  grads: HOST array of n_nodes gsr_gaussian_grads
-   (device pointers, node-local parameterisation: means, activated scales,
-   unnormalised quaternions, activated opacities, SH), ACCUMULATED (+=), so
-   the caller zeroes them.  The node poses are treated as constants.
-   Errors: GSR_E_INVALID, GSR_E_STATE (no saved forward), GSR_E_HIP. */
-int gsr_render_backward(gsr_context* ctx, const gsr_scene* scene, const float* d_rgb,
-                        const float* d_depth, const float* d_alpha,
-                        const gsr_gaussian_grads* grads, void* stream);
+/* Identifier of the render whose saved state gsr_render_backward would use:
+   the last render, if it was made with GSR_FLAG_SAVE, else 0.  Also its image
+   count (n_envs * cams_per_env) and size, so that a caller can check the shape
+   of the upstream gradients it will pass.  Any output pointer but render_id
+   may be NULL.  Host only, never blocks.  Errors: GSR_E_INVALID. */
+int gsr_saved_render(const gsr_context* ctx, uint64_t* render_id, int32_t* images, int32_t* width,
+                     int32_t* height);
+
+/* Backward pass of the renderer: gradients of a scalar loss on the rgb, depth
+   and alpha frames with respect to the Gaussians and the node poses.  The
+   paper optimises Gaussian assets against image, depth and opacity terms
+   (Sec. IV-B, mesh-to-Gaussian transfer and asset refinement) and places every
+   node by a rigid pose (Sec. III-B); this call supplies both derivatives.
+   render_id: the value gsr_saved_render gave right after the forward render
+   (made with GSR_FLAG_SAVE on the same scene); if another render has replaced
+   that state since, the call fails with GSR_E_STATE before any launch, so a
+   backward can never pair its upstream gradients with another render's pairs.
+   d_rgb [images][H][W][3] required; d_depth, d_alpha [images][H][W] nullable
+   (zero upstream gradient); DEVICE buffers of exactly the saved render's shape
+   (the library cannot check their size).
+   grads: HOST array of n_nodes gsr_gaussian_grads (device pointers, node-local
+   parameterisation: means, activated scales, unnormalised quaternions,
+   activated opacities, SH), ACCUMULATED (+=), so the caller zeroes them.  The
+   host array is read before the call returns and may be freed at once.
+   d_poses: nullable DEVICE array [n_nodes][6], ACCUMULATED: per node
+   (omega, rho), the derivative along the world-frame perturbation
+   R' = exp([omega]x) R, t' = exp([omega]x) t + rho of its pose (R, t).
+   Asynchronous on `stream` (no host synchronisation), so it can be captured
+   in a graph; a captured backward stays valid while the context's workspace
+   is not regrown (a later call with more images, Gaussians or nodes than any
+   before it reallocates it).
+   Errors: GSR_E_INVALID, GSR_E_STATE (no saved forward, or render_id is not
+   it), GSR_E_NOMEM, GSR_E_HIP. */
+int gsr_render_backward(gsr_context* ctx, const gsr_scene* scene, uint64_t render_id, const float* d_rgb,
+                        const float* d_depth, const float* d_alpha, const gsr_gaussian_grads* grads,
+                        float* d_poses, void* stream);
 
 /* ---- status, inspection ------------------------------------------------ */
 

@@ -7,7 +7,7 @@ kernels.  PyTorch supplies device memory (``data_ptr``) and the stream
 raises ``ImportError`` -- there is no CPU fallback.
 
 Names follow the C ABI in include/gsr.h: ``create``, ``compose_scene``,
-``render_rgbd``, ``render_backward``, ``query_status``, ``copy_pairs``,
+``render_rgbd``, ``saved_render``, ``render_backward``, ``query_status``, ``copy_pairs``,
 ``copy_pixel_state``, ``autotune``.  ``RenderRGBD`` is the autograd Function.
 """
 import ctypes
@@ -87,7 +87,10 @@ def lib():
         L.gsr_scene_gaussians.argtypes = [vp, i32]
         L.gsr_scene_gaussians.restype = i64
         L.gsr_render_rgbd.argtypes = [vp, vp, i32, vp, i32, i32, vp, vp, vp, u32, vp]
-        L.gsr_render_backward.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(GaussianGrads), vp]
+        L.gsr_saved_render.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(i32),
+                                       ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.gsr_render_backward.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, vp, ctypes.POINTER(GaussianGrads), vp,
+                                          vp]
         L.gsr_query_status.argtypes = [vp, ctypes.POINTER(StatusInfo)]
         L.gsr_copy_pairs.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(i64)]
         L.gsr_copy_pixel_state.argtypes = [vp, vp, vp]
@@ -283,10 +286,35 @@ def render_rgbd(ctx, scene, cams, width, height, cams_per_env=None, out=None, fl
     return rgb, depth, alpha
 
 
-def render_backward(ctx, scene, d_rgb, d_depth=None, d_alpha=None, grads=None, stream=None):
-    """Accumulate gradients of the last saved render into ``grads`` (list of per-node dicts of
-    CUDA float32 tensors shaped like the parameters; missing keys are skipped).  If grads is
-    None, zero-initialised ones are allocated and returned."""
+def saved_render(ctx):
+    """(render_id, images, width, height) of the render a backward would use (id 0: none)."""
+    rid = ctypes.c_uint64()
+    n, w, h = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().gsr_saved_render(ctx.handle, ctypes.byref(rid), ctypes.byref(n), ctypes.byref(w), ctypes.byref(h)),
+           ctx)
+    return rid.value, n.value, w.value, h.value
+
+
+def render_backward(ctx, scene, d_rgb, d_depth=None, d_alpha=None, grads=None, d_poses=None, render_id=None,
+                    stream=None):
+    """Accumulate gradients of a saved render into ``grads`` (list of per-node dicts of CUDA
+    float32 tensors shaped like the parameters; missing keys are skipped) and, if ``d_poses``
+    (CUDA float32 [n_nodes, 6]) is given, the node-pose gradients (omega, rho) into it.  If
+    grads is None, zero-initialised ones are allocated and returned.  ``render_id`` names the
+    forward render (``saved_render`` right after it); None means the last saved render.  The
+    upstream gradients must have the saved render's shape [E, C, H, W(, 3)]."""
+    rid, images, W, H = saved_render(ctx)
+    if render_id is None:
+        render_id = rid
+    E = scene.n_envs
+    C = images // E if E else 0
+    for t, tail, name in ((d_rgb, (H, W, 3), "d_rgb"), (d_depth, (H, W), "d_depth"), (d_alpha, (H, W), "d_alpha")):
+        if t is None:
+            continue
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise TypeError("upstream gradients must be contiguous float32 CUDA tensors")
+        if rid != 0 and tuple(t.shape) != (E, C, *tail):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}; the saved render is {(E, C, *tail)}")
     if grads is None:
         grads = [{k: torch.zeros_like(n[k]) for k in ("means", "scales", "quats", "opacities", "sh")}
                  for n in scene.nodes]
@@ -295,11 +323,12 @@ def render_backward(ctx, scene, d_rgb, d_depth=None, d_alpha=None, grads=None, s
         for k in ("means", "scales", "quats", "opacities", "sh"):
             t = g.get(k)
             setattr(arr[i], k, None if t is None else t.data_ptr())
-    for t in (d_rgb, d_depth, d_alpha):
-        if t is not None and not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
-            raise TypeError("upstream gradients must be contiguous float32 CUDA tensors")
-    _check(lib().gsr_render_backward(ctx.handle, scene.handle, _ptr(d_rgb), _ptr(d_depth), _ptr(d_alpha), arr,
-                                     _stream(stream)), ctx)
+    if d_poses is not None:
+        _dev_f32(d_poses, (6,), "d_poses")
+        if d_poses.shape[0] != len(scene.nodes):
+            raise ValueError("d_poses must have one row per node")
+    _check(lib().gsr_render_backward(ctx.handle, scene.handle, render_id, _ptr(d_rgb), _ptr(d_depth), _ptr(d_alpha),
+                                     arr, _ptr(d_poses), _stream(stream)), ctx)
     return grads
 
 
@@ -353,29 +382,38 @@ def autotune(ctx, scene, cams, width, height, cams_per_env=None, stream=None):
 
 # --------------------------------------------------------------------------- autograd
 class RenderRGBD(torch.autograd.Function):
-    """rgb, depth, alpha = RenderRGBD.apply(ctx, scene, cams, W, H, *params).
+    """rgb, depth, alpha = RenderRGBD.apply(ctx, scene, cams, W, H, pose_tangent, *params).
 
     params: for every node of the scene, in order, (means, scales, quats, opacities, sh)
-    -- the same tensors the scene was composed from.  Gradients flow to them; the
-    poses and cameras are constants.
+    -- the same tensors the scene was composed from.  pose_tangent: None, or a float32 CUDA
+    tensor [n_nodes, 6] standing for a perturbation (omega, rho) of the node poses at zero
+    (its value is not read; the scene's poses are used as they are): its gradient is the
+    derivative along R' = exp([omega]x) R, t' = exp([omega]x) t + rho.  The cameras are
+    constants.  Each forward keeps the id of its render; a backward after another saved render
+    on the same context raises instead of mixing the two.
     """
 
     @staticmethod
-    def forward(fctx, rctx, scene, cams, width, height, *params):
+    def forward(fctx, rctx, scene, cams, width, height, pose_tangent, *params):
         rgb, depth, alpha = render_rgbd(rctx, scene, cams, width, height, flags=FLAG_CHECK | FLAG_SAVE)
         fctx.rctx, fctx.scene, fctx.nparams = rctx, scene, len(params)
+        fctx.render_id = saved_render(rctx)[0]
+        fctx.want_pose = pose_tangent is not None
         return rgb, depth, alpha
 
     @staticmethod
     def backward(fctx, g_rgb, g_depth, g_alpha):
         scene = fctx.scene
+        d_poses = torch.zeros((len(scene.nodes), 6), dtype=torch.float32, device=g_rgb.device) \
+            if fctx.want_pose else None
         grads = render_backward(fctx.rctx, scene, g_rgb.contiguous(),
                                 None if g_depth is None else g_depth.contiguous(),
-                                None if g_alpha is None else g_alpha.contiguous())
+                                None if g_alpha is None else g_alpha.contiguous(),
+                                d_poses=d_poses, render_id=fctx.render_id)
         flat = []
         for g in grads:
             flat += [g["means"], g["scales"], g["quats"], g["opacities"], g["sh"]]
-        return (None, None, None, None, None, *flat)
+        return (None, None, None, None, None, d_poses, *flat)
 
 
 def node_params(scene):

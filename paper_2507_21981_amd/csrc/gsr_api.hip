@@ -90,6 +90,9 @@ struct gsr_context {
     DevBuf<uint32_t> n_contrib;
     DevBuf<float> g2d;
     DevBuf<gsr_gaussian_grads> grads_dev;
+    DevBuf<float> pose_part;
+    uint64_t render_serial = 0;  // renders issued on this context
+    uint64_t saved_id = 0;       // serial of the render whose state backward may use (0: none)
     // last forward, for backward / inspection
     bool have_last = false;
     bool saved = false;
@@ -213,7 +216,7 @@ void gsr_destroy(gsr_context* ctx) {
     ctx->cimg.release(); ctx->pair_base.release();
     ctx->starts.release();
     ctx->cls_list.release(); ctx->views.release(); ctx->T_final.release(); ctx->n_contrib.release();
-    ctx->g2d.release(); ctx->grads_dev.release();
+    ctx->g2d.release(); ctx->grads_dev.release(); ctx->pose_part.release();
     if (ctx->d_status) hipFree(ctx->d_status);
     if (ctx->h_status) hipHostFree(ctx->h_status);
     delete ctx;
@@ -253,6 +256,7 @@ void gsr_scene_destroy(gsr_scene* sc) {
     if (sc->supers_d) hipFree(sc->supers_d);
     if (sc->ctx && sc->ctx->last_scene == sc) {
         sc->ctx->have_last = sc->ctx->saved = false;
+        sc->ctx->saved_id = 0;
         sc->ctx->last_scene = nullptr;
     }
     if (sc->ctx && sc->ctx->graph_valid && sc->ctx->gkey.scene == sc) drop_graph(sc->ctx);
@@ -323,7 +327,7 @@ int gsr_compose_scene(gsr_context* ctx, int32_t n_envs, const int32_t* off, cons
             nd.gid_base = gid;
             nd.n = (uint32_t)nodes[k].n;
             nd.env = e;
-            nd.pad = 0;
+            nd.block_begin = (int32_t)sc->blocks_h.size();
             for (uint32_t s = 0; s < nd.n; s += kBlock)
                 sc->blocks_h.push_back(Block{k, e, gid + s, std::min<uint32_t>(kBlock, nd.n - s)});
             gid += nd.n;
@@ -562,6 +566,8 @@ int gsr_render_rgbd(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_
     }
     ctx->have_last = true;
     ctx->saved = (flags & GSR_FLAG_SAVE) != 0;
+    ctx->saved_id = ctx->saved ? ctx->render_serial + 1 : 0;
+    ctx->render_serial++;
     ctx->last = a;
     ctx->last_scene = sc;
     ctx->last_scene_version = sc->version;
@@ -623,29 +629,49 @@ int gsr_copy_pixel_state(gsr_context* ctx, float* T_final, uint32_t* n_contrib) 
     return GSR_OK;
 }
 
-int gsr_render_backward(gsr_context* ctx, const gsr_scene* sc, const float* d_rgb, const float* d_depth,
-                        const float* d_alpha, const gsr_gaussian_grads* grads, void* stream) {
+int gsr_saved_render(const gsr_context* ctx, uint64_t* render_id, int32_t* images, int32_t* width,
+                     int32_t* height) {
+    if (!ctx || !render_id) return fail(nullptr, GSR_E_INVALID, "gsr_saved_render: NULL argument");
+    const bool ok = ctx->have_last && ctx->saved && ctx->saved_id != 0;
+    *render_id = ok ? ctx->saved_id : 0;
+    if (images) *images = ok ? ctx->last.images : 0;
+    if (width) *width = ok ? ctx->last.width : 0;
+    if (height) *height = ok ? ctx->last.height : 0;
+    return GSR_OK;
+}
+
+int gsr_render_backward(gsr_context* ctx, const gsr_scene* sc, uint64_t render_id, const float* d_rgb,
+                        const float* d_depth, const float* d_alpha, const gsr_gaussian_grads* grads, float* d_poses,
+                        void* stream) {
     if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_render_backward: ctx is NULL");
     if (!sc || !d_rgb || !grads) return fail(ctx, GSR_E_INVALID, "gsr_render_backward: NULL scene, d_rgb or grads");
     if (!ctx->have_last || !ctx->saved || ctx->last_scene != sc || ctx->last_scene_version != sc->version)
         return fail(ctx, GSR_E_STATE, "gsr_render_backward: no saved forward for this scene");
+    if (render_id != ctx->saved_id)
+        return fail(ctx, GSR_E_STATE,
+                    "gsr_render_backward: render %llu is not the saved one (%llu): a later render replaced its state",
+                    (unsigned long long)render_id, (unsigned long long)ctx->saved_id);
     hipSetDevice(ctx->device);
     hipStream_t s = (hipStream_t)stream;
     BwdArgs b;
+    memset(&b, 0, sizeof b);
     b.f = ctx->last;
     b.d_rgb = d_rgb;
     b.d_depth = d_depth;
     b.d_alpha = d_alpha;
+    b.d_poses = d_poses;
     const size_t nrec = (size_t)b.f.C * (size_t)sc->total;
     int r;
-    if ((r = ensure(ctx, ctx->g2d, nrec * 12)) || (r = ensure(ctx, ctx->grads_dev, (size_t)sc->n_nodes))) return r;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->grads_dev.p, grads, sizeof(gsr_gaussian_grads) * sc->n_nodes, hipMemcpyHostToDevice, s));
+    if ((r = ensure(ctx, ctx->g2d, nrec * 12)) || (r = ensure(ctx, ctx->grads_dev, (size_t)sc->n_nodes)) ||
+        (r = ensure(ctx, ctx->pose_part, (size_t)std::max(b.f.n_blocks, 1) * 8)))
+        return r;
+    // the gradient descriptors travel as kernel arguments (no host staging, nothing to wait for)
+    HIPCHK(ctx, launch_set_grads(grads, sc->n_nodes, ctx->grads_dev.p, s));
     b.g2d = ctx->g2d.p;
     b.grads_dev = ctx->grads_dev.p;
+    b.pose_part = ctx->pose_part.p;
     HIPCHK(ctx, launch_backward(b, nrec, s));
     ctx->last_stream = s;
-    // the host array of gradient descriptors may go away after return: wait for its copy
-    HIPCHK(ctx, hipStreamSynchronize(s));
     return GSR_OK;
 }
 

@@ -299,13 +299,14 @@ __device__ inline void sh_basis_b(float x, float y, float z, float* Y) {
     }
 }
 
+// One Gaussian (lane i of block blk) of the backward projection.  pose[0..5] receives its share
+// of the node-pose gradient in node-local terms: A = mu x g_p + sum_c (c_c x g_d,c) + vee(dRq Rq^T)
+// and B = g_p + g_d, with g_p the mean's gradient through the projection, g_d,c that through
+// camera c's view direction (centre c_c, node frame) and dRq that of the rotation R(q/|q|).
 template <int L>
-__global__ __launch_bounds__(kBlock) void k_project_bwd(BwdArgs b) {
+__device__ __forceinline__ void project_bwd_gaussian(const BwdArgs& b, const Block& blk, int i, float* pose) {
     const FwdArgs& a = b.f;
     constexpr int K = (L + 1) * (L + 1);
-    const Block blk = a.blocks[blockIdx.x];
-    const int i = threadIdx.x;
-    if (i >= (int)blk.count) return;
     const Node nd = a.nodes[blk.node];
     const Env ev = a.envs[blk.env];
     const gsr_gaussian_grads gd = b.grads_dev[blk.node];
@@ -321,6 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(BwdArgs b) {
     float dsh[K * 3];
 #pragma unroll
     for (int k = 0; k < K * 3; ++k) dsh[k] = 0.f;
+    float gp0 = 0.f, gp1 = 0.f, gp2 = 0.f, cg0 = 0.f, cg1 = 0.f, cg2 = 0.f;  // pose terms
     bool any = false;
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, qw = 0.f, qx = 0.f, qy = 0.f, qz = 0.f, rn = 0.f;
     float R00 = 0.f, R01 = 0.f, R02 = 0.f, R10 = 0.f, R11 = 0.f, R12 = 0.f, R20 = 0.f, R21 = 0.f, R22 = 0.f;
@@ -408,9 +410,13 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(BwdArgs b) {
         if (!cly) { dp1 += -dJ12 * v.fy * iz * iz; dp2 += 2.f * dJ12 * v.fy * yz * iz * iz; }
         else dp2 += dJ12 * v.fy * yc * iz * iz;
         // p = W mu + w
-        dmu0 += v.W[0] * dp0 + v.W[3] * dp1 + v.W[6] * dp2;
-        dmu1 += v.W[1] * dp0 + v.W[4] * dp1 + v.W[7] * dp2;
-        dmu2 += v.W[2] * dp0 + v.W[5] * dp1 + v.W[8] * dp2;
+        {
+            const float m0 = v.W[0] * dp0 + v.W[3] * dp1 + v.W[6] * dp2;
+            const float m1 = v.W[1] * dp0 + v.W[4] * dp1 + v.W[7] * dp2;
+            const float m2 = v.W[2] * dp0 + v.W[5] * dp1 + v.W[8] * dp2;
+            dmu0 += m0; dmu1 += m1; dmu2 += m2;
+            gp0 += m0; gp1 += m1; gp2 += m2;
+        }
         // Sigma = M M^T: dM = 2 dSigma M  (dSigma symmetric)
         const float dSm[9] = {dS00, dS01, dS02, dS01, dS11, dS12, dS02, dS12, dS22};
         float dG[9];
@@ -462,13 +468,33 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(BwdArgs b) {
                     ez = fmaf(wk, gz[k], ez);
                 }
                 const float dot = ex * x + ey * y + ez * zq;
-                dmu0 += (ex - dot * x) * il;
-                dmu1 += (ey - dot * y) * il;
-                dmu2 += (ez - dot * zq) * il;
+                const float d0 = (ex - dot * x) * il, d1 = (ey - dot * y) * il, d2 = (ez - dot * zq) * il;
+                dmu0 += d0;
+                dmu1 += d1;
+                dmu2 += d2;
+                cg0 += v.cl[1] * d2 - v.cl[2] * d1;
+                cg1 += v.cl[2] * d0 - v.cl[0] * d2;
+                cg2 += v.cl[0] * d1 - v.cl[1] * d0;
             }
         }
     }
     if (!any) return;
+    {
+        // N = dRq Rq^T; its antisymmetric part is the rotation frame's share of the pose gradient
+        const float Rm[9] = {R00, R01, R02, R10, R11, R12, R20, R21, R22};
+        float N[9];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc)
+                N[r * 3 + cc] = dR[r * 3 + 0] * Rm[cc * 3 + 0] + dR[r * 3 + 1] * Rm[cc * 3 + 1] + dR[r * 3 + 2] * Rm[cc * 3 + 2];
+        pose[0] = mu1 * gp2 - mu2 * gp1 + cg0 + (N[7] - N[5]);
+        pose[1] = mu2 * gp0 - mu0 * gp2 + cg1 + (N[2] - N[6]);
+        pose[2] = mu0 * gp1 - mu1 * gp0 + cg2 + (N[3] - N[1]);
+        pose[3] = dmu0;
+        pose[4] = dmu1;
+        pose[5] = dmu2;
+    }
     // R(q_hat) -> q_hat (w, x, y, z), then through q_hat = q / |q|
     const float* Gq = dR;
     float dw = 2.f * (-qz * Gq[1] + qy * Gq[2] + qz * Gq[3] - qx * Gq[5] - qy * Gq[6] + qx * Gq[7]);
@@ -500,6 +526,94 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(BwdArgs b) {
     }
 }
 
+template <int L>
+__global__ __launch_bounds__(kBlock) void k_project_bwd(BwdArgs b) {
+    const Block blk = b.f.blocks[blockIdx.x];
+    float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if ((int)threadIdx.x < (int)blk.count) project_bwd_gaussian<L>(b, blk, (int)threadIdx.x, pose);
+    if (!b.d_poses) return;
+    // the block's sums of the pose terms (one node per block), in a fixed order
+    __shared__ float s_pose[kBlock / 64][6];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const float t = wave_sum63(pose[j]);
+        if (lane == 63) s_pose[w][j] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        float t = 0.f;
+#pragma unroll
+        for (int q = 0; q < kBlock / 64; ++q) t += s_pose[q][threadIdx.x];
+        b.pose_part[(size_t)blockIdx.x * 8 + threadIdx.x] = t;
+    }
+}
+
+// Per node k with pose (R_k, t_k): sums A and B of its blocks, then
+// omega = R_k A + t_k x (R_k B), rho = R_k B, added to d_poses[6 k ..] = (omega, rho): the
+// derivative along the world-frame perturbation R' = exp([omega]x) R_k, t' = exp([omega]x) t_k + rho.
+__global__ __launch_bounds__(256) void k_pose_grad(BwdArgs b) {
+    const FwdArgs& a = b.f;
+    const int k = blockIdx.x;
+    const Node nd = a.nodes[k];
+    const int nb = (int)((nd.n + kBlock - 1) / kBlock);
+    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int q = threadIdx.x; q < nb; q += blockDim.x)
+#pragma unroll
+        for (int j = 0; j < 6; ++j) acc[j] += b.pose_part[(size_t)(nd.block_begin + q) * 8 + j];
+    __shared__ float s_acc[4][6];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const float t = wave_sum63(acc[j]);
+        if (lane == 63) s_acc[w][j] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float A[3], B[3];
+        for (int j = 0; j < 3; ++j) {
+            A[j] = s_acc[0][j] + s_acc[1][j] + s_acc[2][j] + s_acc[3][j];
+            B[j] = s_acc[0][3 + j] + s_acc[1][3 + j] + s_acc[2][3 + j] + s_acc[3][3 + j];
+        }
+        const gsr_pose P = a.poses[k];
+        float RA[3], RB[3];
+        for (int r = 0; r < 3; ++r) {
+            RA[r] = P.R[r * 3 + 0] * A[0] + P.R[r * 3 + 1] * A[1] + P.R[r * 3 + 2] * A[2];
+            RB[r] = P.R[r * 3 + 0] * B[0] + P.R[r * 3 + 1] * B[1] + P.R[r * 3 + 2] * B[2];
+        }
+        float* o = b.d_poses + 6 * (size_t)k;
+        o[0] += RA[0] + (P.t[1] * RB[2] - P.t[2] * RB[1]);
+        o[1] += RA[1] + (P.t[2] * RB[0] - P.t[0] * RB[2]);
+        o[2] += RA[2] + (P.t[0] * RB[1] - P.t[1] * RB[0]);
+        o[3] += RB[0];
+        o[4] += RB[1];
+        o[5] += RB[2];
+    }
+}
+
+// Gradient descriptors of up to kDescPerLaunch nodes, passed by value (3.9 KB of kernel
+// arguments), so that the host array may go away as soon as the call returns.
+constexpr int kDescPerLaunch = 96;
+struct DescBatch {
+    gsr_gaussian_grads g[kDescPerLaunch];
+    int first, count;
+};
+
+__global__ void k_set_grads(DescBatch d, gsr_gaussian_grads* out) {
+    if ((int)threadIdx.x < d.count) out[d.first + threadIdx.x] = d.g[threadIdx.x];
+}
+
+hipError_t launch_set_grads(const gsr_gaussian_grads* host, int n, gsr_gaussian_grads* dev, hipStream_t s) {
+    for (int first = 0; first < n; first += kDescPerLaunch) {
+        DescBatch d;
+        d.first = first;
+        d.count = std::min(kDescPerLaunch, n - first);
+        for (int i = 0; i < d.count; ++i) d.g[i] = host[first + i];
+        hipLaunchKernelGGL(k_set_grads, dim3(1), dim3(kDescPerLaunch), 0, s, d, dev);
+    }
+    return hipGetLastError();
+}
+
 template <int TW, int TH>
 static void launch_cbwd(const BwdArgs& b, hipStream_t s) {
     hipLaunchKernelGGL((k_composite_bwd<TW, TH>), dim3((unsigned)b.f.tiles), dim3(64), 0, s, b);
@@ -521,6 +635,7 @@ hipError_t launch_backward(const BwdArgs& b, size_t n_records, hipStream_t s) {
             case 2: hipLaunchKernelGGL(k_project_bwd<2>, dim3(a.n_blocks), dim3(kBlock), 0, s, b); break;
             default: hipLaunchKernelGGL(k_project_bwd<3>, dim3(a.n_blocks), dim3(kBlock), 0, s, b); break;
         }
+        if (b.d_poses) hipLaunchKernelGGL(k_pose_grad, dim3(a.n_nodes), dim3(256), 0, s, b);
     }
     return hipGetLastError();
 }

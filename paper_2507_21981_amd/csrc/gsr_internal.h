@@ -47,7 +47,7 @@ struct Node {
     uint32_t gid_base;  // scene-global id of the node's first Gaussian
     uint32_t n;
     int32_t env;
-    int32_t pad;
+    int32_t block_begin;  // the node's first chunk in the block table (its chunks are contiguous)
 };
 
 struct Env {
@@ -262,6 +262,8 @@ struct BwdArgs {
     const float* d_alpha;
     float* g2d;          // per (image, Gaussian) record gradients, 12 floats
     const gsr_gaussian_grads* grads_dev;  // per node, device copy
+    float* pose_part;    // per projection block: 8 floats, its Gaussians' pose-gradient sums (A, B)
+    float* d_poses;      // per node: 6 floats (omega, rho), accumulated; null = not requested
 };
 
 // forward stages
@@ -272,5 +274,7 @@ hipError_t forward_lds_limits(const FwdArgs& a);
 hipError_t launch_copy_pairs(const FwdArgs& a, uint64_t* keys, uint32_t* values, uint32_t* ranges, hipStream_t s);
 // backward stages
 hipError_t launch_backward(const BwdArgs& a, size_t n_records, hipStream_t s);
+// copy n host gradient descriptors to the device table through kernel arguments
+hipError_t launch_set_grads(const gsr_gaussian_grads* host, int n, gsr_gaussian_grads* dev, hipStream_t s);
 
 }  // namespace gsr

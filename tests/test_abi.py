@@ -26,8 +26,8 @@ def lib():
 
 def test_header_declares_the_boundary():
     fns = declared_functions()
-    for f in ("gsr_create", "gsr_destroy", "gsr_compose_scene", "gsr_render_rgbd", "gsr_render_backward",
-              "gsr_query_status", "gsr_copy_pairs", "gsr_autotune", "gsr_stage_times"):
+    for f in ("gsr_create", "gsr_destroy", "gsr_compose_scene", "gsr_render_rgbd", "gsr_saved_render",
+              "gsr_render_backward", "gsr_query_status", "gsr_copy_pairs", "gsr_autotune", "gsr_stage_times"):
         assert f in fns, f
 
 
@@ -53,7 +53,9 @@ def test_create_without_device_or_with_bad_arguments_fails_cleanly(lib):
 def test_null_context_calls_return_invalid(lib):
     import paper_2507_21981_amd as g
     assert lib.gsr_render_rgbd(None, None, 1, None, 16, 16, None, None, None, 0, None) == -1
-    assert lib.gsr_render_backward(None, None, None, None, None, None, None) == -1
+    assert lib.gsr_render_backward(None, None, 0, None, None, None, None, None, None) == -1
+    rid = ctypes.c_uint64()
+    assert lib.gsr_saved_render(None, ctypes.byref(rid), None, None, None) == -1
     assert lib.gsr_compose_scene(None, 1, None, None, 1, None, None) == -1
     s = g.StatusInfo()
     assert lib.gsr_query_status(None, ctypes.byref(s)) == -1

@@ -1,9 +1,11 @@
 """GPU backward parity: FP32 gradients against the FP64 oracle's analytic gradient.
 
 The oracle's analytic gradient is itself pinned to FP64 central finite differences
-(tests/test_oracle_pins.py).  Tolerances (no value is stated by the paper): per parameter
-group, relative L2 error <= 2e-3 and max-abs error <= 2e-3 * max|g|; FP32 compositing
-recomputes transmittance by division back to front, which costs a few digits.
+(tests/test_oracle_pins.py).  Tolerances, per parameter group (means, scales, quaternions,
+opacities, SH, node poses): relative L2 error <= 1e-5 and max-abs error <= 1.5e-5 * max|g|.
+The paper states none; the worst measured values over these tests (every tile shape, up to
+the full 500k-Gaussian 8-view workload) are 3.9e-6 and 5.4e-6, and the bounds sit within 3x
+of them (tighter than the 1e-4 / 1e-3 first proposed for this comparison).
 """
 import math
 
@@ -16,8 +18,9 @@ from gpu_util import log, upload
 
 pytestmark = pytest.mark.gpu
 
-REL_L2 = 2e-3
-MAX_ABS = 2e-3
+REL_L2 = 1e-5
+MAX_ABS = 1.5e-5
+GROUPS = ("means", "scales", "quats", "opacities", "sh")
 
 
 @pytest.fixture(scope="module")
@@ -35,7 +38,8 @@ def ctx(gsr):
 
 
 def _oracle_grads(wl, weights, tw, th):
-    """Sum over every image of the oracle's analytic gradient of sum(w . outputs)."""
+    """Sum over every image of the oracle's analytic gradient of sum(w . outputs), per node,
+    with the node-pose gradient (omega, rho) under "pose"."""
     W, H = wl["width"], wl["height"]
     out = []
     image = 0
@@ -47,30 +51,34 @@ def _oracle_grads(wl, weights, tw, th):
             wr, wd, wa = weights[image]
             g = oracle.backward(ref, cam, W, H, wr, wd, wa, tw, th)
             if acc is None:
-                acc = {k: g[k].copy() for k in ("means", "scales", "quats", "opacities", "sh")}
+                acc = {k: g[k].copy() for k in GROUPS + ("pose",)}
             else:
                 for k in acc:
                     acc[k] += g[k]
             image += 1
         # split the env's concatenation back into nodes
         off = 0
-        for n in env["nodes"]:
+        for j, n in enumerate(env["nodes"]):
             m = len(n["means"])
-            out.append({k: v[off:off + m] for k, v in acc.items()})
+            d = {k: acc[k][off:off + m] for k in GROUPS}
+            d["pose"] = acc["pose"][j]
+            out.append(d)
             off += m
     return out
 
 
-def _compare(gpu_grads, ref_grads):
+def _compare(gpu_grads, ref_grads, rel_l2=REL_L2, max_abs=MAX_ABS, groups=GROUPS):
+    """Per parameter group: relative L2 error and max-abs error over max |g| (both asserted)."""
     worst = {}
-    for k in ("means", "scales", "quats", "opacities", "sh"):
-        g = np.concatenate([gg[k].detach().cpu().numpy().reshape(-1) for gg in gpu_grads])
-        r = np.concatenate([rr[k].reshape(-1) for rr in ref_grads])
+    for k in groups:
+        g = np.concatenate([np.asarray(gg[k].detach().cpu().numpy() if hasattr(gg[k], "detach") else gg[k],
+                                       np.float64).reshape(-1) for gg in gpu_grads])
+        r = np.concatenate([np.asarray(rr[k], np.float64).reshape(-1) for rr in ref_grads])
         nr = np.linalg.norm(r)
         rel = np.linalg.norm(g - r) / max(nr, 1e-30)
         mx = np.abs(g - r).max() / max(np.abs(r).max(), 1e-30)
-        worst[k] = (rel, mx)
-        assert rel <= REL_L2 and mx <= MAX_ABS, f"{k}: rel L2 {rel:.3g}, max-abs/max {mx:.3g}"
+        worst[k] = (float(f"{rel:.3g}"), float(f"{mx:.3g}"))
+        assert rel <= rel_l2 and mx <= max_abs, f"{k}: rel L2 {rel:.3g}, max-abs/max {mx:.3g}"
     return worst
 
 
@@ -91,8 +99,11 @@ def _gpu_grads(gsr, ctx, wl, weights, tile):
     wr = torch.tensor(np.stack([w[0] for w in weights]).reshape(E, C, H, W, 3), dtype=torch.float32, device="cuda")
     wd = torch.tensor(np.stack([w[1] for w in weights]).reshape(E, C, H, W), dtype=torch.float32, device="cuda")
     wa = torch.tensor(np.stack([w[2] for w in weights]).reshape(E, C, H, W), dtype=torch.float32, device="cuda")
-    grads = gsr.render_backward(ctx, scene, wr, wd, wa)
+    d_poses = torch.zeros((len(scene.nodes), 6), dtype=torch.float32, device="cuda")
+    grads = gsr.render_backward(ctx, scene, wr, wd, wa, d_poses=d_poses)
     torch.cuda.synchronize()
+    for g, p in zip(grads, d_poses.cpu().numpy().astype(np.float64)):
+        g["pose"] = p
     return grads
 
 
@@ -109,10 +120,10 @@ def test_gradients_small_posed_scene(gsr, ctx):
     w = _weights(wl, 1)
     ref = _oracle_grads(wl, w, 16, 16)
     got = _gpu_grads(gsr, ctx, wl, w, (16, 16))
-    log("worst", _compare(got, ref))
+    log("worst", _compare(got, ref, groups=GROUPS + ("pose",)))
 
 
-@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (16, 8), (32, 8)])
 def test_gradients_differentiable_subset(gsr, ctx, tile):
     # the differentiable workload's finite-difference subset: 2,000 Gaussians (cube geometry,
     # SH3) seen from two ring views at 64x64 (fx = 55.43)
@@ -158,14 +169,15 @@ def test_gradients_batched_envs(gsr, ctx):
     w = _weights(wl, 3)
     ref = _oracle_grads(wl, w, 16, 8)
     got = _gpu_grads(gsr, ctx, wl, w, (16, 8))
-    log("worst", _compare(got, ref))
+    log("worst", _compare(got, ref, groups=GROUPS + ("pose",)))
 
 
 def test_autograd_function_l1_loss(gsr, ctx):
     import torch
     nd = synth.gaussians_uniform_cube(1500, 71, sh_degree=1)
     cam = synth.camera((0.3, 0.2, -3.0), (0, 0, 0), 48, 48)
-    env = dict(nodes=[nd], poses=[(np.eye(3, dtype=np.float32), np.zeros(3, np.float32))], cams=[cam])
+    R = synth.random_rotation(synth.rng(72)).astype(np.float32)
+    env = dict(nodes=[nd], poses=[(R, np.array([0.05, -0.1, 0.2], np.float32))], cams=[cam])
     wl = dict(envs=[env], cams_per_env=1, width=48, height=48)
     envs_t, poses, cams = upload(wl)
     ctx.set_tile(16, 16)
@@ -173,7 +185,8 @@ def test_autograd_function_l1_loss(gsr, ctx):
     node = dict(zip(("means", "scales", "quats", "opacities", "sh"), params))
     scene = gsr.compose_scene(ctx, [[node]], poses)
     target = torch.rand((1, 1, 48, 48, 3), device="cuda")
-    rgb, depth, alpha = gsr.RenderRGBD.apply(ctx, scene, cams, 48, 48, *params)
+    tangent = torch.zeros((1, 6), device="cuda", requires_grad=True)
+    rgb, depth, alpha = gsr.RenderRGBD.apply(ctx, scene, cams, 48, 48, tangent, *params)
     loss = (rgb - target).abs().mean() + 0.1 * depth.mean()
     loss.backward()
     # oracle: d loss / d rgb = sign(rgb - target) / n, d loss / d depth = 0.1 / n
@@ -182,6 +195,92 @@ def test_autograd_function_l1_loss(gsr, ctx):
     gd = np.full((48, 48), 0.1 / (48 * 48))
     og = oracle.backward(ref, cam, 48, 48, gr, gd, None)
     got = [dict(means=params[0].grad, scales=params[1].grad, quats=params[2].grad, opacities=params[3].grad,
-                sh=params[4].grad)]
+                sh=params[4].grad, pose=tangent.grad[0])]
     want = [{k: og[k] for k in ("means", "scales", "quats", "opacities", "sh")}]
-    log("worst", _compare(got, want))
+    want[0]["pose"] = og["pose"][0]
+    log("worst", _compare(got, want, groups=GROUPS + ("pose",)))
+
+
+def test_backward_of_a_replaced_render_is_refused(gsr, ctx):
+    """Two differentiable renders on one context, then the earlier one's backward: its saved
+    state is gone, so the call fails before any launch instead of pairing its upstream
+    gradients with the later render's pairs; upstream gradients of the wrong shape are
+    refused too."""
+    import torch
+    nd = synth.gaussians_uniform_cube(400, 81)
+    cam = synth.camera((0.0, 0.0, -3.0), (0, 0, 0), 32, 32)
+    env = dict(nodes=[nd], poses=[(np.eye(3, dtype=np.float32), np.zeros(3, np.float32))], cams=[cam])
+    wl = dict(envs=[env], cams_per_env=1, width=32, height=32)
+    envs_t, poses, cams = upload(wl)
+    ctx.set_tile(16, 16)
+    params = [envs_t[0][0][k].clone().requires_grad_(True) for k in ("means", "scales", "quats", "opacities", "sh")]
+    scene = gsr.compose_scene(ctx, [[dict(zip(("means", "scales", "quats", "opacities", "sh"), params))]], poses)
+    rgb1, _, _ = gsr.RenderRGBD.apply(ctx, scene, cams, 32, 32, None, *params)
+    rgb2, _, _ = gsr.RenderRGBD.apply(ctx, scene, cams, 32, 32, None, *params)
+    rgb2.sum().backward()  # the saved render: fine
+    g_ok = params[0].grad.clone()
+    with pytest.raises(gsr.GsrError) as e:
+        rgb1.sum().backward()
+    assert e.value.code == -6
+    torch.cuda.synchronize()
+    assert torch.equal(params[0].grad, g_ok)  # nothing was accumulated by the refused call
+    gsr.render_rgbd(ctx, scene, cams, 32, 32, flags=gsr.FLAG_CHECK | gsr.FLAG_SAVE)
+    with pytest.raises(ValueError):
+        gsr.render_backward(ctx, scene, torch.zeros((1, 1, 16, 16, 3), device="cuda"))
+
+
+def test_gradients_differentiable_500k_8views_sampled_pixels(gsr):
+    """The differentiable workload at full size, in the benchmark's launch configuration
+    (500k Gaussians SH3, 8 ring views 640x480, 16x16 tiles, two pixels per lane): upstream
+    gradients on 2,000 seeded pixels per view (N(0, 1) for rgb, depth and alpha), zero at
+    pixels where the oracle finds a blending decision within the FP32 bound of its threshold
+    (there two results are correct).  The oracle differentiates those pixels one by one."""
+    import torch
+    wl = synth.scene_config(4, seed=4)
+    env = wl["envs"][0]
+    W, H, tw, th = 640, 480, 16, 16
+    fe = oracle.FlatEnv(env)
+    g = np.random.default_rng(11)
+    C = len(env["cams"])
+    d_rgb = np.zeros((1, C, H, W, 3), np.float32)
+    d_depth = np.zeros((1, C, H, W), np.float32)
+    d_alpha = np.zeros((1, C, H, W), np.float32)
+    acc = None
+    for v, cam in enumerate(env["cams"]):
+        log(f"oracle view {v}")
+        rect, zb, vis = oracle.keyspec(fe, cam, W, H, tw, th)
+        geo = oracle.project(fe, cam, W, H)
+        _, _, lv, ranges = oracle.pairs(rect, zb, vis, W, H, tw, th)
+        pix = np.sort(g.choice(W * H, size=2000, replace=False))
+        fwd = oracle.composite_sample(geo, ranges, lv, W, H, tw, th, cam["bg"], pix)
+        clean = (fwd["flags"] == 0).astype(np.float64)
+        gr = g.standard_normal((pix.size, 3)).astype(np.float32).astype(np.float64) * clean[:, None]
+        gd = g.standard_normal(pix.size).astype(np.float32).astype(np.float64) * clean
+        ga = g.standard_normal(pix.size).astype(np.float32).astype(np.float64) * clean
+        d_rgb[0, v].reshape(-1, 3)[pix] = gr
+        d_depth[0, v].reshape(-1)[pix] = gd
+        d_alpha[0, v].reshape(-1)[pix] = ga
+        ref = dict(fe=fe, ranges=ranges, lvals=lv, geo=geo)
+        og = oracle.backward_sample(ref, cam, W, H, pix, gr, gd, ga, tw, th)
+        log(f"  pairs {len(lv)}, ambiguous sampled pixels {int(pix.size - clean.sum())}")
+        if acc is None:
+            acc = {k: og[k].copy() for k in GROUPS + ("pose",)}
+        else:
+            for k in acc:
+                acc[k] += og[k]
+    ctx = gsr.create(0, tile=(tw, th))
+    try:
+        ctx.set_pixels_per_thread(2)
+        envs_t, poses, cams = upload(wl)
+        scene = gsr.compose_scene(ctx, envs_t, poses)
+        gsr.render_rgbd(ctx, scene, cams, W, H, C, flags=gsr.FLAG_CHECK | gsr.FLAG_SAVE)
+        d_poses = torch.zeros((1, 6), device="cuda")
+        grads = gsr.render_backward(ctx, scene, torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_depth).cuda(),
+                                    torch.from_numpy(d_alpha).cuda(), d_poses=d_poses)
+        torch.cuda.synchronize()
+        grads[0]["pose"] = d_poses[0]
+        ref = {k: acc[k] for k in GROUPS}
+        ref["pose"] = acc["pose"][0]
+        log("worst", _compare(grads, [ref], groups=GROUPS + ("pose",)))
+    finally:
+        ctx.close()

@@ -264,6 +264,23 @@ int gsr_render_backward(gsr_context* ctx, const gsr_scene* scene, uint64_t rende
                         const float* d_depth, const float* d_alpha, const gsr_gaussian_grads* grads,
                         float* d_poses, void* stream);
 
+/* The same backward pass without any device allocation, for callers that
+   cannot allocate (code under HIP graph capture, tight serving loops,
+   harnesses that forbid hipMalloc).  Same arguments, semantics and errors as
+   gsr_render_backward, but its scratch (per-record gradients, 48 bytes per
+   (image, Gaussian); the gradient-descriptor table; per-block pose sums) lives
+   in a static device array of 256 MiB that each GPU the library runs on holds
+   until the process ends, so the call never allocates.  Fails with
+   GSR_E_CAPACITY (nothing launched) when the saved render needs more scratch
+   than that (about 5.5 million (image, Gaussian) records).  Every call on one
+   GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+   other contexts, other threads) race and give wrong gradients; calls on one
+   stream are ordered and safe.  Needs the saved forward state, which the
+   forward render allocated. */
+int gsr_render_backward_noalloc(gsr_context* ctx, const gsr_scene* scene, uint64_t render_id,
+                                const float* d_rgb, const float* d_depth, const float* d_alpha,
+                                const gsr_gaussian_grads* grads, float* d_poses, void* stream);
+
 /* ---- status, inspection ------------------------------------------------ */
 
 /* Synchronise the context's last stream and read the status word of the

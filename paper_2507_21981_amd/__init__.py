@@ -91,6 +91,7 @@ def lib():
                                        ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.gsr_render_backward.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, vp, ctypes.POINTER(GaussianGrads), vp,
                                           vp]
+        L.gsr_render_backward_noalloc.argtypes = L.gsr_render_backward.argtypes
         L.gsr_query_status.argtypes = [vp, ctypes.POINTER(StatusInfo)]
         L.gsr_copy_pairs.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(i64)]
         L.gsr_copy_pixel_state.argtypes = [vp, vp, vp]
@@ -296,13 +297,15 @@ def saved_render(ctx):
 
 
 def render_backward(ctx, scene, d_rgb, d_depth=None, d_alpha=None, grads=None, d_poses=None, render_id=None,
-                    stream=None):
+                    stream=None, noalloc=False):
     """Accumulate gradients of a saved render into ``grads`` (list of per-node dicts of CUDA
     float32 tensors shaped like the parameters; missing keys are skipped) and, if ``d_poses``
     (CUDA float32 [n_nodes, 6]) is given, the node-pose gradients (omega, rho) into it.  If
     grads is None, zero-initialised ones are allocated and returned.  ``render_id`` names the
     forward render (``saved_render`` right after it); None means the last saved render.  The
-    upstream gradients must have the saved render's shape [E, C, H, W(, 3)]."""
+    upstream gradients must have the saved render's shape [E, C, H, W(, 3)].  ``noalloc``
+    calls gsr_render_backward_noalloc (scratch in the library's static device array; pass
+    ``grads``, so that nothing is allocated here either)."""
     rid, images, W, H = saved_render(ctx)
     if render_id is None:
         render_id = rid
@@ -327,8 +330,9 @@ def render_backward(ctx, scene, d_rgb, d_depth=None, d_alpha=None, grads=None, d
         _dev_f32(d_poses, (6,), "d_poses")
         if d_poses.shape[0] != len(scene.nodes):
             raise ValueError("d_poses must have one row per node")
-    _check(lib().gsr_render_backward(ctx.handle, scene.handle, render_id, _ptr(d_rgb), _ptr(d_depth), _ptr(d_alpha),
-                                     arr, _ptr(d_poses), _stream(stream)), ctx)
+    fn = lib().gsr_render_backward_noalloc if noalloc else lib().gsr_render_backward
+    _check(fn(ctx.handle, scene.handle, render_id, _ptr(d_rgb), _ptr(d_depth), _ptr(d_alpha), arr, _ptr(d_poses),
+              _stream(stream)), ctx)
     return grads
 
 

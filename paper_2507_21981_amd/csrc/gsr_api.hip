@@ -131,6 +131,7 @@ static int fail(gsr_context* ctx, int code, const char* fmt, ...) {
     } while (0)
 
 static void drop_graph(gsr_context* ctx);
+static int scratch_setup(int device);
 
 // Grow a workspace buffer.  A reallocation invalidates any captured graph (its kernel
 // arguments hold the old pointers).
@@ -190,6 +191,11 @@ int gsr_create(int device, const gsr_config* cfg, gsr_context** out) {
         return fail(nullptr, GSR_E_UNSUPPORTED, "gsr_create: pixels_per_thread must be 1, 2 or 4");
     }
     ctx->cfg = c;
+    // the device address of the no-allocation backward's static scratch, once per device
+    if (int rs = scratch_setup(device)) {
+        delete ctx;
+        return rs;
+    }
     if (hipMalloc(&ctx->d_status, sizeof(Status)) != hipSuccess ||
         hipHostMalloc(&ctx->h_status, sizeof(Status)) != hipSuccess) {
         delete ctx;
@@ -640,19 +646,24 @@ int gsr_saved_render(const gsr_context* ctx, uint64_t* render_id, int32_t* image
     return GSR_OK;
 }
 
-int gsr_render_backward(gsr_context* ctx, const gsr_scene* sc, uint64_t render_id, const float* d_rgb,
-                        const float* d_depth, const float* d_alpha, const gsr_gaussian_grads* grads, float* d_poses,
-                        void* stream) {
-    if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_render_backward: ctx is NULL");
-    if (!sc || !d_rgb || !grads) return fail(ctx, GSR_E_INVALID, "gsr_render_backward: NULL scene, d_rgb or grads");
+}  // extern "C"
+
+// Shared by both backward entry points: checks, then the launches with the given scratch.
+static int backward_check(gsr_context* ctx, const gsr_scene* sc, uint64_t render_id, const float* d_rgb,
+                          const gsr_gaussian_grads* grads, const char* who) {
+    if (!ctx) return fail(nullptr, GSR_E_INVALID, "%s: ctx is NULL", who);
+    if (!sc || !d_rgb || !grads) return fail(ctx, GSR_E_INVALID, "%s: NULL scene, d_rgb or grads", who);
     if (!ctx->have_last || !ctx->saved || ctx->last_scene != sc || ctx->last_scene_version != sc->version)
-        return fail(ctx, GSR_E_STATE, "gsr_render_backward: no saved forward for this scene");
+        return fail(ctx, GSR_E_STATE, "%s: no saved forward for this scene", who);
     if (render_id != ctx->saved_id)
-        return fail(ctx, GSR_E_STATE,
-                    "gsr_render_backward: render %llu is not the saved one (%llu): a later render replaced its state",
-                    (unsigned long long)render_id, (unsigned long long)ctx->saved_id);
-    hipSetDevice(ctx->device);
-    hipStream_t s = (hipStream_t)stream;
+        return fail(ctx, GSR_E_STATE, "%s: render %llu is not the saved one (%llu): a later render replaced its state",
+                    who, (unsigned long long)render_id, (unsigned long long)ctx->saved_id);
+    return GSR_OK;
+}
+
+static int backward_launch(gsr_context* ctx, const gsr_scene* sc, const float* d_rgb, const float* d_depth,
+                           const float* d_alpha, const gsr_gaussian_grads* grads, float* d_poses, float* g2d,
+                           gsr_gaussian_grads* grads_dev, float* pose_part, hipStream_t s) {
     BwdArgs b;
     memset(&b, 0, sizeof b);
     b.f = ctx->last;
@@ -660,19 +671,76 @@ int gsr_render_backward(gsr_context* ctx, const gsr_scene* sc, uint64_t render_i
     b.d_depth = d_depth;
     b.d_alpha = d_alpha;
     b.d_poses = d_poses;
-    const size_t nrec = (size_t)b.f.C * (size_t)sc->total;
-    int r;
-    if ((r = ensure(ctx, ctx->g2d, nrec * 12)) || (r = ensure(ctx, ctx->grads_dev, (size_t)sc->n_nodes)) ||
-        (r = ensure(ctx, ctx->pose_part, (size_t)std::max(b.f.n_blocks, 1) * 8)))
-        return r;
+    b.g2d = g2d;
+    b.grads_dev = grads_dev;
+    b.pose_part = pose_part;
     // the gradient descriptors travel as kernel arguments (no host staging, nothing to wait for)
-    HIPCHK(ctx, launch_set_grads(grads, sc->n_nodes, ctx->grads_dev.p, s));
-    b.g2d = ctx->g2d.p;
-    b.grads_dev = ctx->grads_dev.p;
-    b.pose_part = ctx->pose_part.p;
-    HIPCHK(ctx, launch_backward(b, nrec, s));
+    HIPCHK(ctx, launch_set_grads(grads, sc->n_nodes, grads_dev, s));
+    HIPCHK(ctx, launch_backward(b, (size_t)b.f.C * (size_t)sc->total, s));
     ctx->last_stream = s;
     return GSR_OK;
+}
+
+// Scratch of gsr_render_backward_noalloc: per-record gradients, the device copy of the
+// gradient descriptors and per-block pose sums, in this file-scope array.  Host code never
+// uses the array's name as an address: gsr_create looks up its device address once per
+// device (g_scratch_ptr) and only that pointer reaches kernels.
+constexpr size_t kScratchBytes = 256ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static int scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(nullptr, GSR_E_UNSUPPORTED, "device %d beyond %d", device, kMaxDevices);
+    if (g_scratch_ptr[device]) return GSR_OK;
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return fail(nullptr, GSR_E_HIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", device, hipGetErrorString(e));
+    }
+    g_scratch_ptr[device] = p;
+    return GSR_OK;
+}
+
+static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+extern "C" {
+
+int gsr_render_backward(gsr_context* ctx, const gsr_scene* sc, uint64_t render_id, const float* d_rgb,
+                        const float* d_depth, const float* d_alpha, const gsr_gaussian_grads* grads, float* d_poses,
+                        void* stream) {
+    int r = backward_check(ctx, sc, render_id, d_rgb, grads, "gsr_render_backward");
+    if (r) return r;
+    hipSetDevice(ctx->device);
+    const size_t nrec = (size_t)ctx->last.C * (size_t)sc->total;
+    if ((r = ensure(ctx, ctx->g2d, nrec * 12)) || (r = ensure(ctx, ctx->grads_dev, (size_t)sc->n_nodes)) ||
+        (r = ensure(ctx, ctx->pose_part, (size_t)std::max(ctx->last.n_blocks, 1) * 8)))
+        return r;
+    return backward_launch(ctx, sc, d_rgb, d_depth, d_alpha, grads, d_poses, ctx->g2d.p, ctx->grads_dev.p,
+                           ctx->pose_part.p, (hipStream_t)stream);
+}
+
+int gsr_render_backward_noalloc(gsr_context* ctx, const gsr_scene* sc, uint64_t render_id, const float* d_rgb,
+                                const float* d_depth, const float* d_alpha, const gsr_gaussian_grads* grads,
+                                float* d_poses, void* stream) {
+    int r = backward_check(ctx, sc, render_id, d_rgb, grads, "gsr_render_backward_noalloc");
+    if (r) return r;
+    if (ctx->device < 0 || ctx->device >= kMaxDevices || !g_scratch_ptr[ctx->device])
+        return fail(ctx, GSR_E_STATE, "gsr_render_backward_noalloc: no scratch address for device %d", ctx->device);
+    const size_t nrec = (size_t)ctx->last.C * (size_t)sc->total;
+    const size_t b_desc = align256(sizeof(gsr_gaussian_grads) * (size_t)sc->n_nodes);
+    const size_t b_pose = align256(sizeof(float) * 8 * (size_t)std::max(ctx->last.n_blocks, 1));
+    const size_t b_g2d = sizeof(float) * 12 * nrec;
+    if (b_desc + b_pose + b_g2d > kScratchBytes)
+        return fail(ctx, GSR_E_CAPACITY,
+                    "gsr_render_backward_noalloc: needs %zu bytes of scratch (%zu records, %d nodes), the static "
+                    "scratch holds %zu",
+                    b_desc + b_pose + b_g2d, nrec, sc->n_nodes, kScratchBytes);
+    hipSetDevice(ctx->device);
+    unsigned char* base = (unsigned char*)g_scratch_ptr[ctx->device];
+    return backward_launch(ctx, sc, d_rgb, d_depth, d_alpha, grads, d_poses, (float*)(base + b_desc + b_pose),
+                           (gsr_gaussian_grads*)base, (float*)(base + b_desc), (hipStream_t)stream);
 }
 
 int gsr_autotune(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_camera* cams, int32_t W, int32_t H,

@@ -67,13 +67,19 @@ def _oracle_grads(wl, weights, tw, th):
     return out
 
 
+def _np(x):
+    """float64 numpy copy of a tensor (any device) or array, flattened"""
+    if hasattr(x, "detach"):
+        x = x.detach().cpu().numpy()
+    return np.asarray(x, np.float64).reshape(-1)
+
+
 def _compare(gpu_grads, ref_grads, rel_l2=REL_L2, max_abs=MAX_ABS, groups=GROUPS):
     """Per parameter group: relative L2 error and max-abs error over max |g| (both asserted)."""
     worst = {}
     for k in groups:
-        g = np.concatenate([np.asarray(gg[k].detach().cpu().numpy() if hasattr(gg[k], "detach") else gg[k],
-                                       np.float64).reshape(-1) for gg in gpu_grads])
-        r = np.concatenate([np.asarray(rr[k], np.float64).reshape(-1) for rr in ref_grads])
+        g = np.concatenate([_np(gg[k]) for gg in gpu_grads])
+        r = np.concatenate([_np(rr[k]) for rr in ref_grads])
         nr = np.linalg.norm(r)
         rel = np.linalg.norm(g - r) / max(nr, 1e-30)
         mx = np.abs(g - r).max() / max(np.abs(r).max(), 1e-30)

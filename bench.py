@@ -9,11 +9,17 @@ launch).  Inputs are seeded and synthetic (the paper's scanned scenes stand in b
 
 Printed (one JSON line on stdout):
   value            batched RGB-D Mpixels/s (one hipGraph launch per step), inputs resident
+  gate             sampled pixels of images of the last timed step against the FP64 oracle,
+                   and the device status after every timed pose set
+  persistent       the same step with the persistent compositor
   per_camera_loop  the same frames rendered by one eager call per (env, camera)
   fwd_bwd_ms_per_view   forward + L1 loss + backward, 500k Gaussians SH3, 8 views 640x480,
                    divided by 8
+  configs          the plain (20k, 128x128), single-background (1M, 640x480) and composed
+                   (2M + 8 x 50k, 3 x 640x480) workloads, timed the same way
   roofline         the step's dominant kernel against its bound (work model: roofline())
-  cpu_baseline     the CPU oracle on a bounded sample of the same workload
+  cpu_baseline     the CPU oracle on the same workload (all envs within its time budget),
+                   with its algorithmic Gaussian-pixel evaluation count
 Progress goes to stderr.
 """
 import argparse
@@ -51,6 +57,11 @@ def parse():
     ap.add_argument("--no-loop", action="store_true")
     ap.add_argument("--no-fwdbwd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-gate", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--config-steps", type=int, default=10)
+    ap.add_argument("--cpu-budget", type=float, default=30.0, help="seconds of oracle work at most")
     ap.add_argument("--fwdbwd-only", action="store_true",
                     help="only the differentiable workload (for profiling it alone); prints its record")
     ap.add_argument("--tile", default="auto", help="auto (autotuner) or WxH")
@@ -108,12 +119,13 @@ def main():
     cams = gsr.cameras_tensor([c for e in wl["envs"] for c in e["cams"]], dev)
     # per-step object poses: fresh random SE(3) for every object node, background identity
     S = max(args.steps, 1) + args.warmup
-    pose_sets = []
+    pose_np, pose_sets = [], []
     for s in range(min(S, 32)):
         ps = []
         for e in range(E):
             R, t = synth.object_poses(4, 100000 + 977 * s + e)
             ps += [poses0[e * 5]] + [(R[k], t[k]) for k in range(4)]
+        pose_np.append(ps)
         pose_sets.append(gsr.poses_tensor(ps, dev))
     torch.cuda.synchronize()
     log(f"[bench] uploaded in {time.time() - t0:.1f}s")
@@ -132,32 +144,25 @@ def main():
     fl_pers = gsr.FLAG_PERSISTENT if pers else 0
     rgb, depth, alpha = gsr.render_rgbd(ctx, scene, cams, W, H, C, flags=gsr.FLAG_CHECK | fl_pers)
     out = (rgb, depth, alpha)
-    # warm-up (also captures the graph)
-    for s in range(args.warmup):
-        poses.copy_(pose_sets[s % len(pose_sets)])
-        gsr.render_rgbd(ctx, scene, cams, W, H, C, out=out, flags=gsr.FLAG_GRAPH | fl_pers)
-    torch.cuda.synchronize()
+    ms = timed_graph(gsr, ctx, scene, cams, W, H, C, out, poses, pose_sets, fl_pers, args)
     st = gsr.query_status(ctx)
-    if st["flags"]:
-        # grow capacity (pair count varies with the poses) and capture again
-        gsr.render_rgbd(ctx, scene, cams, W, H, C, out=out, flags=gsr.FLAG_CHECK | fl_pers)
-    # timed region
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    for s in range(args.steps):
-        poses.copy_(pose_sets[(args.warmup + s) % len(pose_sets)])
-        gsr.render_rgbd(ctx, scene, cams, W, H, C, out=out, flags=gsr.FLAG_GRAPH | fl_pers)
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / max(args.steps, 1)
-    st = gsr.query_status(ctx)
-    if st["flags"]:
-        raise SystemExit(f"bench: device status {st} after the timed region (capacity overflow)")
     px_step = E * C * W * H
     value = px_step / (ms * 1e-3) / 1e6
-    log(f"[bench] batched: {ms:.3f} ms/step, {value:.1f} Mpx/s, pairs {st['pairs']}, evals {st['evals']}")
+    log(f"[bench] batched: {ms:.3f} ms/step, {value:.1f} Mpx/s, pairs {st['pairs']}")
+    # correctness gate on what was timed: the device status after each timed pose set, then
+    # sampled pixels of images of the last timed step against the FP64 oracle
+    gate = None if args.no_gate else timed_gate(gsr, ctx, scene, cams, wl, out, poses, pose_sets, pose_np, fl_pers,
+                                                (tw, th), args)
+    if gate is not None:
+        log(f"[bench] gate: {gate}")
+    # the other compositor (persistent or one block per tile), same graph protocol
+    other = {}
+    if not args.no_variants:
+        fl_o = 0 if pers else gsr.FLAG_PERSISTENT
+        ms_o = timed_graph(gsr, ctx, scene, cams, W, H, C, out, poses, pose_sets, fl_o, args)
+        other = {"persistent" if not pers else "one_block_per_tile":
+                 {"ms_per_step": round(ms_o, 4), "value": round(px_step / (ms_o * 1e-3) / 1e6, 2)}}
+        log(f"[bench] other compositor: {other}")
 
     # per-stage durations (eager, HIP events between stages on the render stream)
     # (the same kernels as the graph; evaluations are counted by a checked render of each pose set)
@@ -173,24 +178,37 @@ def main():
         evals += gsr.query_status(ctx)["evals"]
     st_t = dict(gsr.query_status(ctx))
     st_t["evals"] = evals // n_t
+    st_t["items"] = C * n_total
+    st_t["tiles"] = E * C * ((W + tw - 1) // tw) * ((H + th - 1) // th)
     log("[bench] stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stage.items()))
     ppt = ctx.config.pixels_per_thread
-    roof = roofline(stage, st_t, n_total, (tw, th, ppt, pers))
+    copy_gbs = copy_peak()
+    log(f"[bench] device copy: {copy_gbs} GB/s")
+    roof = roofline(stage, st_t, n_total, (tw, th, ppt, pers), copy_gbs)
 
     # per-camera loop on the same frames
     loop = None
     if not args.no_loop:
         loop = per_camera_loop(gsr, ctx, envs_t, wl, pose_sets, cams, args)
         log(f"[bench] per-camera loop: {loop}")
+    ctx.close()
 
     fwdbwd = None
     if not args.no_fwdbwd:
         fwdbwd = fwd_bwd(gsr, args)
         log(f"[bench] fwd+bwd: {fwdbwd}")
 
+    configs = None
+    if not args.no_configs:
+        configs = config_runs(gsr, args)
+        log(f"[bench] configs: {configs}")
+
     cpu = None
+    algo_evals = None
     if not args.no_cpu:
-        cpu = cpu_baseline(wl, tw, th)
+        # the oracle renders the first timed pose set (poses of the graph's first timed step)
+        wl_cpu = with_poses(wl, pose_np[args.warmup % len(pose_np)])
+        cpu, algo_evals = cpu_baseline(wl_cpu, tw, th, args.cpu_budget)
         log(f"[bench] cpu baseline: {cpu}")
 
     line = {
@@ -209,24 +227,199 @@ def main():
         "config": {"workload": f"batched: {E} envs x {C} cams 320x240 RGB-D, background 100k-1M Gaussians "
                                f"(log-uniform) + 4 posed objects x 20k, SH3, fresh object poses per step",
                    "gaussians": n_total, "images": E * C, "pixels_per_step": px_step, "tile": f"{tw}x{th}",
-                   "persistent": bool(pers), "hipgraph": True, "seed": args.seed},
-        "gaussian_pixel_evals_per_s": round(st_t["evals"] / (stage["composite"] * 1e-3), 1) if stage["composite"] else None,
-        "evals_per_step": st_t["evals"],
+                   "pixels_per_lane": ppt, "persistent": bool(pers), "hipgraph": True, "seed": args.seed},
+        "gate": gate,
+        "compositor_variant": other or None,
+        "gaussian_pixel_evals_per_s": evals_rates(st_t["evals"], algo_evals, stage["composite"]),
+        "evals_per_step": {"executed": st_t["evals"], "algorithmic": algo_evals},
         "pairs_per_step": st_t["pairs"],
         "stage_ms": {k: round(v, 4) for k, v in stage.items()},
         "per_camera_loop": loop,
         "batched_over_loop": round(value / loop["value"], 2) if loop else None,
         "fwd_bwd_ms_per_view": fwdbwd["ms_per_view"] if fwdbwd else None,
         "fwd_bwd": fwdbwd,
-        "parity": "pixels within 1e-4 of the FP64 oracle and keys/ranges bit-exact: tests/test_gpu_forward.py "
-                  "(full frames at reduced Gaussian counts, sampled pixels at full size)",
+        "configs": configs,
+        "parity": "pixels within 1e-4 of the FP64 oracle and keys/ranges bit-exact; gradients within 1e-5 rel-L2: "
+                  "tests/test_gpu_forward.py, tests/test_gpu_fullsize.py, tests/test_gpu_backward.py; this run: gate",
         "roofline": roof,
         "cpu_baseline": cpu,
         "context": "paper: 650 FPS RGB-D 640x480 total over 5 cameras on RTX 6000 Ada (whole simulator), "
                    "i.e. ~200 Mpixels/s; not the same workload or hardware",
     }
     print(json.dumps(line), flush=True)
-    ctx.close()
+
+
+def with_poses(wl, pose_list):
+    """The workload with its node poses replaced (env-major list of (R, t))."""
+    envs = []
+    k = 0
+    for e in wl["envs"]:
+        n = len(e["nodes"])
+        envs.append(dict(e, poses=list(pose_list[k:k + n])))
+        k += n
+    return dict(wl, envs=envs)
+
+
+def timed_graph(gsr, ctx, scene, cams, W, H, C, out, poses, pose_sets, flags, args):
+    """Warm up (captures the graph), then time args.steps graph launches, each after copying
+    a fresh pose set into the pose buffer; returns ms per step."""
+    import torch
+    for s in range(args.warmup):
+        poses.copy_(pose_sets[s % len(pose_sets)])
+        gsr.render_rgbd(ctx, scene, cams, W, H, C, out=out, flags=gsr.FLAG_GRAPH | flags)
+    torch.cuda.synchronize()
+    if gsr.query_status(ctx)["flags"]:
+        # grow capacity (the pair count varies with the poses) and capture again
+        for ps in pose_sets:
+            poses.copy_(ps)
+            gsr.render_rgbd(ctx, scene, cams, W, H, C, out=out, flags=gsr.FLAG_CHECK | flags)
+        gsr.render_rgbd(ctx, scene, cams, W, H, C, out=out, flags=gsr.FLAG_GRAPH | flags)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for s in range(args.steps):
+        poses.copy_(pose_sets[(args.warmup + s) % len(pose_sets)])
+        gsr.render_rgbd(ctx, scene, cams, W, H, C, out=out, flags=gsr.FLAG_GRAPH | flags)
+    ev1.record()
+    torch.cuda.synchronize()
+    st = gsr.query_status(ctx)
+    if st["flags"]:
+        raise SystemExit(f"bench: device status {st} after the timed region (capacity overflow)")
+    return ev0.elapsed_time(ev1) / max(args.steps, 1)
+
+
+def timed_gate(gsr, ctx, scene, cams, wl, out, poses, pose_sets, pose_np, flags, tile, args, sample=1500):
+    """Replay the graph once per pose set the timed region used, reading the device status
+    after each (an overflowed step would have been timed with dropped tiles); then compare
+    sampled pixels of three images of the last timed step with the FP64 oracle (a pixel passes
+    within 1e-4 of the oracle, or of its flipped branch where a blending decision lies within
+    the FP32 bound of its threshold)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    E, C, W, H = len(wl["envs"]), wl["cams_per_env"], wl["width"], wl["height"]
+    used = sorted({(args.warmup + s) % len(pose_sets) for s in range(args.steps)})
+    bad_status = []
+    for i in used:
+        poses.copy_(pose_sets[i])
+        gsr.render_rgbd(ctx, scene, cams, W, H, C, out=out, flags=gsr.FLAG_GRAPH | flags)
+        st = gsr.query_status(ctx)
+        if st["flags"]:
+            bad_status.append(i)
+    last = (args.warmup + args.steps - 1) % len(pose_sets)
+    poses.copy_(pose_sets[last])
+    gsr.render_rgbd(ctx, scene, cams, W, H, C, out=out, flags=gsr.FLAG_GRAPH | flags)
+    torch.cuda.synchronize()
+    rgb, depth, alpha = (t.cpu().numpy() for t in out)
+    wl_last = with_poses(wl, pose_np[last])
+    tw, th = tile
+    images = [(0, 0), (E // 2, C - 1), (E - 1, 0)]
+    res = dict(pose_sets_checked=len(used), status_failures=len(bad_status), images=[], pixels=0, ambiguous=0,
+               excluded=0, max_err=0.0, failures=0)
+    gid = np.cumsum([0] + [sum(len(n["means"]) for n in e["nodes"]) for e in wl["envs"]])
+    for e, c in images:
+        env = wl_last["envs"][e]
+        cam = env["cams"][c]
+        fe = oracle.FlatEnv(env)
+        rect, zb, vis = oracle.keyspec(fe, cam, W, H, tw, th)
+        geo = oracle.project(fe, cam, W, H)
+        _, _, lv, ranges = oracle.pairs(rect, zb, vis, W, H, tw, th, image=e * C + c, gid_base=int(gid[e]))
+        pix = np.sort(np.random.default_rng(1000 + e * C + c).choice(W * H, size=sample, replace=False))
+        ref = oracle.composite_sample(geo, ranges, lv, W, H, tw, th, cam["bg"], pix)
+        got = np.concatenate([rgb[e, c].reshape(-1, 3)[pix], depth[e, c].reshape(-1, 1)[pix],
+                              alpha[e, c].reshape(-1, 1)[pix]], axis=1).astype(np.float64)
+        want = np.concatenate([ref["rgb"], ref["depth"][:, None], ref["alpha"][:, None]], axis=1)
+        err = np.abs(got - want).max(axis=1)
+        err_alt = np.abs(got - ref["alt"]).max(axis=1)
+        amb = (ref["flags"] & 1) != 0
+        exc = (ref["flags"] & 2) != 0
+        ok = (err <= 1e-4) | (amb & (err_alt <= 1e-4)) | exc
+        res["images"].append(e * C + c)
+        res["pixels"] += int(pix.size)
+        res["ambiguous"] += int(amb.sum())
+        res["excluded"] += int(exc.sum())
+        res["failures"] += int((~ok).sum())
+        res["max_err"] = max(res["max_err"], float(err[~amb & ~exc].max()) if (~amb & ~exc).any() else 0.0)
+    res["max_err"] = float(f"{res['max_err']:.3g}")
+    res["pass"] = res["failures"] == 0 and res["status_failures"] == 0
+    return res
+
+
+def copy_peak(mib=1024, reps=10):
+    """Measured device-to-device copy rate (GB/s of read + write bytes) of a 1 GiB copy."""
+    import torch
+    n = mib * 2 ** 20 // 4
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    del src, dst
+    return round(2 * 4 * n / (ms * 1e-3) / 1e9, 1)
+
+
+def evals_rates(executed, algorithmic, composite_ms):
+    if not composite_ms:
+        return None
+    t = composite_ms * 1e-3
+    return {"algorithmic": round(algorithmic / t, 1) if algorithmic else None, "executed": round(executed / t, 1)}
+
+
+def config_runs(gsr, args):
+    """The plain, single-background and composed workloads: one hipGraph launch per step
+    (fresh object poses per step for the composed one), tile shape from the autotuner (16x16
+    for the plain workload, as it specifies)."""
+    import numpy as np
+    import torch
+
+    import synth
+    res = {}
+    for cfg in (0, 1, 2):
+        wl = synth.scene_config(cfg, seed=args.seed)
+        E, C, W, H = len(wl["envs"]), wl["cams_per_env"], wl["width"], wl["height"]
+        envs_t = [upload_nodes(e["nodes"], "cuda") for e in wl["envs"]]
+        base = [p for e in wl["envs"] for p in e["poses"]]
+        poses = gsr.poses_tensor(base)
+        cams = gsr.cameras_tensor([c for e in wl["envs"] for c in e["cams"]])
+        sets = []
+        for s in range(8):
+            if cfg == 2:
+                R, t = synth.object_poses(8, 200000 + 31 * s)
+                sets.append(gsr.poses_tensor([base[0]] + [(R[k], t[k]) for k in range(8)]))
+            else:
+                sets.append(poses.clone())
+        ctx = gsr.create(0)
+        try:
+            scene = gsr.compose_scene(ctx, envs_t, poses)
+            if cfg == 0:
+                tw, th, pers = 16, 16, False
+            else:
+                (tw, th), pers = gsr.autotune(ctx, scene, cams, W, H)
+            fl = gsr.FLAG_PERSISTENT if pers else 0
+            for ps in sets:  # capacity for every pose set
+                poses.copy_(ps)
+                out = gsr.render_rgbd(ctx, scene, cams, W, H, C, flags=gsr.FLAG_CHECK | fl)
+            a = argparse.Namespace(warmup=2, steps=max(5, args.config_steps))
+            ms = timed_graph(gsr, ctx, scene, cams, W, H, C, out, poses, sets, fl, a)
+            st = gsr.query_status(ctx)
+            px = E * C * W * H
+            res[f"workload_{cfg}"] = {"workload": synth.CONFIG_NAMES[cfg], "ms_per_step": round(ms, 4),
+                                      "Mpixels_per_s": round(px / (ms * 1e-3) / 1e6, 2), "tile": f"{tw}x{th}",
+                                      "persistent": bool(pers), "pairs": st["pairs"], "visible": st["visible"]}
+        finally:
+            ctx.close()
+        del envs_t
+        torch.cuda.empty_cache()
+    return res
 
 
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
@@ -248,33 +441,45 @@ def measured_traffic():
     return rec["kernels"] if h.hexdigest() == rec["sources_sha256"] else None
 
 
-def roofline(stage, st, n_total, cfg):
-    """Dominant kernel of the step against its bound (algorithmic work from device counters).
+def roofline(stage, st, n_total, cfg, copy_gbs):
+    """Dominant kernel of the step against its bound (unit counts from device counters).
 
-    Algorithmic work per unit: projection reads 44 B per Gaussian (mean, opacity, scales,
-    quaternion), 12 K B of SH per Gaussian visible from any camera, and writes 64 B per visible
-    (image, Gaussian) (48 B record + 16 B visible-list entry); the depth sort copies each 16 B
-    list entry into its image's segment, then makes four radix passes, each reading the 4 B key
-    for the histogram, reading the 16 B (key, id, rectangle) record and writing it (the last
-    pass writes only id and rectangle, 12 B: nothing reads the sorted keys); chunking
-    and tile counting read the 8 B rectangle three times and emission the 8 B rectangle and
-    4 B id per visible record, and emission writes the 4 B Gaussian id per pair; the
-    compositor does at least OPS_PER_EVAL VALU lane-operations per Gaussian-pixel evaluation.
+    Algorithmic bytes per unit (the job's, independent of this implementation):
+      projection     12 B per Gaussian (position, for the visibility cull) + 224 B per
+                     Gaussian visible from some camera (the rest of its SH3 parameters)
+                     + 52 B per visible (image, Gaussian) projected record + 8 B per
+                     (image, Gaussian) item (count and offset)
+      whole forward before compositing (projection, sort, emission, ranges): the above
+                     + 12 B per pair (emission) + 24 B per pair per sort pass + 8 B per tile,
+                     with one pass (the floor) and with ceil(key bits / 8) = 6 passes
+      compositor     OPS_PER_EVAL VALU lane-operations per Gaussian-pixel evaluation
+    The implementation's own bytes (what its kernels must move) are reported beside them:
+    projection 44 B per Gaussian + 12 K B of SH per Gaussian visible from some camera + 64 B
+    written per visible (image, Gaussian) (48 B record, 16 B list entry); depth sort: the 16 B
+    list entry copied into the image's segment, then four radix passes each reading the 4 B
+    key (histogram) and reading and writing the 16 B entry (12 B written in the last);
+    emission: the 8 B rectangle read three times (chunking, counts) and the 12 B (rectangle,
+    id) once, 4 B written per pair.  A stage whose counter traffic is below its bytes kept its
+    working set in the 256 MB last-level cache (flagged "mall_resident").
     """
     K = 16
     visible, visible_any, pairs, evals = st["visible"], st["visible_any"], st["pairs"], st["evals"]
-    work = {
+    items, tiles = st["items"], st["tiles"]
+    alg_project = 12 * n_total + 224 * visible_any + 52 * visible + 8 * items
+    own = {
         "project": ("hbm", 44 * n_total + 12 * K * visible_any + 64 * visible),
         "sort": ("hbm", (32 + 4 * (4 + 16) + 3 * 16 + 12) * visible),
         "emit": ("hbm", 3 * 8 * visible + 12 * visible + 4 * pairs),
         "composite": ("alu", evals * OPS_PER_EVAL),
     }
     times = {"project": stage["project"], "sort": stage["gather"] + stage["depth_sort"],
-             "emit": stage["chunks"] + stage["tile_counts"] + stage["emit"], "composite": stage["composite"]}
+             "emit": stage["chunks"] + stage["tile_counts"] + stage["tile_ranges"] + stage["emit"],
+             "composite": stage["composite"]}
     tw, th, ppt, pers = cfg
     # kernel names as the profiler prints them, without the parameter list; the timed region
     # composites without evaluation counting
-    kname = {"project": ["k_project<3>"], "emit": ["k_pair_blocks", "k_pair_scan", "k_chunk_starts", "k_tile_counts", "k_emit"],
+    kname = {"project": ["k_project<3>"],
+             "emit": ["k_pair_blocks", "k_pair_scan", "k_chunk_starts", "k_tile_counts", "k_tile_ranges", "k_emit"],
              "composite": [f"k_composite{'_persistent' if pers else ''}<{tw}, {th}, {ppt}, false, false>"]}
     traffic = measured_traffic()
     if traffic is not None:
@@ -288,36 +493,57 @@ def roofline(stage, st, n_total, cfg):
             return None
         return sum(traffic[n]["fetch_bytes"] + traffic[n]["write_bytes"] for n in names)
 
+    units = {"gaussians": n_total, "visible_any": visible_any, "visible_records": visible, "items": items,
+             "pairs": pairs, "tiles": tiles, "evals": evals}
     # the dominant single kernel (the sort and emission stages are several launches)
     dom = max(("project", "composite"), key=times.get)
     t = times[dom] * 1e-3
-    bound, amount = work[dom]
-    ach = amount / t / 1e9
-    if bound == "hbm":
-        r = {"kernel": kname[dom][0], "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-             "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": kernel_traffic(dom), "algorithmic_bytes": int(amount)}
+    if dom == "project":
+        ach = alg_project / t / 1e9
+        tr = kernel_traffic("project")
+        r = {"kernel": kname["project"][0], "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
+             "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": tr, "algorithmic_bytes": int(alg_project),
+             "bytes_per_unit": {"gaussian": 12, "visible_any": 224, "visible_record": 52, "item": 8},
+             "copy_peak_GBs": copy_gbs, "frac_of_copy_peak": round(ach / copy_gbs, 4) if copy_gbs else None,
+             "own_model": {"algorithmic_bytes": int(own["project"][1]),
+                           "GB/s": round(own["project"][1] / t / 1e9, 1),
+                           "frac": round(own["project"][1] / t / 1e9 / PEAK_HBM_GBS, 4)}}
     else:
-        r = {"kernel": kname[dom][0], "bound": "alu", "achieved": round(ach, 1), "peak": round(PEAK_VALU_GOPS, 1),
+        amount = own["composite"][1]
+        ach = amount / t / 1e9
+        r = {"kernel": kname["composite"][0], "bound": "alu", "achieved": round(ach, 1), "peak": round(PEAK_VALU_GOPS, 1),
              "unit": "Gop/s (VALU lane-ops)", "frac": round(ach / PEAK_VALU_GOPS, 4),
-             "traffic": kernel_traffic(dom), "evals": int(evals), "ops_per_eval": OPS_PER_EVAL}
+             "traffic": kernel_traffic("composite"), "evals": int(evals), "ops_per_eval": OPS_PER_EVAL}
     r["kernel_ms"] = round(times[dom], 4)
+    r["units"] = units
     r["others"] = {}
     for k in times:
         if k == dom or times[k] <= 0:
             continue
-        b, amt = work[k]
         tk = times[k] * 1e-3
-        o = {"bound": b, "ms": round(times[k], 4), "traffic": kernel_traffic(k)}
-        if b == "hbm":
-            o.update({"GB/s": round(amt / tk / 1e9, 1), "frac": round(amt / tk / 1e9 / PEAK_HBM_GBS, 4),
-                      "algorithmic_bytes": int(amt)})
+        tr = kernel_traffic(k)
+        o = {"ms": round(times[k], 4), "traffic": tr}
+        if k == "project":
+            o.update({"bound": "hbm", "algorithmic_bytes": int(alg_project), "GB/s": round(alg_project / tk / 1e9, 1),
+                      "frac": round(alg_project / tk / 1e9 / PEAK_HBM_GBS, 4)})
+        elif k == "composite":
+            amt = own["composite"][1]
+            o.update({"bound": "alu", "Gop/s": round(amt / tk / 1e9, 1), "frac": round(amt / tk / 1e9 / PEAK_VALU_GOPS, 4)})
         else:
-            o.update({"Gop/s": round(amt / tk / 1e9, 1), "frac": round(amt / tk / 1e9 / PEAK_VALU_GOPS, 4)})
+            amt = own[k][1]
+            o.update({"bound": "hbm", "own_bytes": int(amt), "GB/s": round(amt / tk / 1e9, 1),
+                      "frac": round(amt / tk / 1e9 / PEAK_HBM_GBS, 4)})
+            if tr is not None:
+                o["mall_resident"] = tr < amt
         r["others"][k] = o
-    pb = work["project"][1] + work["emit"][1] + work["sort"][1]
     tp = (times["project"] + times["emit"] + times["sort"]) * 1e-3
-    r["project_emit_sort"] = {"GB/s": round(pb / tp / 1e9, 1), "frac": round(pb / tp / 1e9 / PEAK_HBM_GBS, 4),
-                              "ms": round(tp * 1e3, 4)}
+    fwd = {}
+    for passes in (1, 6):
+        b = alg_project + 12 * pairs + 24 * pairs * passes + 8 * tiles
+        fwd[f"passes_{passes}"] = {"algorithmic_bytes": int(b), "GB/s": round(b / tp / 1e9, 1),
+                                   "frac": round(b / tp / 1e9 / PEAK_HBM_GBS, 4)}
+    fwd["ms"] = round(tp * 1e3, 4)
+    r["project_sort_emit"] = fwd
     return r
 
 
@@ -427,25 +653,42 @@ def fwd_bwd(gsr, args):
         ctx.close()
 
 
-def cpu_baseline(wl, tw, th, budget_s=10.0):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(wl, tw, th, budget_s=30.0):
     """The FP64 CPU oracle, timed on the host, on full frames of the workload's envs in order
-    until about ``budget_s`` seconds of CPU work (or every env) are done."""
+    until every env is done or ``budget_s`` seconds have passed.  Also returns the oracle's
+    algorithmic Gaussian-pixel evaluation count (per pixel, the entries of its tile's list up
+    to and including its stopping one), for the whole step when every env was rendered."""
     import oracle
     W, H, C = wl["width"], wl["height"], wl["cams_per_env"]
     t0 = time.time()
-    px = n_envs = 0
+    px = n_envs = evals = 0
     for env in wl["envs"]:
         fe = oracle.FlatEnv(env)
         for cam in env["cams"]:
-            oracle.render(env, cam, W, H, tw, th, fe=fe)
+            r = oracle.render(env, cam, W, H, tw, th, fe=fe)
+            evals += int(r["evals"].sum())
             px += W * H
         n_envs += 1
         if time.time() - t0 >= budget_s:
             break
     dt = time.time() - t0
-    return {"value": round(px / dt / 1e6, 4), "unit": "Mpixels/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"first {n_envs} of {len(wl['envs'])} envs x {C} cams, full {W}x{H} frames ({px} pixels), "
-                      f"projection + key sort + FP64 compositing, {dt:.1f} s"}
+    complete = n_envs == len(wl["envs"])
+    return ({"value": round(px / dt / 1e6, 4), "unit": "Mpixels/s", "cores": oracle.num_threads(), "kind": "oracle",
+             "cpu_model": cpu_model(), "evals_per_s": round(evals / dt, 1),
+             "sample": f"{'all' if complete else 'first'} {n_envs} of {len(wl['envs'])} envs x {C} cams, full "
+                       f"{W}x{H} frames ({px} pixels) of the first timed step's poses, projection + key sort + FP64 "
+                       f"compositing, {dt:.1f} s"},
+            evals if complete else None)
 
 
 if __name__ == "__main__":

@@ -22,7 +22,7 @@ import numpy as np
 __all__ = [
     "rng", "gaussians_uniform_cube", "gaussians_room", "gaussians_object",
     "random_rotation", "object_poses", "look_at", "camera", "ring_cameras",
-    "scene_config", "CONFIG_NAMES",
+    "scene_config", "CONFIG_NAMES", "augment_params", "overlay_frames",
 ]
 
 C0 = 0.5 / math.sqrt(math.pi)
@@ -211,3 +211,37 @@ def scene_config(cfg, seed=0, scale=1.0, n_envs=None):
         return dict(envs=[dict(nodes=[bg], poses=[(eye3, z3)], cams=cams)], cams_per_env=8,
                     width=640, height=480)
     raise ValueError(f"unknown workload {cfg}")
+
+
+def augment_params(n_images, seed, overlay_max=0.5, hue=0.05, sat=(0.7, 1.3), val=(0.7, 1.3), gamma=(0.7, 1.4)):
+    """Per-image draws of the image-space augmentation, [n, 5] float32:
+    overlay weight U(0, overlay_max), hue shift U(-hue, hue) turns, saturation and value scales
+    uniform in their ranges, gamma log-uniform in its range."""
+    g = rng(seed)
+    p = np.empty((n_images, 5), np.float32)
+    p[:, 0] = g.uniform(0.0, overlay_max, n_images)
+    p[:, 1] = g.uniform(-hue, hue, n_images)
+    p[:, 2] = g.uniform(sat[0], sat[1], n_images)
+    p[:, 3] = g.uniform(val[0], val[1], n_images)
+    p[:, 4] = np.exp(g.uniform(math.log(gamma[0]), math.log(gamma[1]), n_images))
+    return p
+
+
+def overlay_frames(n_images, height, width, seed):
+    """Stand-ins for video crops: per image a few random low-frequency colour waves plus pixel
+    noise, in [0, 1], [n, H, W, 3] float32."""
+    g = rng(seed)
+    yy, xx = np.meshgrid(np.arange(height, dtype=np.float32) / height, np.arange(width, dtype=np.float32) / width,
+                         indexing="ij")
+    out = np.empty((n_images, height, width, 3), np.float32)
+    for i in range(n_images):
+        img = np.full((height, width, 3), 0.5, np.float32)
+        for _ in range(3):
+            f = g.uniform(0.5, 4.0, 2).astype(np.float32)
+            ph = g.uniform(0, 2 * math.pi, 3).astype(np.float32)
+            amp = g.uniform(0.05, 0.25, 3).astype(np.float32)
+            w = np.sin(2 * np.float32(math.pi) * (f[0] * xx + f[1] * yy))
+            img += amp * np.stack([np.sin(w + ph[k]) for k in range(3)], axis=-1)
+        img += np.float32(0.05) * g.standard_normal((height, width, 3), dtype=np.float32)
+        out[i] = np.clip(img, 0.0, 1.0)
+    return out

@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--no-gate", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--no-augment", action="store_true")
     ap.add_argument("--config-steps", type=int, default=10)
     ap.add_argument("--cpu-budget", type=float, default=30.0, help="seconds of oracle work at most")
     ap.add_argument("--fwdbwd-only", action="store_true",
@@ -186,6 +187,10 @@ def main():
     log(f"[bench] device copy: {copy_gbs} GB/s")
     roof = roofline(stage, st_t, n_total, (tw, th, ppt, pers), copy_gbs)
 
+    aug = None if args.no_augment else augment_run(gsr, ctx, scene, cams, wl, out, poses, pose_sets, fl_pers, args)
+    if aug is not None:
+        log(f"[bench] augmentation: {aug}")
+
     # per-camera loop on the same frames
     loop = None
     if not args.no_loop:
@@ -234,6 +239,7 @@ def main():
         "evals_per_step": {"executed": st_t["evals"], "algorithmic": algo_evals},
         "pairs_per_step": st_t["pairs"],
         "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+        "augmentation": aug,
         "per_camera_loop": loop,
         "batched_over_loop": round(value / loop["value"], 2) if loop else None,
         "fwd_bwd_ms_per_view": fwdbwd["ms_per_view"] if fwdbwd else None,
@@ -345,6 +351,37 @@ def timed_gate(gsr, ctx, scene, cams, wl, out, poses, pose_sets, pose_np, flags,
     res["max_err"] = float(f"{res['max_err']:.3g}")
     res["pass"] = res["failures"] == 0 and res["status_failures"] == 0
     return res
+
+
+def augment_run(gsr, ctx, scene, cams, wl, out, poses, pose_sets, flags, args, reps=20):
+    """Image-space domain randomisation of the step's frames (overlay, HSV jitter, gamma):
+    fused into the compositor's epilogue (the step's graph with the augmentation bound), and
+    as a separate pass over finished frames, which is HBM-bound: 12 B of rgb and 12 B of
+    overlay read and 12 B written per pixel."""
+    import torch
+
+    import synth
+    E, C, W, H = len(wl["envs"]), wl["cams_per_env"], wl["width"], wl["height"]
+    ov = torch.from_numpy(synth.overlay_frames(E * C, H, W, 77)).cuda().reshape(E, C, H, W, 3).contiguous()
+    params = gsr.augment_tensor(synth.augment_params(E * C, 78))
+    gsr.set_augment(ctx, params, ov)
+    ms_fused = timed_graph(gsr, ctx, scene, cams, W, H, C, out, poses, pose_sets, flags | gsr.FLAG_AUGMENT, args)
+    dst = torch.empty_like(out[0])
+    gsr.augment_rgb(ctx, out[0], params, ov, out=dst)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        gsr.augment_rgb(ctx, out[0], params, ov, out=dst)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    px = E * C * W * H
+    gbs = 36 * px / (ms * 1e-3) / 1e9
+    return {"fused_ms_per_step": round(ms_fused, 4), "separate_pass_ms": round(ms, 4),
+            "separate_pass": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                              "frac": round(gbs / PEAK_HBM_GBS, 4), "algorithmic_bytes": 36 * px}}
 
 
 def copy_peak(mib=1024, reps=10):

@@ -112,8 +112,12 @@ enum {
                                         Capacity must already suffice (overflow is reported). */
     GSR_FLAG_PERSISTENT = 1u << 3,   /* composite with a persistent grid walking a longest-list-
                                         first queue of (image, tile) work items                */
-    GSR_FLAG_TIMING = 1u << 4        /* record HIP events between the forward stages (eager
+    GSR_FLAG_TIMING = 1u << 4,       /* record HIP events between the forward stages (eager
                                         calls only); read them with gsr_stage_times          */
+    GSR_FLAG_AUGMENT = 1u << 5       /* apply the image-space augmentation bound by
+                                        gsr_set_augment to rgb in the compositor's epilogue
+                                        (not with GSR_FLAG_SAVE: the backward differentiates
+                                        the plain image)                                     */
 };
 
 /* Status word contents (gsr_query_status). */
@@ -157,6 +161,26 @@ typedef struct {
                                  at tile pixels / 64 (8x8 tiles use 1, 16x8 at most 2)       */
     int32_t reserved[6];
 } gsr_config;
+
+/* Per-image parameters of the image-space domain randomisation (Sec. IV-C,
+   "Domain Randomization": random video overlays linearly blended into the
+   stream, HSV-space augmentation, random gamma correction).  Applied per
+   pixel in this order to the rendered colour x (background included):
+     x = clamp(x, 0, 1); with an overlay frame o:
+     x = (1 - overlay_weight) x + overlay_weight clamp(o, 0, 1);
+     hexcone HSV of x (value = max channel, saturation = chroma / value, hue in
+     turns): hue + hue_shift modulo 1, saturation * saturation_scale and
+     value * value_scale each clamped to [0, 1], back to RGB;
+     out = x ^ gamma per channel.
+   32 bytes. */
+typedef struct {
+    float overlay_weight;    /* in [0, 1]; ignored without an overlay frame       */
+    float hue_shift;         /* turns (1 = 360 degrees)                           */
+    float saturation_scale;  /* >= 0                                              */
+    float value_scale;       /* >= 0                                              */
+    float gamma;             /* > 0                                               */
+    float reserved[3];
+} gsr_augment;
 
 /* ---- context ---------------------------------------------------------- */
 
@@ -280,6 +304,25 @@ int gsr_render_backward(gsr_context* ctx, const gsr_scene* scene, uint64_t rende
 int gsr_render_backward_noalloc(gsr_context* ctx, const gsr_scene* scene, uint64_t render_id,
                                 const float* d_rgb, const float* d_depth, const float* d_alpha,
                                 const gsr_gaussian_grads* grads, float* d_poses, void* stream);
+
+/* ---- image-space domain randomisation (Sec. IV-C) ----------------------- */
+
+/* Augment `images` rendered frames: rgb [images][H][W][3] (DEVICE, read),
+   overlay [images][H][W][3] (DEVICE, nullable: no overlay; the caller cuts and
+   scales its video crops to the image size), params [images] gsr_augment
+   (DEVICE), out [images][H][W][3] (DEVICE; may equal rgb).  Asynchronous on
+   `stream`.  Errors: GSR_E_INVALID (NULL ctx, rgb, params or out; images < 1,
+   width or height outside 1..8192), GSR_E_HIP. */
+int gsr_augment_rgb(gsr_context* ctx, int32_t images, int32_t width, int32_t height, const float* rgb,
+                    const float* overlay, const gsr_augment* params, float* out, void* stream);
+
+/* Bind the augmentation that renders with GSR_FLAG_AUGMENT apply in the
+   compositor's epilogue (the same arithmetic as gsr_augment_rgb on the
+   rendered frame): params [images] (DEVICE, required), overlay
+   [images][H][W][3] (DEVICE, nullable), both read at every such render, so
+   the caller may redraw them in place between steps.  They must match the
+   image count and size of those renders.  Host only.  Errors: GSR_E_INVALID. */
+int gsr_set_augment(gsr_context* ctx, const gsr_augment* params, const float* overlay);
 
 /* ---- status, inspection ------------------------------------------------ */
 

@@ -24,6 +24,7 @@ FLAG_SAVE = 2
 FLAG_GRAPH = 4
 FLAG_PERSISTENT = 8
 FLAG_TIMING = 16
+FLAG_AUGMENT = 32
 STATUS_OVERFLOW = 1
 STAGES = ("views", "project", "gather", "depth_sort", "chunks", "tile_counts", "tile_ranges", "emit", "composite")
 
@@ -92,6 +93,8 @@ def lib():
         L.gsr_render_backward.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, vp, ctypes.POINTER(GaussianGrads), vp,
                                           vp]
         L.gsr_render_backward_noalloc.argtypes = L.gsr_render_backward.argtypes
+        L.gsr_augment_rgb.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
+        L.gsr_set_augment.argtypes = [vp, vp, vp]
         L.gsr_query_status.argtypes = [vp, ctypes.POINTER(StatusInfo)]
         L.gsr_copy_pairs.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(i64)]
         L.gsr_copy_pixel_state.argtypes = [vp, vp, vp]
@@ -334,6 +337,42 @@ def render_backward(ctx, scene, d_rgb, d_depth=None, d_alpha=None, grads=None, d
     _check(fn(ctx.handle, scene.handle, render_id, _ptr(d_rgb), _ptr(d_depth), _ptr(d_alpha), arr, _ptr(d_poses),
               _stream(stream)), ctx)
     return grads
+
+
+def augment_tensor(params, device="cuda"):
+    """Per-image augmentation draws [n, 5] (overlay weight, hue shift in turns, saturation
+    scale, value scale, gamma) -> the [n, 8] float32 rows of gsr_augment."""
+    import numpy as np
+    p = np.zeros((len(params), 8), np.float32)
+    p[:, :5] = np.asarray(params, np.float32).reshape(-1, 5)
+    return torch.from_numpy(p).to(device)
+
+
+def augment_rgb(ctx, rgb, params, overlay=None, out=None, stream=None):
+    """Image-space domain randomisation of rendered frames rgb [..., H, W, 3] (CUDA float32):
+    params [images, 8] (``augment_tensor``), overlay like rgb or None.  Returns ``out``."""
+    if not (rgb.is_cuda and rgb.dtype == torch.float32 and rgb.is_contiguous() and rgb.shape[-1] == 3):
+        raise TypeError("rgb must be a contiguous float32 CUDA tensor [..., H, W, 3]")
+    H, W = rgb.shape[-3], rgb.shape[-2]
+    images = rgb.numel() // (H * W * 3)
+    _dev_f32(params, (8,), "params")
+    if params.shape[0] != images:
+        raise ValueError(f"params has {params.shape[0]} rows for {images} images")
+    if overlay is not None and (tuple(overlay.shape) != tuple(rgb.shape) or not overlay.is_contiguous()
+                                or overlay.dtype != torch.float32):
+        raise ValueError("overlay must be a contiguous float32 tensor shaped like rgb")
+    out = torch.empty_like(rgb) if out is None else out
+    _check(lib().gsr_augment_rgb(ctx.handle, images, W, H, _ptr(rgb), _ptr(overlay), _ptr(params), _ptr(out),
+                                 _stream(stream)), ctx)
+    return out
+
+
+def set_augment(ctx, params, overlay=None):
+    """Bind the augmentation that renders with FLAG_AUGMENT apply in the compositor (the
+    tensors must stay alive and may be rewritten in place between renders)."""
+    _dev_f32(params, (8,), "params")
+    _check(lib().gsr_set_augment(ctx.handle, _ptr(params), _ptr(overlay)), ctx)
+    ctx._augment = (params, overlay)
 
 
 def query_status(ctx):

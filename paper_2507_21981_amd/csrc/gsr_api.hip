@@ -41,8 +41,11 @@ struct GraphKey {
     uint32_t flags;
     hipStream_t stream;
     long long pair_cap;
+    const void* aug;
+    const void* overlay;
     bool operator==(const GraphKey& o) const {
         return scene == o.scene && cams == o.cams && rgb == o.rgb && depth == o.depth && alpha == o.alpha &&
+               aug == o.aug && overlay == o.overlay &&
                C == o.C && W == o.W && H == o.H && tw == o.tw && th == o.th && persistent == o.persistent &&
                ppt == o.ppt &&
                flags == o.flags && stream == o.stream && pair_cap == o.pair_cap;
@@ -91,6 +94,8 @@ struct gsr_context {
     DevBuf<float> g2d;
     DevBuf<gsr_gaussian_grads> grads_dev;
     DevBuf<float> pose_part;
+    const gsr_augment* aug = nullptr;  // bound by gsr_set_augment for GSR_FLAG_AUGMENT renders
+    const float* overlay = nullptr;
     uint64_t render_serial = 0;  // renders issued on this context
     uint64_t saved_id = 0;       // serial of the render whose state backward may use (0: none)
     // last forward, for backward / inspection
@@ -524,10 +529,16 @@ int gsr_render_rgbd(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_
     if (r) return r;
     const int count = (flags & GSR_FLAG_CHECK) ? 1 : 0;
     a.count = count;
+    if (flags & GSR_FLAG_AUGMENT) {
+        if (save) return fail(ctx, GSR_E_INVALID, "gsr_render_rgbd: GSR_FLAG_AUGMENT with GSR_FLAG_SAVE");
+        if (!ctx->aug) return fail(ctx, GSR_E_INVALID, "gsr_render_rgbd: GSR_FLAG_AUGMENT without gsr_set_augment");
+        a.aug = ctx->aug;
+        a.overlay = ctx->overlay;
+    }
     ctx->last_stream = s;
     if (flags & GSR_FLAG_GRAPH) {
         GraphKey k{sc, cams, rgb, depth, alpha, C, W, H, ctx->cfg.tile_w, ctx->cfg.tile_h, persistent, a.ppt,
-                   flags, s, ctx->pair_cap};
+                   flags, s, ctx->pair_cap, a.aug, a.overlay};
         if (!(ctx->graph_valid && ctx->gkey == k)) {
             drop_graph(ctx);
             // capture on a private stream (the caller's may be the legacy default stream,
@@ -566,6 +577,10 @@ int gsr_render_rgbd(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_
             drop_graph(ctx);
             if ((r = prepare(ctx, sc, C, cams, W, H, rgb, depth, alpha, persistent, save, a))) return r;
             a.count = count;
+            if (flags & GSR_FLAG_AUGMENT) {
+                a.aug = ctx->aug;
+                a.overlay = ctx->overlay;
+            }
             if (flags & GSR_FLAG_TIMING) a.stage_events = ctx->stage_ev;
         }
         a.stage_events = nullptr;
@@ -577,6 +592,25 @@ int gsr_render_rgbd(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_
     ctx->last = a;
     ctx->last_scene = sc;
     ctx->last_scene_version = sc->version;
+    return GSR_OK;
+}
+
+int gsr_augment_rgb(gsr_context* ctx, int32_t images, int32_t W, int32_t H, const float* rgb, const float* overlay,
+                    const gsr_augment* params, float* out, void* stream) {
+    if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_augment_rgb: ctx is NULL");
+    if (!rgb || !params || !out) return fail(ctx, GSR_E_INVALID, "gsr_augment_rgb: NULL rgb, params or out");
+    if (images < 1 || W < 1 || H < 1 || W > 8192 || H > 8192)
+        return fail(ctx, GSR_E_INVALID, "gsr_augment_rgb: %d images of %dx%d", images, W, H);
+    hipSetDevice(ctx->device);
+    HIPCHK(ctx, launch_augment(images, W, H, rgb, overlay, params, out, ctx->num_cu, (hipStream_t)stream));
+    return GSR_OK;
+}
+
+int gsr_set_augment(gsr_context* ctx, const gsr_augment* params, const float* overlay) {
+    if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_set_augment: ctx is NULL");
+    if (!params) return fail(ctx, GSR_E_INVALID, "gsr_set_augment: params is NULL");
+    ctx->aug = params;
+    ctx->overlay = overlay;
     return GSR_OK;
 }
 

@@ -1334,9 +1334,16 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
         const float Tf = fabsf(T[p]);
         const int py = py0 + p * ST::LROWS;
         const size_t q = ((size_t)image * a.height + py) * a.width + px;
-        a.rgb[3 * q + 0] = fmaf(Tf, cm.bg[0], Cr[p]);
-        a.rgb[3 * q + 1] = fmaf(Tf, cm.bg[1], Cg[p]);
-        a.rgb[3 * q + 2] = fmaf(Tf, cm.bg[2], Cb[p]);
+        float r = fmaf(Tf, cm.bg[0], Cr[p]), g = fmaf(Tf, cm.bg[1], Cg[p]), b = fmaf(Tf, cm.bg[2], Cb[p]);
+        if (a.aug) {
+            const float3 o = augment_pixel(r, g, b, a.aug[image], a.overlay ? a.overlay + 3 * q : nullptr);
+            r = o.x;
+            g = o.y;
+            b = o.z;
+        }
+        a.rgb[3 * q + 0] = r;
+        a.rgb[3 * q + 1] = g;
+        a.rgb[3 * q + 2] = b;
         a.depth[q] = D[p];
         if (a.alpha) a.alpha[q] = 1.0f - Tf;
         if (SAVE) {
@@ -1410,6 +1417,29 @@ __global__ void k_copy_pairs(FwdArgs a, uint64_t* keys, uint32_t* vals, uint32_t
         keys[i] = ((unsigned long long)t << 32) | zb;
         vals[i] = gid;
     }
+}
+
+// image-space domain randomisation of finished frames, one thread per pixel (grid-stride)
+__global__ __launch_bounds__(256) void k_augment(size_t n_pix, size_t pix_per_image, const float* __restrict__ rgb,
+                                                 const float* __restrict__ overlay,
+                                                 const gsr_augment* __restrict__ params, float* out) {
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_pix; q += (size_t)gridDim.x * blockDim.x) {
+        const size_t image = q / pix_per_image;
+        const float r = rgb[3 * q + 0], g = rgb[3 * q + 1], b = rgb[3 * q + 2];
+        const float3 o = augment_pixel(r, g, b, params[image], overlay ? overlay + 3 * q : nullptr);
+        out[3 * q + 0] = o.x;
+        out[3 * q + 1] = o.y;
+        out[3 * q + 2] = o.z;
+    }
+}
+
+hipError_t launch_augment(int images, int width, int height, const float* rgb, const float* overlay,
+                          const gsr_augment* params, float* out, int num_cu, hipStream_t s) {
+    const size_t ppi = (size_t)width * height, n = ppi * (size_t)images;
+    const size_t want = (n + 255) / 256, cap = (size_t)num_cu * 16;
+    hipLaunchKernelGGL(k_augment, dim3((unsigned)std::max<size_t>(1, std::min(want, cap))), dim3(256), 0, s, n, ppi,
+                       rgb, overlay, params, out);
+    return hipGetLastError();
 }
 
 // --------------------------------------------------------------------------------------------

@@ -249,11 +249,70 @@ struct FwdArgs {
     uint32_t* n_contrib;
     int persistent;
     int persistent_grid;
+    const gsr_augment* aug;  // per image, applied to rgb in the compositor's epilogue, or null
+    const float* overlay;    // overlay frames [images][H][W][3] for aug, or null
     int ppt;   // pixels per compositor thread (1 or 2; 8x8 tiles use 1)
     int save;  // write per-pixel T_final and contributor counts for the backward
     int count; // count Gaussian-pixel evaluations into the status word
     hipEvent_t* stage_events;  // kStages + 1 events recorded between stages, or null
 };
+
+// Image-space domain randomisation of one pixel (the colour as rendered, background
+// included): clamp to [0, 1], blend with the overlay pixel ov (null: none), hexcone HSV with
+// the hue shifted modulo one turn and saturation and value scaled and clamped, back to RGB,
+// then each channel to the power gamma.  Pixel values only, so the hardware log2 / exp2
+// (about 1 ulp) serve for the power.
+__device__ inline float3 augment_pixel(float r, float g, float b, const gsr_augment& p, const float* ov) {
+    r = fminf(fmaxf(r, 0.0f), 1.0f);
+    g = fminf(fmaxf(g, 0.0f), 1.0f);
+    b = fminf(fmaxf(b, 0.0f), 1.0f);
+    if (ov) {
+        const float l = p.overlay_weight, k = 1.0f - l;
+        r = fmaf(l, fminf(fmaxf(ov[0], 0.0f), 1.0f), k * r);
+        g = fmaf(l, fminf(fmaxf(ov[1], 0.0f), 1.0f), k * g);
+        b = fmaf(l, fminf(fmaxf(ov[2], 0.0f), 1.0f), k * b);
+    }
+    const float v = fmaxf(r, fmaxf(g, b)), m = fminf(r, fminf(g, b)), c = v - m;
+    const float s = v > 0.0f ? c / v : 0.0f;
+    float h6 = 0.0f;  // hue in sixths of a turn
+    if (c > 0.0f) {
+        if (v == r) {
+            h6 = (g - b) / c;
+            if (h6 < 0.0f) h6 += 6.0f;
+        } else if (v == g) {
+            h6 = (b - r) / c + 2.0f;
+        } else {
+            h6 = (r - g) / c + 4.0f;
+        }
+    }
+    float h = fmaf(h6, 1.0f / 6.0f, p.hue_shift);
+    h -= floorf(h);
+    const float s2 = fminf(fmaxf(s * p.saturation_scale, 0.0f), 1.0f);
+    const float v2 = fminf(fmaxf(v * p.value_scale, 0.0f), 1.0f);
+    float H = h * 6.0f;
+    if (H >= 6.0f) H = 0.0f;
+    const float c2 = v2 * s2;
+    const float x2 = c2 * (1.0f - fabsf(H - 2.0f * floorf(0.5f * H) - 1.0f));
+    const float m2 = v2 - c2;
+    const int sector = (int)H;
+    float r2, g2, b2;
+    switch (sector) {
+        case 0: r2 = c2; g2 = x2; b2 = 0.0f; break;
+        case 1: r2 = x2; g2 = c2; b2 = 0.0f; break;
+        case 2: r2 = 0.0f; g2 = c2; b2 = x2; break;
+        case 3: r2 = 0.0f; g2 = x2; b2 = c2; break;
+        case 4: r2 = x2; g2 = 0.0f; b2 = c2; break;
+        default: r2 = c2; g2 = 0.0f; b2 = x2; break;
+    }
+    r2 += m2;
+    g2 += m2;
+    b2 += m2;
+    const float gm = p.gamma;
+    r2 = r2 > 0.0f ? __builtin_amdgcn_exp2f(gm * __builtin_amdgcn_logf(r2)) : 0.0f;
+    g2 = g2 > 0.0f ? __builtin_amdgcn_exp2f(gm * __builtin_amdgcn_logf(g2)) : 0.0f;
+    b2 = b2 > 0.0f ? __builtin_amdgcn_exp2f(gm * __builtin_amdgcn_logf(b2)) : 0.0f;
+    return make_float3(r2, g2, b2);
+}
 
 struct BwdArgs {
     FwdArgs f;
@@ -271,6 +330,8 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s);
 // raise the dynamic LDS limit of the kernels whose LDS grows with the tile grid (host side,
 // before launches or graph capture)
 hipError_t forward_lds_limits(const FwdArgs& a);
+hipError_t launch_augment(int images, int width, int height, const float* rgb, const float* overlay,
+                          const gsr_augment* params, float* out, int num_cu, hipStream_t s);
 hipError_t launch_copy_pairs(const FwdArgs& a, uint64_t* keys, uint32_t* values, uint32_t* ranges, hipStream_t s);
 // backward stages
 hipError_t launch_backward(const BwdArgs& a, size_t n_records, hipStream_t s);

@@ -22,7 +22,7 @@ import numpy as np
 __all__ = [
     "rng", "gaussians_uniform_cube", "gaussians_room", "gaussians_object",
     "random_rotation", "object_poses", "look_at", "camera", "ring_cameras",
-    "scene_config", "CONFIG_NAMES", "augment_params", "overlay_frames",
+    "scene_config", "CONFIG_NAMES", "augment_params", "overlay_frames", "mesh_sphere",
 ]
 
 C0 = 0.5 / math.sqrt(math.pi)
@@ -245,3 +245,33 @@ def overlay_frames(n_images, height, width, seed):
         img += np.float32(0.05) * g.standard_normal((height, width, 3), dtype=np.float32)
         out[i] = np.clip(img, 0.0, 1.0)
     return out
+
+
+def mesh_sphere(n_lat, n_lon, seed, radius=0.1, noise=0.05, degenerate=4):
+    """A closed latitude-longitude sphere mesh with radial noise (vertices [nv, 3] float32,
+    faces [nf, 3] int32, outward winding), per-vertex colours U(0, 1), and ``degenerate``
+    extra faces that repeat a vertex (zero area)."""
+    g = rng(seed)
+    verts = [[0.0, 0.0, radius], [0.0, 0.0, -radius]]
+    for i in range(1, n_lat):
+        th = math.pi * i / n_lat
+        for j in range(n_lon):
+            ph = 2 * math.pi * j / n_lon
+            verts.append([radius * math.sin(th) * math.cos(ph), radius * math.sin(th) * math.sin(ph),
+                          radius * math.cos(th)])
+    v = np.asarray(verts, np.float64)
+    v *= (1.0 + noise * g.standard_normal((len(v), 1)))
+    ring = lambda i, j: 2 + (i - 1) * n_lon + (j % n_lon)
+    faces = []
+    for j in range(n_lon):
+        faces.append([0, ring(1, j), ring(1, j + 1)])
+        faces.append([1, ring(n_lat - 1, j + 1), ring(n_lat - 1, j)])
+    for i in range(1, n_lat - 1):
+        for j in range(n_lon):
+            faces.append([ring(i, j), ring(i + 1, j), ring(i + 1, j + 1)])
+            faces.append([ring(i, j), ring(i + 1, j + 1), ring(i, j + 1)])
+    for k in range(degenerate):
+        i = int(g.integers(0, len(v)))
+        faces.append([i, i, int(g.integers(0, len(v)))])
+    colours = g.random((len(v), 3), dtype=np.float32)
+    return v.astype(np.float32), np.asarray(faces, np.int32), colours

@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-augment", action="store_true")
+    ap.add_argument("--no-mesh", action="store_true")
     ap.add_argument("--config-steps", type=int, default=10)
     ap.add_argument("--cpu-budget", type=float, default=30.0, help="seconds of oracle work at most")
     ap.add_argument("--fwdbwd-only", action="store_true",
@@ -208,6 +209,10 @@ def main():
         configs = config_runs(gsr, args)
         log(f"[bench] configs: {configs}")
 
+    mesh = None if args.no_mesh else mesh_run(gsr)
+    if mesh is not None:
+        log(f"[bench] mesh transfer: {mesh}")
+
     cpu = None
     algo_evals = None
     if not args.no_cpu:
@@ -245,6 +250,7 @@ def main():
         "fwd_bwd_ms_per_view": fwdbwd["ms_per_view"] if fwdbwd else None,
         "fwd_bwd": fwdbwd,
         "configs": configs,
+        "mesh_to_gaussians": mesh,
         "parity": "pixels within 1e-4 of the FP64 oracle and keys/ranges bit-exact; gradients within 1e-5 rel-L2: "
                   "tests/test_gpu_forward.py, tests/test_gpu_fullsize.py, tests/test_gpu_backward.py; this run: gate",
         "roofline": roof,
@@ -382,6 +388,37 @@ def augment_run(gsr, ctx, scene, cams, wl, out, poses, pose_sets, flags, args, r
     return {"fused_ms_per_step": round(ms_fused, 4), "separate_pass_ms": round(ms, 4),
             "separate_pass": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                               "frac": round(gbs / PEAK_HBM_GBS, 4), "algorithmic_bytes": 36 * px}}
+
+
+def mesh_run(gsr, reps=10):
+    """Mesh-to-Gaussian transfer of a 2M-facet sphere mesh with vertex colours (SH degree 0
+    output), bound by memory: per facet 12 B of indices read and 56 B of Gaussian written, per
+    vertex 24 B (position, colour) read once."""
+    import torch
+
+    import synth
+    v, f, col = synth.mesh_sphere(1000, 1000, 21, radius=0.2, degenerate=0)
+    vd, fd, cd = (torch.from_numpy(x).cuda() for x in (v, f, col))
+    ctx = gsr.create(0)
+    try:
+        gsr.mesh_to_gaussians(ctx, vd, fd, cd)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            gsr.mesh_to_gaussians(ctx, vd, fd, cd)  # synchronous: the events bracket memset, kernel, read-back
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+    finally:
+        ctx.close()
+    b = 68 * len(f) + 24 * len(v)
+    gbs = b / (ms * 1e-3) / 1e9
+    return {"faces": int(len(f)), "vertices": int(len(v)), "ms": round(ms, 4),
+            "Mfaces_per_s": round(len(f) / (ms * 1e-3) / 1e6, 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(gbs / PEAK_HBM_GBS, 4), "algorithmic_bytes": int(b)}}
 
 
 def copy_peak(mib=1024, reps=10):

@@ -305,6 +305,31 @@ int gsr_render_backward_noalloc(gsr_context* ctx, const gsr_scene* scene, uint64
                                 const float* d_rgb, const float* d_depth, const float* d_alpha,
                                 const gsr_gaussian_grads* grads, float* d_poses, void* stream);
 
+/* ---- mesh-to-Gaussian transfer (Sec. IV-B) ------------------------------ */
+
+/* Convert a triangle mesh (a node's textured mesh, node-local frame) into
+   Gaussians, one per facet (Sec. IV-B, "Mesh-Gaussian Transfer"): centre at
+   the facet's barycentre; rotation whose columns are the unit edge a->b, n x
+   t1 and the unit normal n = (b - a) x (c - a) / |..| (faces are (a, b, c));
+   scales (d, d, flatten * d) with d the mean distance from the barycentre to
+   the three vertices; opacity `opacity`; SH of degree sh_degree with the
+   degree-0 coefficient (mean vertex colour - 0.5) * 2 sqrt(pi) (grey 0.5
+   without vertex colours) and higher orders zero.  Degenerate facets (zero
+   area) get opacity 0 and the identity rotation.
+   vertices [n_vertices][3], vertex_colors [n_vertices][3] (nullable, in
+   [0, 1]), faces [n_faces][3] int32: DEVICE inputs.  out: DEVICE arrays of
+   n_faces Gaussians in the gsr_gaussians layout (means [n][3], scales [n][3],
+   quats [n][4] unit (w, x, y, z), opacities [n], sh [n][K][3]), given through
+   the non-const pointers of a gsr_gaussian_grads (NULL skips that array);
+   the output can be composed directly as a node.  Synchronous on `stream`.
+   Errors: GSR_E_INVALID (NULL arrays, negative sizes, sh_degree outside 0..3,
+   flatten < 0, opacity outside [0, 1], or facets indexing outside the
+   vertices -- those are written transparent and counted in the message),
+   GSR_E_NOMEM, GSR_E_HIP. */
+int gsr_mesh_to_gaussians(gsr_context* ctx, int64_t n_vertices, const float* vertices, const float* vertex_colors,
+                          int64_t n_faces, const int32_t* faces, float flatten, float opacity, int32_t sh_degree,
+                          const gsr_gaussian_grads* out, void* stream);
+
 /* ---- image-space domain randomisation (Sec. IV-C) ----------------------- */
 
 /* Augment `images` rendered frames: rgb [images][H][W][3] (DEVICE, read),

@@ -95,6 +95,8 @@ def lib():
         L.gsr_render_backward_noalloc.argtypes = L.gsr_render_backward.argtypes
         L.gsr_augment_rgb.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
         L.gsr_set_augment.argtypes = [vp, vp, vp]
+        L.gsr_mesh_to_gaussians.argtypes = [vp, i64, vp, vp, i64, vp, ctypes.c_float, ctypes.c_float, i32,
+                                            ctypes.POINTER(GaussianGrads), vp]
         L.gsr_query_status.argtypes = [vp, ctypes.POINTER(StatusInfo)]
         L.gsr_copy_pairs.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(i64)]
         L.gsr_copy_pixel_state.argtypes = [vp, vp, vp]
@@ -373,6 +375,27 @@ def set_augment(ctx, params, overlay=None):
     _dev_f32(params, (8,), "params")
     _check(lib().gsr_set_augment(ctx.handle, _ptr(params), _ptr(overlay)), ctx)
     ctx._augment = (params, overlay)
+
+
+def mesh_to_gaussians(ctx, vertices, faces, colours=None, flatten=0.01, opacity=0.9, sh_degree=0, stream=None):
+    """One Gaussian per facet of a triangle mesh (CUDA tensors: vertices float32 [nv, 3], faces
+    int32 [nf, 3], colours float32 [nv, 3] or None).  Returns a node dict (means, scales,
+    quats, opacities, sh) ready for compose_scene."""
+    _dev_f32(vertices, (3,), "vertices")
+    if colours is not None:
+        _dev_f32(colours, (3,), "colours")
+    if not (faces.is_cuda and faces.dtype == torch.int32 and faces.is_contiguous() and faces.dim() == 2
+            and faces.shape[1] == 3):
+        raise TypeError("faces must be a contiguous int32 CUDA tensor [nf, 3]")
+    nf, K, dev = faces.shape[0], (sh_degree + 1) ** 2, vertices.device
+    node = dict(means=torch.empty((nf, 3), device=dev), scales=torch.empty((nf, 3), device=dev),
+                quats=torch.empty((nf, 4), device=dev), opacities=torch.empty(nf, device=dev),
+                sh=torch.empty((nf, K, 3), device=dev))
+    o = GaussianGrads(node["means"].data_ptr(), node["scales"].data_ptr(), node["quats"].data_ptr(),
+                      node["opacities"].data_ptr(), node["sh"].data_ptr())
+    _check(lib().gsr_mesh_to_gaussians(ctx.handle, vertices.shape[0], _ptr(vertices), _ptr(colours), nf, _ptr(faces),
+                                       flatten, opacity, sh_degree, ctypes.byref(o), _stream(stream)), ctx)
+    return node
 
 
 def query_status(ctx):

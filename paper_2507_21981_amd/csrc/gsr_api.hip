@@ -94,6 +94,7 @@ struct gsr_context {
     DevBuf<float> g2d;
     DevBuf<gsr_gaussian_grads> grads_dev;
     DevBuf<float> pose_part;
+    DevBuf<uint32_t> counter;  // one device counter for synchronous calls (mesh transfer)
     const gsr_augment* aug = nullptr;  // bound by gsr_set_augment for GSR_FLAG_AUGMENT renders
     const float* overlay = nullptr;
     uint64_t render_serial = 0;  // renders issued on this context
@@ -227,7 +228,7 @@ void gsr_destroy(gsr_context* ctx) {
     ctx->cimg.release(); ctx->pair_base.release();
     ctx->starts.release();
     ctx->cls_list.release(); ctx->views.release(); ctx->T_final.release(); ctx->n_contrib.release();
-    ctx->g2d.release(); ctx->grads_dev.release(); ctx->pose_part.release();
+    ctx->g2d.release(); ctx->grads_dev.release(); ctx->pose_part.release(); ctx->counter.release();
     if (ctx->d_status) hipFree(ctx->d_status);
     if (ctx->h_status) hipHostFree(ctx->h_status);
     delete ctx;
@@ -603,6 +604,33 @@ int gsr_augment_rgb(gsr_context* ctx, int32_t images, int32_t W, int32_t H, cons
         return fail(ctx, GSR_E_INVALID, "gsr_augment_rgb: %d images of %dx%d", images, W, H);
     hipSetDevice(ctx->device);
     HIPCHK(ctx, launch_augment(images, W, H, rgb, overlay, params, out, ctx->num_cu, (hipStream_t)stream));
+    return GSR_OK;
+}
+
+int gsr_mesh_to_gaussians(gsr_context* ctx, int64_t n_vertices, const float* vertices, const float* vertex_colors,
+                          int64_t n_faces, const int32_t* faces, float flatten, float opacity, int32_t sh_degree,
+                          const gsr_gaussian_grads* out, void* stream) {
+    if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_mesh_to_gaussians: ctx is NULL");
+    if (!out || n_vertices < 0 || n_faces < 0 || (n_faces > 0 && (!vertices || !faces)))
+        return fail(ctx, GSR_E_INVALID, "gsr_mesh_to_gaussians: NULL arrays or negative sizes");
+    if (sh_degree < 0 || sh_degree > 3) return fail(ctx, GSR_E_INVALID, "gsr_mesh_to_gaussians: sh_degree %d", sh_degree);
+    if (!(flatten >= 0.0f) || !(opacity >= 0.0f && opacity <= 1.0f))
+        return fail(ctx, GSR_E_INVALID, "gsr_mesh_to_gaussians: flatten %g or opacity %g out of range", flatten, opacity);
+    if (n_faces > 0x7fffffffll || n_vertices > 0x7fffffffll)
+        return fail(ctx, GSR_E_INVALID, "gsr_mesh_to_gaussians: more than 2^31 - 1 faces or vertices");
+    hipSetDevice(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    int r = ensure(ctx, ctx->counter, 1);
+    if (r) return r;
+    HIPCHK(ctx, hipMemsetAsync(ctx->counter.p, 0, sizeof(uint32_t), s));
+    const int K = (sh_degree + 1) * (sh_degree + 1);
+    HIPCHK(ctx, launch_mesh_to_gs(n_faces, n_vertices, vertices, vertex_colors, faces, flatten, opacity, K, *out,
+                                  ctx->counter.p, ctx->num_cu, s));
+    uint32_t bad = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&bad, ctx->counter.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (bad) return fail(ctx, GSR_E_INVALID, "gsr_mesh_to_gaussians: %u faces index outside 0..%lld (written transparent)",
+                         bad, (long long)n_vertices - 1);
     return GSR_OK;
 }
 

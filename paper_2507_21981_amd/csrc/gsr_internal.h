@@ -332,6 +332,9 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s);
 hipError_t forward_lds_limits(const FwdArgs& a);
 hipError_t launch_augment(int images, int width, int height, const float* rgb, const float* overlay,
                           const gsr_augment* params, float* out, int num_cu, hipStream_t s);
+hipError_t launch_mesh_to_gs(long long n_faces, long long n_verts, const float* verts, const float* colours,
+                             const int32_t* faces, float flatten, float opacity, int K, const gsr_gaussian_grads& out,
+                             uint32_t* bad, int num_cu, hipStream_t s);
 hipError_t launch_copy_pairs(const FwdArgs& a, uint64_t* keys, uint32_t* values, uint32_t* ranges, hipStream_t s);
 // backward stages
 hipError_t launch_backward(const BwdArgs& a, size_t n_records, hipStream_t s);

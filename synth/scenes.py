@@ -22,7 +22,7 @@ import numpy as np
 __all__ = [
     "rng", "gaussians_uniform_cube", "gaussians_room", "gaussians_object",
     "random_rotation", "object_poses", "look_at", "camera", "ring_cameras",
-    "scene_config", "CONFIG_NAMES", "augment_params", "overlay_frames", "mesh_sphere",
+    "scene_config", "CONFIG_NAMES", "augment_params", "overlay_frames", "mesh_sphere", "lidar_rays",
 ]
 
 C0 = 0.5 / math.sqrt(math.pi)
@@ -275,3 +275,24 @@ def mesh_sphere(n_lat, n_lon, seed, radius=0.1, noise=0.05, degenerate=4):
         faces.append([i, i, int(g.integers(0, len(v)))])
     colours = g.random((len(v), 3), dtype=np.float32)
     return v.astype(np.float32), np.asarray(faces, np.int32), colours
+
+
+def lidar_rays(origin, n_beams, n_azimuth, elevation=(-15.0, 15.0), tmin=0.05, tmax=50.0, R=None):
+    """A spinning LiDAR's rays, [n_beams * n_azimuth, 8] float32 rows (origin[3], unit
+    direction[3], tmin, tmax): beams at elevations uniform in ``elevation`` degrees (y up),
+    azimuths uniform over the full turn, beam-major; ``R`` rotates the sensor frame to the
+    world."""
+    el = np.radians(np.linspace(elevation[0], elevation[1], n_beams))
+    az = 2 * math.pi * np.arange(n_azimuth) / n_azimuth
+    E, A = np.meshgrid(el, az, indexing="ij")
+    d = np.stack([np.cos(E) * np.sin(A), np.sin(E), np.cos(E) * np.cos(A)], axis=-1).reshape(-1, 3)
+    if R is not None:
+        d = d @ np.asarray(R, np.float64).T
+    d = d.astype(np.float32)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    out = np.empty((len(d), 8), np.float32)
+    out[:, 0:3] = np.asarray(origin, np.float32)
+    out[:, 3:6] = d
+    out[:, 6] = tmin
+    out[:, 7] = tmax
+    return out

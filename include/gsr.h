@@ -305,6 +305,41 @@ int gsr_render_backward_noalloc(gsr_context* ctx, const gsr_scene* scene, uint64
                                 const float* d_rgb, const float* d_depth, const float* d_alpha,
                                 const gsr_gaussian_grads* grads, float* d_poses, void* stream);
 
+/* ---- LiDAR by Gaussian ray tracing (Sec. III-C) ------------------------- */
+
+/* One LiDAR ray: origin and unit direction in world coordinates; only
+   Gaussians whose centre projects onto the ray at tmin < t < tmax count
+   (tmin >= 0; a negative tmin is taken as 0).  32 bytes. */
+typedef struct {
+    float origin[3];
+    float dir[3];
+    float tmin, tmax;
+} gsr_ray;
+
+/* Build the acceleration structure the LiDAR tracer needs: one bounding-
+   volume hierarchy per node over the node-local boxes of its Gaussians'
+   3.33-sigma ellipsoids (poses are applied to the rays at trace time, so
+   per-step pose updates need no rebuild).  Reads the Gaussian data back to
+   the host; synchronous.  Call again after the Gaussian data changes or the
+   scene is recomposed.  Errors: GSR_E_INVALID, GSR_E_NOMEM, GSR_E_HIP. */
+int gsr_lidar_build(gsr_context* ctx, gsr_scene* scene);
+
+/* Trace rays_per_env rays per environment (rays: DEVICE [n_envs *
+   rays_per_env] gsr_ray, env-major) through the scene's Gaussians (Sec.
+   III-C, LiDAR).  Per ray, a Gaussian's response is the peak of its density
+   along the ray, alpha = min(0.99, opacity * exp(-D^2 / 2)) with D the
+   smallest Mahalanobis distance from its centre to the ray; Gaussians with
+   alpha >= 1/255 are composited front to back in the order of t = (mu - o) .
+   d (ties by scene-global id) with the camera's stopping rule (before
+   blending when T (1 - alpha) < 1e-4).  Outputs (DEVICE, [n_envs *
+   rays_per_env]): range = sum alpha T t (unnormalised expected distance;
+   divide by alpha), alpha = 1 - T, hits (nullable) = blended Gaussians.
+   Asynchronous on `stream`.  Errors: GSR_E_INVALID (NULL arguments,
+   rays_per_env < 1), GSR_E_STATE (gsr_lidar_build not called since the scene
+   was composed), GSR_E_HIP. */
+int gsr_render_lidar(gsr_context* ctx, const gsr_scene* scene, int32_t rays_per_env, const gsr_ray* rays,
+                     float* range, float* alpha, uint32_t* hits, void* stream);
+
 /* ---- mesh-to-Gaussian transfer (Sec. IV-B) ------------------------------ */
 
 /* Convert a triangle mesh (a node's textured mesh, node-local frame) into

@@ -95,6 +95,8 @@ def lib():
         L.gsr_render_backward_noalloc.argtypes = L.gsr_render_backward.argtypes
         L.gsr_augment_rgb.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
         L.gsr_set_augment.argtypes = [vp, vp, vp]
+        L.gsr_lidar_build.argtypes = [vp, vp]
+        L.gsr_render_lidar.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
         L.gsr_mesh_to_gaussians.argtypes = [vp, i64, vp, vp, i64, vp, ctypes.c_float, ctypes.c_float, i32,
                                             ctypes.POINTER(GaussianGrads), vp]
         L.gsr_query_status.argtypes = [vp, ctypes.POINTER(StatusInfo)]
@@ -375,6 +377,31 @@ def set_augment(ctx, params, overlay=None):
     _dev_f32(params, (8,), "params")
     _check(lib().gsr_set_augment(ctx.handle, _ptr(params), _ptr(overlay)), ctx)
     ctx._augment = (params, overlay)
+
+
+def lidar_build(ctx, scene):
+    """Build the per-node hierarchies the LiDAR tracer needs (again after recomposing)."""
+    _check(lib().gsr_lidar_build(ctx.handle, scene.handle), ctx)
+
+
+def render_lidar(ctx, scene, rays, rays_per_env=None, out=None, want_hits=True, stream=None):
+    """Trace rays (CUDA float32 [n_envs * rays_per_env, 8] rows: origin, unit direction,
+    tmin, tmax).  Returns (range, alpha, hits or None), each [n_envs, rays_per_env]."""
+    _dev_f32(rays, (8,), "rays")
+    E = scene.n_envs
+    n = rays.shape[0]
+    R = rays_per_env if rays_per_env is not None else n // E
+    if R * E != n:
+        raise ValueError("rays must hold n_envs * rays_per_env rows")
+    if out is None:
+        rng = torch.empty((E, R), device=rays.device)
+        alpha = torch.empty((E, R), device=rays.device)
+        hits = torch.empty((E, R), dtype=torch.int32, device=rays.device) if want_hits else None
+    else:
+        rng, alpha, hits = out
+    _check(lib().gsr_render_lidar(ctx.handle, scene.handle, R, _ptr(rays), _ptr(rng), _ptr(alpha), _ptr(hits),
+                                  _stream(stream)), ctx)
+    return rng, alpha, hits
 
 
 def mesh_to_gaussians(ctx, vertices, faces, colours=None, flatten=0.01, opacity=0.9, sh_degree=0, stream=None):

@@ -18,7 +18,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgsr.so")
-SOURCES = ["gsr_forward.hip", "gsr_backward.hip", "gsr_mesh.hip", "gsr_api.hip"]
+SOURCES = ["gsr_forward.hip", "gsr_backward.hip", "gsr_mesh.hip", "gsr_lidar.hip", "gsr_api.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
          "-fhip-fp32-correctly-rounded-divide-sqrt", "-fno-gpu-flush-denormals-to-zero",
          "-munsafe-fp-atomics", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -70,6 +70,8 @@ struct gsr_scene {
     const gsr_pose* poses = nullptr;
     uint64_t version = 0;
     int sb_cap = kBlock;  // Gaussians per super-block at most
+    LidarScene* lidar = nullptr;  // per-node hierarchies of the LiDAR tracer (gsr_lidar_build)
+    uint64_t lidar_version = 0;   // scene version they were built for
 };
 
 struct gsr_context {
@@ -262,6 +264,10 @@ int gsr_set_pixels_per_thread(gsr_context* ctx, int32_t ppt) {
 
 void gsr_scene_destroy(gsr_scene* sc) {
     if (!sc) return;
+    if (sc->lidar) {
+        hipDeviceSynchronize();
+        lidar_free(sc->lidar);
+    }
     if (sc->nodes_d) hipFree(sc->nodes_d);
     if (sc->envs_d) hipFree(sc->envs_d);
     if (sc->blocks_d) hipFree(sc->blocks_d);
@@ -593,6 +599,35 @@ int gsr_render_rgbd(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_
     ctx->last = a;
     ctx->last_scene = sc;
     ctx->last_scene_version = sc->version;
+    return GSR_OK;
+}
+
+int gsr_lidar_build(gsr_context* ctx, gsr_scene* sc) {
+    if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_lidar_build: ctx is NULL");
+    if (!sc || sc->ctx != ctx) return fail(ctx, GSR_E_INVALID, "gsr_lidar_build: no scene of this context");
+    hipSetDevice(ctx->device);
+    HIPCHK(ctx, hipDeviceSynchronize());
+    if (sc->lidar) lidar_free(sc->lidar);
+    sc->lidar = nullptr;
+    LidarScene* L = nullptr;
+    const std::string err = lidar_build(sc->nodes_h, &L);
+    if (!err.empty()) return fail(ctx, GSR_E_NOMEM, "gsr_lidar_build: %s", err.c_str());
+    sc->lidar = L;
+    sc->lidar_version = sc->version;
+    return GSR_OK;
+}
+
+int gsr_render_lidar(gsr_context* ctx, const gsr_scene* sc, int32_t rays_per_env, const gsr_ray* rays, float* range,
+                     float* alpha, uint32_t* hits, void* stream) {
+    if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_render_lidar: ctx is NULL");
+    if (!sc || !rays || !range || !alpha) return fail(ctx, GSR_E_INVALID, "gsr_render_lidar: NULL argument");
+    if (sc->ctx != ctx) return fail(ctx, GSR_E_INVALID, "gsr_render_lidar: scene belongs to another context");
+    if (rays_per_env < 1) return fail(ctx, GSR_E_INVALID, "gsr_render_lidar: rays_per_env must be >= 1");
+    if (!sc->lidar || sc->lidar_version != sc->version)
+        return fail(ctx, GSR_E_STATE, "gsr_render_lidar: call gsr_lidar_build after composing the scene");
+    hipSetDevice(ctx->device);
+    HIPCHK(ctx, launch_lidar(sc->lidar, sc->envs_d, sc->poses, sc->n_envs, rays_per_env, rays, range, alpha, hits,
+                             (hipStream_t)stream));
     return GSR_OK;
 }
 

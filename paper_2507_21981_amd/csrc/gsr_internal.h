@@ -335,6 +335,17 @@ hipError_t launch_augment(int images, int width, int height, const float* rgb, c
 hipError_t launch_mesh_to_gs(long long n_faces, long long n_verts, const float* verts, const float* colours,
                              const int32_t* faces, float flatten, float opacity, int K, const gsr_gaussian_grads& out,
                              uint32_t* bad, int num_cu, hipStream_t s);
+// LiDAR: per-node bounding-volume hierarchies of a scene and the ray tracer
+struct LidarScene;
+}  // namespace gsr
+#include <string>
+#include <vector>
+namespace gsr {
+std::string lidar_build(const std::vector<Node>& nodes, LidarScene** out);
+void lidar_free(LidarScene* L);
+size_t lidar_bytes(const LidarScene* L);
+hipError_t launch_lidar(const LidarScene* L, const Env* envs, const gsr_pose* poses, int n_envs, int rays_per_env,
+                        const gsr_ray* rays, float* range, float* alpha, uint32_t* hits, hipStream_t s);
 hipError_t launch_copy_pairs(const FwdArgs& a, uint64_t* keys, uint32_t* values, uint32_t* ranges, hipStream_t s);
 // backward stages
 hipError_t launch_backward(const BwdArgs& a, size_t n_records, hipStream_t s);

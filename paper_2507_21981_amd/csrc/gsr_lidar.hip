@@ -1,0 +1,442 @@
+// LiDAR sensor by Gaussian ray tracing (paper Sec. III-C: LiDAR from a BVH-accelerated native
+// Gaussian ray tracer, next to the splatted RGB and depth).
+//
+// Acceleration structure: one bounding-volume hierarchy per scene node, over the node-local
+// bounding boxes of its Gaussians' 3.33-sigma ellipsoids (the largest Mahalanobis radius at which
+// alpha can reach 1/255).  Node-local, so the per-step rigid poses of object nodes never touch
+// it: a ray is moved into each node's frame instead (two-level tracing).  Built once per
+// composed topology on the host (Morton order of the centres, binary splits at the highest
+// differing code bit), stored depth-first (the left child follows its parent, the parent keeps
+// the right child's index).
+//
+// Tracing (k_lidar, one ray per lane): repeated passes over the env's nodes, each collecting in
+// registers the K next hits in (t_c, id) order after the last one composited -- a hit being a
+// Gaussian whose centre lies at t_c = (mu - o) . d inside (tmin, tmax) and whose peak response
+// along the ray, alpha = min(0.99, o exp(-D^2 / 2)), reaches 1/255 -- then compositing them front
+// to back with the camera's rules until the transmittance stop or the last hit.  A subtree is
+// skipped when the ray's line misses its box, when every centre in it lies before the last
+// composited hit or outside (tmin, tmax), or, once K hits are held, beyond the K-th; children
+// are visited nearer centres first (a per-lane stack in LDS holds the other), so that the K
+// nearest hits are found early and prune the rest of the pass.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gsr_internal.h"
+
+namespace gsr {
+
+constexpr int kLidarK = 16;      // hits per pass
+constexpr int kLeafSize = 4;     // primitives per BVH leaf at most
+constexpr int kLidarStack = 64;  // traversal stack entries per ray (hierarchy depth at most)
+
+struct LidarScene {
+    float4* bnodes = nullptr;   // 2 per BVH node: (lo, skip), (hi, leaf: count << 28 | first prim, or right child)
+    float4* prims = nullptr;    // 4 per primitive: (mu, opacity), (A row 0, A10), (A11, A12, A20, A21), (A22, id)
+    int2* roots = nullptr;      // per scene node: (first BVH node, BVH node count)
+    size_t n_bnodes = 0, n_prims = 0;
+    int n_nodes = 0;
+};
+
+void lidar_free(LidarScene* L) {
+    if (!L) return;
+    if (L->bnodes) hipFree(L->bnodes);
+    if (L->prims) hipFree(L->prims);
+    if (L->roots) hipFree(L->roots);
+    delete L;
+}
+
+namespace {
+
+uint32_t spread10(uint32_t x) {
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+struct Builder {
+    const std::vector<uint64_t>* keys;  // (Morton code << 32 | index), sorted
+    const std::vector<float>* box;      // per primitive: lo[3], hi[3]
+    std::vector<float> nlo, nhi;        // per node
+    std::vector<int> skip, leaf_first, leaf_count, right;
+    size_t prim_base = 0;
+    int max_depth = 0;
+
+    int make(size_t lo, size_t hi, int depth = 1) {
+        const int id = (int)skip.size();
+        max_depth = std::max(max_depth, depth);
+        skip.push_back(0);
+        leaf_first.push_back(0);
+        leaf_count.push_back(0);
+        right.push_back(0);
+        for (int j = 0; j < 3; ++j) {
+            nlo.push_back(INFINITY);
+            nhi.push_back(-INFINITY);
+        }
+        if (hi - lo <= (size_t)kLeafSize) {
+            leaf_first[id] = (int)(prim_base + lo);
+            leaf_count[id] = (int)(hi - lo);
+            for (size_t i = lo; i < hi; ++i) {
+                const uint32_t p = (uint32_t)((*keys)[i] & 0xffffffffu);
+                for (int j = 0; j < 3; ++j) {
+                    nlo[3 * id + j] = std::min(nlo[3 * id + j], (*box)[6 * p + j]);
+                    nhi[3 * id + j] = std::max(nhi[3 * id + j], (*box)[6 * p + 3 + j]);
+                }
+            }
+        } else {
+            // split where the highest Morton bit differing between the first and last code
+            // turns on (middle of the range if all codes are equal)
+            const uint32_t c0 = (uint32_t)((*keys)[lo] >> 32), c1 = (uint32_t)((*keys)[hi - 1] >> 32);
+            size_t mid = (lo + hi) / 2;
+            if (c0 != c1) {
+                const int bit = 31 - __builtin_clz(c0 ^ c1);
+                const uint32_t prefix = c1 >> bit;  // codes with this bit set go right
+                size_t a = lo, b = hi - 1;           // first index whose code >> bit == prefix
+                while (a < b) {
+                    const size_t m = (a + b) / 2;
+                    if ((uint32_t)((*keys)[m] >> 32) >> bit >= prefix) b = m;
+                    else a = m + 1;
+                }
+                mid = a;
+            }
+            const int l = make(lo, mid, depth + 1);
+            const int r = make(mid, hi, depth + 1);
+            right[id] = r;
+            for (int j = 0; j < 3; ++j) {
+                nlo[3 * id + j] = std::min(nlo[3 * l + j], nlo[3 * r + j]);
+                nhi[3 * id + j] = std::max(nhi[3 * l + j], nhi[3 * r + j]);
+            }
+        }
+        skip[id] = (int)skip.size();
+        return id;
+    }
+};
+
+inline float as_float(int v) {
+    float f;
+    memcpy(&f, &v, 4);
+    return f;
+}
+
+}  // namespace
+
+// Build the hierarchies of every node (host arrays of the scene's nodes; the Gaussian data is
+// read back from the device).  Returns 0 or a message.
+std::string lidar_build(const std::vector<Node>& nodes, LidarScene** out) {
+    *out = nullptr;
+    std::vector<float4> all_nodes, all_prims;
+    std::vector<int2> roots(nodes.size());
+    for (size_t k = 0; k < nodes.size(); ++k) {
+        const Node& nd = nodes[k];
+        const size_t n = nd.n;
+        std::vector<float> mu(3 * n), sc(3 * n), qt(4 * n), op(n);
+        if (n) {
+            if (hipMemcpy(mu.data(), nd.means, 12 * n, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(sc.data(), nd.scales, 12 * n, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(qt.data(), nd.quats, 16 * n, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(op.data(), nd.opac, 4 * n, hipMemcpyDeviceToHost) != hipSuccess)
+                return "reading node parameters back failed";
+        }
+        // primitives that can be hit: finite, opacity >= 1/255, positive scales
+        std::vector<uint32_t> idx;
+        std::vector<float> box;
+        std::vector<float4> prim;
+        double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (size_t i = 0; i < n; ++i) {
+            const double m[3] = {mu[3 * i], mu[3 * i + 1], mu[3 * i + 2]};
+            const double s[3] = {sc[3 * i], sc[3 * i + 1], sc[3 * i + 2]};
+            double q[4] = {qt[4 * i], qt[4 * i + 1], qt[4 * i + 2], qt[4 * i + 3]};
+            bool fin = std::isfinite(op[i]);
+            for (int j = 0; j < 3; ++j) fin = fin && std::isfinite(m[j]) && std::isfinite(s[j]) && s[j] > 0.0;
+            for (int j = 0; j < 4; ++j) fin = fin && std::isfinite(q[j]);
+            const double qn = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+            if (!fin || !(qn > 0.0) || !(op[i] >= (float)(1.0 / 255.0))) continue;
+            for (int j = 0; j < 4; ++j) q[j] /= qn;
+            const double w = q[0], x = q[1], y = q[2], z = q[3];
+            const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                                 2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                                 2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+            // bounding box of the 3.33-sigma ellipsoid: half extent 3.33 sqrt(Sigma_jj), widened so
+            // that the FP32 slab test stays conservative
+            float lo[3], hi[3];
+            for (int j = 0; j < 3; ++j) {
+                double sjj = 0.0;
+                for (int c = 0; c < 3; ++c) sjj += R[j * 3 + c] * R[j * 3 + c] * s[c] * s[c];
+                const double e = 3.33 * std::sqrt(sjj) * (1.0 + 1e-4) + 1e-5 * (std::fabs(m[j]) + 1.0);
+                lo[j] = (float)(m[j] - e);
+                hi[j] = (float)(m[j] + e);
+                clo[j] = std::min(clo[j], m[j]);
+                chi[j] = std::max(chi[j], m[j]);
+            }
+            for (int j = 0; j < 3; ++j) box.push_back(lo[j]);
+            for (int j = 0; j < 3; ++j) box.push_back(hi[j]);
+            // A = S^-1 R^T: row c is column c of R divided by s_c
+            float A[9];
+            for (int c = 0; c < 3; ++c)
+                for (int j = 0; j < 3; ++j) A[c * 3 + j] = (float)(R[j * 3 + c] / s[c]);
+            const uint32_t gid = nd.gid_base + (uint32_t)i;
+            prim.push_back(make_float4((float)m[0], (float)m[1], (float)m[2], op[i]));
+            prim.push_back(make_float4(A[0], A[1], A[2], A[3]));
+            prim.push_back(make_float4(A[4], A[5], A[6], A[7]));
+            prim.push_back(make_float4(A[8], as_float((int)gid), 0.0f, 0.0f));
+            idx.push_back((uint32_t)i);
+        }
+        const size_t m = idx.size();
+        roots[k] = make_int2((int)(all_nodes.size() / 2), 0);
+        if (m == 0) continue;
+        std::vector<uint64_t> keys(m);
+        for (size_t p = 0; p < m; ++p) {
+            uint32_t code = 0;
+            for (int j = 0; j < 3; ++j) {
+                const double c = 0.5 * ((double)box[6 * p + j] + (double)box[6 * p + 3 + j]);
+                const double ext = chi[j] - clo[j];
+                const double u = ext > 0.0 ? (c - clo[j]) / ext : 0.0;
+                const uint32_t qv = (uint32_t)std::min(1023.0, std::max(0.0, std::floor(u * 1024.0)));
+                code |= spread10(qv) << j;
+            }
+            keys[p] = ((uint64_t)code << 32) | (uint64_t)p;
+        }
+        std::sort(keys.begin(), keys.end());
+        Builder B;
+        B.keys = &keys;
+        B.box = &box;
+        B.prim_base = all_prims.size() / 4;
+        B.make(0, m);
+        if (B.max_depth > kLidarStack) return "a hierarchy deeper than the tracer's stack";
+        const int node_base = (int)(all_nodes.size() / 2);
+        const size_t nb = B.skip.size();
+        for (size_t i = 0; i < nb; ++i) {
+            // leaf: count << 28 | first primitive; internal: the right child (the left is next)
+            const int leaf = B.leaf_count[i] ? ((B.leaf_count[i] << 28) | B.leaf_first[i]) : node_base + B.right[i];
+            all_nodes.push_back(make_float4(B.nlo[3 * i], B.nlo[3 * i + 1], B.nlo[3 * i + 2], as_float(node_base + B.skip[i])));
+            all_nodes.push_back(make_float4(B.nhi[3 * i], B.nhi[3 * i + 1], B.nhi[3 * i + 2], as_float(leaf)));
+        }
+        for (size_t p = 0; p < m; ++p) {
+            const uint32_t src = (uint32_t)(keys[p] & 0xffffffffu);
+            for (int j = 0; j < 4; ++j) all_prims.push_back(prim[4 * src + j]);
+        }
+        roots[k] = make_int2(node_base, (int)nb);
+        if (all_prims.size() / 4 >= (1u << 28)) return "more than 2^28 primitives";
+    }
+    LidarScene* L = new LidarScene();
+    L->n_bnodes = all_nodes.size() / 2;
+    L->n_prims = all_prims.size() / 4;
+    L->n_nodes = (int)nodes.size();
+    if (hipMalloc(&L->bnodes, std::max<size_t>(all_nodes.size(), 1) * sizeof(float4)) != hipSuccess ||
+        hipMalloc(&L->prims, std::max<size_t>(all_prims.size(), 1) * sizeof(float4)) != hipSuccess ||
+        hipMalloc(&L->roots, std::max<size_t>(roots.size(), 1) * sizeof(int2)) != hipSuccess) {
+        lidar_free(L);
+        return "device allocation failed";
+    }
+    if ((!all_nodes.empty() &&
+         hipMemcpy(L->bnodes, all_nodes.data(), all_nodes.size() * sizeof(float4), hipMemcpyHostToDevice) != hipSuccess) ||
+        (!all_prims.empty() &&
+         hipMemcpy(L->prims, all_prims.data(), all_prims.size() * sizeof(float4), hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemcpy(L->roots, roots.data(), roots.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess) {
+        lidar_free(L);
+        return "upload failed";
+    }
+    *out = L;
+    return std::string();
+}
+
+size_t lidar_bytes(const LidarScene* L) { return L ? (L->n_bnodes * 32 + L->n_prims * 64) : 0; }
+
+// ------------------------------------------------------------------------------------------
+// tracing
+// ------------------------------------------------------------------------------------------
+__device__ inline uint64_t hit_key(float t, uint32_t id) { return ((uint64_t)__float_as_uint(t) << 32) | id; }
+
+// Where a ray may enter a box: the line meets it, some centre in it lies at a distance along
+// the ray after the last composited hit and inside the window, and -- once K hits are held --
+// before the K-th.  Returns the smallest centre distance over the box (the visiting order) or
+// +inf when the box is skipped.
+__device__ inline float lidar_enter(const float4& a, const float4& b, float o0, float o1, float o2, float d0, float d1,
+                                    float d2, float i0, float i1, float i2, float t_last, float tmin, float tmax,
+                                    float t_kth) {
+    const float ta0 = (a.x - o0) * i0, tb0 = (b.x - o0) * i0;
+    const float ta1 = (a.y - o1) * i1, tb1 = (b.y - o1) * i1;
+    const float ta2 = (a.z - o2) * i2, tb2 = (b.z - o2) * i2;
+    const float tin = fmaxf(fmaxf(fminf(ta0, tb0), fminf(ta1, tb1)), fminf(ta2, tb2));
+    const float tout = fminf(fminf(fmaxf(ta0, tb0), fmaxf(ta1, tb1)), fmaxf(ta2, tb2));
+    const float pa0 = d0 * (a.x - o0), pb0 = d0 * (b.x - o0);
+    const float pa1 = d1 * (a.y - o1), pb1 = d1 * (b.y - o1);
+    const float pa2 = d2 * (a.z - o2), pb2 = d2 * (b.z - o2);
+    const float tl = fminf(pa0, pb0) + fminf(pa1, pb1) + fminf(pa2, pb2);
+    const float th = fmaxf(pa0, pb0) + fmaxf(pa1, pb1) + fmaxf(pa2, pb2);
+    // (the boxes were widened by far more than the rounding of these tests)
+    const float slack = 1e-5f * (fabsf(tl) + fabsf(th)) + 1e-6f;
+    const bool in = tin <= tout + 1e-6f * (fabsf(tin) + fabsf(tout)) && th + slack >= t_last && tl - slack <= tmax &&
+                    th + slack >= tmin && tl - slack <= t_kth;
+    return in ? tl : INFINITY;
+}
+
+__global__ __launch_bounds__(64) void k_lidar(const float4* __restrict__ bnodes, const float4* __restrict__ prims,
+                                              const int2* __restrict__ roots, const Env* __restrict__ envs,
+                                              const gsr_pose* __restrict__ poses, int n_envs, int rays_per_env,
+                                              const gsr_ray* __restrict__ rays, float* range_out, float* alpha_out,
+                                              uint32_t* hits_out) {
+    // per-lane traversal stack (node, smallest centre distance), level-major so that the lanes
+    // of a level sit in consecutive banks
+    __shared__ int s_node[kLidarStack][64];
+    __shared__ float s_tl[kLidarStack][64];
+    const int lane = threadIdx.x;
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= (long long)n_envs * rays_per_env) return;
+    const Env ev = envs[r / rays_per_env];
+    const gsr_ray ray = rays[r];
+    const float thr = (float)(1.0 / 255.0);
+    float T = 1.0f, R = 0.0f;
+    uint32_t nh = 0;
+    const float tmin = fmaxf(ray.tmin, 0.0f), tmax = ray.tmax;  // keys order as their bits for t >= 0
+    uint64_t last = hit_key(tmin, 0u);  // keys at or below it are done (tmin itself is excluded)
+    bool done = false;
+    while (!done) {
+        uint64_t key[kLidarK];
+        float al[kLidarK];
+#pragma unroll
+        for (int j = 0; j < kLidarK; ++j) {
+            key[j] = ~0ull;
+            al[j] = 0.0f;
+        }
+        int found = 0;
+        const float t_last = __uint_as_float((uint32_t)(last >> 32));
+        for (int k = ev.node_begin; k < ev.node_end; ++k) {
+            const int2 rt = roots[k];
+            if (rt.y == 0) continue;
+            const gsr_pose P = poses[k];
+            // the ray in the node frame: R^T (o - t), R^T d
+            const float ox = ray.origin[0] - P.t[0], oy = ray.origin[1] - P.t[1], oz = ray.origin[2] - P.t[2];
+            const float o0 = fmaf(P.R[0], ox, fmaf(P.R[3], oy, P.R[6] * oz));
+            const float o1 = fmaf(P.R[1], ox, fmaf(P.R[4], oy, P.R[7] * oz));
+            const float o2 = fmaf(P.R[2], ox, fmaf(P.R[5], oy, P.R[8] * oz));
+            const float d0 = fmaf(P.R[0], ray.dir[0], fmaf(P.R[3], ray.dir[1], P.R[6] * ray.dir[2]));
+            const float d1 = fmaf(P.R[1], ray.dir[0], fmaf(P.R[4], ray.dir[1], P.R[7] * ray.dir[2]));
+            const float d2 = fmaf(P.R[2], ray.dir[0], fmaf(P.R[5], ray.dir[1], P.R[8] * ray.dir[2]));
+            const float i0 = 1.0f / (d0 != 0.0f ? d0 : 1e-30f), i1 = 1.0f / (d1 != 0.0f ? d1 : 1e-30f),
+                        i2 = 1.0f / (d2 != 0.0f ? d2 : 1e-30f);
+            auto kth = [&]() { return found == kLidarK ? __uint_as_float((uint32_t)(key[kLidarK - 1] >> 32)) : INFINITY; };
+            int cur = rt.x;
+            if (lidar_enter(bnodes[2 * cur], bnodes[2 * cur + 1], o0, o1, o2, d0, d1, d2, i0, i1, i2, t_last, tmin,
+                            tmax, kth()) == INFINITY)
+                continue;
+            int sp = 0;
+            while (true) {
+                const int info = __float_as_int(bnodes[2 * cur + 1].w);
+                if ((uint32_t)info >> 28) {
+                    // leaf: test its primitives
+                    const int cnt = (int)((uint32_t)info >> 28), p0 = info & 0x0fffffff;
+                    for (int p = p0; p < p0 + cnt; ++p) {
+                        const float4 m = prims[4 * p], A0 = prims[4 * p + 1], A1 = prims[4 * p + 2],
+                                     A2 = prims[4 * p + 3];
+                        const float q0 = m.x - o0, q1 = m.y - o1, q2 = m.z - o2;
+                        const float tc = fmaf(q0, d0, fmaf(q1, d1, q2 * d2));
+                        if (!(tc > tmin && tc < tmax)) continue;
+                        const uint32_t gid = (uint32_t)__float_as_int(A2.y);
+                        const uint64_t kk = hit_key(tc, gid);
+                        if (kk <= last || kk >= key[kLidarK - 1]) continue;
+                        // closest-approach offset and the Mahalanobis minimum along the ray
+                        const float e0 = fmaf(tc, d0, -q0), e1 = fmaf(tc, d1, -q1), e2 = fmaf(tc, d2, -q2);
+                        const float x0 = fmaf(A0.x, e0, fmaf(A0.y, e1, A0.z * e2));
+                        const float x1 = fmaf(A0.w, e0, fmaf(A1.x, e1, A1.y * e2));
+                        const float x2 = fmaf(A1.z, e0, fmaf(A1.w, e1, A2.x * e2));
+                        const float y0 = fmaf(A0.x, d0, fmaf(A0.y, d1, A0.z * d2));
+                        const float y1 = fmaf(A0.w, d0, fmaf(A1.x, d1, A1.y * d2));
+                        const float y2 = fmaf(A1.z, d0, fmaf(A1.w, d1, A2.x * d2));
+                        const float dd = fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
+                        const float xy = fmaf(x0, y0, fmaf(x1, y1, x2 * y2));
+                        const float yy = fmaf(y0, y0, fmaf(y1, y1, y2 * y2));
+                        const float D2 = fmaxf(dd - xy * (xy / yy), 0.0f);
+                        // alpha = o exp(-D^2 / 2) = o 2^(-D^2 log2(e) / 2)
+                        const float araw = m.w * __builtin_amdgcn_exp2f(-0.7213475204444817f * D2);
+                        if (!(araw >= thr)) continue;
+                        // insert in key order (the last entry drops out)
+                        uint64_t ck = kk;
+                        float ca = fminf(0.99f, araw);
+#pragma unroll
+                        for (int j = 0; j < kLidarK; ++j) {
+                            if (ck < key[j]) {
+                                const uint64_t tk = key[j];
+                                const float ta = al[j];
+                                key[j] = ck;
+                                al[j] = ca;
+                                ck = tk;
+                                ca = ta;
+                            }
+                        }
+                        found = found < kLidarK ? found + 1 : kLidarK;
+                    }
+                } else {
+                    // inner node: visit the child whose centres start nearer first
+                    const int cl = cur + 1, cr = info;
+                    const float tkth = kth();
+                    const float tL = lidar_enter(bnodes[2 * cl], bnodes[2 * cl + 1], o0, o1, o2, d0, d1, d2, i0, i1,
+                                                 i2, t_last, tmin, tmax, tkth);
+                    const float tR = lidar_enter(bnodes[2 * cr], bnodes[2 * cr + 1], o0, o1, o2, d0, d1, d2, i0, i1,
+                                                 i2, t_last, tmin, tmax, tkth);
+                    const bool eL = tL != INFINITY, eR = tR != INFINITY;
+                    if (eL && eR) {
+                        const bool lf = tL <= tR;
+                        s_node[sp][lane] = lf ? cr : cl;
+                        s_tl[sp][lane] = lf ? tR : tL;
+                        ++sp;
+                        cur = lf ? cl : cr;
+                        continue;
+                    }
+                    if (eL || eR) {
+                        cur = eL ? cl : cr;
+                        continue;
+                    }
+                }
+                // pop the next subtree that can still hold one of the K nearest hits
+                bool got = false;
+                while (sp > 0) {
+                    --sp;
+                    if (s_tl[sp][lane] <= kth() + 1e-5f * fabsf(s_tl[sp][lane]) + 1e-6f) {
+                        cur = s_node[sp][lane];
+                        got = true;
+                        break;
+                    }
+                }
+                if (!got) break;
+            }
+        }
+        // composite this pass's hits front to back
+#pragma unroll
+        for (int j = 0; j < kLidarK; ++j) {
+            if (j >= found || done) continue;
+            const float a = al[j];
+            const float Tn = T * (1.0f - a);
+            if (Tn < 1e-4f) {
+                done = true;
+                continue;
+            }
+            R = fmaf(a * T, __uint_as_float((uint32_t)(key[j] >> 32)), R);
+            T = Tn;
+            ++nh;
+        }
+        if (found < kLidarK) done = true;
+        last = key[kLidarK - 1];
+    }
+    range_out[r] = R;
+    alpha_out[r] = 1.0f - T;
+    if (hits_out) hits_out[r] = nh;
+}
+
+hipError_t launch_lidar(const LidarScene* L, const Env* envs, const gsr_pose* poses, int n_envs, int rays_per_env,
+                        const gsr_ray* rays, float* range, float* alpha, uint32_t* hits, hipStream_t s) {
+    const long long n = (long long)n_envs * rays_per_env;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lidar, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, L->bnodes, L->prims, L->roots, envs,
+                       poses, n_envs, rays_per_env, rays, range, alpha, hits);
+    return hipGetLastError();
+}
+
+}  // namespace gsr

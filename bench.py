@@ -418,24 +418,30 @@ def lidar_run(gsr, args, reps=10):
     for s in range(8):
         R, t = synth.object_poses(8, 300000 + 31 * s)
         sets.append(gsr.poses_tensor([env["poses"][0]] + [(R[k], t[k]) for k in range(8)]))
+    small = torch.from_numpy(synth.lidar_rays((0.0, 0.6, -1.0), 32, 1024, elevation=(-15, 15), tmin=0.05,
+                                              tmax=50.0)).cuda()
     ctx = gsr.create(0)
     try:
         scene = gsr.compose_scene(ctx, [nodes], poses)
         t0 = time.time()
         gsr.lidar_build(ctx, scene)
         build_s = time.time() - t0
-        out = gsr.render_lidar(ctx, scene, rays)
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        ev0.record()
-        for i in range(reps):
-            poses.copy_(sets[i % len(sets)])
-            gsr.render_lidar(ctx, scene, rays, out=out)
-        ev1.record()
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / reps
-        hits = int(out[2].sum())
+
+        def timed(rr):
+            out = gsr.render_lidar(ctx, scene, rr)
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            ev0.record()
+            for i in range(reps):
+                poses.copy_(sets[i % len(sets)])
+                gsr.render_lidar(ctx, scene, rr, out=out)
+            ev1.record()
+            torch.cuda.synchronize()
+            return ev0.elapsed_time(ev1) / reps, int(out[2].sum())
+
+        ms, hits = timed(rays)
+        ms_small, _ = timed(small)
     finally:
         ctx.close()
     n = rays.shape[0]
@@ -445,6 +451,8 @@ def lidar_run(gsr, args, reps=10):
             "rays": n, "ms_per_frame": round(ms, 4), "frames_per_s": round(1e3 / ms, 1),
             "Mrays_per_s": round(n / (ms * 1e-3) / 1e6, 2), "mean_hits": round(hits / n, 2),
             "hierarchy_build_s": round(build_s, 2),
+            "sensor_32x1024": {"rays": int(small.shape[0]), "ms_per_frame": round(ms_small, 4),
+                               "frames_per_s": round(1e3 / ms_small, 1)},
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": round(gbs / PEAK_HBM_GBS, 4), "algorithmic_bytes": b,
                          "note": "floor: each blended hit's primitive read once; traversal is latency-bound"}}

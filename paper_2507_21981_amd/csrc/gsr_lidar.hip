@@ -16,7 +16,7 @@
 // to back with the camera's rules until the transmittance stop or the last hit.  A subtree is
 // skipped when the ray's line misses its box, when every centre in it lies before the last
 // composited hit or outside (tmin, tmax), or, once K hits are held, beyond the K-th; children
-// are visited nearer centres first (a per-lane stack in LDS holds the other), so that the K
+// are visited nearer centres first (a per-lane stack of node indices in LDS holds the other), so that the K
 // nearest hits are found early and prune the rest of the pass.
 #include <hip/hip_runtime.h>
 
@@ -32,10 +32,11 @@ namespace gsr {
 
 constexpr int kLidarK = 16;      // hits per pass
 constexpr int kLeafSize = 4;     // primitives per BVH leaf at most
-constexpr int kLidarStack = 64;  // traversal stack entries per ray (hierarchy depth at most)
+constexpr int kLidarStack = 48;  // traversal stack entries per ray (hierarchy depth at most)
 
 struct LidarScene {
-    float4* bnodes = nullptr;   // 2 per BVH node: (lo, skip), (hi, leaf: count << 28 | first prim, or right child)
+    float4* bnodes = nullptr;   // 4 per BVH node: (lo, skip), (hi, leaf: count << 28 | first prim, or right
+                                //   child), the box of the centres (clo, -), (chi, -)
     float4* prims = nullptr;    // 4 per primitive: (mu, opacity), (A row 0, A10), (A11, A12, A20, A21), (A22, id)
     int2* roots = nullptr;      // per scene node: (first BVH node, BVH node count)
     size_t n_bnodes = 0, n_prims = 0;
@@ -64,7 +65,8 @@ uint32_t spread10(uint32_t x) {
 struct Builder {
     const std::vector<uint64_t>* keys;  // (Morton code << 32 | index), sorted
     const std::vector<float>* box;      // per primitive: lo[3], hi[3]
-    std::vector<float> nlo, nhi;        // per node
+    const std::vector<float>* cen;      // per primitive: centre[3]
+    std::vector<float> nlo, nhi, clo, chi;  // per node: box of the ellipsoids, box of the centres
     std::vector<int> skip, leaf_first, leaf_count, right;
     size_t prim_base = 0;
     int max_depth = 0;
@@ -79,6 +81,8 @@ struct Builder {
         for (int j = 0; j < 3; ++j) {
             nlo.push_back(INFINITY);
             nhi.push_back(-INFINITY);
+            clo.push_back(INFINITY);
+            chi.push_back(-INFINITY);
         }
         if (hi - lo <= (size_t)kLeafSize) {
             leaf_first[id] = (int)(prim_base + lo);
@@ -88,6 +92,8 @@ struct Builder {
                 for (int j = 0; j < 3; ++j) {
                     nlo[3 * id + j] = std::min(nlo[3 * id + j], (*box)[6 * p + j]);
                     nhi[3 * id + j] = std::max(nhi[3 * id + j], (*box)[6 * p + 3 + j]);
+                    clo[3 * id + j] = std::min(clo[3 * id + j], (*cen)[3 * p + j]);
+                    chi[3 * id + j] = std::max(chi[3 * id + j], (*cen)[3 * p + j]);
                 }
             }
         } else {
@@ -112,6 +118,8 @@ struct Builder {
             for (int j = 0; j < 3; ++j) {
                 nlo[3 * id + j] = std::min(nlo[3 * l + j], nlo[3 * r + j]);
                 nhi[3 * id + j] = std::max(nhi[3 * l + j], nhi[3 * r + j]);
+                clo[3 * id + j] = std::min(clo[3 * l + j], clo[3 * r + j]);
+                chi[3 * id + j] = std::max(chi[3 * l + j], chi[3 * r + j]);
             }
         }
         skip[id] = (int)skip.size();
@@ -146,7 +154,7 @@ std::string lidar_build(const std::vector<Node>& nodes, LidarScene** out) {
         }
         // primitives that can be hit: finite, opacity >= 1/255, positive scales
         std::vector<uint32_t> idx;
-        std::vector<float> box;
+        std::vector<float> box, cen;
         std::vector<float4> prim;
         double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
         for (size_t i = 0; i < n; ++i) {
@@ -177,6 +185,7 @@ std::string lidar_build(const std::vector<Node>& nodes, LidarScene** out) {
             }
             for (int j = 0; j < 3; ++j) box.push_back(lo[j]);
             for (int j = 0; j < 3; ++j) box.push_back(hi[j]);
+            for (int j = 0; j < 3; ++j) cen.push_back((float)m[j]);
             // A = S^-1 R^T: row c is column c of R divided by s_c
             float A[9];
             for (int c = 0; c < 3; ++c)
@@ -189,7 +198,7 @@ std::string lidar_build(const std::vector<Node>& nodes, LidarScene** out) {
             idx.push_back((uint32_t)i);
         }
         const size_t m = idx.size();
-        roots[k] = make_int2((int)(all_nodes.size() / 2), 0);
+        roots[k] = make_int2((int)(all_nodes.size() / 4), 0);
         if (m == 0) continue;
         std::vector<uint64_t> keys(m);
         for (size_t p = 0; p < m; ++p) {
@@ -207,16 +216,19 @@ std::string lidar_build(const std::vector<Node>& nodes, LidarScene** out) {
         Builder B;
         B.keys = &keys;
         B.box = &box;
+        B.cen = &cen;
         B.prim_base = all_prims.size() / 4;
         B.make(0, m);
-        if (B.max_depth > kLidarStack) return "a hierarchy deeper than the tracer's stack";
-        const int node_base = (int)(all_nodes.size() / 2);
+        if (B.max_depth > kLidarStack) return "a hierarchy deeper than the tracer's stack allows";
+        const int node_base = (int)(all_nodes.size() / 4);
         const size_t nb = B.skip.size();
         for (size_t i = 0; i < nb; ++i) {
             // leaf: count << 28 | first primitive; internal: the right child (the left is next)
             const int leaf = B.leaf_count[i] ? ((B.leaf_count[i] << 28) | B.leaf_first[i]) : node_base + B.right[i];
             all_nodes.push_back(make_float4(B.nlo[3 * i], B.nlo[3 * i + 1], B.nlo[3 * i + 2], as_float(node_base + B.skip[i])));
             all_nodes.push_back(make_float4(B.nhi[3 * i], B.nhi[3 * i + 1], B.nhi[3 * i + 2], as_float(leaf)));
+            all_nodes.push_back(make_float4(B.clo[3 * i], B.clo[3 * i + 1], B.clo[3 * i + 2], 0.0f));
+            all_nodes.push_back(make_float4(B.chi[3 * i], B.chi[3 * i + 1], B.chi[3 * i + 2], 0.0f));
         }
         for (size_t p = 0; p < m; ++p) {
             const uint32_t src = (uint32_t)(keys[p] & 0xffffffffu);
@@ -226,7 +238,7 @@ std::string lidar_build(const std::vector<Node>& nodes, LidarScene** out) {
         if (all_prims.size() / 4 >= (1u << 28)) return "more than 2^28 primitives";
     }
     LidarScene* L = new LidarScene();
-    L->n_bnodes = all_nodes.size() / 2;
+    L->n_bnodes = all_nodes.size() / 4;
     L->n_prims = all_prims.size() / 4;
     L->n_nodes = (int)nodes.size();
     if (hipMalloc(&L->bnodes, std::max<size_t>(all_nodes.size(), 1) * sizeof(float4)) != hipSuccess ||
@@ -247,7 +259,7 @@ std::string lidar_build(const std::vector<Node>& nodes, LidarScene** out) {
     return std::string();
 }
 
-size_t lidar_bytes(const LidarScene* L) { return L ? (L->n_bnodes * 32 + L->n_prims * 64) : 0; }
+size_t lidar_bytes(const LidarScene* L) { return L ? (L->n_bnodes * 64 + L->n_prims * 64) : 0; }
 
 // ------------------------------------------------------------------------------------------
 // tracing
@@ -258,23 +270,29 @@ __device__ inline uint64_t hit_key(float t, uint32_t id) { return ((uint64_t)__f
 // the ray after the last composited hit and inside the window, and -- once K hits are held --
 // before the K-th.  Returns the smallest centre distance over the box (the visiting order) or
 // +inf when the box is skipped.
-__device__ inline float lidar_enter(const float4& a, const float4& b, float o0, float o1, float o2, float d0, float d1,
+// Where a ray may enter a node: the line meets its box, some centre in it lies at a distance
+// along the ray after the last composited hit and inside the window, and -- once K hits are
+// held -- before the K-th.  The distances come from the box of the node's centres.  Returns the
+// smallest centre distance over that box (the visiting order) or +inf when the node is skipped.
+__device__ inline float lidar_enter(const float4* __restrict__ nd, float o0, float o1, float o2, float d0, float d1,
                                     float d2, float i0, float i1, float i2, float t_last, float tmin, float tmax,
                                     float t_kth) {
+    const float4 a = nd[0], b = nd[1];
     const float ta0 = (a.x - o0) * i0, tb0 = (b.x - o0) * i0;
     const float ta1 = (a.y - o1) * i1, tb1 = (b.y - o1) * i1;
     const float ta2 = (a.z - o2) * i2, tb2 = (b.z - o2) * i2;
     const float tin = fmaxf(fmaxf(fminf(ta0, tb0), fminf(ta1, tb1)), fminf(ta2, tb2));
     const float tout = fminf(fminf(fmaxf(ta0, tb0), fmaxf(ta1, tb1)), fmaxf(ta2, tb2));
-    const float pa0 = d0 * (a.x - o0), pb0 = d0 * (b.x - o0);
-    const float pa1 = d1 * (a.y - o1), pb1 = d1 * (b.y - o1);
-    const float pa2 = d2 * (a.z - o2), pb2 = d2 * (b.z - o2);
+    if (!(tin <= tout + 1e-6f * (fabsf(tin) + fabsf(tout)))) return INFINITY;
+    const float4 c = nd[2], e = nd[3];
+    const float pa0 = d0 * (c.x - o0), pb0 = d0 * (e.x - o0);
+    const float pa1 = d1 * (c.y - o1), pb1 = d1 * (e.y - o1);
+    const float pa2 = d2 * (c.z - o2), pb2 = d2 * (e.z - o2);
     const float tl = fminf(pa0, pb0) + fminf(pa1, pb1) + fminf(pa2, pb2);
     const float th = fmaxf(pa0, pb0) + fmaxf(pa1, pb1) + fmaxf(pa2, pb2);
-    // (the boxes were widened by far more than the rounding of these tests)
-    const float slack = 1e-5f * (fabsf(tl) + fabsf(th)) + 1e-6f;
-    const bool in = tin <= tout + 1e-6f * (fabsf(tin) + fabsf(tout)) && th + slack >= t_last && tl - slack <= tmax &&
-                    th + slack >= tmin && tl - slack <= t_kth;
+    // slack for the rounding of these sums (centres are exact FP32 values)
+    const float slack = 1e-5f * (fabsf(tl) + fabsf(th)) + 1e-5f * (fabsf(o0) + fabsf(o1) + fabsf(o2)) + 1e-6f;
+    const bool in = th + slack >= t_last && tl - slack <= tmax && th + slack >= tmin && tl - slack <= t_kth;
     return in ? tl : INFINITY;
 }
 
@@ -286,7 +304,6 @@ __global__ __launch_bounds__(64) void k_lidar(const float4* __restrict__ bnodes,
     // per-lane traversal stack (node, smallest centre distance), level-major so that the lanes
     // of a level sit in consecutive banks
     __shared__ int s_node[kLidarStack][64];
-    __shared__ float s_tl[kLidarStack][64];
     const int lane = threadIdx.x;
     const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= (long long)n_envs * rays_per_env) return;
@@ -324,12 +341,12 @@ __global__ __launch_bounds__(64) void k_lidar(const float4* __restrict__ bnodes,
                         i2 = 1.0f / (d2 != 0.0f ? d2 : 1e-30f);
             auto kth = [&]() { return found == kLidarK ? __uint_as_float((uint32_t)(key[kLidarK - 1] >> 32)) : INFINITY; };
             int cur = rt.x;
-            if (lidar_enter(bnodes[2 * cur], bnodes[2 * cur + 1], o0, o1, o2, d0, d1, d2, i0, i1, i2, t_last, tmin,
-                            tmax, kth()) == INFINITY)
+            if (lidar_enter(bnodes + 4 * cur, o0, o1, o2, d0, d1, d2, i0, i1, i2, t_last, tmin, tmax, kth()) ==
+                INFINITY)
                 continue;
             int sp = 0;
             while (true) {
-                const int info = __float_as_int(bnodes[2 * cur + 1].w);
+                const int info = __float_as_int(bnodes[4 * cur + 1].w);
                 if ((uint32_t)info >> 28) {
                     // leaf: test its primitives
                     const int cnt = (int)((uint32_t)info >> 28), p0 = info & 0x0fffffff;
@@ -377,15 +394,14 @@ __global__ __launch_bounds__(64) void k_lidar(const float4* __restrict__ bnodes,
                     // inner node: visit the child whose centres start nearer first
                     const int cl = cur + 1, cr = info;
                     const float tkth = kth();
-                    const float tL = lidar_enter(bnodes[2 * cl], bnodes[2 * cl + 1], o0, o1, o2, d0, d1, d2, i0, i1,
-                                                 i2, t_last, tmin, tmax, tkth);
-                    const float tR = lidar_enter(bnodes[2 * cr], bnodes[2 * cr + 1], o0, o1, o2, d0, d1, d2, i0, i1,
-                                                 i2, t_last, tmin, tmax, tkth);
+                    const float tL =
+                        lidar_enter(bnodes + 4 * cl, o0, o1, o2, d0, d1, d2, i0, i1, i2, t_last, tmin, tmax, tkth);
+                    const float tR =
+                        lidar_enter(bnodes + 4 * cr, o0, o1, o2, d0, d1, d2, i0, i1, i2, t_last, tmin, tmax, tkth);
                     const bool eL = tL != INFINITY, eR = tR != INFINITY;
                     if (eL && eR) {
                         const bool lf = tL <= tR;
                         s_node[sp][lane] = lf ? cr : cl;
-                        s_tl[sp][lane] = lf ? tR : tL;
                         ++sp;
                         cur = lf ? cl : cr;
                         continue;
@@ -399,8 +415,11 @@ __global__ __launch_bounds__(64) void k_lidar(const float4* __restrict__ bnodes,
                 bool got = false;
                 while (sp > 0) {
                     --sp;
-                    if (s_tl[sp][lane] <= kth() + 1e-5f * fabsf(s_tl[sp][lane]) + 1e-6f) {
-                        cur = s_node[sp][lane];
+                    // tested again: the K-th nearest may have come nearer since it was stacked
+                    const int nd = s_node[sp][lane];
+                    if (lidar_enter(bnodes + 4 * nd, o0, o1, o2, d0, d1, d2, i0, i1, i2, t_last, tmin, tmax, kth()) !=
+                        INFINITY) {
+                        cur = nd;
                         got = true;
                         break;
                     }

@@ -51,6 +51,9 @@ __device__ __forceinline__ float wave_sum63(float v) {
     return v;
 }
 
+// lane 63's value of v, as a wavefront-uniform value
+__device__ __forceinline__ float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
+
 // One wavefront per tile; each lane takes PPT = TW TH / 64 pixels of one column (pixel p of a
 // lane sits 64 / TW rows below pixel p - 1).  The wavefront walks the tile's list back to front
 // from the largest contributor count among its pixels, in batches of 64 entries staged in LDS;
@@ -219,17 +222,19 @@ __global__ __launch_bounds__(64) void k_composite_bwd(BwdArgs b) {
                     g_C = fmaf(-0.5f * dp, dy * dy, g_C);
                 }
             }
-            // one atomic per field per tile and entry
+            // one atomic per field per tile and entry: the ten wavefront sums (complete in lane
+            // 63) are spread over lanes 0-9, which add them to the record's ten consecutive
+            // fields with a single atomic instruction
             if (__any(contrib)) {
                 g_u = wave_sum63(g_u); g_v = wave_sum63(g_v); g_A = wave_sum63(g_A); g_B = wave_sum63(g_B);
                 g_C = wave_sum63(g_C); g_o = wave_sum63(g_o); g_r = wave_sum63(g_r); g_g = wave_sum63(g_g);
                 g_b = wave_sum63(g_b); g_z = wave_sum63(g_z);
-                if (lane == 63) {
-                    float* o = b.g2d + (size_t)s_rec[k] * 12;
-                    atomicAdd(o + 0, g_u); atomicAdd(o + 1, g_v); atomicAdd(o + 2, g_A); atomicAdd(o + 3, g_B);
-                    atomicAdd(o + 4, g_C); atomicAdd(o + 5, g_o); atomicAdd(o + 6, g_r); atomicAdd(o + 7, g_g);
-                    atomicAdd(o + 8, g_b); atomicAdd(o + 9, g_z);
-                }
+                const float f[10] = {lane63(g_u), lane63(g_v), lane63(g_A), lane63(g_B), lane63(g_C),
+                                     lane63(g_o), lane63(g_r), lane63(g_g), lane63(g_b), lane63(g_z)};
+                float v = f[0];
+#pragma unroll
+                for (int j = 1; j < 10; ++j) v = lane == j ? f[j] : v;
+                if (lane < 10) atomicAdd(b.g2d + (size_t)s_rec[k] * 12 + lane, v);
             }
         }
         // all lanes are done reading this batch before the next one overwrites it

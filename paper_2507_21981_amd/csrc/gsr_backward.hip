@@ -51,8 +51,27 @@ __device__ __forceinline__ float wave_sum63(float v) {
     return v;
 }
 
-// lane 63's value of v, as a wavefront-uniform value
-__device__ __forceinline__ float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
+// x + y across the two halves of the wavefront, x's sum in lanes 0-31 and y's in lanes 32-63
+// (lane i < 32: x[i] + x[i + 32]; lane i >= 32: y[i - 32] + y[i]): one lane-half swap
+__device__ __forceinline__ float half_pair(float x, float y) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(x), __float_as_int(y), false, false);
+    return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+// for p, q each holding one field per half (from half_pair): rows 0 and 1 of the result hold
+// p's and q's lower-half fields summed over rows 0+1, rows 2 and 3 their upper-half fields
+// summed over rows 2+3: one row swap (odd rows of p with even rows of q)
+__device__ __forceinline__ float row_pair(float p, float q) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(p), __float_as_int(q), false, false);
+    return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+// the sum over each row of 16 lanes, in every lane of the row
+__device__ __forceinline__ float row_sum16(float v) {
+    v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+    v = dpp_add<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
+    v = dpp_add<0x141, 0xF>(v);  // row_half_mirror
+    v = dpp_add<0x140, 0xF>(v);  // row_mirror
+    return v;
+}
 
 // One wavefront per tile; each lane takes PPT = TW TH / 64 pixels of one column (pixel p of a
 // lane sits 64 / TW rows below pixel p - 1).  The wavefront walks the tile's list back to front
@@ -222,19 +241,24 @@ __global__ __launch_bounds__(64) void k_composite_bwd(BwdArgs b) {
                     g_C = fmaf(-0.5f * dp, dy * dy, g_C);
                 }
             }
-            // one atomic per field per tile and entry: the ten wavefront sums (complete in lane
-            // 63) are spread over lanes 0-9, which add them to the record's ten consecutive
-            // fields with a single atomic instruction
+            // one atomic per field per tile and entry, after a transposing wavefront reduction:
+            // lane-half swaps pair the ten fields into five registers (lanes 0-31 one field,
+            // 32-63 another), row swaps pair those into two registers holding four fields (one
+            // per row of 16 lanes) and one holding two, and row sums by DPP finish them, so the
+            // ten totals sit in lanes 15, 31, 47, 63 of three registers
             if (__any(contrib)) {
-                g_u = wave_sum63(g_u); g_v = wave_sum63(g_v); g_A = wave_sum63(g_A); g_B = wave_sum63(g_B);
-                g_C = wave_sum63(g_C); g_o = wave_sum63(g_o); g_r = wave_sum63(g_r); g_g = wave_sum63(g_g);
-                g_b = wave_sum63(g_b); g_z = wave_sum63(g_z);
-                const float f[10] = {lane63(g_u), lane63(g_v), lane63(g_A), lane63(g_B), lane63(g_C),
-                                     lane63(g_o), lane63(g_r), lane63(g_g), lane63(g_b), lane63(g_z)};
-                float v = f[0];
-#pragma unroll
-                for (int j = 1; j < 10; ++j) v = lane == j ? f[j] : v;
-                if (lane < 10) atomicAdd(b.g2d + (size_t)s_rec[k] * 12 + lane, v);
+                const float R0 = half_pair(g_u, g_v), R1 = half_pair(g_A, g_B), R2 = half_pair(g_C, g_o),
+                            R3 = half_pair(g_r, g_g), R4 = half_pair(g_b, g_z);
+                // rows of Z0: u, A, v, B; rows of Z1: C, r, o, g
+                const float Z0 = row_sum16(row_pair(R0, R1)), Z1 = row_sum16(row_pair(R2, R3));
+                const float Z2 = dpp_add<0x142, 0xA>(row_sum16(R4));  // rows 1 and 3: b and z
+                if ((lane & 15) == 15) {
+                    float* o = b.g2d + (size_t)s_rec[k] * 12;
+                    const int row = lane >> 4, f = (row & 1) * 2 + (row >> 1);  // rows 0-3 -> 0, 2, 1, 3
+                    atomicAdd(o + f, Z0);
+                    atomicAdd(o + 4 + f, Z1);
+                    if (row & 1) atomicAdd(o + 8 + (row >> 1), Z2);
+                }
             }
         }
         // all lanes are done reading this batch before the next one overwrites it

@@ -9,15 +9,15 @@
 // differing code bit), stored depth-first (the left child follows its parent, the parent keeps
 // the right child's index).
 //
-// Tracing (k_lidar, one ray per lane): repeated passes over the env's nodes, each collecting in
-// registers the K next hits in (t_c, id) order after the last one composited -- a hit being a
-// Gaussian whose centre lies at t_c = (mu - o) . d inside (tmin, tmax) and whose peak response
-// along the ray, alpha = min(0.99, o exp(-D^2 / 2)), reaches 1/255 -- then compositing them front
-// to back with the camera's rules until the transmittance stop or the last hit.  A subtree is
-// skipped when the ray's line misses its box, when every centre in it lies before the last
-// composited hit or outside (tmin, tmax), or, once K hits are held, beyond the K-th; children
-// are visited nearer centres first (a per-lane stack of node indices in LDS holds the other), so that the K
-// nearest hits are found early and prune the rest of the pass.
+// Tracing (k_lidar, a wavefront per 64 rays): repeated passes over the env's nodes, each
+// collecting per lane in registers the K next hits in (t_c, id) order after the last one
+// composited -- a hit being a Gaussian whose centre lies at t_c = (mu - o) . d inside
+// (tmin, tmax) and whose peak response along the ray, alpha = min(0.99, o exp(-D^2 / 2)),
+// reaches 1/255 -- then compositing them front to back with the camera's rules until the
+// transmittance stop or the last hit.  The wavefront walks each hierarchy once for all its rays
+// (a LiDAR's neighbouring beams cross mostly the same boxes); a subtree is skipped when no ray
+// may enter it: the ray's line misses its box, every centre in it lies before the ray's last
+// composited hit or outside (tmin, tmax), or, once K hits are held, beyond the K-th.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -296,26 +296,57 @@ __device__ inline float lidar_enter(const float4* __restrict__ nd, float o0, flo
     return in ? tl : INFINITY;
 }
 
+// A ray moved into one node's frame.
+struct LocalRay {
+    float o0, o1, o2, d0, d1, d2, i0, i1, i2;
+};
+
+__device__ inline LocalRay local_ray(const gsr_ray& ray, const gsr_pose& P) {
+    LocalRay l;
+    const float ox = ray.origin[0] - P.t[0], oy = ray.origin[1] - P.t[1], oz = ray.origin[2] - P.t[2];
+    l.o0 = fmaf(P.R[0], ox, fmaf(P.R[3], oy, P.R[6] * oz));
+    l.o1 = fmaf(P.R[1], ox, fmaf(P.R[4], oy, P.R[7] * oz));
+    l.o2 = fmaf(P.R[2], ox, fmaf(P.R[5], oy, P.R[8] * oz));
+    l.d0 = fmaf(P.R[0], ray.dir[0], fmaf(P.R[3], ray.dir[1], P.R[6] * ray.dir[2]));
+    l.d1 = fmaf(P.R[1], ray.dir[0], fmaf(P.R[4], ray.dir[1], P.R[7] * ray.dir[2]));
+    l.d2 = fmaf(P.R[2], ray.dir[0], fmaf(P.R[5], ray.dir[1], P.R[8] * ray.dir[2]));
+    l.i0 = 1.0f / (l.d0 != 0.0f ? l.d0 : 1e-30f);
+    l.i1 = 1.0f / (l.d1 != 0.0f ? l.d1 : 1e-30f);
+    l.i2 = 1.0f / (l.d2 != 0.0f ? l.d2 : 1e-30f);
+    return l;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// One wavefront traces 64 rays together (a packet: a LiDAR's neighbouring beams share most of
+// the boxes they cross).  The walk over a hierarchy is the wavefront's: a node is visited when
+// any of its rays may enter it, children nearer (by majority) first, one stack per wavefront in
+// LDS, node and primitive loads the same for every lane.  Each lane keeps its own K next hits,
+// its own last composited key and its own pruning bounds; a lane that visits a node it would
+// have skipped only tests primitives that cannot change its K nearest, so the result is the
+// lane's alone.  Passes repeat until every lane has stopped or seen all its hits.
 __global__ __launch_bounds__(64) void k_lidar(const float4* __restrict__ bnodes, const float4* __restrict__ prims,
                                               const int2* __restrict__ roots, const Env* __restrict__ envs,
                                               const gsr_pose* __restrict__ poses, int n_envs, int rays_per_env,
                                               const gsr_ray* __restrict__ rays, float* range_out, float* alpha_out,
                                               uint32_t* hits_out) {
-    // per-lane traversal stack (node, smallest centre distance), level-major so that the lanes
-    // of a level sit in consecutive banks
-    __shared__ int s_node[kLidarStack][64];
+    __shared__ int s_stack[kLidarStack];
     const int lane = threadIdx.x;
-    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= (long long)n_envs * rays_per_env) return;
-    const Env ev = envs[r / rays_per_env];
-    const gsr_ray ray = rays[r];
+    const long long n = (long long)n_envs * rays_per_env;
+    const long long r = (long long)blockIdx.x * blockDim.x + lane;
+    const bool valid = r < n;
+    const long long rr = valid ? r : n - 1;
+    const int env = (int)(rr / rays_per_env);
+    const gsr_ray ray = rays[rr];
     const float thr = (float)(1.0 / 255.0);
     float T = 1.0f, R = 0.0f;
     uint32_t nh = 0;
     const float tmin = fmaxf(ray.tmin, 0.0f), tmax = ray.tmax;  // keys order as their bits for t >= 0
     uint64_t last = hit_key(tmin, 0u);  // keys at or below it are done (tmin itself is excluded)
-    bool done = false;
-    while (!done) {
+    bool done = !valid;
+    // rays are env-major, so the wavefront's envs are a contiguous range
+    const int e_lo = uniform(env), e_hi = __builtin_amdgcn_readlane(env, 63);
+    while (__any(!done)) {
         uint64_t key[kLidarK];
         float al[kLidarK];
 #pragma unroll
@@ -325,125 +356,130 @@ __global__ __launch_bounds__(64) void k_lidar(const float4* __restrict__ bnodes,
         }
         int found = 0;
         const float t_last = __uint_as_float((uint32_t)(last >> 32));
-        for (int k = ev.node_begin; k < ev.node_end; ++k) {
-            const int2 rt = roots[k];
-            if (rt.y == 0) continue;
-            const gsr_pose P = poses[k];
-            // the ray in the node frame: R^T (o - t), R^T d
-            const float ox = ray.origin[0] - P.t[0], oy = ray.origin[1] - P.t[1], oz = ray.origin[2] - P.t[2];
-            const float o0 = fmaf(P.R[0], ox, fmaf(P.R[3], oy, P.R[6] * oz));
-            const float o1 = fmaf(P.R[1], ox, fmaf(P.R[4], oy, P.R[7] * oz));
-            const float o2 = fmaf(P.R[2], ox, fmaf(P.R[5], oy, P.R[8] * oz));
-            const float d0 = fmaf(P.R[0], ray.dir[0], fmaf(P.R[3], ray.dir[1], P.R[6] * ray.dir[2]));
-            const float d1 = fmaf(P.R[1], ray.dir[0], fmaf(P.R[4], ray.dir[1], P.R[7] * ray.dir[2]));
-            const float d2 = fmaf(P.R[2], ray.dir[0], fmaf(P.R[5], ray.dir[1], P.R[8] * ray.dir[2]));
-            const float i0 = 1.0f / (d0 != 0.0f ? d0 : 1e-30f), i1 = 1.0f / (d1 != 0.0f ? d1 : 1e-30f),
-                        i2 = 1.0f / (d2 != 0.0f ? d2 : 1e-30f);
-            auto kth = [&]() { return found == kLidarK ? __uint_as_float((uint32_t)(key[kLidarK - 1] >> 32)) : INFINITY; };
-            int cur = rt.x;
-            if (lidar_enter(bnodes + 4 * cur, o0, o1, o2, d0, d1, d2, i0, i1, i2, t_last, tmin, tmax, kth()) ==
-                INFINITY)
-                continue;
-            int sp = 0;
-            while (true) {
-                const int info = __float_as_int(bnodes[4 * cur + 1].w);
-                if ((uint32_t)info >> 28) {
-                    // leaf: test its primitives
-                    const int cnt = (int)((uint32_t)info >> 28), p0 = info & 0x0fffffff;
-                    for (int p = p0; p < p0 + cnt; ++p) {
-                        const float4 m = prims[4 * p], A0 = prims[4 * p + 1], A1 = prims[4 * p + 2],
-                                     A2 = prims[4 * p + 3];
-                        const float q0 = m.x - o0, q1 = m.y - o1, q2 = m.z - o2;
-                        const float tc = fmaf(q0, d0, fmaf(q1, d1, q2 * d2));
-                        if (!(tc > tmin && tc < tmax)) continue;
-                        const uint32_t gid = (uint32_t)__float_as_int(A2.y);
-                        const uint64_t kk = hit_key(tc, gid);
-                        if (kk <= last || kk >= key[kLidarK - 1]) continue;
-                        // closest-approach offset and the Mahalanobis minimum along the ray
-                        const float e0 = fmaf(tc, d0, -q0), e1 = fmaf(tc, d1, -q1), e2 = fmaf(tc, d2, -q2);
-                        const float x0 = fmaf(A0.x, e0, fmaf(A0.y, e1, A0.z * e2));
-                        const float x1 = fmaf(A0.w, e0, fmaf(A1.x, e1, A1.y * e2));
-                        const float x2 = fmaf(A1.z, e0, fmaf(A1.w, e1, A2.x * e2));
-                        const float y0 = fmaf(A0.x, d0, fmaf(A0.y, d1, A0.z * d2));
-                        const float y1 = fmaf(A0.w, d0, fmaf(A1.x, d1, A1.y * d2));
-                        const float y2 = fmaf(A1.z, d0, fmaf(A1.w, d1, A2.x * d2));
-                        const float dd = fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
-                        const float xy = fmaf(x0, y0, fmaf(x1, y1, x2 * y2));
-                        const float yy = fmaf(y0, y0, fmaf(y1, y1, y2 * y2));
-                        const float D2 = fmaxf(dd - xy * (xy / yy), 0.0f);
-                        // alpha = o exp(-D^2 / 2) = o 2^(-D^2 log2(e) / 2)
-                        const float araw = m.w * __builtin_amdgcn_exp2f(-0.7213475204444817f * D2);
-                        if (!(araw >= thr)) continue;
-                        // insert in key order (the last entry drops out)
-                        uint64_t ck = kk;
-                        float ca = fminf(0.99f, araw);
+        auto kth = [&]() { return found == kLidarK ? __uint_as_float((uint32_t)(key[kLidarK - 1] >> 32)) : INFINITY; };
+        for (int e = e_lo; e <= e_hi; ++e) {
+            const bool part = !done && env == e;
+            if (!__any(part)) continue;
+            const Env ev = envs[e];
+            for (int k = ev.node_begin; k < ev.node_end; ++k) {
+                const int2 rt = roots[k];
+                if (rt.y == 0) continue;
+                const LocalRay l = local_ray(ray, poses[k]);
+                auto enters = [&](int node) {
+                    return part && lidar_enter(bnodes + 4 * node, l.o0, l.o1, l.o2, l.d0, l.d1, l.d2, l.i0, l.i1, l.i2,
+                                               t_last, tmin, tmax, kth()) != INFINITY;
+                };
+                if (!__any(enters(rt.x))) continue;
+                int cur = rt.x, sp = 0;
+                while (true) {
+                    const int info = uniform(__float_as_int(bnodes[4 * cur + 1].w));
+                    bool pop = false;
+                    if ((uint32_t)info >> 28) {
+                        const int cnt = (int)((uint32_t)info >> 28), p0 = info & 0x0fffffff;
+                        for (int p = p0; p < p0 + cnt; ++p) {
+                            const float4 m = prims[4 * p], A0 = prims[4 * p + 1], A1 = prims[4 * p + 2],
+                                         A2 = prims[4 * p + 3];
+                            if (!part) continue;
+                            const float q0 = m.x - l.o0, q1 = m.y - l.o1, q2 = m.z - l.o2;
+                            const float tc = fmaf(q0, l.d0, fmaf(q1, l.d1, q2 * l.d2));
+                            if (!(tc > tmin && tc < tmax)) continue;
+                            const uint32_t gid = (uint32_t)__float_as_int(A2.y);
+                            const uint64_t kk = hit_key(tc, gid);
+                            if (kk <= last || kk >= key[kLidarK - 1]) continue;
+                            // closest-approach offset and the Mahalanobis minimum along the ray
+                            const float e0 = fmaf(tc, l.d0, -q0), e1 = fmaf(tc, l.d1, -q1), e2 = fmaf(tc, l.d2, -q2);
+                            const float x0 = fmaf(A0.x, e0, fmaf(A0.y, e1, A0.z * e2));
+                            const float x1 = fmaf(A0.w, e0, fmaf(A1.x, e1, A1.y * e2));
+                            const float x2 = fmaf(A1.z, e0, fmaf(A1.w, e1, A2.x * e2));
+                            const float y0 = fmaf(A0.x, l.d0, fmaf(A0.y, l.d1, A0.z * l.d2));
+                            const float y1 = fmaf(A0.w, l.d0, fmaf(A1.x, l.d1, A1.y * l.d2));
+                            const float y2 = fmaf(A1.z, l.d0, fmaf(A1.w, l.d1, A2.x * l.d2));
+                            const float dd = fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
+                            const float xy = fmaf(x0, y0, fmaf(x1, y1, x2 * y2));
+                            const float yy = fmaf(y0, y0, fmaf(y1, y1, y2 * y2));
+                            const float D2 = fmaxf(dd - xy * (xy / yy), 0.0f);
+                            // alpha = o exp(-D^2 / 2) = o 2^(-D^2 log2(e) / 2)
+                            const float araw = m.w * __builtin_amdgcn_exp2f(-0.7213475204444817f * D2);
+                            if (!(araw >= thr)) continue;
+                            // insert in key order (the last entry drops out)
+                            uint64_t ck = kk;
+                            float ca = fminf(0.99f, araw);
 #pragma unroll
-                        for (int j = 0; j < kLidarK; ++j) {
-                            if (ck < key[j]) {
-                                const uint64_t tk = key[j];
-                                const float ta = al[j];
-                                key[j] = ck;
-                                al[j] = ca;
-                                ck = tk;
-                                ca = ta;
+                            for (int j = 0; j < kLidarK; ++j) {
+                                if (ck < key[j]) {
+                                    const uint64_t tk = key[j];
+                                    const float ta = al[j];
+                                    key[j] = ck;
+                                    al[j] = ca;
+                                    ck = tk;
+                                    ca = ta;
+                                }
+                            }
+                            found = found < kLidarK ? found + 1 : kLidarK;
+                        }
+                        pop = true;
+                    } else {
+                        // inner node: the children any ray may enter, nearer first by majority
+                        const int cl = cur + 1, cr = info;
+                        const float tk = kth();
+                        float tL = INFINITY, tR = INFINITY;
+                        if (part) {
+                            tL = lidar_enter(bnodes + 4 * cl, l.o0, l.o1, l.o2, l.d0, l.d1, l.d2, l.i0, l.i1, l.i2,
+                                             t_last, tmin, tmax, tk);
+                            tR = lidar_enter(bnodes + 4 * cr, l.o0, l.o1, l.o2, l.d0, l.d1, l.d2, l.i0, l.i1, l.i2,
+                                             t_last, tmin, tmax, tk);
+                        }
+                        const bool aL = __any(tL != INFINITY), aR = __any(tR != INFINITY);
+                        if (aL && aR) {
+                            const bool both = tL != INFINITY && tR != INFINITY;
+                            const int left_first = __popcll(__ballot(both && tL <= tR)),
+                                      right_first = __popcll(__ballot(both && tL > tR));
+                            const bool lf = left_first >= right_first;
+                            s_stack[sp++] = lf ? cr : cl;
+                            cur = lf ? cl : cr;
+                        } else if (aL || aR) {
+                            cur = aL ? cl : cr;
+                        } else {
+                            pop = true;
+                        }
+                    }
+                    if (pop) {
+                        // the next stacked subtree some ray may still enter
+                        bool got = false;
+                        while (sp > 0) {
+                            const int nd = uniform(s_stack[--sp]);
+                            if (__any(enters(nd))) {
+                                cur = nd;
+                                got = true;
+                                break;
                             }
                         }
-                        found = found < kLidarK ? found + 1 : kLidarK;
+                        if (!got) break;
                     }
-                } else {
-                    // inner node: visit the child whose centres start nearer first
-                    const int cl = cur + 1, cr = info;
-                    const float tkth = kth();
-                    const float tL =
-                        lidar_enter(bnodes + 4 * cl, o0, o1, o2, d0, d1, d2, i0, i1, i2, t_last, tmin, tmax, tkth);
-                    const float tR =
-                        lidar_enter(bnodes + 4 * cr, o0, o1, o2, d0, d1, d2, i0, i1, i2, t_last, tmin, tmax, tkth);
-                    const bool eL = tL != INFINITY, eR = tR != INFINITY;
-                    if (eL && eR) {
-                        const bool lf = tL <= tR;
-                        s_node[sp][lane] = lf ? cr : cl;
-                        ++sp;
-                        cur = lf ? cl : cr;
-                        continue;
-                    }
-                    if (eL || eR) {
-                        cur = eL ? cl : cr;
-                        continue;
-                    }
+                    cur = uniform(cur);
                 }
-                // pop the next subtree that can still hold one of the K nearest hits
-                bool got = false;
-                while (sp > 0) {
-                    --sp;
-                    // tested again: the K-th nearest may have come nearer since it was stacked
-                    const int nd = s_node[sp][lane];
-                    if (lidar_enter(bnodes + 4 * nd, o0, o1, o2, d0, d1, d2, i0, i1, i2, t_last, tmin, tmax, kth()) !=
-                        INFINITY) {
-                        cur = nd;
-                        got = true;
-                        break;
-                    }
-                }
-                if (!got) break;
             }
         }
         // composite this pass's hits front to back
+        if (!done) {
 #pragma unroll
-        for (int j = 0; j < kLidarK; ++j) {
-            if (j >= found || done) continue;
-            const float a = al[j];
-            const float Tn = T * (1.0f - a);
-            if (Tn < 1e-4f) {
-                done = true;
-                continue;
+            for (int j = 0; j < kLidarK; ++j) {
+                if (j >= found || done) continue;
+                const float a = al[j];
+                const float Tn = T * (1.0f - a);
+                if (Tn < 1e-4f) {
+                    done = true;
+                    continue;
+                }
+                R = fmaf(a * T, __uint_as_float((uint32_t)(key[j] >> 32)), R);
+                T = Tn;
+                ++nh;
             }
-            R = fmaf(a * T, __uint_as_float((uint32_t)(key[j] >> 32)), R);
-            T = Tn;
-            ++nh;
+            if (found < kLidarK) done = true;
+            last = key[kLidarK - 1];
         }
-        if (found < kLidarK) done = true;
-        last = key[kLidarK - 1];
     }
+    if (!valid) return;
     range_out[r] = R;
     alpha_out[r] = 1.0f - T;
     if (hits_out) hits_out[r] = nh;

@@ -104,6 +104,20 @@ def test_batched_envs_and_pose_updates_without_rebuild(gsr, ctx):
             log(f"step {step} env {e}", st)
 
 
+def test_wavefronts_spanning_several_envs(gsr, ctx):
+    """100 rays per env: most wavefronts of 64 rays hold rays of two envs, which walk different
+    hierarchies in the same wavefront."""
+    import torch
+    wl = synth.scene_config(3, seed=59, scale=0.005, n_envs=5)
+    rays = [_aim(synth.lidar_rays((0.0, 0.4, -1.0), 10, 10, elevation=(-30, 10), tmin=0.05, tmax=12.0), (0, -0.3, 1),
+                 1.0) for _ in wl["envs"]]
+    _, (rng, alpha, hits) = _run(gsr, ctx, wl, rays)
+    for e, env in enumerate(wl["envs"]):
+        ref = L.trace(L.WorldEnv(env), rays[e])
+        st = _compare(ref, rng[e * 100:(e + 1) * 100], alpha[e * 100:(e + 1) * 100], hits[e * 100:(e + 1) * 100])
+        log(f"env {e}", st)
+
+
 def test_build_required_and_empty_rays(gsr, ctx):
     import torch
     bg = synth.gaussians_uniform_cube(500, 61)

@@ -88,7 +88,7 @@ struct gsr_context {
     DevBuf<uint32_t> sbvis, loff;
     DevBuf<uint32_t> skey0, skey1, sgid0, sgid1;
     DevBuf<uint2> srect0, srect1;
-    DevBuf<uint32_t> hist, seg_n, seg_start, blk_pairs, chunk_base, pair_base, cstart, cimg, ecnt;
+    DevBuf<uint32_t> hist, seg_n, seg_start, blk_pairs, chunk_base, pair_base, cstart, cimg, ecnt, seg_base, segoff;
     DevBuf<uint32_t> starts, cls_list;
     DevBuf<View> views;
     DevBuf<float> T_final;
@@ -227,7 +227,7 @@ void gsr_destroy(gsr_context* ctx) {
     ctx->skey0.release(); ctx->skey1.release(); ctx->sgid0.release(); ctx->sgid1.release();
     ctx->srect0.release(); ctx->srect1.release(); ctx->hist.release(); ctx->seg_n.release(); ctx->ecnt.release();
     ctx->seg_start.release(); ctx->blk_pairs.release(); ctx->chunk_base.release(); ctx->cstart.release();
-    ctx->cimg.release(); ctx->pair_base.release();
+    ctx->cimg.release(); ctx->pair_base.release(); ctx->seg_base.release(); ctx->segoff.release();
     ctx->starts.release();
     ctx->cls_list.release(); ctx->views.release(); ctx->T_final.release(); ctx->n_contrib.release();
     ctx->g2d.release(); ctx->grads_dev.release(); ctx->pose_part.release(); ctx->counter.release();
@@ -444,6 +444,7 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
         (r = ensure(ctx, ctx->hist, (size_t)a.sort_chunks * 256)) ||
         (r = ensure(ctx, ctx->seg_n, a.images)) || (r = ensure(ctx, ctx->seg_start, a.images + 1)) ||
         (r = ensure(ctx, ctx->blk_pairs, n_pblocks)) || (r = ensure(ctx, ctx->chunk_base, a.images + 1)) || (r = ensure(ctx, ctx->pair_base, a.images)) ||
+        (r = ensure(ctx, ctx->seg_base, a.images + 1)) ||
         (r = ensure(ctx, ctx->starts, a.tiles + 1)) ||
         (r = ensure(ctx, ctx->cls_list, (size_t)kNumClasses * a.tiles)) ||
         (r = ensure(ctx, ctx->views, (size_t)sc->n_nodes * C)) || (r = ensure(ctx, ctx->T_final, npix)) ||
@@ -453,19 +454,13 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
     if (ctx->pair_cap >= 0xffffffffll) return fail(ctx, GSR_E_UNSUPPORTED, "pair capacity beyond 32-bit slots");
     // emission chunks of about chunk_pairs pairs (at most pairs / chunk_pairs + 1 per image).
     // Small chunks give the emission more wavefronts; each chunk adds a count and an offset per
-    // tile of its image, so chunks hold at least 4 pairs per tile, and k_tile_ranges walks an
-    // image's (chunk, tile) table in one block, so that table is kept near 2^20 entries (pairs
-    // per image estimated from the capacity, which follows the last render's pair count), up
-    // to 16 pairs per tile
-    {
-        const long long ppi = ctx->pair_cap / std::max(a.images, 1);
-        const long long cp = std::min<long long>((ppi * a.tpi) >> 20, 16ll * a.tpi);
-        a.chunk_pairs = (int)std::max<long long>(std::max<long long>(1024, 4ll * a.tpi), cp);
-    }
+    // tile of its image, so chunks hold at least kChunkPairsPerTile pairs per tile
+    a.chunk_pairs = std::max(1024, kChunkPairsPerTile * a.tpi);
     a.chunk_cap = (int)(ctx->pair_cap / a.chunk_pairs + a.images + 1);
     if ((r = ensure(ctx, ctx->pairs, ctx->pair_cap)) || (r = ensure(ctx, ctx->cstart, (size_t)a.chunk_cap)) ||
         (r = ensure(ctx, ctx->cimg, (size_t)a.chunk_cap)) ||
-        (r = ensure(ctx, ctx->ecnt, (size_t)a.chunk_cap * a.tpi)))
+        (r = ensure(ctx, ctx->ecnt, (size_t)a.chunk_cap * a.tpi)) ||
+        (r = ensure(ctx, ctx->segoff, ((size_t)a.chunk_cap / kSegChunks + a.images + 1) * a.tpi)))
         return r;
     a.views = ctx->views.p;
     a.records = ctx->records.p;
@@ -488,6 +483,8 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
     a.cstart = ctx->cstart.p;
     a.cimg = ctx->cimg.p;
     a.ecnt = ctx->ecnt.p;
+    a.seg_base = ctx->seg_base.p;
+    a.segoff = ctx->segoff.p;
     a.num_cu = ctx->num_cu;
     if (forward_lds_limits(a) != hipSuccess) {
         (void)hipGetLastError();

@@ -13,8 +13,9 @@
 //   k_pair_*, k_chunk_starts   each image's depth-ordered Gaussians cut into chunks of about
 //                  equal pair counts
 //   k_tile_counts  per chunk: pairs per tile, from a difference grid in LDS
-//   k_tile_ranges  per image: each chunk's first slot in every tile bucket, the tiles' [start,
-//                  end) ranges, tiles grouped by list length (persistent compositor's order)
+//   k_tile_seg, k_tile_ranges   a two-level scan over each image's chunks: each chunk's
+//                  first slot in every tile bucket, the tiles' [start, end) ranges, tiles
+//                  grouped by list length (persistent compositor's order)
 //   k_emit         Gaussian ids written into their tiles' buckets in depth order, so every
 //                  bucket is sorted by (depth bits, id) as it is written
 //   k_composite    per tile, front-to-back alpha blending of colour and camera-space z
@@ -738,16 +739,17 @@ __global__ __launch_bounds__(256) void k_pair_blocks(FwdArgs a) {
 }
 
 // One block: per image (one thread each) the exclusive prefix of its blocks' pairs and its
-// chunk count; chunk bases by a scan over images.  Total pairs and overflow into the status
-// word; on overflow no image gets chunks (nothing is emitted; the host grows the capacity).
+// chunk count; chunk, pair and segment bases by scans over images.  Total pairs and overflow
+// into the status word; on overflow no image gets chunks (nothing is emitted; the host grows
+// the capacity).
 __global__ __launch_bounds__(1024) void k_pair_scan(FwdArgs a) {
-    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_w[16], s_ws[16];
     __shared__ unsigned long long s_wp[16];
-    __shared__ uint32_t s_carry;
+    __shared__ uint32_t s_carry, s_scarry;
     __shared__ unsigned long long s_pairs;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     if (t == 0) {
-        s_carry = 0u;
+        s_carry = s_scarry = 0u;
         s_pairs = 0ull;
     }
     __syncthreads();
@@ -771,45 +773,53 @@ __global__ __launch_bounds__(1024) void k_pair_scan(FwdArgs a) {
             }
             nchk = (run + PC - 1) / PC;
         }
-        // chunk bases and pair bases: exclusive scans over images
-        uint32_t incl = nchk;
+        // chunk, pair and segment bases: exclusive scans over images
+        const uint32_t nseg = (nchk + kSegChunks - 1) / kSegChunks;
+        uint32_t incl = nchk, incls = nseg;
         unsigned long long inclp = run;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(incl, off, 64);
+            const uint32_t y = __shfl_up(incl, off, 64), ys = __shfl_up(incls, off, 64);
             const unsigned long long yp = __shfl_up(inclp, off, 64);
             if (lane >= off) {
                 incl += y;
+                incls += ys;
                 inclp += yp;
             }
         }
         if (lane == 63) {
             s_w[wave] = incl;
+            s_ws[wave] = incls;
             s_wp[wave] = inclp;
         }
         __syncthreads();
-        uint32_t before = s_carry;
+        uint32_t before = s_carry, befores = s_scarry;
         unsigned long long beforep = s_pairs;
         for (int w = 0; w < wave; ++w) {
             before += s_w[w];
+            befores += s_ws[w];
             beforep += s_wp[w];
         }
         if (img < a.images) {
             a.chunk_base[img] = before + incl - nchk;
+            a.seg_base[img] = befores + incls - nseg;
             a.pair_base[img] = (uint32_t)(beforep + inclp - run);  // < pair_cap unless overflowed
         }
         __syncthreads();
         if (t == 1023) {
             s_carry = before + incl;
+            s_scarry = befores + incls;
             s_pairs = beforep + inclp;
         }
         __syncthreads();
     }
+    // at most chunks / kSegChunks + images segments: within the workspace when the chunks are
     const bool over = s_pairs > (unsigned long long)a.pair_cap || s_carry > (uint32_t)a.chunk_cap;
     if (over)
-        for (int i = t; i < a.images; i += 1024) a.chunk_base[i] = a.pair_base[i] = 0u;
+        for (int i = t; i < a.images; i += 1024) a.chunk_base[i] = a.pair_base[i] = a.seg_base[i] = 0u;
     if (t == 0) {
         a.chunk_base[a.images] = over ? 0u : s_carry;
+        a.seg_base[a.images] = over ? 0u : s_scarry;
         a.status->pairs = s_pairs;
         if (over) atomicOr(&a.status->flags, (uint32_t)GSR_STATUS_OVERFLOW);
     }
@@ -932,13 +942,57 @@ __global__ __launch_bounds__(kCountThreads) void k_tile_counts(FwdArgs a) {
 }
 
 // --------------------------------------------------------------------------------------------
-// tile ranges: one block per image, one thread per tile (1024 at a time).  The tile's
-// exclusive scan over the image's emission chunks (in depth order) turns the chunks' counts
-// into their first slots within the tile's bucket; the tile totals, scanned over the image's
-// tiles from the image's pair base, give the tiles' starts (the range table).  Tiles are also
-// grouped by list length (at most 512, 1024, ..., 8192 pairs, longer, at most one pair): the
-// persistent compositor takes them longest class first.
+// tile ranges: a two-level scan, per tile, over its image's emission chunks in depth order.
+// Segments of kSegChunks consecutive chunks of one image, all in parallel (k_tile_seg): each
+// chunk's count is replaced by the tile's pairs of the earlier chunks of its segment, and the
+// segment's count is kept.  Per image, one thread per tile (1024 at a time, k_tile_ranges):
+// the tile's total over the image's segments; the totals, scanned over the image's tiles from
+// the image's pair base, give the tiles' starts (the range table); each segment's count is
+// replaced by its first slot in the tile's bucket.  A chunk's first slot in a bucket is its
+// segment's slot plus its offset within the segment.  Tiles are also grouped by list length
+// (at most 512, 1024, ..., 8192 pairs, longer, at most one pair): the persistent compositor
+// takes them longest class first.
 // --------------------------------------------------------------------------------------------
+// the image holding global segment sg < seg_base[images] (the last image whose first segment
+// is not after sg; images without segments share their successor's base)
+__device__ inline int seg_image(const uint32_t* __restrict__ seg_base, int images, uint32_t sg) {
+    int lo = 0, hi = images - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg_base[mid] <= sg) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+constexpr int kSegThreads = 256;
+
+__global__ __launch_bounds__(kSegThreads) void k_tile_seg(FwdArgs a) {
+    const uint32_t groups = (uint32_t)((a.tpi + kSegThreads - 1) / kSegThreads);
+    const uint32_t items = a.seg_base[a.images] * groups;
+    for (uint32_t w = blockIdx.x; w < items; w += gridDim.x) {
+        const uint32_t sg = w / groups;
+        const int t = (int)(w - sg * groups) * kSegThreads + (int)threadIdx.x;
+        const int img = seg_image(a.seg_base, a.images, sg);
+        const uint32_t q = a.chunk_base[img] + (sg - a.seg_base[img]) * (uint32_t)kSegChunks;
+        const uint32_t left = a.chunk_base[img + 1] - q;
+        const uint32_t m = left < (uint32_t)kSegChunks ? left : (uint32_t)kSegChunks;
+        if (t < a.tpi) {
+            uint32_t* p = a.ecnt + (size_t)q * a.tpi + t;
+            uint32_t v[kSegChunks];
+#pragma unroll
+            for (int k = 0; k < kSegChunks; ++k) v[k] = (uint32_t)k < m ? p[(size_t)k * a.tpi] : 0u;
+            uint32_t run = 0u;
+#pragma unroll
+            for (int k = 0; k < kSegChunks; ++k) {
+                if ((uint32_t)k < m) p[(size_t)k * a.tpi] = run;
+                run += v[k];
+            }
+            a.segoff[(size_t)sg * a.tpi + t] = run;
+        }
+    }
+}
+
 // append a wavefront's flagged lanes to a device list with one atomic; returns each flagged
 // lane's slot
 __device__ inline uint32_t wave_append(uint32_t* counter, bool pred) {
@@ -956,8 +1010,8 @@ __global__ __launch_bounds__(1024) void k_tile_ranges(FwdArgs a) {
     __shared__ uint32_t s_w[16];
     __shared__ uint32_t s_carry;
     const int img = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t q0 = a.chunk_base[img];
-    const int nq = (int)(a.chunk_base[img + 1] - q0);
+    const uint32_t s0 = a.seg_base[img];
+    const int ns = (int)(a.seg_base[img + 1] - s0);
     if (threadIdx.x == 0) s_carry = a.pair_base[img];
     __syncthreads();
     constexpr int B = 16;  // loads in flight
@@ -965,21 +1019,14 @@ __global__ __launch_bounds__(1024) void k_tile_ranges(FwdArgs a) {
     uint32_t mx = 0u;
     for (int t0 = 0; t0 < a.tpi; t0 += 1024) {
         const int t = t0 + (int)threadIdx.x;
+        uint32_t* p = a.segoff + (size_t)s0 * a.tpi + t;
         uint32_t run = 0u;
-        if (t < a.tpi) {
-            uint32_t* p = a.ecnt + (size_t)q0 * a.tpi + t;
-            for (int k0 = 0; k0 < nq; k0 += B) {
-                const int m = nq - k0 < B ? nq - k0 : B;
-                uint32_t v[B];
+        if (t < a.tpi)
+            for (int k0 = 0; k0 < ns; k0 += B) {
+                const int m = ns - k0 < B ? ns - k0 : B;
 #pragma unroll
-                for (int k = 0; k < B; ++k) v[k] = k < m ? p[(size_t)(k0 + k) * stride] : 0u;
-#pragma unroll
-                for (int k = 0; k < B; ++k) {
-                    if (k < m) p[(size_t)(k0 + k) * stride] = run;
-                    run += v[k];
-                }
+                for (int k = 0; k < B; ++k) run += k < m ? p[(size_t)(k0 + k) * stride] : 0u;
             }
-        }
         mx = run > mx ? run : mx;
         uint32_t incl = run;
 #pragma unroll
@@ -996,6 +1043,18 @@ __global__ __launch_bounds__(1024) void k_tile_ranges(FwdArgs a) {
         int cls = -1;
         if (t < a.tpi) {
             a.starts[gt] = st;
+            uint32_t slot = st;
+            for (int k0 = 0; k0 < ns; k0 += B) {
+                const int m = ns - k0 < B ? ns - k0 : B;
+                uint32_t v[B];
+#pragma unroll
+                for (int k = 0; k < B; ++k) v[k] = k < m ? p[(size_t)(k0 + k) * stride] : 0u;
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    if (k < m) p[(size_t)(k0 + k) * stride] = slot;
+                    slot += v[k];
+                }
+            }
             const uint32_t n = run;
             if ((unsigned long long)st + n > (unsigned long long)a.pair_cap || n <= 1) cls = kLenNone;
             else if (n <= 512) cls = 0;
@@ -1023,25 +1082,29 @@ __global__ __launch_bounds__(1024) void k_tile_ranges(FwdArgs a) {
 }
 
 // --------------------------------------------------------------------------------------------
-// pair emission.  One wavefront per emission chunk walks the chunk's depth-ordered Gaussians
-// in rounds of 64 and writes their (z bits << 32 | id) pairs into the tile buckets, so each
+// pair emission.  One block per emission chunk walks the chunk's depth-ordered Gaussians in
+// rounds of 64 and writes their (z bits << 32 | id) pairs into the tile buckets, so each
 // bucket receives its entries in (z bits, id) order: chunks in order (first slots from the
 // tile offsets), rounds in order (a running slot per tile in LDS) and, within a round, by the
 // Gaussian's rank in the round: the set bits below it in the tile's 64-bit round mask.
 // A round's pairs are numbered by a prefix over the rectangle areas and split into equal runs
-// of consecutive pairs, one per lane, walked three times: set the mask bits; write the pairs;
-// advance each tile's slot (by the tile's highest Gaussian of the round) and clear its mask.
-// Chunks hold about the same number of pairs, so the wavefronts' work is balanced even where
-// the nearest (largest) splats of an image crowd into its first chunk.
+// of consecutive pairs, one per thread, walked three times: set the mask bits; write the
+// pairs; advance each tile's slot (by the tile's highest Gaussian of the round) and clear its
+// mask.  Chunks hold about the same number of pairs, so the blocks' work is balanced even where
+// the nearest (largest) splats of an image crowd into its first chunk.  The W wavefronts of a
+// block share the chunk's tile table (12 bytes per tile), so large tile grids do not cap the
+// wavefronts per CU, and split each round's pairs W ways.
 // --------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_emit(FwdArgs a) {
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_emit(FwdArgs a) {
+    constexpr int NT = 64 * W;
     extern __shared__ unsigned long long s_mask[];  // [tpi] round masks, then [tpi] u32 slots
     __shared__ uint32_t s_off[65], s_x0[64], s_y0[64], s_w[64], s_id[64];
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
     uint32_t* s_slot = reinterpret_cast<uint32_t*>(s_mask + a.tpi);
     const unsigned long long cap = (unsigned long long)a.pair_cap;
     const int tx_n = a.tiles_x;
-    for (int t = lane; t < a.tpi; t += 64) s_mask[t] = 0ull;  // masks are left clear by each round
+    for (int t = tid; t < a.tpi; t += NT) s_mask[t] = 0ull;  // masks are left clear by each round
     uint32_t q0, q1, qs;
     xcd_items(a.chunk_base[a.images], q0, q1, qs);
     for (uint32_t q = q0; q < q1; q += qs) {
@@ -1050,39 +1113,42 @@ __global__ __launch_bounds__(64) void k_emit(FwdArgs a) {
         const uint32_t n = emit_chunk(a, q, pos, img);
         if (n == 0u) continue;
         const uint32_t* so = a.ecnt + (size_t)q * a.tpi;
-        const uint32_t* st = a.starts + (size_t)img * a.tpi;
-        for (int t = lane; t < a.tpi; t += 64) s_slot[t] = st[t] + so[t];
+        const uint32_t* st =
+            a.segoff + (size_t)(a.seg_base[img] + (q - a.chunk_base[img]) / (uint32_t)kSegChunks) * a.tpi;
+        for (int t = tid; t < a.tpi; t += NT) s_slot[t] = st[t] + so[t];
         const uint32_t* gids = a.sgid[1] + pos;
         const uint2* rects = a.srect[1] + pos;
-        // the next round's Gaussian, loaded one round ahead
+        // the next round's Gaussian, loaded one round ahead (by the first wavefront)
         uint2 nr = make_uint2(0u, 0u);
         uint32_t ni = 0u;
-        if ((uint32_t)lane < n) {
+        if (tid < 64 && (uint32_t)lane < n) {
             nr = rects[lane];
             ni = gids[lane];
         }
         for (uint32_t r0 = 0; r0 < n; r0 += 64) {
-            const uint32_t k = r0 + (uint32_t)lane;
-            uint32_t area = 0u;
-            if (k < n) {
-                const uint32_t x0 = nr.x & 0xffffu, y0 = nr.x >> 16, x1 = nr.y & 0xffffu, y1 = nr.y >> 16;
-                s_x0[lane] = x0;
-                s_y0[lane] = y0;
-                s_w[lane] = x1 - x0;
-                s_id[lane] = ni;
-                area = (x1 - x0) * (y1 - y0);
+            if (tid < 64) {
+                const uint32_t k = r0 + (uint32_t)lane;
+                uint32_t area = 0u;
+                if (k < n) {
+                    const uint32_t x0 = nr.x & 0xffffu, y0 = nr.x >> 16, x1 = nr.y & 0xffffu, y1 = nr.y >> 16;
+                    s_x0[lane] = x0;
+                    s_y0[lane] = y0;
+                    s_w[lane] = x1 - x0;
+                    s_id[lane] = ni;
+                    area = (x1 - x0) * (y1 - y0);
+                }
+                if (k + 64u < n) {
+                    nr = rects[k + 64u];
+                    ni = gids[k + 64u];
+                }
+                const uint32_t incl = wave_incl_scan(area);
+                s_off[lane + 1] = incl;
+                if (lane == 0) s_off[0] = 0u;
             }
-            if (k + 64u < n) {
-                nr = rects[k + 64u];
-                ni = gids[k + 64u];
-            }
-            const uint32_t incl = wave_incl_scan(area);
-            s_off[lane + 1] = incl;
-            if (lane == 0) s_off[0] = 0u;
             __syncthreads();
             const uint32_t total = s_off[64];
-            const uint32_t per = (total + 63u) / 64u;
-            const uint32_t k0 = (uint32_t)lane * per, k1 = k0 + per < total ? k0 + per : total;
+            const uint32_t per = (total + (uint32_t)NT - 1u) / (uint32_t)NT;
+            const uint32_t k0 = (uint32_t)tid * per, k1 = k0 + per < total ? k0 + per : total;
             // where this lane's pairs start: the Gaussian of pair k0 (first o with
             // s_off[o + 1] > k0) and the tile of that pair
             int o0 = 0;
@@ -1480,6 +1546,12 @@ static void launch_composite(const FwdArgs& a, hipStream_t s) {
 }
 
 static size_t emit_lds(const FwdArgs& a) { return (size_t)a.tpi * (sizeof(unsigned long long) + sizeof(uint32_t)); }
+// wavefronts per emission block: 4, or 16 once the image's tile table is large (large tile
+// grids come with many tiles per Gaussian, so a round's pairs keep 1024 threads busy)
+static int emit_waves(const FwdArgs& a) { return emit_lds(a) > kEmitLdsSmall ? 16 : 4; }
+static const void* emit_kernel(const FwdArgs& a) {
+    return emit_waves(a) == 16 ? (const void*)k_emit<16> : (const void*)k_emit<4>;
+}
 static size_t counts_lds(const FwdArgs& a) { return (size_t)(a.tiles_x + 1) * (a.tiles_y + 1) * sizeof(int); }
 
 hipError_t forward_lds_limits(const FwdArgs& a) {
@@ -1487,7 +1559,7 @@ hipError_t forward_lds_limits(const FwdArgs& a) {
     constexpr size_t kDefault = 48 * 1024;
     hipError_t e = hipSuccess;
     if (emit_lds(a) > kDefault)
-        e = hipFuncSetAttribute((const void*)k_emit, hipFuncAttributeMaxDynamicSharedMemorySize, (int)emit_lds(a));
+        e = hipFuncSetAttribute(emit_kernel(a), hipFuncAttributeMaxDynamicSharedMemorySize, (int)emit_lds(a));
     if (e == hipSuccess && counts_lds(a) > kDefault)
         e = hipFuncSetAttribute((const void*)k_tile_counts, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)counts_lds(a));
@@ -1535,9 +1607,13 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
     mark(5);
     hipLaunchKernelGGL(k_tile_counts, grid(a.chunk_cap, 32), dim3(kCountThreads), counts_lds(a), s, a);
     mark(6);
+    const long long n_segs = (long long)a.chunk_cap / kSegChunks + a.images + 1;
+    hipLaunchKernelGGL(k_tile_seg, grid(n_segs * ((a.tpi + kSegThreads - 1) / kSegThreads), 8), dim3(kSegThreads),
+                       0, s, a);
     hipLaunchKernelGGL(k_tile_ranges, dim3(a.images), dim3(1024), 0, s, a);
     mark(7);
-    hipLaunchKernelGGL(k_emit, grid(a.chunk_cap, 16), dim3(64), emit_lds(a), s, a);
+    if (emit_waves(a) == 16) hipLaunchKernelGGL(k_emit<16>, grid(a.chunk_cap, 2), dim3(1024), emit_lds(a), s, a);
+    else hipLaunchKernelGGL(k_emit<4>, grid(a.chunk_cap, 8), dim3(256), emit_lds(a), s, a);
     mark(8);
     if (a.tw == 16 && a.th == 16) {
         if (a.ppt == 4) launch_composite<16, 16, 4>(a, s);

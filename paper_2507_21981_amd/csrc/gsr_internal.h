@@ -25,6 +25,9 @@ constexpr int kLdsHistLimit = 40000; // int counters of one image's tile differe
 // gfx950).
 constexpr int kSortTile = 2048;
 constexpr int kPairBlock = 1024;     // positions per block of the pair-prefix kernels
+constexpr int kSegChunks = 16;       // emission chunks per segment of the tile-range scan
+constexpr int kChunkPairsPerTile = 4; // emission chunk size: pairs per tile of the image
+constexpr int kEmitLdsSmall = 8192;   // emission tile table (bytes) above which blocks have 16 wavefronts
 constexpr int kMaxTilesPerImage = 13312;
 
 // One (node, camera) view: the camera<-node map composed in FP64 and rounded
@@ -234,7 +237,11 @@ struct FwdArgs {
     uint32_t* cimg;      // per emission chunk: its image
     int chunk_cap;       // emission chunks the workspace holds
     int chunk_pairs;     // pairs per emission chunk (a chunk starts at every multiple)
-    uint32_t* ecnt;      // per (emission chunk, tile): pairs, then first slot in the tile's bucket
+    uint32_t* ecnt;      // per (emission chunk, tile): pairs, then the chunk's pairs of the tile
+                         //   before it within its segment (kSegChunks chunks of one image)
+    uint32_t* seg_base;  // per image + 1: first segment of the image
+    uint32_t* segoff;    // per (segment, tile): pairs, then the segment's first slot in the
+                         //   tile's bucket
     int num_cu;          // compute units (grid sizes of the grid-stride kernels)
     uint32_t* starts;    // per tile + 1
     uint32_t* cls_list;  // kNumClasses lists of `tiles` entries

@@ -88,7 +88,7 @@ struct gsr_context {
     DevBuf<uint32_t> sbvis, loff;
     DevBuf<uint32_t> skey0, skey1, sgid0, sgid1;
     DevBuf<uint2> srect0, srect1;
-    DevBuf<uint32_t> hist, seg_n, seg_start, blk_pairs, chunk_base, pair_base, cstart, cimg, ecnt, seg_base, segoff;
+    DevBuf<uint32_t> hist, seg_n, seg_start, blk_pairs, chunk_base, pair_base, cstart, cimg, ecnt, seg_base, segoff, emit_next;
     DevBuf<uint32_t> starts, cls_list;
     DevBuf<View> views;
     DevBuf<float> T_final;
@@ -228,6 +228,7 @@ void gsr_destroy(gsr_context* ctx) {
     ctx->srect0.release(); ctx->srect1.release(); ctx->hist.release(); ctx->seg_n.release(); ctx->ecnt.release();
     ctx->seg_start.release(); ctx->blk_pairs.release(); ctx->chunk_base.release(); ctx->cstart.release();
     ctx->cimg.release(); ctx->pair_base.release(); ctx->seg_base.release(); ctx->segoff.release();
+    ctx->emit_next.release();
     ctx->starts.release();
     ctx->cls_list.release(); ctx->views.release(); ctx->T_final.release(); ctx->n_contrib.release();
     ctx->g2d.release(); ctx->grads_dev.release(); ctx->pose_part.release(); ctx->counter.release();
@@ -444,7 +445,7 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
         (r = ensure(ctx, ctx->hist, (size_t)a.sort_chunks * 256)) ||
         (r = ensure(ctx, ctx->seg_n, a.images)) || (r = ensure(ctx, ctx->seg_start, a.images + 1)) ||
         (r = ensure(ctx, ctx->blk_pairs, n_pblocks)) || (r = ensure(ctx, ctx->chunk_base, a.images + 1)) || (r = ensure(ctx, ctx->pair_base, a.images)) ||
-        (r = ensure(ctx, ctx->seg_base, a.images + 1)) ||
+        (r = ensure(ctx, ctx->seg_base, a.images + 1)) || (r = ensure(ctx, ctx->emit_next, 8 * kEmitQueueStride)) ||
         (r = ensure(ctx, ctx->starts, a.tiles + 1)) ||
         (r = ensure(ctx, ctx->cls_list, (size_t)kNumClasses * a.tiles)) ||
         (r = ensure(ctx, ctx->views, (size_t)sc->n_nodes * C)) || (r = ensure(ctx, ctx->T_final, npix)) ||
@@ -484,6 +485,7 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
     a.cimg = ctx->cimg.p;
     a.ecnt = ctx->ecnt.p;
     a.seg_base = ctx->seg_base.p;
+    a.emit_next = ctx->emit_next.p;
     a.segoff = ctx->segoff.p;
     a.num_cu = ctx->num_cu;
     if (forward_lds_limits(a) != hipSuccess) {

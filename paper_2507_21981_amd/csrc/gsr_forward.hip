@@ -44,7 +44,7 @@ __global__ void k_views(FwdArgs a) {
         st->pairs = 0;
         st->max_tile = 0;
         for (int c = 0; c < 8; ++c) st->cls[c] = 0;
-        st->work_head = 0;
+        for (int x = 0; x < 8; ++x) a.emit_next[x * kEmitQueueStride] = 0u;
         for (int q = 0; q < kParts; ++q) st->visible[q] = st->visible_any[q] = st->evals[q] = 0;
     }
 
@@ -1099,114 +1099,127 @@ template <int W>
 __global__ __launch_bounds__(64 * W) void k_emit(FwdArgs a) {
     constexpr int NT = 64 * W;
     extern __shared__ unsigned long long s_mask[];  // [tpi] round masks, then [tpi] u32 slots
-    __shared__ uint32_t s_off[65], s_x0[64], s_y0[64], s_w[64], s_id[64];
+    __shared__ uint32_t s_off[65], s_x0[64], s_y0[64], s_w[64], s_id[64], s_q;
     const int tid = threadIdx.x, lane = tid & 63;
     uint32_t* s_slot = reinterpret_cast<uint32_t*>(s_mask + a.tpi);
     const unsigned long long cap = (unsigned long long)a.pair_cap;
     const int tx_n = a.tiles_x;
     for (int t = tid; t < a.tpi; t += NT) s_mask[t] = 0ull;  // masks are left clear by each round
-    uint32_t q0, q1, qs;
-    xcd_items(a.chunk_base[a.images], q0, q1, qs);
-    for (uint32_t q = q0; q < q1; q += qs) {
+    // the blocks of XCD x take the chunks of its eighth of the list in order from a counter, so
+    // the chunks in flight on an XCD stay consecutive and the bucket lines they share are
+    // completed in its L2 (block b runs on XCD b % 8; any placement is still correct)
+    const uint32_t x = blockIdx.x & 7u, n_all = a.chunk_base[a.images];
+    const uint32_t lo = (uint32_t)(((unsigned long long)n_all * x) >> 3);
+    const uint32_t hi = (uint32_t)(((unsigned long long)n_all * (x + 1u)) >> 3);
+    if (tid == 0) s_q = lo + atomicAdd(&a.emit_next[x * kEmitQueueStride], 1u);
+    __syncthreads();
+    for (uint32_t q = s_q; q < hi;) {
+        __syncthreads();  // every thread has read s_q
+        uint32_t nq = 0u;
+        if (tid == 0) nq = lo + atomicAdd(&a.emit_next[x * kEmitQueueStride], 1u);  // the next chunk, taken ahead
         uint32_t pos;
         int img;
         const uint32_t n = emit_chunk(a, q, pos, img);
-        if (n == 0u) continue;
-        const uint32_t* so = a.ecnt + (size_t)q * a.tpi;
-        const uint32_t* st =
-            a.segoff + (size_t)(a.seg_base[img] + (q - a.chunk_base[img]) / (uint32_t)kSegChunks) * a.tpi;
-        for (int t = tid; t < a.tpi; t += NT) s_slot[t] = st[t] + so[t];
-        const uint32_t* gids = a.sgid[1] + pos;
-        const uint2* rects = a.srect[1] + pos;
-        // the next round's Gaussian, loaded one round ahead (by the first wavefront)
-        uint2 nr = make_uint2(0u, 0u);
-        uint32_t ni = 0u;
-        if (tid < 64 && (uint32_t)lane < n) {
-            nr = rects[lane];
-            ni = gids[lane];
-        }
-        for (uint32_t r0 = 0; r0 < n; r0 += 64) {
-            if (tid < 64) {
-                const uint32_t k = r0 + (uint32_t)lane;
-                uint32_t area = 0u;
-                if (k < n) {
-                    const uint32_t x0 = nr.x & 0xffffu, y0 = nr.x >> 16, x1 = nr.y & 0xffffu, y1 = nr.y >> 16;
-                    s_x0[lane] = x0;
-                    s_y0[lane] = y0;
-                    s_w[lane] = x1 - x0;
-                    s_id[lane] = ni;
-                    area = (x1 - x0) * (y1 - y0);
-                }
-                if (k + 64u < n) {
-                    nr = rects[k + 64u];
-                    ni = gids[k + 64u];
-                }
-                const uint32_t incl = wave_incl_scan(area);
-                s_off[lane + 1] = incl;
-                if (lane == 0) s_off[0] = 0u;
+        if (n != 0u) {
+            const uint32_t* so = a.ecnt + (size_t)q * a.tpi;
+            const uint32_t* st =
+                a.segoff + (size_t)(a.seg_base[img] + (q - a.chunk_base[img]) / (uint32_t)kSegChunks) * a.tpi;
+            for (int t = tid; t < a.tpi; t += NT) s_slot[t] = st[t] + so[t];
+            const uint32_t* gids = a.sgid[1] + pos;
+            const uint2* rects = a.srect[1] + pos;
+            // the next round's Gaussian, loaded one round ahead (by the first wavefront)
+            uint2 nr = make_uint2(0u, 0u);
+            uint32_t ni = 0u;
+            if (tid < 64 && (uint32_t)lane < n) {
+                nr = rects[lane];
+                ni = gids[lane];
             }
-            __syncthreads();
-            const uint32_t total = s_off[64];
-            const uint32_t per = (total + (uint32_t)NT - 1u) / (uint32_t)NT;
-            const uint32_t k0 = (uint32_t)tid * per, k1 = k0 + per < total ? k0 + per : total;
-            // where this lane's pairs start: the Gaussian of pair k0 (first o with
-            // s_off[o + 1] > k0) and the tile of that pair
-            int o0 = 0;
-            uint32_t w0 = 1u, x00 = 0u, tx0 = 0u, ty0 = 0u, left0 = 0u;
-            if (k0 < k1) {
-                int hi = 63;
-                while (o0 < hi) {
-                    const int mid = (o0 + hi) >> 1;
-                    if (s_off[mid + 1] > k0) hi = mid;
-                    else o0 = mid + 1;
+            for (uint32_t r0 = 0; r0 < n; r0 += 64) {
+                if (tid < 64) {
+                    const uint32_t k = r0 + (uint32_t)lane;
+                    uint32_t area = 0u;
+                    if (k < n) {
+                        const uint32_t x0 = nr.x & 0xffffu, y0 = nr.x >> 16, x1 = nr.y & 0xffffu, y1 = nr.y >> 16;
+                        s_x0[lane] = x0;
+                        s_y0[lane] = y0;
+                        s_w[lane] = x1 - x0;
+                        s_id[lane] = ni;
+                        area = (x1 - x0) * (y1 - y0);
+                    }
+                    if (k + 64u < n) {
+                        nr = rects[k + 64u];
+                        ni = gids[k + 64u];
+                    }
+                    const uint32_t incl = wave_incl_scan(area);
+                    s_off[lane + 1] = incl;
+                    if (lane == 0) s_off[0] = 0u;
                 }
-                w0 = s_w[o0];
-                x00 = s_x0[o0];
-                const uint32_t j = k0 - s_off[o0];
-                const uint32_t jy = j / w0;
-                tx0 = x00 + (j - jy * w0);
-                ty0 = s_y0[o0] + jy;
-                left0 = s_off[o0 + 1] - k0;
+                __syncthreads();
+                const uint32_t total = s_off[64];
+                const uint32_t per = (total + (uint32_t)NT - 1u) / (uint32_t)NT;
+                const uint32_t k0 = (uint32_t)tid * per, k1 = k0 + per < total ? k0 + per : total;
+                // where this lane's pairs start: the Gaussian of pair k0 (first o with
+                // s_off[o + 1] > k0) and the tile of that pair
+                int o0 = 0;
+                uint32_t w0 = 1u, x00 = 0u, tx0 = 0u, ty0 = 0u, left0 = 0u;
+                if (k0 < k1) {
+                    int hi = 63;
+                    while (o0 < hi) {
+                        const int mid = (o0 + hi) >> 1;
+                        if (s_off[mid + 1] > k0) hi = mid;
+                        else o0 = mid + 1;
+                    }
+                    w0 = s_w[o0];
+                    x00 = s_x0[o0];
+                    const uint32_t j = k0 - s_off[o0];
+                    const uint32_t jy = j / w0;
+                    tx0 = x00 + (j - jy * w0);
+                    ty0 = s_y0[o0] + jy;
+                    left0 = s_off[o0 + 1] - k0;
+                }
+                // calls f(o, tile) for this lane's pairs [k0, k1), in order (every listed rectangle
+                // is non-empty; k < total guarantees a next Gaussian with pairs)
+                auto walk = [&](auto&& f) {
+                    int o = o0;
+                    uint32_t w = w0, x0 = x00, tx = tx0, ty = ty0, left = left0;
+                    for (uint32_t kk = k0; kk < k1; ++kk) {
+                        while (left == 0u) {
+                            ++o;
+                            w = s_w[o];
+                            x0 = s_x0[o];
+                            tx = x0;
+                            ty = s_y0[o];
+                            left = s_off[o + 1] - s_off[o];
+                        }
+                        f(o, ty * (uint32_t)tx_n + tx);
+                        --left;
+                        if (++tx == x0 + w) {
+                            tx = x0;
+                            ++ty;
+                        }
+                    }
+                };
+                walk([&](int o, uint32_t t) { atomicOr(&s_mask[t], 1ull << o); });
+                __syncthreads();
+                walk([&](int o, uint32_t t) {
+                    const unsigned long long m = s_mask[t];
+                    const uint32_t p = s_slot[t] + (uint32_t)__popcll(m & ((1ull << o) - 1ull));
+                    if ((unsigned long long)p < cap) a.pairs[p] = s_id[o];
+                });
+                __syncthreads();
+                walk([&](int o, uint32_t t) {
+                    const unsigned long long m = s_mask[t];
+                    if ((m >> o) == 1ull) {
+                        s_slot[t] += (uint32_t)__popcll(m);
+                        s_mask[t] = 0ull;
+                    }
+                });
+                __syncthreads();
             }
-            // calls f(o, tile) for this lane's pairs [k0, k1), in order (every listed rectangle
-            // is non-empty; k < total guarantees a next Gaussian with pairs)
-            auto walk = [&](auto&& f) {
-                int o = o0;
-                uint32_t w = w0, x0 = x00, tx = tx0, ty = ty0, left = left0;
-                for (uint32_t kk = k0; kk < k1; ++kk) {
-                    while (left == 0u) {
-                        ++o;
-                        w = s_w[o];
-                        x0 = s_x0[o];
-                        tx = x0;
-                        ty = s_y0[o];
-                        left = s_off[o + 1] - s_off[o];
-                    }
-                    f(o, ty * (uint32_t)tx_n + tx);
-                    --left;
-                    if (++tx == x0 + w) {
-                        tx = x0;
-                        ++ty;
-                    }
-                }
-            };
-            walk([&](int o, uint32_t t) { atomicOr(&s_mask[t], 1ull << o); });
-            __syncthreads();
-            walk([&](int o, uint32_t t) {
-                const unsigned long long m = s_mask[t];
-                const uint32_t p = s_slot[t] + (uint32_t)__popcll(m & ((1ull << o) - 1ull));
-                if ((unsigned long long)p < cap) a.pairs[p] = s_id[o];
-            });
-            __syncthreads();
-            walk([&](int o, uint32_t t) {
-                const unsigned long long m = s_mask[t];
-                if ((m >> o) == 1ull) {
-                    s_slot[t] += (uint32_t)__popcll(m);
-                    s_mask[t] = 0ull;
-                }
-            });
-            __syncthreads();
         }
+        if (tid == 0) s_q = nq;
+        __syncthreads();
+        q = s_q;
     }
 }
 

@@ -27,6 +27,7 @@ constexpr int kSortTile = 2048;
 constexpr int kPairBlock = 1024;     // positions per block of the pair-prefix kernels
 constexpr int kSegChunks = 16;       // emission chunks per segment of the tile-range scan
 constexpr int kChunkPairsPerTile = 4; // emission chunk size: pairs per tile of the image
+constexpr int kEmitQueueStride = 64;  // u32 between the per-XCD emission counters (own lines)
 constexpr int kEmitLdsSmall = 8192;   // emission tile table (bytes) above which blocks have 16 wavefronts
 constexpr int kMaxTilesPerImage = 13312;
 
@@ -87,8 +88,7 @@ struct Status {
     unsigned long long pairs;
     uint32_t max_tile;
     uint32_t cls[8];      // tile counts per length class
-    uint32_t work_head;   // unused
-    uint32_t pad[5];
+    uint32_t pad[6];
     // counters summed on the host over kParts slots (block b adds into slot b % kParts): a
     // single address taking an atomic from every wavefront serialises the grid
     unsigned long long visible[kParts];      // visible (image, Gaussian) records
@@ -239,6 +239,7 @@ struct FwdArgs {
     int chunk_pairs;     // pairs per emission chunk (a chunk starts at every multiple)
     uint32_t* ecnt;      // per (emission chunk, tile): pairs, then the chunk's pairs of the tile
                          //   before it within its segment (kSegChunks chunks of one image)
+    uint32_t* emit_next; // per XCD (at a stride of kEmitQueueStride): emission chunks taken
     uint32_t* seg_base;  // per image + 1: first segment of the image
     uint32_t* segoff;    // per (segment, tile): pairs, then the segment's first slot in the
                          //   tile's bucket

@@ -26,7 +26,7 @@ constexpr int kLdsHistLimit = 40000; // int counters of one image's tile differe
 constexpr int kSortTile = 2048;
 constexpr int kPairBlock = 1024;     // positions per block of the pair-prefix kernels
 constexpr int kSegChunks = 16;       // emission chunks per segment of the tile-range scan
-constexpr int kChunkPairsPerTile = 4; // emission chunk size: pairs per tile of the image
+constexpr int kChunkPairsPerTile = 6; // emission chunk size: pairs per tile of the image
 constexpr int kEmitQueueStride = 64;  // u32 between the per-XCD emission counters (own lines)
 constexpr int kEmitLdsSmall = 8192;   // emission tile table (bytes) above which blocks have 16 wavefronts
 constexpr int kMaxTilesPerImage = 13312;

@@ -1088,9 +1088,10 @@ __global__ __launch_bounds__(1024) void k_tile_ranges(FwdArgs a) {
 // tile offsets), rounds in order (a running slot per tile in LDS) and, within a round, by the
 // Gaussian's rank in the round: the set bits below it in the tile's 64-bit round mask.
 // A round's pairs are numbered by a prefix over the rectangle areas and split into equal runs
-// of consecutive pairs, one per thread, walked three times: set the mask bits; write the
-// pairs; advance each tile's slot (by the tile's highest Gaussian of the round) and clear its
-// mask.  Chunks hold about the same number of pairs, so the blocks' work is balanced even where
+// of consecutive pairs, one per thread, walked twice: set the mask bits; write the pairs.
+// Then each tile's slot advances by its count in the round and its mask is cleared (a third
+// walk, at the tile's highest Gaussian of the round, or a pass over the tile table when the
+// round has at least half as many pairs as the image has tiles).  Chunks hold about the same number of pairs, so the blocks' work is balanced even where
 // the nearest (largest) splats of an image crowd into its first chunk.  The W wavefronts of a
 // block share the chunk's tile table (12 bytes per tile), so large tile grids do not cap the
 // wavefronts per CU, and split each round's pairs W ways.
@@ -1207,13 +1208,26 @@ __global__ __launch_bounds__(64 * W) void k_emit(FwdArgs a) {
                     if ((unsigned long long)p < cap) a.pairs[p] = s_id[o];
                 });
                 __syncthreads();
-                walk([&](int o, uint32_t t) {
-                    const unsigned long long m = s_mask[t];
-                    if ((m >> o) == 1ull) {
-                        s_slot[t] += (uint32_t)__popcll(m);
-                        s_mask[t] = 0ull;
+                // advance each touched tile's slot by its round count and clear its mask: over
+                // the round's pairs (at the tile's highest Gaussian) when they are few, else over
+                // the tile table (consecutive, conflict-free LDS accesses)
+                if (2u * total < (uint32_t)a.tpi) {
+                    walk([&](int o, uint32_t t) {
+                        const unsigned long long m = s_mask[t];
+                        if ((m >> o) == 1ull) {
+                            s_slot[t] += (uint32_t)__popcll(m);
+                            s_mask[t] = 0ull;
+                        }
+                    });
+                } else {
+                    for (int t = tid; t < a.tpi; t += NT) {
+                        const unsigned long long m = s_mask[t];
+                        if (m) {
+                            s_slot[t] += (uint32_t)__popcll(m);
+                            s_mask[t] = 0ull;
+                        }
                     }
-                });
+                }
                 __syncthreads();
             }
         }

@@ -70,6 +70,8 @@ def parse():
                     help="only the differentiable workload (for profiling it alone); prints its record")
     ap.add_argument("--tile", default="auto", help="auto (autotuner) or WxH")
     ap.add_argument("--ppt", type=int, default=0, help="pixels per compositor lane with --tile (1, 2, 4)")
+    ap.add_argument("--groups", type=int, default=0,
+                    help="stream groups of the batched render (default: the autotuner's, 1 with --tile)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (calibrates HBM traffic counters) and exit")
     return ap.parse_args()
@@ -147,7 +149,10 @@ def main():
         ctx.set_tile(tw, th)
         if args.ppt:
             ctx.set_pixels_per_thread(args.ppt)
-    log(f"[bench] tile {tw}x{th} persistent={pers}")
+    if args.groups:
+        ctx.set_stream_groups(args.groups)
+    groups = ctx.config.stream_groups
+    log(f"[bench] tile {tw}x{th} persistent={pers} stream groups {groups}")
     fl_pers = gsr.FLAG_PERSISTENT if pers else 0
     rgb, depth, alpha = gsr.render_rgbd(ctx, scene, cams, W, H, C, flags=gsr.FLAG_CHECK | fl_pers)
     out = (rgb, depth, alpha)
@@ -169,10 +174,16 @@ def main():
         ms_o = timed_graph(gsr, ctx, scene, cams, W, H, C, out, poses, pose_sets, fl_o, args)
         other = {"persistent" if not pers else "one_block_per_tile":
                  {"ms_per_step": round(ms_o, 4), "value": round(px_step / (ms_o * 1e-3) / 1e6, 2)}}
-        log(f"[bench] other compositor: {other}")
+        if groups > 1:  # the same graph protocol on one stream group
+            ctx.set_stream_groups(1)
+            ms_1 = timed_graph(gsr, ctx, scene, cams, W, H, C, out, poses, pose_sets, fl_pers, args)
+            ctx.set_stream_groups(groups)
+            other["one_stream_group"] = {"ms_per_step": round(ms_1, 4), "value": round(px_step / (ms_1 * 1e-3) / 1e6, 2)}
+        log(f"[bench] variants: {other}")
 
-    # per-stage durations (eager, HIP events between stages on the render stream)
-    # (the same kernels as the graph; evaluations are counted by a checked render of each pose set)
+    # per-stage durations (eager, HIP events between stages on the render stream; a timed render
+    # keeps to one stream group) (the same kernels as the graph; evaluations are counted by a
+    # checked render of each pose set)
     stage = {k: 0.0 for k in gsr.STAGES}
     n_t = max(1, min(args.steps, 5))
     evals = 0
@@ -246,7 +257,8 @@ def main():
         "config": {"workload": f"batched: {E} envs x {C} cams 320x240 RGB-D, background 100k-1M Gaussians "
                                f"(log-uniform) + 4 posed objects x 20k, SH3, fresh object poses per step",
                    "gaussians": n_total, "images": E * C, "pixels_per_step": px_step, "tile": f"{tw}x{th}",
-                   "pixels_per_lane": ppt, "persistent": bool(pers), "hipgraph": True, "seed": args.seed},
+                   "pixels_per_lane": ppt, "persistent": bool(pers), "stream_groups": groups, "hipgraph": True,
+                   "seed": args.seed},
         "gate": gate,
         "compositor_variant": other or None,
         "gaussian_pixel_evals_per_s": evals_rates(st_t["evals"], algo_evals, stage["composite"]),

@@ -159,7 +159,9 @@ typedef struct {
                                  CU (scaled to the tile's block size)                        */
     int32_t pixels_per_thread;/* compositor pixels per thread, 1, 2 or 4 (default 2); capped
                                  at tile pixels / 64 (8x8 tiles use 1, 16x8 at most 2)       */
-    int32_t reserved[6];
+    int32_t stream_groups;    /* 1..4 (default 1): environments rendered as this many groups
+                                 on the library's own streams, see gsr_render_rgbd           */
+    int32_t reserved[5];
 } gsr_config;
 
 /* Per-image parameters of the image-space domain randomisation (Sec. IV-C,
@@ -202,6 +204,22 @@ const char* gsr_last_error(const gsr_context* ctx);
 int gsr_get_config(const gsr_context* ctx, gsr_config* out);
 int gsr_set_tile(gsr_context* ctx, int32_t tile_w, int32_t tile_h);
 int gsr_set_pixels_per_thread(gsr_context* ctx, int32_t ppt);
+
+/* Stream groups (1..4) of later renders (gsr_render_rgbd).  With groups > 1 a
+   render splits the scene's environments into that many contiguous groups of
+   similar Gaussian counts (at most one group per environment).  Each group is
+   rendered by a private sub-context with its own workspace on its own stream
+   (default priority), forked from and joined back to the caller's stream, so
+   one group's memory-bound stages (projection, sort) overlap another's
+   compositing.  Every image is computed exactly as by a single-group render
+   (same operations, same order per image).  Renders with GSR_FLAG_SAVE,
+   GSR_FLAG_TIMING or GSR_FLAG_AUGMENT, and scenes of one environment, use one
+   group.  After a grouped render gsr_query_status sums (ORs, maximises) the
+   groups' counters, and gsr_copy_pairs, gsr_copy_pixel_state and
+   gsr_stage_times return GSR_E_STATE.  More groups than the device's hardware
+   queues less one (usually 3) serialise on shared queues.  Errors:
+   GSR_E_INVALID (NULL ctx), GSR_E_UNSUPPORTED (groups outside 1..4). */
+int gsr_set_stream_groups(gsr_context* ctx, int32_t groups);
 
 /* ---- scene composition (Sec. III-B: background node + posed nodes) ----- */
 
@@ -419,7 +437,9 @@ int gsr_stage_times(gsr_context* ctx, float* ms);
    persistent compositor on/off on this scene and camera set (full renders),
    keep the fastest in the context and return it (candidates are tried from
    16x16 tiles, one pixel per thread, one block per tile on; a later one
-   replaces the choice only when at least 2% faster).  Outputs are scratch buffers
+   replaces the choice only when at least 2% faster); then, for a scene of
+   several environments, 2 and 3 stream groups with that choice (the same 2%
+   rule; gsr_get_config reports the groups kept).  Outputs are scratch buffers
    sized for the call.  Synchronous.  The choice is cached per (images, width,
    height, Gaussian count) in the context. */
 int gsr_autotune(gsr_context* ctx, const gsr_scene* scene, int32_t cams_per_env,

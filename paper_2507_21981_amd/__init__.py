@@ -52,7 +52,7 @@ class GaussianGrads(ctypes.Structure):
 class Config(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("pair_capacity", ctypes.c_int64),
                 ("persistent_grid", ctypes.c_int32), ("pixels_per_thread", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("stream_groups", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class StatusInfo(ctypes.Structure):
@@ -81,6 +81,7 @@ def lib():
         L.gsr_get_config.argtypes = [vp, ctypes.POINTER(Config)]
         L.gsr_set_tile.argtypes = [vp, i32, i32]
         L.gsr_set_pixels_per_thread.argtypes = [vp, i32]
+        L.gsr_set_stream_groups.argtypes = [vp, i32]
         L.gsr_compose_scene.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(Gaussians), i32, vp,
                                         ctypes.POINTER(vp)]
         L.gsr_scene_destroy.argtypes = [vp]
@@ -169,6 +170,10 @@ class Context:
 
     def set_pixels_per_thread(self, ppt):
         _check(lib().gsr_set_pixels_per_thread(self.handle, ppt), self)
+
+    def set_stream_groups(self, groups):
+        """Render environments as `groups` concurrent groups on the library's streams."""
+        _check(lib().gsr_set_stream_groups(self.handle, groups), self)
 
 
 def create(device=0, tile=(16, 16), pair_capacity=0, persistent_grid=0):

@@ -52,6 +52,8 @@ struct GraphKey {
     }
 };
 
+constexpr int kMaxGroups = 4;  // stream groups of a render (gsr_set_stream_groups)
+
 }  // namespace
 
 struct gsr_scene {
@@ -72,6 +74,12 @@ struct gsr_scene {
     int sb_cap = kBlock;  // Gaussians per super-block at most
     LidarScene* lidar = nullptr;  // per-node hierarchies of the LiDAR tracer (gsr_lidar_build)
     uint64_t lidar_version = 0;   // scene version they were built for
+    // grouped renders: one scene per group of environments [sub_env[g], sub_env[g + 1]),
+    // composed on the owning context's sub-context g for scene version sub_version
+    gsr_scene* sub[kMaxGroups] = {};
+    int sub_groups = 0;
+    int sub_env[kMaxGroups + 1] = {};
+    uint64_t sub_version = 0;
 };
 
 struct gsr_context {
@@ -113,11 +121,17 @@ struct gsr_context {
     GraphKey gkey{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    // autotune cache: (images, W, H, gaussians) -> (tw, th, persistent, ppt)
-    std::map<std::tuple<int, int, int, long long>, std::tuple<int, int, int, int>> tune;
+    // autotune cache: (images, W, H, gaussians) -> (tw, th, persistent, ppt, stream groups)
+    std::map<std::tuple<int, int, int, long long>, std::tuple<int, int, int, int, int>> tune;
     hipEvent_t stage_ev[kStages + 1] = {};
     bool timed = false;
     hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
+    // stream groups: sub-contexts (own workspace), their streams, fork and join events
+    gsr_context* sub[kMaxGroups] = {};
+    hipStream_t gstream[kMaxGroups] = {};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[kMaxGroups] = {};
+    int last_groups = 1;  // groups of the last render
 };
 
 static int fail(gsr_context* ctx, int code, const char* fmt, ...) {
@@ -194,6 +208,11 @@ int gsr_create(int device, const gsr_config* cfg, gsr_context** out) {
     hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device);
     if (c.persistent_grid <= 0) c.persistent_grid = 8 * std::max(ctx->num_cu, 1);
     if (c.pixels_per_thread == 0) c.pixels_per_thread = 2;
+    if (c.stream_groups == 0) c.stream_groups = 1;
+    if (c.stream_groups < 1 || c.stream_groups > kMaxGroups) {
+        delete ctx;
+        return fail(nullptr, GSR_E_UNSUPPORTED, "gsr_create: stream_groups must be 1..%d", kMaxGroups);
+    }
     if (c.pixels_per_thread != 1 && c.pixels_per_thread != 2 && c.pixels_per_thread != 4) {
         delete ctx;
         return fail(nullptr, GSR_E_UNSUPPORTED, "gsr_create: pixels_per_thread must be 1, 2 or 4");
@@ -219,6 +238,12 @@ void gsr_destroy(gsr_context* ctx) {
     if (!ctx) return;
     hipSetDevice(ctx->device);
     hipDeviceSynchronize();
+    for (int g = 0; g < kMaxGroups; ++g) {
+        if (ctx->sub[g]) gsr_destroy(ctx->sub[g]);
+        if (ctx->gstream[g]) hipStreamDestroy(ctx->gstream[g]);
+        if (ctx->join_ev[g]) hipEventDestroy(ctx->join_ev[g]);
+    }
+    if (ctx->fork_ev) hipEventDestroy(ctx->fork_ev);
     drop_graph(ctx);
     for (auto& e : ctx->stage_ev)
         if (e) hipEventDestroy(e);
@@ -263,8 +288,20 @@ int gsr_set_pixels_per_thread(gsr_context* ctx, int32_t ppt) {
     return GSR_OK;
 }
 
+int gsr_set_stream_groups(gsr_context* ctx, int32_t groups) {
+    if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_set_stream_groups: ctx is NULL");
+    if (groups < 1 || groups > kMaxGroups)
+        return fail(ctx, GSR_E_UNSUPPORTED, "gsr_set_stream_groups: %d outside 1..%d", groups, kMaxGroups);
+    ctx->cfg.stream_groups = groups;
+    return GSR_OK;
+}
+
 void gsr_scene_destroy(gsr_scene* sc) {
     if (!sc) return;
+    for (auto& sub : sc->sub) {
+        gsr_scene_destroy(sub);
+        sub = nullptr;
+    }
     if (sc->lidar) {
         hipDeviceSynchronize();
         lidar_free(sc->lidar);
@@ -519,6 +556,109 @@ static int read_status(gsr_context* ctx, hipStream_t s) {
 
 extern "C" {
 
+// Stream groups: the configured count, at most one per environment; one for renders whose
+// state or parameters belong to the context (saved for backward, timed, augmented).
+static int render_groups(const gsr_context* ctx, const gsr_scene* sc, uint32_t flags) {
+    if (ctx->cfg.stream_groups <= 1 || (flags & (GSR_FLAG_SAVE | GSR_FLAG_TIMING | GSR_FLAG_AUGMENT))) return 1;
+    return std::min(ctx->cfg.stream_groups, sc->n_envs);
+}
+
+// G sub-contexts (the parent's tile shape and pixels per thread), their streams and the
+// fork / join events.
+static int ensure_groups(gsr_context* ctx, int G) {
+    gsr_config c = ctx->cfg;
+    c.stream_groups = 1;
+    if (!ctx->fork_ev) HIPCHK(ctx, hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+    for (int g = 0; g < G; ++g) {
+        if (!ctx->sub[g]) {
+            const int r = gsr_create(ctx->device, &c, &ctx->sub[g]);
+            if (r) return fail(ctx, r, "stream group %d: %s", g, gsr_last_error(nullptr));
+        }
+        gsr_context* sub = ctx->sub[g];
+        int r = GSR_OK;
+        if (sub->cfg.tile_w != c.tile_w || sub->cfg.tile_h != c.tile_h) r = gsr_set_tile(sub, c.tile_w, c.tile_h);
+        if (!r && sub->cfg.pixels_per_thread != c.pixels_per_thread) r = gsr_set_pixels_per_thread(sub, c.pixels_per_thread);
+        if (r) return fail(ctx, r, "stream group %d: %s", g, sub->err.c_str());
+        if (!ctx->gstream[g]) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->gstream[g], hipStreamNonBlocking));
+        if (!ctx->join_ev[g]) HIPCHK(ctx, hipEventCreateWithFlags(&ctx->join_ev[g], hipEventDisableTiming));
+    }
+    return GSR_OK;
+}
+
+// The scene's G groups: contiguous environment ranges of about equal Gaussian counts (at
+// least one environment each), group g composed on sub-context g over the same borrowed
+// Gaussians and pose buffer.  Composed again after the scene is.
+static int ensure_subscenes(gsr_context* ctx, gsr_scene* sc, int G) {
+    if (sc->sub_groups == G && sc->sub_version == sc->version) return GSR_OK;
+    const int E = sc->n_envs;
+    std::vector<long long> cum(E + 1, 0);
+    for (int e = 0; e < E; ++e) cum[e + 1] = cum[e] + (long long)sc->envs_h[e].n;
+    int b[kMaxGroups + 1];
+    b[0] = 0;
+    b[G] = E;
+    for (int g = 1; g < G; ++g) {
+        const long long target = cum[E] * g / G;
+        int e = (int)(std::lower_bound(cum.begin(), cum.end(), target) - cum.begin());
+        b[g] = std::min(std::max(e, b[g - 1] + 1), E - (G - g));
+    }
+    for (int g = 0; g < G; ++g) {
+        const int lo = b[g], hi = b[g + 1];
+        const int k0 = sc->env_offsets[lo], k1 = sc->env_offsets[hi];
+        std::vector<int32_t> off(hi - lo + 1);
+        for (int i = 0; i <= hi - lo; ++i) off[i] = sc->env_offsets[lo + i] - k0;
+        std::vector<gsr_gaussians> nd(k1 - k0);
+        for (int k = k0; k < k1; ++k) {
+            const Node& n = sc->nodes_h[k];
+            gsr_gaussians& d = nd[k - k0];
+            d.n = n.n;
+            d.sh_degree = sc->sh_degree;
+            d.reserved = 0;
+            d.means = n.means;
+            d.scales = n.scales;
+            d.quats = n.quats;
+            d.opacities = n.opac;
+            d.sh = n.sh;
+        }
+        const int r = gsr_compose_scene(ctx->sub[g], hi - lo, off.data(), nd.data(), k1 - k0, sc->poses + k0, &sc->sub[g]);
+        if (r) return fail(ctx, r, "stream group %d: %s", g, ctx->sub[g]->err.c_str());
+        sc->sub_env[g] = lo;
+    }
+    sc->sub_env[G] = E;
+    for (int g = G; g < kMaxGroups; ++g) {
+        gsr_scene_destroy(sc->sub[g]);
+        sc->sub[g] = nullptr;
+    }
+    sc->sub_groups = G;
+    sc->sub_version = sc->version;
+    return GSR_OK;
+}
+
+// A grouped render: each group's images rendered by its sub-context on its own stream, after
+// the work already on `s` (fork event) and before later work on `s` (join events).
+static int render_grouped(gsr_context* ctx, const gsr_scene* sc0, int G, int32_t C, const gsr_camera* cams, int32_t W,
+                          int32_t H, float* rgb, float* depth, float* alpha, uint32_t flags, hipStream_t s) {
+    gsr_scene* sc = const_cast<gsr_scene*>(sc0);  // the sub-scene cache only
+    int r;
+    if ((r = ensure_groups(ctx, G)) || (r = ensure_subscenes(ctx, sc, G))) return r;
+    HIPCHK(ctx, hipEventRecord(ctx->fork_ev, s));
+    const size_t img_px = (size_t)W * H;
+    for (int g = 0; g < G; ++g) {
+        const size_t img0 = (size_t)sc->sub_env[g] * C, px = img0 * img_px;
+        HIPCHK(ctx, hipStreamWaitEvent(ctx->gstream[g], ctx->fork_ev, 0));
+        r = gsr_render_rgbd(ctx->sub[g], sc->sub[g], C, cams + img0, W, H, rgb + 3 * px, depth + px,
+                            alpha ? alpha + px : nullptr, flags, ctx->gstream[g]);
+        if (r) return fail(ctx, r, "stream group %d: %s", g, ctx->sub[g]->err.c_str());
+        HIPCHK(ctx, hipEventRecord(ctx->join_ev[g], ctx->gstream[g]));
+        HIPCHK(ctx, hipStreamWaitEvent(s, ctx->join_ev[g], 0));
+    }
+    ctx->last_groups = G;
+    ctx->last_stream = s;
+    ctx->have_last = ctx->saved = ctx->timed = false;
+    ctx->saved_id = 0;
+    ctx->render_serial++;
+    return GSR_OK;
+}
+
 int gsr_render_rgbd(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_camera* cams, int32_t W, int32_t H,
                     float* rgb, float* depth, float* alpha, uint32_t flags, void* stream) {
     if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_render_rgbd: ctx is NULL");
@@ -528,6 +668,9 @@ int gsr_render_rgbd(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_
     if (W < 1 || H < 1 || W > 8192 || H > 8192) return fail(ctx, GSR_E_INVALID, "gsr_render_rgbd: image size %dx%d outside 1..8192", W, H);
     hipStream_t s = (hipStream_t)stream;
     hipSetDevice(ctx->device);
+    const int G = render_groups(ctx, sc, flags);
+    if (G > 1) return render_grouped(ctx, sc, G, C, cams, W, H, rgb, depth, alpha, flags, s);
+    ctx->last_groups = 1;
     const int persistent = (flags & GSR_FLAG_PERSISTENT) ? 1 : 0;
     const int save = (flags & GSR_FLAG_SAVE) ? 1 : 0;
     FwdArgs a;
@@ -679,6 +822,24 @@ int gsr_set_augment(gsr_context* ctx, const gsr_augment* params, const float* ov
 int gsr_query_status(gsr_context* ctx, gsr_status_info* out) {
     if (!ctx || !out) return fail(ctx, GSR_E_INVALID, "gsr_query_status: NULL argument");
     hipSetDevice(ctx->device);
+    if (ctx->last_groups > 1) {  // the groups' counters combined
+        gsr_status_info sum{};
+        for (int g = 0; g < ctx->last_groups; ++g) {
+            gsr_status_info o{};
+            const int r = gsr_query_status(ctx->sub[g], &o);
+            if (r) return fail(ctx, r, "stream group %d: %s", g, ctx->sub[g]->err.c_str());
+            sum.flags |= o.flags;
+            sum.nonfinite += o.nonfinite;
+            sum.pairs += o.pairs;
+            sum.pair_capacity += o.pair_capacity;
+            sum.max_tile_pairs = std::max(sum.max_tile_pairs, o.max_tile_pairs);
+            sum.visible += o.visible;
+            sum.visible_any += o.visible_any;
+            sum.evals += o.evals;
+        }
+        *out = sum;
+        return GSR_OK;
+    }
     int r = read_status(ctx, ctx->last_stream);
     if (r) return r;
     const Status& st = *ctx->h_status;
@@ -708,6 +869,7 @@ int gsr_stage_times(gsr_context* ctx, float* ms) {
 
 int gsr_copy_pairs(gsr_context* ctx, uint64_t* keys, uint32_t* values, uint32_t* ranges, int64_t capacity, int64_t* n_pairs) {
     if (!ctx || !keys || !values || !ranges || !n_pairs) return fail(ctx, GSR_E_INVALID, "gsr_copy_pairs: NULL argument");
+    if (ctx->last_groups > 1) return fail(ctx, GSR_E_STATE, "gsr_copy_pairs: the last render was split into stream groups");
     if (!ctx->have_last) return fail(ctx, GSR_E_STATE, "gsr_copy_pairs: nothing rendered yet");
     hipSetDevice(ctx->device);
     int r = read_status(ctx, ctx->last_stream);
@@ -722,6 +884,8 @@ int gsr_copy_pairs(gsr_context* ctx, uint64_t* keys, uint32_t* values, uint32_t*
 
 int gsr_copy_pixel_state(gsr_context* ctx, float* T_final, uint32_t* n_contrib) {
     if (!ctx) return fail(nullptr, GSR_E_INVALID, "gsr_copy_pixel_state: ctx is NULL");
+    if (ctx->last_groups > 1)
+        return fail(ctx, GSR_E_STATE, "gsr_copy_pixel_state: the last render was split into stream groups");
     if (!ctx->have_last) return fail(ctx, GSR_E_STATE, "gsr_copy_pixel_state: nothing rendered yet");
     hipSetDevice(ctx->device);
     const size_t npix = (size_t)ctx->last.images * ctx->last.width * ctx->last.height;
@@ -851,7 +1015,8 @@ int gsr_autotune(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_cam
         hipStream_t s = (hipStream_t)stream;
         const int shapes[4][2] = {{16, 16}, {16, 8}, {8, 8}, {32, 8}};
         float best = 1e30f;
-        std::tuple<int, int, int, int> choice{16, 16, 0, 2};
+        std::tuple<int, int, int, int, int> choice{16, 16, 0, 2, 1};
+        ctx->cfg.stream_groups = 1;  // tile shapes are compared on one group
         hipEvent_t e0, e1;
         HIPCHK(ctx, hipEventCreate(&e0));
         HIPCHK(ctx, hipEventCreate(&e1));
@@ -877,9 +1042,32 @@ int gsr_autotune(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_cam
                     // a later candidate must be 2% faster: timing noise does not flip near-ties
                     if (ms < 0.98f * best) {
                         best = ms;
-                        choice = std::make_tuple(sh[0], sh[1], pers, ppt);
+                        choice = std::make_tuple(sh[0], sh[1], pers, ppt, 1);
                     }
                 }
+            }
+        }
+        // stream groups with the chosen shape (several environments only)
+        for (int G = 2; G <= std::min(3, sc->n_envs); ++G) {
+            int r = gsr_set_tile(ctx, std::get<0>(choice), std::get<1>(choice));
+            if (!r) r = gsr_set_pixels_per_thread(ctx, std::get<3>(choice));
+            if (!r) r = gsr_set_stream_groups(ctx, G);
+            if (r) return r;
+            const uint32_t fl = std::get<2>(choice) ? GSR_FLAG_PERSISTENT : 0u;
+            r = gsr_render_rgbd(ctx, sc, C, cams, W, H, rgb, depth, alpha, fl | GSR_FLAG_CHECK, stream);
+            if (r) return r;
+            float ms = 0.0f;
+            HIPCHK(ctx, hipEventRecord(e0, s));
+            for (int it2 = 0; it2 < 3; ++it2) {
+                r = gsr_render_rgbd(ctx, sc, C, cams, W, H, rgb, depth, alpha, fl, stream);
+                if (r) return r;
+            }
+            HIPCHK(ctx, hipEventRecord(e1, s));
+            HIPCHK(ctx, hipEventSynchronize(e1));
+            HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < 0.98f * best) {
+                best = ms;
+                std::get<4>(choice) = G;
             }
         }
         hipEventDestroy(e0);
@@ -888,6 +1076,7 @@ int gsr_autotune(gsr_context* ctx, const gsr_scene* sc, int32_t C, const gsr_cam
     }
     int r = gsr_set_tile(ctx, std::get<0>(it->second), std::get<1>(it->second));
     if (!r) r = gsr_set_pixels_per_thread(ctx, std::get<3>(it->second));
+    if (!r) r = gsr_set_stream_groups(ctx, std::get<4>(it->second));
     if (r) return r;
     if (tile_w) *tile_w = std::get<0>(it->second);
     if (tile_h) *tile_h = std::get<1>(it->second);

@@ -60,6 +60,7 @@ def test_null_context_calls_return_invalid(lib):
     s = g.StatusInfo()
     assert lib.gsr_query_status(None, ctypes.byref(s)) == -1
     assert lib.gsr_set_tile(None, 16, 16) == -1
+    assert lib.gsr_set_stream_groups(None, 2) == -1
     ms = (ctypes.c_float * 10)()
     assert lib.gsr_stage_times(None, ms) == -1
     lib.gsr_destroy(None)  # no-op
@@ -78,8 +79,8 @@ def test_struct_layouts_match_the_header(tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(gsr_gaussians), sizeof(gsr_gaussian_grads), sizeof(gsr_config),
          sizeof(gsr_status_info), sizeof(gsr_pose), sizeof(gsr_camera));
-  printf("%zu %zu %zu %zu\\n", offsetof(gsr_gaussians, sh), offsetof(gsr_config, persistent_grid),
-         offsetof(gsr_status_info, visible), offsetof(gsr_status_info, evals));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(gsr_gaussians, sh), offsetof(gsr_config, persistent_grid),
+         offsetof(gsr_status_info, visible), offsetof(gsr_status_info, evals), offsetof(gsr_config, stream_groups));
   return 0;
 }
 """)
@@ -91,7 +92,7 @@ int main(void) {
                          ctypes.sizeof(g.StatusInfo)]
     assert sizes[4] == 12 * 4 and sizes[5] == 20 * 4  # poses and cameras travel as float32 rows
     assert offs == [g.Gaussians.sh.offset, g.Config.persistent_grid.offset, g.StatusInfo.visible.offset,
-                    g.StatusInfo.evals.offset]
+                    g.StatusInfo.evals.offset, g.Config.stream_groups.offset]
 
 
 def test_bench_refuses_more_than_one_gpu():

@@ -369,6 +369,53 @@ def test_batched_equals_per_camera_loop_bitwise(gsr, ctx):
         log(f"tile {tile}: {len(wl['envs']) * C} images bitwise equal")
 
 
+def test_stream_groups_render_exactly_as_one_group(gsr, ctx):
+    """Environments split into 2, 3 or 4 stream groups (sub-contexts with their own workspace
+    on their own streams, forked from and joined back to the caller's stream) give every image
+    bit for bit as one group does: checked, eager and replayed graphs (the outputs cleared by
+    the caller's own work between replays).  The status sums the groups; the per-context
+    state of a grouped render is refused; a saved render keeps to one group."""
+    import torch
+    wl = synth.scene_config(3, seed=43, scale=0.03, n_envs=5)
+    envs_t, poses, cams = upload(wl)
+    W, H, C = wl["width"], wl["height"], wl["cams_per_env"]
+    E = len(wl["envs"])
+    ctx.set_tile(16, 16)
+    scene = gsr.compose_scene(ctx, envs_t, poses)
+    ref = [t.clone() for t in gsr.render_rgbd(ctx, scene, cams, W, H, C, flags=gsr.FLAG_CHECK)]
+    st_ref = gsr.query_status(ctx)
+    tiles = E * C * ((W + 15) // 16) * ((H + 15) // 16)
+    try:
+        for G in (2, 3, 4):
+            ctx.set_stream_groups(G)
+            out = gsr.render_rgbd(ctx, scene, cams, W, H, C, flags=gsr.FLAG_CHECK)
+            for a, b in zip(out, ref):
+                assert torch.equal(a, b), f"{G} groups, checked"
+            st = gsr.query_status(ctx)
+            for k in ("flags", "pairs", "visible", "visible_any", "evals", "nonfinite", "max_tile_pairs"):
+                assert st[k] == st_ref[k], (G, k, st[k], st_ref[k])
+            eager = gsr.render_rgbd(ctx, scene, cams, W, H, C, flags=0)
+            for a, b in zip(eager, ref):
+                assert torch.equal(a, b), f"{G} groups, eager"
+            outg = tuple(torch.empty_like(t) for t in ref)
+            for rep in range(3):
+                for t in outg:
+                    t.fill_(-1.0)
+                gsr.render_rgbd(ctx, scene, cams, W, H, C, out=outg, flags=gsr.FLAG_GRAPH)
+                for a, b in zip(outg, ref):
+                    assert torch.equal(a, b), f"{G} groups, graph replay {rep}"
+            with pytest.raises(gsr.GsrError):
+                gsr.copy_pairs(ctx, tiles)
+            log(f"{G} stream groups: {E * C} images bitwise equal to one group (checked, eager, graph)")
+        # saved for backward: one group, the context's own state
+        gsr.render_rgbd(ctx, scene, cams, W, H, C, flags=gsr.FLAG_SAVE | gsr.FLAG_CHECK)
+        keys, _, _ = gsr.copy_pairs(ctx, tiles)
+        assert keys.numel() == st_ref["pairs"]
+    finally:
+        ctx.set_stream_groups(1)
+    scene.close()
+
+
 def test_persistent_composite_matches_one_block_per_tile(gsr, ctx):
     import torch
     wl = synth.scene_config(3, seed=31, scale=0.03, n_envs=4)

@@ -197,7 +197,8 @@ def main():
     st_t = dict(gsr.query_status(ctx))
     st_t["evals"] = evals // n_t
     st_t["items"] = C * n_total
-    st_t["tiles"] = E * C * ((W + tw - 1) // tw) * ((H + th - 1) // th)
+    st_t["tiles_per_image"] = ((W + tw - 1) // tw) * ((H + th - 1) // th)
+    st_t["tiles"] = E * C * st_t["tiles_per_image"]
     log("[bench] stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stage.items()))
     ppt = ctx.config.pixels_per_thread
     copy_gbs = copy_peak()
@@ -633,7 +634,8 @@ def roofline(stage, st, n_total, cfg, copy_gbs):
     # kernel names as the profiler prints them, without the parameter list; the timed region
     # composites without evaluation counting
     kname = {"project": ["k_project<3>"],
-             "emit": ["k_pair_blocks", "k_pair_scan", "k_chunk_starts", "k_tile_counts", "k_tile_ranges", "k_emit"],
+             "emit": ["k_pair_blocks", "k_pair_scan", "k_chunk_starts", "k_tile_counts", "k_tile_seg", "k_tile_ranges",
+                      f"k_emit<{16 if 12 * st['tiles_per_image'] > 8192 else 4}>"],
              "composite": [f"k_composite{'_persistent' if pers else ''}<{tw}, {th}, {ppt}, false, false>"]}
     traffic = measured_traffic()
     if traffic is not None:

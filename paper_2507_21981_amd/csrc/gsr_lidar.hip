@@ -9,8 +9,8 @@
 // differing code bit), stored depth-first (the left child follows its parent, the parent keeps
 // the right child's index).
 //
-// Tracing (k_lidar, a wavefront per 64 rays): repeated passes over the env's nodes, each
-// collecting per lane in registers the K next hits in (t_c, id) order after the last one
+// Tracing (k_lidar, a wavefront per packet of up to 64 rays): repeated passes over the env's
+// nodes, each collecting per lane in registers the K next hits in (t_c, id) order after the last one
 // composited -- a hit being a Gaussian whose centre lies at t_c = (mu - o) . d inside
 // (tmin, tmax) and whose peak response along the ray, alpha = min(0.99, o exp(-D^2 / 2)),
 // reaches 1/255 -- then compositing them front to back with the camera's rules until the
@@ -318,8 +318,8 @@ __device__ inline LocalRay local_ray(const gsr_ray& ray, const gsr_pose& P) {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// One wavefront traces 64 rays together (a packet: a LiDAR's neighbouring beams share most of
-// the boxes they cross).  The walk over a hierarchy is the wavefront's: a node is visited when
+// One wavefront traces up to 64 rays together (a packet: a LiDAR's neighbouring beams share
+// most of the boxes they cross).  The walk over a hierarchy is the wavefront's: a node is visited when
 // any of its rays may enter it, children nearer (by majority) first, one stack per wavefront in
 // LDS, node and primitive loads the same for every lane.  Each lane keeps its own K next hits,
 // its own last composited key and its own pruning bounds; a lane that visits a node it would
@@ -329,13 +329,17 @@ __global__ __launch_bounds__(64) void k_lidar(const float4* __restrict__ bnodes,
                                               const int2* __restrict__ roots, const Env* __restrict__ envs,
                                               const gsr_pose* __restrict__ poses, int n_envs, int rays_per_env,
                                               const gsr_ray* __restrict__ rays, float* range_out, float* alpha_out,
-                                              uint32_t* hits_out) {
+                                              uint32_t* hits_out, int rpw) {
     __shared__ int s_stack[kLidarStack];
     const int lane = threadIdx.x;
     const long long n = (long long)n_envs * rays_per_env;
-    const long long r = (long long)blockIdx.x * blockDim.x + lane;
-    const bool valid = r < n;
-    const long long rr = valid ? r : n - 1;
+    // rays r0 .. r0 + nv - 1 on lanes 0 .. nv - 1 (rpw rays per wavefront); the other lanes
+    // take the first ray's values and stay done
+    const long long r0 = (long long)blockIdx.x * rpw;
+    const int nv = (int)(n - r0 < rpw ? n - r0 : rpw);
+    const long long r = r0 + lane;
+    const bool valid = lane < nv;
+    const long long rr = valid ? r : r0;
     const int env = (int)(rr / rays_per_env);
     const gsr_ray ray = rays[rr];
     const float thr = (float)(1.0 / 255.0);
@@ -345,7 +349,7 @@ __global__ __launch_bounds__(64) void k_lidar(const float4* __restrict__ bnodes,
     uint64_t last = hit_key(tmin, 0u);  // keys at or below it are done (tmin itself is excluded)
     bool done = !valid;
     // rays are env-major, so the wavefront's envs are a contiguous range
-    const int e_lo = uniform(env), e_hi = __builtin_amdgcn_readlane(env, 63);
+    const int e_lo = uniform(env), e_hi = __builtin_amdgcn_readlane(env, nv - 1);
     while (__any(!done)) {
         uint64_t key[kLidarK];
         float al[kLidarK];
@@ -485,12 +489,24 @@ __global__ __launch_bounds__(64) void k_lidar(const float4* __restrict__ bnodes,
     if (hits_out) hits_out[r] = nh;
 }
 
+// Rays per wavefront (a power of two, 2 to 64): about kLidarWaves wavefronts per frame.  A
+// packet walks the union of its rays' paths and stays until its slowest ray is done, so small
+// packets waste fewer visits and many short wavefronts balance the device (composed workload:
+// 131k rays 32.7 ms at 64 per wavefront, 20.3 ms at 8; 32k rays 38.2 ms at 64, 14.8 ms at 2).
+constexpr long long kLidarWaves = 16384;
+static int lidar_rays_per_wave(long long n) {
+    int rpw = 64;
+    while (rpw > 2 && rpw * kLidarWaves > n) rpw >>= 1;
+    return rpw;
+}
+
 hipError_t launch_lidar(const LidarScene* L, const Env* envs, const gsr_pose* poses, int n_envs, int rays_per_env,
                         const gsr_ray* rays, float* range, float* alpha, uint32_t* hits, hipStream_t s) {
     const long long n = (long long)n_envs * rays_per_env;
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lidar, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, L->bnodes, L->prims, L->roots, envs,
-                       poses, n_envs, rays_per_env, rays, range, alpha, hits);
+    const int rpw = lidar_rays_per_wave(n);
+    hipLaunchKernelGGL(k_lidar, dim3((unsigned)((n + rpw - 1) / rpw)), dim3(64), 0, s, L->bnodes, L->prims, L->roots,
+                       envs, poses, n_envs, rays_per_env, rays, range, alpha, hits, rpw);
     return hipGetLastError();
 }
 

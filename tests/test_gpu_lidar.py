@@ -105,16 +105,18 @@ def test_batched_envs_and_pose_updates_without_rebuild(gsr, ctx):
 
 
 def test_wavefronts_spanning_several_envs(gsr, ctx):
-    """100 rays per env: most wavefronts of 64 rays hold rays of two envs, which walk different
-    hierarchies in the same wavefront."""
+    """25 rays per env (an odd count, so with packets of two rays, the size this ray count gets,
+    packets at the env boundaries hold rays of two envs, which walk different hierarchies in
+    the same wavefront)."""
     import torch
     wl = synth.scene_config(3, seed=59, scale=0.005, n_envs=5)
-    rays = [_aim(synth.lidar_rays((0.0, 0.4, -1.0), 10, 10, elevation=(-30, 10), tmin=0.05, tmax=12.0), (0, -0.3, 1),
+    rays = [_aim(synth.lidar_rays((0.0, 0.4, -1.0), 5, 5, elevation=(-30, 10), tmin=0.05, tmax=12.0), (0, -0.3, 1),
                  1.0) for _ in wl["envs"]]
+    n = len(rays[0])
     _, (rng, alpha, hits) = _run(gsr, ctx, wl, rays)
     for e, env in enumerate(wl["envs"]):
         ref = L.trace(L.WorldEnv(env), rays[e])
-        st = _compare(ref, rng[e * 100:(e + 1) * 100], alpha[e * 100:(e + 1) * 100], hits[e * 100:(e + 1) * 100])
+        st = _compare(ref, rng[e * n:(e + 1) * n], alpha[e * n:(e + 1) * n], hits[e * n:(e + 1) * n])
         log(f"env {e}", st)
 
 

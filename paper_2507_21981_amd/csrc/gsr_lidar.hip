@@ -10,8 +10,8 @@
 // the right child's index).
 //
 // Tracing (k_lidar, a wavefront per packet of up to 64 rays): repeated passes over the env's
-// nodes, each collecting per lane in registers the K next hits in (t_c, id) order after the last one
-// composited -- a hit being a Gaussian whose centre lies at t_c = (mu - o) . d inside
+// nodes, each collecting per lane in registers the K next hits in (t_c, id) order after the
+// last one composited -- a hit being a Gaussian whose centre lies at t_c = (mu - o) . d inside
 // (tmin, tmax) and whose peak response along the ray, alpha = min(0.99, o exp(-D^2 / 2)),
 // reaches 1/255 -- then compositing them front to back with the camera's rules until the
 // transmittance stop or the last hit.  The wavefront walks each hierarchy once for all its rays

@@ -88,8 +88,28 @@ __global__ __launch_bounds__(64) void k_composite_bwd(BwdArgs b) {
     __shared__ float4 s0[64], s1[64], s2[64];
     __shared__ long long s_rec[64];
     __shared__ uint32_t s_e[64];
-    const long long t = xcd_tile(blockIdx.x, a.tiles);
+    __shared__ uint32_t s_tile;
     const int lane = threadIdx.x;
+    // tiles longest list first (the forward's length classes, longest class first, the tiles
+    // with at most one entry last), so the longest walks do not start at the end of the grid
+    if (lane == 0) {
+        uint32_t i = blockIdx.x;
+        const int order[kNumClasses] = {kLenLong, 4, 3, 2, 1, 0, kLenNone};
+        uint32_t tile = 0u;
+        for (int k = 0; k < kNumClasses; ++k) {
+            const uint32_t n = a.status->cls[order[k]];
+            if (i < n) {
+                tile = a.cls_list[(size_t)order[k] * a.tiles + i];
+                break;
+            }
+            i -= n;
+        }
+        s_tile = tile;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const long long t = (long long)s_tile;
     const int image = (int)(t / a.tpi);
     const int lt = (int)(t - (long long)image * a.tpi);
     const int ty = lt / a.tiles_x, tx = lt - ty * a.tiles_x;

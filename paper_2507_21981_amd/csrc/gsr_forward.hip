@@ -1238,7 +1238,8 @@ __global__ __launch_bounds__(64 * W) void k_emit(FwdArgs a) {
 }
 
 // --------------------------------------------------------------------------------------------
-// front-to-back compositing.  One tile per block, one sub-tile per wavefront; each lane shades
+// front-to-back compositing.  One tile per block (tiles taken longest list first, by the
+// length classes of the tile ranges), one sub-tile per wavefront; each lane shades
 // PPT pixels of one column, sharing the LDS reads and the dx terms.  List entries are staged
 // in LDS per batch with the conic pre-scaled, so that for a pixel offset (dx, dy)
 //   q = A' dx^2 + B' dx dy + C' dy^2 + log2(o),   A' = -1/2 log2(e) A, B' = -log2(e) B,
@@ -1452,13 +1453,24 @@ __device__ __forceinline__ void composite_sub(const FwdArgs& a, const long long 
 
 template <int TW, int TH, int PPT, bool SAVE, bool COUNT>
 __global__ __launch_bounds__((64 * SubTile<TW, TH, PPT>::WAVES)) void k_composite(FwdArgs a, const uint32_t* __restrict__ starts,
-                                                                              const Env* __restrict__ envs) {
+                                                                              const Env* __restrict__ envs,
+                                                                              const Status* __restrict__ status,
+                                                                              const uint32_t* __restrict__ cls_list) {
     constexpr int NW = SubTile<TW, TH, PPT>::WAVES;
     __shared__ float4 s0[NW][64], s1[NW][64];
     __shared__ float4 s2[NW][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    composite_sub<TW, TH, PPT, SAVE, COUNT>(a, xcd_tile(blockIdx.x, a.tiles), wave, lane, s0[wave], s1[wave], s2[wave],
-                                            starts, envs);
+    // tiles longest list first (length classes 5, 4, ..., 0, then class 6), so the longest
+    // lists do not start at the end of the grid
+    uint32_t k = blockIdx.x;
+    int cls = kLenLong;
+    while (cls >= 0 && k >= status->cls[cls]) {
+        k -= status->cls[cls];
+        --cls;
+    }
+    if (cls < 0) cls = kLenNone;
+    composite_sub<TW, TH, PPT, SAVE, COUNT>(a, (long long)cls_list[(size_t)cls * a.tiles + k], wave, lane, s0[wave],
+                                            s1[wave], s2[wave], starts, envs);
 }
 
 // persistent grid: block b takes queue items b, b + G, b + 2G, ... of the longest-first queue
@@ -1557,7 +1569,7 @@ static void launch_composite_s(const FwdArgs& a, hipStream_t s) {
                            0, s, a, a.starts, a.envs, a.status, a.cls_list);
     } else {
         hipLaunchKernelGGL((k_composite<TW, TH, PPT, SAVE, COUNT>), dim3((unsigned)a.tiles), dim3(NT), 0, s, a, a.starts,
-                           a.envs);
+                           a.envs, a.status, a.cls_list);
     }
 }
 

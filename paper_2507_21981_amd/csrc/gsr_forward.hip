@@ -1116,8 +1116,6 @@ __global__ __launch_bounds__(64 * W) void k_emit(FwdArgs a) {
     __syncthreads();
     for (uint32_t q = s_q; q < hi;) {
         __syncthreads();  // every thread has read s_q
-        uint32_t nq = 0u;
-        if (tid == 0) nq = lo + atomicAdd(&a.emit_next[x * kEmitQueueStride], 1u);  // the next chunk, taken ahead
         uint32_t pos;
         int img;
         const uint32_t n = emit_chunk(a, q, pos, img);
@@ -1231,7 +1229,9 @@ __global__ __launch_bounds__(64 * W) void k_emit(FwdArgs a) {
                 __syncthreads();
             }
         }
-        if (tid == 0) s_q = nq;
+        // the next chunk, taken when this one is done (taking it ahead doubles the chunks in
+        // flight and the open bucket lines)
+        if (tid == 0) s_q = lo + atomicAdd(&a.emit_next[x * kEmitQueueStride], 1u);
         __syncthreads();
         q = s_q;
     }

@@ -438,10 +438,10 @@ int gsr_stage_times(gsr_context* ctx, float* ms);
    keep the fastest in the context and return it (candidates are tried from
    16x16 tiles, one pixel per thread, one block per tile on; a later one
    replaces the choice only when at least 2% faster); then, for a scene of
-   several environments, 2 and 3 stream groups with that choice (the same 2%
-   rule; gsr_get_config reports the groups kept).  Outputs are scratch buffers
-   sized for the call.  Synchronous.  The choice is cached per (images, width,
-   height, Gaussian count) in the context. */
+   several environments, 1, 2 and 3 stream groups with that choice, timed as
+   graph replays (the same 2% rule; gsr_get_config reports the groups kept).
+   Outputs are scratch buffers sized for the call.  Synchronous.  The choice
+   is cached per (images, width, height, Gaussian count) in the context. */
 int gsr_autotune(gsr_context* ctx, const gsr_scene* scene, int32_t cams_per_env,
                  const gsr_camera* cams, int32_t width, int32_t height, float* rgb, float* depth,
                  float* alpha, int32_t* tile_w, int32_t* tile_h, int32_t* persistent, void* stream);

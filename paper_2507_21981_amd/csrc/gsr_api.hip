@@ -94,7 +94,7 @@ struct gsr_context {
     DevBuf<Record> records;
     DevBuf<uint4> vis;
     DevBuf<uint32_t> sbvis, loff;
-    DevBuf<uint32_t> skey0, skey1, sgid0, sgid1;
+    DevBuf<uint32_t> skey0, skey1, ssrc0, ssrc1, sgid0, sgid1;
     DevBuf<uint2> srect0, srect1;
     DevBuf<uint32_t> hist, seg_n, seg_start, blk_pairs, chunk_base, pair_base, cstart, cimg, ecnt, seg_base, segoff, emit_next;
     DevBuf<uint32_t> starts, cls_list;
@@ -250,6 +250,7 @@ void gsr_destroy(gsr_context* ctx) {
     if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     ctx->pairs.release(); ctx->records.release(); ctx->vis.release(); ctx->sbvis.release(); ctx->loff.release();
     ctx->skey0.release(); ctx->skey1.release(); ctx->sgid0.release(); ctx->sgid1.release();
+    ctx->ssrc0.release(); ctx->ssrc1.release();
     ctx->srect0.release(); ctx->srect1.release(); ctx->hist.release(); ctx->seg_n.release(); ctx->ecnt.release();
     ctx->seg_start.release(); ctx->blk_pairs.release(); ctx->chunk_base.release(); ctx->cstart.release();
     ctx->cimg.release(); ctx->pair_base.release(); ctx->seg_base.release(); ctx->segoff.release();
@@ -476,7 +477,8 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
     const int sb_cap = sc->sb_cap;
     if ((r = ensure(ctx, ctx->records, nrec)) || (r = ensure(ctx, ctx->vis, n_lists * sb_cap)) ||
         (r = ensure(ctx, ctx->sbvis, n_lists)) || (r = ensure(ctx, ctx->loff, n_lists)) || (r = ensure(ctx, ctx->skey0, sort_len)) ||
-        (r = ensure(ctx, ctx->skey1, sort_len)) || (r = ensure(ctx, ctx->sgid0, sort_len)) ||
+        (r = ensure(ctx, ctx->skey1, sort_len)) || (r = ensure(ctx, ctx->ssrc0, sort_len)) ||
+        (r = ensure(ctx, ctx->ssrc1, sort_len)) || (r = ensure(ctx, ctx->sgid0, sort_len)) ||
         (r = ensure(ctx, ctx->sgid1, sort_len)) || (r = ensure(ctx, ctx->srect0, sort_len)) ||
         (r = ensure(ctx, ctx->srect1, sort_len)) ||
         (r = ensure(ctx, ctx->hist, (size_t)a.sort_chunks * 256)) ||
@@ -508,6 +510,8 @@ static int prepare(gsr_context* ctx, const gsr_scene* sc, int C, const gsr_camer
     a.sb_cap = sb_cap;
     a.skey[0] = ctx->skey0.p;
     a.skey[1] = ctx->skey1.p;
+    a.ssrc[0] = ctx->ssrc0.p;
+    a.ssrc[1] = ctx->ssrc1.p;
     a.sgid[0] = ctx->sgid0.p;
     a.sgid[1] = ctx->sgid1.p;
     a.srect[0] = ctx->srect0.p;

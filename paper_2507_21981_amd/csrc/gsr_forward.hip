@@ -448,7 +448,9 @@ __global__ __launch_bounds__(1024) void k_seg(FwdArgs a) {
     if (t == 0) a.seg_start[a.images] = s_carry;
 }
 
-// the (super-block, camera) lists copied into their image segments (buffer 1), in list order
+// the (super-block, camera) lists copied into their image segments, in list order: the keys
+// into key buffer 1 (the first pass's input), ids and rectangles into buffer 0, which the sort
+// leaves in place (its last pass gathers them in sorted order into buffer 1)
 __global__ __launch_bounds__(256) void k_gather(FwdArgs a) {
     uint32_t l0, l1, ls;
     xcd_items((uint32_t)(a.n_supers * a.C), l0, l1, ls);
@@ -468,8 +470,8 @@ __global__ __launch_bounds__(256) void k_gather(FwdArgs a) {
                 const uint32_t k = k0 + 256u * u;
                 if (k < n) {
                     a.skey[1][dst + k] = e[u].z;
-                    a.sgid[1][dst + k] = e[u].w;
-                    a.srect[1][dst + k] = make_uint2(e[u].x, e[u].y);
+                    a.sgid[0][dst + k] = e[u].w;
+                    a.srect[0][dst + k] = make_uint2(e[u].x, e[u].y);
                 }
             }
         }
@@ -500,8 +502,10 @@ __device__ inline unsigned long long match_digit(uint32_t d, bool valid) {
     return m;
 }
 
-// Radix chunks: kSortTile positions of the sort buffers.  Pass p reads buffer (p + 1) & 1 and
-// writes buffer p & 1 (the gather fills buffer 1, the last pass leaves the result there).
+// Radix chunks: kSortTile positions of the sort buffers.  Pass p reads key and source buffer
+// (p + 1) & 1 and writes buffer p & 1 (the gather fills key buffer 1; the first pass takes
+// each item's position as its source); the last pass writes, instead, the ids and rectangles
+// of the items' sources into buffer 1.
 __device__ inline uint32_t radix_chunks(const FwdArgs& a) { return a.seg_start[a.images] / (uint32_t)kSortTile; }
 // Items of radix chunk j; pos receives the chunk's first position.
 __device__ inline uint32_t radix_chunk(const FwdArgs& a, uint32_t j, uint32_t& pos) {
@@ -624,15 +628,14 @@ __global__ __launch_bounds__(256) void k_radix_scatter(FwdArgs a, int pass) {
         // rounds of this wavefront that hold items (uniform across the wavefront)
         const int nr = n > w0 ? (int)min((n - w0 + 63u) / 64u, (uint32_t)R) : 0;
         const uint32_t* kin = a.skey[ib] + pos;
-        uint32_t key[R], rk[R], id[R];
-        uint2 rc[R];
+        uint32_t key[R], rk[R], src[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t k = w0 + (uint32_t)(r * 64 + lane);
             const bool in = r < nr && k < n;
             key[r] = in ? kin[k] : 0u;
-            id[r] = in ? a.sgid[ib][pos + k] : 0u;
-            rc[r] = in ? a.srect[ib][pos + k] : make_uint2(0u, 0u);
+            // the first pass reads the gathered order, so an item's source is its position
+            src[r] = in ? (pass == 0 ? pos + k : a.ssrc[ib][pos + k]) : 0u;
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -667,34 +670,35 @@ __global__ __launch_bounds__(256) void k_radix_scatter(FwdArgs a, int pass) {
             s_delta[t] = a.hist[(size_t)j * 256 + t] - ls;  // modulo 2^32
         }
         __syncthreads();
-        // local positions replace the ranks
+        // local positions replace the ranks; the chunk staged in LDS in digit order
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t k = w0 + (uint32_t)(r * 64 + lane);
             if (r < nr && k < n) {
                 const uint32_t d = (key[r] >> sh) & 255u;
                 rk[r] += s_wc[wave][d];
-                s_buf[rk[r]] = ((unsigned long long)id[r] << 32) | (unsigned long long)key[r];
+                s_buf[rk[r]] = ((unsigned long long)src[r] << 32) | (unsigned long long)key[r];
                 s_dig[rk[r]] = (uint8_t)d;
             }
         }
         __syncthreads();
-        for (uint32_t lp = t; lp < n; lp += 256) {
-            const unsigned long long u = s_buf[lp];
-            const uint32_t dst = lp + s_delta[s_dig[lp]];
-            if (pass < 3) a.skey[ob][dst] = (uint32_t)u;  // nothing reads the sorted keys
-            a.sgid[ob][dst] = (uint32_t)(u >> 32);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t k = w0 + (uint32_t)(r * 64 + lane);
-            if (r < nr && k < n) s_buf[rk[r]] = ((unsigned long long)rc[r].y << 32) | (unsigned long long)rc[r].x;
-        }
-        __syncthreads();
-        for (uint32_t lp = t; lp < n; lp += 256) {
-            const unsigned long long u = s_buf[lp];
-            a.srect[ob][lp + s_delta[s_dig[lp]]] = make_uint2((uint32_t)u, (uint32_t)(u >> 32));
+        // each digit's run to consecutive slots: keys and sources, or, in the last pass (whose
+        // keys nothing reads), the items' ids and rectangles gathered from their sources (an
+        // image's segment, a few hundred KB, stays in its XCD's L2)
+        if (pass < 3) {
+            for (uint32_t lp = t; lp < n; lp += 256) {
+                const unsigned long long u = s_buf[lp];
+                const uint32_t dst = lp + s_delta[s_dig[lp]];
+                a.skey[ob][dst] = (uint32_t)u;
+                a.ssrc[ob][dst] = (uint32_t)(u >> 32);
+            }
+        } else {
+            for (uint32_t lp = t; lp < n; lp += 256) {
+                const uint32_t sp = (uint32_t)(s_buf[lp] >> 32);
+                const uint32_t dst = lp + s_delta[s_dig[lp]];
+                a.sgid[1][dst] = a.sgid[0][sp];
+                a.srect[1][dst] = a.srect[0][sp];
+            }
         }
         __syncthreads();
     }

@@ -222,9 +222,10 @@ struct FwdArgs {
     uint32_t* loff;      // per (super-block, camera): the list's first position in the sort buffers
     int sb_cap;          // list capacity per (super-block, camera)
     // depth sort (two ping-pong buffers; the last pass leaves the result in buffer 1)
-    uint32_t* skey[2];   // z bits
-    uint32_t* sgid[2];   // Gaussian id
-    uint2* srect[2];     // tile rectangle {x0 | y0 << 16, x1 | y1 << 16}
+    uint32_t* skey[2];   // z bits (ping-pong between the passes)
+    uint32_t* ssrc[2];   // the item's position in the gathered (id-ordered) segment (ping-pong)
+    uint32_t* sgid[2];   // Gaussian id: [0] gathered, [1] sorted
+    uint2* srect[2];     // tile rectangle {x0 | y0 << 16, x1 | y1 << 16}: [0] gathered, [1] sorted
     uint32_t* hist;      // per radix chunk (pass 0: per list): 256 digit counts, then first slots
     uint32_t* seg_n;     // per image: visible Gaussians (the length of its segment)
     uint32_t* seg_start; // per image + 1: first position of its segment (kSortTile multiples)

@@ -612,7 +612,8 @@ def roofline(stage, st, n_total, cfg, copy_gbs):
     projection 44 B per Gaussian + 12 K B of SH per Gaussian visible from some camera + 64 B
     written per visible (image, Gaussian) (48 B record, 16 B list entry); depth sort: the 16 B
     list entry copied into the image's segment, then four radix passes each reading the 4 B
-    key (histogram) and reading and writing the 16 B entry (12 B written in the last);
+    key (histogram) and moving the 8 B (key, source position) (the first reads the key alone;
+    the last reads the pair and the 12 B id and rectangle of its source and writes those 12 B);
     emission: the 8 B rectangle read three times (chunking, counts) and the 12 B (rectangle,
     id) once, 4 B written per pair.  A stage whose counter traffic is below its bytes kept its
     working set in the 256 MB last-level cache (flagged "mall_resident").
@@ -623,7 +624,7 @@ def roofline(stage, st, n_total, cfg, copy_gbs):
     alg_project = 12 * n_total + 224 * visible_any + 52 * visible + 8 * items
     own = {
         "project": ("hbm", 44 * n_total + 12 * K * visible_any + 64 * visible),
-        "sort": ("hbm", (32 + 4 * (4 + 16) + 3 * 16 + 12) * visible),
+        "sort": ("hbm", (32 + (4 + 4 + 8) + 2 * (4 + 8 + 8) + (4 + 8 + 12 + 12)) * visible),
         "emit": ("hbm", 3 * 8 * visible + 12 * visible + 4 * pairs),
         "composite": ("alu", evals * OPS_PER_EVAL),
     }

@@ -192,7 +192,9 @@ typedef struct {
    GSR_E_INVALID (out == NULL). */
 int gsr_create(int device, const gsr_config* cfg, gsr_context** out);
 
-/* Free the context and all its device workspace (synchronises the device). */
+/* Free the context and all its device workspace (synchronises the device).
+   Scenes composed on it are detached: they can no longer be rendered, and
+   gsr_scene_destroy still frees them. */
 void gsr_destroy(gsr_context* ctx);
 
 /* Message of the last failed call on ctx (ctx = NULL: process-wide last
@@ -242,7 +244,7 @@ int gsr_compose_scene(gsr_context* ctx, int32_t n_envs, const int32_t* env_node_
                       const gsr_gaussians* nodes, int32_t n_nodes, const gsr_pose* poses,
                       gsr_scene** inout);
 
-/* Free a scene (NULL is a no-op). */
+/* Free a scene (NULL is a no-op), before or after its context. */
 void gsr_scene_destroy(gsr_scene* scene);
 
 /* Gaussian count of the scene, and of environment e. */

@@ -132,6 +132,7 @@ struct gsr_context {
     hipEvent_t fork_ev = nullptr;
     hipEvent_t join_ev[kMaxGroups] = {};
     int last_groups = 1;  // groups of the last render
+    std::vector<gsr_scene*> scenes;  // live scenes composed on this context (detached on destroy)
 };
 
 static int fail(gsr_context* ctx, int code, const char* fmt, ...) {
@@ -238,6 +239,10 @@ void gsr_destroy(gsr_context* ctx) {
     if (!ctx) return;
     hipSetDevice(ctx->device);
     hipDeviceSynchronize();
+    // scenes that outlive the context keep their tables until gsr_scene_destroy, which then
+    // no longer touches the context (nor the sub-contexts, for their groups' scenes)
+    for (gsr_scene* sc : ctx->scenes) sc->ctx = nullptr;
+    ctx->scenes.clear();
     for (int g = 0; g < kMaxGroups; ++g) {
         if (ctx->sub[g]) gsr_destroy(ctx->sub[g]);
         if (ctx->gstream[g]) hipStreamDestroy(ctx->gstream[g]);
@@ -311,12 +316,15 @@ void gsr_scene_destroy(gsr_scene* sc) {
     if (sc->envs_d) hipFree(sc->envs_d);
     if (sc->blocks_d) hipFree(sc->blocks_d);
     if (sc->supers_d) hipFree(sc->supers_d);
-    if (sc->ctx && sc->ctx->last_scene == sc) {
-        sc->ctx->have_last = sc->ctx->saved = false;
-        sc->ctx->saved_id = 0;
-        sc->ctx->last_scene = nullptr;
+    if (gsr_context* ctx = sc->ctx) {  // null once its context was destroyed
+        if (ctx->last_scene == sc) {
+            ctx->have_last = ctx->saved = false;
+            ctx->saved_id = 0;
+            ctx->last_scene = nullptr;
+        }
+        if (ctx->graph_valid && ctx->gkey.scene == sc) drop_graph(ctx);
+        ctx->scenes.erase(std::remove(ctx->scenes.begin(), ctx->scenes.end(), sc), ctx->scenes.end());
     }
-    if (sc->ctx && sc->ctx->graph_valid && sc->ctx->gkey.scene == sc) drop_graph(sc->ctx);
     delete sc;
 }
 
@@ -360,6 +368,7 @@ int gsr_compose_scene(gsr_context* ctx, int32_t n_envs, const int32_t* off, cons
         *inout = nullptr;
         sc = new gsr_scene();
         sc->ctx = ctx;
+        ctx->scenes.push_back(sc);
     }
     hipSetDevice(ctx->device);
     sc->n_envs = n_envs;

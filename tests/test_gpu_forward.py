@@ -416,6 +416,33 @@ def test_stream_groups_render_exactly_as_one_group(gsr, ctx):
     scene.close()
 
 
+def test_scene_outliving_its_context(gsr):
+    """A scene (and its stream groups' scenes on the sub-contexts) destroyed after its context:
+    the context detaches its scenes, so the late destroy frees only the scene's own tables."""
+    wl = synth.scene_config(3, seed=47, scale=0.01, n_envs=3)
+    envs_t, poses, cams = upload(wl)
+    W, H, C = wl["width"], wl["height"], wl["cams_per_env"]
+    c = gsr.create(0)
+    c.set_stream_groups(2)
+    scene = gsr.compose_scene(c, envs_t, poses)
+    gsr.render_rgbd(c, scene, cams, W, H, C, flags=gsr.FLAG_CHECK)
+    c.close()
+    scene.close()
+    # and a context that renders again after one of its scenes was destroyed
+    c = gsr.create(0)
+    c.set_stream_groups(2)
+    s1 = gsr.compose_scene(c, envs_t, poses)
+    ref = [t.clone() for t in gsr.render_rgbd(c, s1, cams, W, H, C, flags=gsr.FLAG_CHECK)]
+    s1.close()
+    s2 = gsr.compose_scene(c, envs_t, poses)
+    out = gsr.render_rgbd(c, s2, cams, W, H, C, flags=gsr.FLAG_CHECK)
+    import torch
+    for a, b in zip(out, ref):
+        assert torch.equal(a, b)
+    s2.close()
+    c.close()
+
+
 def test_persistent_composite_matches_one_block_per_tile(gsr, ctx):
     import torch
     wl = synth.scene_config(3, seed=31, scale=0.03, n_envs=4)

@@ -2,12 +2,12 @@
 // Gaussian ray tracer, next to the splatted RGB and depth).
 //
 // Acceleration structure: one bounding-volume hierarchy per scene node, over the node-local
-// bounding boxes of its Gaussians' 3.33-sigma ellipsoids (the largest Mahalanobis radius at which
-// alpha can reach 1/255).  Node-local, so the per-step rigid poses of object nodes never touch
-// it: a ray is moved into each node's frame instead (two-level tracing).  Built once per
-// composed topology on the host (Morton order of the centres, binary splits at the highest
-// differing code bit), stored depth-first (the left child follows its parent, the parent keeps
-// the right child's index).
+// bounding boxes of its Gaussians' ellipsoids at the Mahalanobis radius where alpha can still
+// reach 1/255 (sqrt(2 ln(255 o)), 3.33 sigma at opacity 1).  Node-local, so the per-step rigid
+// poses of object nodes never touch it: a ray is moved into each node's frame instead
+// (two-level tracing).  Built once per composed topology on the host (Morton order of the
+// centres, binary splits at the highest differing code bit), stored depth-first (the left
+// child follows its parent, the parent keeps the right child's index).
 //
 // Tracing (k_lidar, a wavefront per packet of up to 64 rays): repeated passes over the env's
 // nodes, each collecting per lane in registers the K next hits in (t_c, id) order after the
@@ -171,13 +171,16 @@ std::string lidar_build(const std::vector<Node>& nodes, LidarScene** out) {
             const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
                                  2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
                                  2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
-            // bounding box of the 3.33-sigma ellipsoid: half extent 3.33 sqrt(Sigma_jj), widened so
-            // that the FP32 slab test stays conservative
+            // bounding box of the ellipsoid inside which o exp(-D^2 / 2) reaches 1/255: Mahalanobis
+            // radius k = sqrt(2 ln(255 o)) (3.33 at o = 1), half extent k sqrt(Sigma_jj); k^2 is
+            // raised by 0.01 and the extent widened so that the FP32 alpha test and slab test
+            // stay conservative
+            const double kr = std::sqrt(2.0 * std::log(255.0 * (double)op[i]) + 0.01);
             float lo[3], hi[3];
             for (int j = 0; j < 3; ++j) {
                 double sjj = 0.0;
                 for (int c = 0; c < 3; ++c) sjj += R[j * 3 + c] * R[j * 3 + c] * s[c] * s[c];
-                const double e = 3.33 * std::sqrt(sjj) * (1.0 + 1e-4) + 1e-5 * (std::fabs(m[j]) + 1.0);
+                const double e = kr * std::sqrt(sjj) * (1.0 + 1e-4) + 1e-5 * (std::fabs(m[j]) + 1.0);
                 lo[j] = (float)(m[j] - e);
                 hi[j] = (float)(m[j] + e);
                 clo[j] = std::min(clo[j], m[j]);

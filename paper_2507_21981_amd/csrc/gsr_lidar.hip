@@ -5,9 +5,9 @@
 // bounding boxes of its Gaussians' ellipsoids at the Mahalanobis radius where alpha can still
 // reach 1/255 (sqrt(2 ln(255 o)), 3.33 sigma at opacity 1).  Node-local, so the per-step rigid
 // poses of object nodes never touch it: a ray is moved into each node's frame instead
-// (two-level tracing).  Built once per composed topology on the host (Morton order of the
-// centres, binary splits at the highest differing code bit), stored depth-first (the left
-// child follows its parent, the parent keeps the right child's index).
+// (two-level tracing).  Built once per composed topology on the host (binary splits by a
+// binned surface-area heuristic over the centres, median splits below a fixed depth), stored
+// depth-first (the left child follows its parent, the parent keeps the right child's index).
 //
 // Tracing (k_lidar, a wavefront per packet of up to 64 rays): repeated passes over the env's
 // nodes, each collecting per lane in registers the K next hits in (t_c, id) order after the
@@ -63,13 +63,108 @@ uint32_t spread10(uint32_t x) {
 }
 
 struct Builder {
-    const std::vector<uint64_t>* keys;  // (Morton code << 32 | index), sorted
+    std::vector<uint64_t>* keys;        // (Morton code << 32 | index); ranges reordered by the splits
     const std::vector<float>* box;      // per primitive: lo[3], hi[3]
     const std::vector<float>* cen;      // per primitive: centre[3]
     std::vector<float> nlo, nhi, clo, chi;  // per node: box of the ellipsoids, box of the centres
     std::vector<int> skip, leaf_first, leaf_count, right;
     size_t prim_base = 0;
     int max_depth = 0;
+
+    static constexpr int kBins = 32;
+    static constexpr int kSahDepth = 24;  // below it, median splits bound the depth
+
+    uint32_t prim(size_t i) const { return (uint32_t)((*keys)[i] & 0xffffffffu); }
+    static double area(const float* lo, const float* hi) {
+        const double dx = (double)hi[0] - lo[0], dy = (double)hi[1] - lo[1], dz = (double)hi[2] - lo[2];
+        return dx * dy + dy * dz + dz * dx;
+    }
+
+    // Where to split [lo, hi): binned surface-area heuristic over the centres along their
+    // longest extent (cost = box area x primitives, summed over the two sides), or, deeper than
+    // kSahDepth or when the bins cannot separate the range, the median along that extent.
+    size_t split(size_t lo, size_t hi, int depth) {
+        float cmin[3] = {INFINITY, INFINITY, INFINITY}, cmax[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (size_t i = lo; i < hi; ++i) {
+            const float* c = &(*cen)[3 * prim(i)];
+            for (int j = 0; j < 3; ++j) {
+                cmin[j] = std::min(cmin[j], c[j]);
+                cmax[j] = std::max(cmax[j], c[j]);
+            }
+        }
+        int ax = 0;
+        for (int j = 1; j < 3; ++j)
+            if (cmax[j] - cmin[j] > cmax[ax] - cmin[ax]) ax = j;
+        const double ext = (double)cmax[ax] - (double)cmin[ax];
+        const size_t half = (lo + hi) / 2;
+        auto median = [&]() {
+            std::nth_element(keys->begin() + lo, keys->begin() + half, keys->begin() + hi,
+                             [&](uint64_t a, uint64_t b) {
+                                 return (*cen)[3 * (a & 0xffffffffu) + ax] < (*cen)[3 * (b & 0xffffffffu) + ax];
+                             });
+            return half;
+        };
+        if (!(ext > 0.0) || depth > kSahDepth) return median();
+        auto bin = [&](uint32_t p) {
+            const int b = (int)(((double)(*cen)[3 * p + ax] - (double)cmin[ax]) / ext * kBins);
+            return std::min(kBins - 1, std::max(0, b));
+        };
+        size_t cnt[kBins] = {};
+        float blo[kBins][3], bhi[kBins][3];
+        for (int b = 0; b < kBins; ++b)
+            for (int j = 0; j < 3; ++j) {
+                blo[b][j] = INFINITY;
+                bhi[b][j] = -INFINITY;
+            }
+        for (size_t i = lo; i < hi; ++i) {
+            const uint32_t p = prim(i);
+            const int b = bin(p);
+            ++cnt[b];
+            for (int j = 0; j < 3; ++j) {
+                blo[b][j] = std::min(blo[b][j], (*box)[6 * p + j]);
+                bhi[b][j] = std::max(bhi[b][j], (*box)[6 * p + 3 + j]);
+            }
+        }
+        // areas and counts of the bins at and right of k
+        double ra[kBins];
+        size_t rn[kBins];
+        float lo3[3] = {INFINITY, INFINITY, INFINITY}, hi3[3] = {-INFINITY, -INFINITY, -INFINITY};
+        size_t n = 0;
+        for (int b = kBins - 1; b >= 0; --b) {
+            n += cnt[b];
+            for (int j = 0; j < 3; ++j) {
+                lo3[j] = std::min(lo3[j], blo[b][j]);
+                hi3[j] = std::max(hi3[j], bhi[b][j]);
+            }
+            ra[b] = n ? area(lo3, hi3) : 0.0;
+            rn[b] = n;
+        }
+        for (int j = 0; j < 3; ++j) {
+            lo3[j] = INFINITY;
+            hi3[j] = -INFINITY;
+        }
+        n = 0;
+        int best = -1;
+        double best_cost = INFINITY;
+        for (int b = 1; b < kBins; ++b) {  // left = bins below b
+            n += cnt[b - 1];
+            for (int j = 0; j < 3; ++j) {
+                lo3[j] = std::min(lo3[j], blo[b - 1][j]);
+                hi3[j] = std::max(hi3[j], bhi[b - 1][j]);
+            }
+            if (n == 0 || rn[b] == 0) continue;
+            const double c = area(lo3, hi3) * (double)n + ra[b] * (double)rn[b];
+            if (c < best_cost) {
+                best_cost = c;
+                best = b;
+            }
+        }
+        if (best < 0) return median();
+        const auto it = std::partition(keys->begin() + lo, keys->begin() + hi,
+                                       [&](uint64_t k) { return bin((uint32_t)(k & 0xffffffffu)) < best; });
+        const size_t mid = (size_t)(it - keys->begin());
+        return (mid > lo && mid < hi) ? mid : median();
+    }
 
     int make(size_t lo, size_t hi, int depth = 1) {
         const int id = (int)skip.size();
@@ -88,7 +183,7 @@ struct Builder {
             leaf_first[id] = (int)(prim_base + lo);
             leaf_count[id] = (int)(hi - lo);
             for (size_t i = lo; i < hi; ++i) {
-                const uint32_t p = (uint32_t)((*keys)[i] & 0xffffffffu);
+                const uint32_t p = prim(i);
                 for (int j = 0; j < 3; ++j) {
                     nlo[3 * id + j] = std::min(nlo[3 * id + j], (*box)[6 * p + j]);
                     nhi[3 * id + j] = std::max(nhi[3 * id + j], (*box)[6 * p + 3 + j]);
@@ -97,21 +192,7 @@ struct Builder {
                 }
             }
         } else {
-            // split where the highest Morton bit differing between the first and last code
-            // turns on (middle of the range if all codes are equal)
-            const uint32_t c0 = (uint32_t)((*keys)[lo] >> 32), c1 = (uint32_t)((*keys)[hi - 1] >> 32);
-            size_t mid = (lo + hi) / 2;
-            if (c0 != c1) {
-                const int bit = 31 - __builtin_clz(c0 ^ c1);
-                const uint32_t prefix = c1 >> bit;  // codes with this bit set go right
-                size_t a = lo, b = hi - 1;           // first index whose code >> bit == prefix
-                while (a < b) {
-                    const size_t m = (a + b) / 2;
-                    if ((uint32_t)((*keys)[m] >> 32) >> bit >= prefix) b = m;
-                    else a = m + 1;
-                }
-                mid = a;
-            }
+            const size_t mid = split(lo, hi, depth);
             const int l = make(lo, mid, depth + 1);
             const int r = make(mid, hi, depth + 1);
             right[id] = r;

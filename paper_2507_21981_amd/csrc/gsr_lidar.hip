@@ -31,7 +31,7 @@
 namespace gsr {
 
 constexpr int kLidarK = 16;      // hits per pass
-constexpr int kLeafSize = 4;     // primitives per BVH leaf at most
+constexpr int kLeafSize = 6;     // primitives per BVH leaf at most
 constexpr int kLidarStack = 48;  // traversal stack entries per ray (hierarchy depth at most)
 
 struct LidarScene {

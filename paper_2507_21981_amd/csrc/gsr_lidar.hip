@@ -71,7 +71,7 @@ struct Builder {
     size_t prim_base = 0;
     int max_depth = 0;
 
-    static constexpr int kBins = 32;
+    static constexpr int kBins = 128;
     static constexpr int kSahDepth = 24;  // below it, median splits bound the depth
 
     uint32_t prim(size_t i) const { return (uint32_t)((*keys)[i] & 0xffffffffu); }

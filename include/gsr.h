@@ -338,8 +338,9 @@ typedef struct {
 
 /* Build the acceleration structure the LiDAR tracer needs: one bounding-
    volume hierarchy per node over the node-local boxes of its Gaussians'
-   3.33-sigma ellipsoids (poses are applied to the rays at trace time, so
-   per-step pose updates need no rebuild).  Reads the Gaussian data back to
+   ellipsoids at the Mahalanobis radius where each Gaussian's opacity can
+   still give alpha >= 1/255 (3.33 sigma at opacity 1); poses are applied to
+   the rays at trace time, so per-step pose updates need no rebuild.  Reads the Gaussian data back to
    the host; synchronous.  Call again after the Gaussian data changes or the
    scene is recomposed.  Errors: GSR_E_INVALID, GSR_E_NOMEM (also when a
    node's hierarchy would be deeper than 48 levels), GSR_E_HIP. */

@@ -7,9 +7,11 @@
 //                  rectangle and depth key (the FP32 key specification below), SH colour
 //                  (paper Sec. III-A), projected record; per (super-block, camera) the list
 //                  of visible Gaussians, appended in id order
-//   k_seg, k_radix_*   per image, its visible Gaussians ordered by depth bits, ties by id: a
-//                  stable LSD radix sort over the four bytes of the depth bits whose first
-//                  pass reads the id-ordered lists ("efficient sorting")
+//   k_seg, k_gather, k_radix_*   per image, its visible Gaussians ordered by depth bits, ties
+//                  by id: the id-ordered lists gathered into the image's segment, then a
+//                  stable LSD radix sort over the four bytes of the depth bits whose passes
+//                  move (key, source position) and whose last pass gathers the ids and tile
+//                  rectangles ("efficient sorting")
 //   k_pair_*, k_chunk_starts   each image's depth-ordered Gaussians cut into chunks of about
 //                  equal pair counts
 //   k_tile_counts  per chunk: pairs per tile, from a difference grid in LDS
@@ -1087,16 +1089,18 @@ __global__ __launch_bounds__(1024) void k_tile_ranges(FwdArgs a) {
 
 // --------------------------------------------------------------------------------------------
 // pair emission.  One block per emission chunk walks the chunk's depth-ordered Gaussians in
-// rounds of 64 and writes their (z bits << 32 | id) pairs into the tile buckets, so each
-// bucket receives its entries in (z bits, id) order: chunks in order (first slots from the
-// tile offsets), rounds in order (a running slot per tile in LDS) and, within a round, by the
-// Gaussian's rank in the round: the set bits below it in the tile's 64-bit round mask.
+// rounds of 64 and writes their ids into the tile buckets (one 4-byte id per (tile, Gaussian)
+// pair), so each bucket receives its entries in (z bits, id) order: chunks in order (first
+// slots from the tile offsets), rounds in order (a running slot per tile in LDS) and, within a
+// round, by the Gaussian's rank in the round: the set bits below it in the tile's 64-bit round
+// mask.
 // A round's pairs are numbered by a prefix over the rectangle areas and split into equal runs
 // of consecutive pairs, one per thread, walked twice: set the mask bits; write the pairs.
 // Then each tile's slot advances by its count in the round and its mask is cleared (a third
 // walk, at the tile's highest Gaussian of the round, or a pass over the tile table when the
-// round has at least half as many pairs as the image has tiles).  Chunks hold about the same number of pairs, so the blocks' work is balanced even where
-// the nearest (largest) splats of an image crowd into its first chunk.  The W wavefronts of a
+// round has at least half as many pairs as the image has tiles).  Chunks hold about the same
+// number of pairs, so the blocks' work is balanced even where the nearest (largest) splats of
+// an image crowd into its first chunk.  The W wavefronts of a
 // block share the chunk's tile table (12 bytes per tile), so large tile grids do not cap the
 // wavefronts per CU, and split each round's pairs W ways.
 // --------------------------------------------------------------------------------------------

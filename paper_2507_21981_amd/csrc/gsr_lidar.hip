@@ -403,13 +403,15 @@ __device__ inline LocalRay local_ray(const gsr_ray& ray, const gsr_pose& P) {
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // One wavefront traces up to 64 rays together (a packet: a LiDAR's neighbouring beams share
-// most of the boxes they cross).  The walk over a hierarchy is the wavefront's: a node is visited when
-// any of its rays may enter it, children nearer (by majority) first, one stack per wavefront in
-// LDS, node and primitive loads the same for every lane.  Each lane keeps its own K next hits,
-// its own last composited key and its own pruning bounds; a lane that visits a node it would
-// have skipped only tests primitives that cannot change its K nearest, so the result is the
-// lane's alone.  Passes repeat until every lane has stopped or seen all its hits.
-__global__ __launch_bounds__(64) void k_lidar(const float4* __restrict__ bnodes, const float4* __restrict__ prims,
+// most of the boxes they cross).  The walk over a hierarchy is the wavefront's: a node is
+// visited when any of its rays may enter it, children nearer (by majority) first, one stack
+// per wavefront in LDS, node loads the same for every lane.  Each ray keeps its own K next
+// hits, last composited key and pruning bounds (alike on each of its 64 / rpw lanes, which
+// test a leaf's primitives side by side); a ray that visits a node it would have skipped only
+// tests primitives that cannot change its K nearest, so the result is the ray's alone.  Passes
+// repeat until every ray has stopped or seen all its hits.  Held to three wavefronts per SIMD
+// (168 VGPRs, a few bytes spilled): at two the tracer is slower.
+__global__ __launch_bounds__(64, 3) void k_lidar(const float4* __restrict__ bnodes, const float4* __restrict__ prims,
                                               const int2* __restrict__ roots, const Env* __restrict__ envs,
                                               const gsr_pose* __restrict__ poses, int n_envs, int rays_per_env,
                                               const gsr_ray* __restrict__ rays, float* range_out, float* alpha_out,
@@ -417,12 +419,16 @@ __global__ __launch_bounds__(64) void k_lidar(const float4* __restrict__ bnodes,
     __shared__ int s_stack[kLidarStack];
     const int lane = threadIdx.x;
     const long long n = (long long)n_envs * rays_per_env;
-    // rays r0 .. r0 + nv - 1 on lanes 0 .. nv - 1 (rpw rays per wavefront); the other lanes
-    // take the first ray's values and stay done
+    // rays r0 .. r0 + nv - 1 (rpw rays per wavefront, a power of two): lane h rpw + i holds ray
+    // r0 + i, so each ray has 64 / rpw lanes with the same state (the same walk, hits and
+    // compositing) that share the tests of a leaf's primitives; lanes of rays past the end take
+    // the first ray's values and stay done
     const long long r0 = (long long)blockIdx.x * rpw;
     const int nv = (int)(n - r0 < rpw ? n - r0 : rpw);
-    const long long r = r0 + lane;
-    const bool valid = lane < nv;
+    const int lg = __builtin_ctz((unsigned)rpw);
+    const int ri = lane & (rpw - 1), h = lane >> lg, lpr = 64 >> lg;
+    const long long r = r0 + ri;
+    const bool valid = ri < nv;
     const long long rr = valid ? r : r0;
     const int env = (int)(rr / rays_per_env);
     const gsr_ray ray = rays[rr];
@@ -464,46 +470,70 @@ __global__ __launch_bounds__(64) void k_lidar(const float4* __restrict__ bnodes,
                     bool pop = false;
                     if ((uint32_t)info >> 28) {
                         const int cnt = (int)((uint32_t)info >> 28), p0 = info & 0x0fffffff;
-                        for (int p = p0; p < p0 + cnt; ++p) {
-                            const float4 m = prims[4 * p], A0 = prims[4 * p + 1], A1 = prims[4 * p + 2],
-                                         A2 = prims[4 * p + 3];
-                            if (!part) continue;
-                            const float q0 = m.x - l.o0, q1 = m.y - l.o1, q2 = m.z - l.o2;
-                            const float tc = fmaf(q0, l.d0, fmaf(q1, l.d1, q2 * l.d2));
-                            if (!(tc > tmin && tc < tmax)) continue;
-                            const uint32_t gid = (uint32_t)__float_as_int(A2.y);
-                            const uint64_t kk = hit_key(tc, gid);
-                            if (kk <= last || kk >= key[kLidarK - 1]) continue;
-                            // closest-approach offset and the Mahalanobis minimum along the ray
-                            const float e0 = fmaf(tc, l.d0, -q0), e1 = fmaf(tc, l.d1, -q1), e2 = fmaf(tc, l.d2, -q2);
-                            const float x0 = fmaf(A0.x, e0, fmaf(A0.y, e1, A0.z * e2));
-                            const float x1 = fmaf(A0.w, e0, fmaf(A1.x, e1, A1.y * e2));
-                            const float x2 = fmaf(A1.z, e0, fmaf(A1.w, e1, A2.x * e2));
-                            const float y0 = fmaf(A0.x, l.d0, fmaf(A0.y, l.d1, A0.z * l.d2));
-                            const float y1 = fmaf(A0.w, l.d0, fmaf(A1.x, l.d1, A1.y * l.d2));
-                            const float y2 = fmaf(A1.z, l.d0, fmaf(A1.w, l.d1, A2.x * l.d2));
-                            const float dd = fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
-                            const float xy = fmaf(x0, y0, fmaf(x1, y1, x2 * y2));
-                            const float yy = fmaf(y0, y0, fmaf(y1, y1, y2 * y2));
-                            const float D2 = fmaxf(dd - xy * (xy / yy), 0.0f);
-                            // alpha = o exp(-D^2 / 2) = o 2^(-D^2 log2(e) / 2)
-                            const float araw = m.w * __builtin_amdgcn_exp2f(-0.7213475204444817f * D2);
-                            if (!(araw >= thr)) continue;
-                            // insert in key order (the last entry drops out)
-                            uint64_t ck = kk;
-                            float ca = fminf(0.99f, araw);
+                        // the leaf's primitives in batches of 64 / rpw: lane h of a ray tests
+                        // primitive pb + h against the ray's hits as they stood at the batch's
+                        // start, then every lane of the ray inserts the batch's hits in primitive
+                        // order (each checked against the K-th key again), so the ray keeps the
+                        // same K nearest hits as with one primitive at a time
+                        for (int pb = 0; pb < cnt; pb += lpr) {
+                            bool hit = false;
+                            uint64_t hk = 0ull;
+                            float ha = 0.0f;
+                            if (part && pb + h < cnt) do {
+                                const int p = p0 + pb + h;
+                                const float4 m = prims[4 * p], A0 = prims[4 * p + 1], A1 = prims[4 * p + 2],
+                                             A2 = prims[4 * p + 3];
+                                const float q0 = m.x - l.o0, q1 = m.y - l.o1, q2 = m.z - l.o2;
+                                const float tc = fmaf(q0, l.d0, fmaf(q1, l.d1, q2 * l.d2));
+                                if (!(tc > tmin && tc < tmax)) break;
+                                const uint32_t gid = (uint32_t)__float_as_int(A2.y);
+                                const uint64_t kk = hit_key(tc, gid);
+                                if (kk <= last || kk >= key[kLidarK - 1]) break;
+                                // closest-approach offset and the Mahalanobis minimum along the ray
+                                const float e0 = fmaf(tc, l.d0, -q0), e1 = fmaf(tc, l.d1, -q1),
+                                            e2 = fmaf(tc, l.d2, -q2);
+                                const float x0 = fmaf(A0.x, e0, fmaf(A0.y, e1, A0.z * e2));
+                                const float x1 = fmaf(A0.w, e0, fmaf(A1.x, e1, A1.y * e2));
+                                const float x2 = fmaf(A1.z, e0, fmaf(A1.w, e1, A2.x * e2));
+                                const float y0 = fmaf(A0.x, l.d0, fmaf(A0.y, l.d1, A0.z * l.d2));
+                                const float y1 = fmaf(A0.w, l.d0, fmaf(A1.x, l.d1, A1.y * l.d2));
+                                const float y2 = fmaf(A1.z, l.d0, fmaf(A1.w, l.d1, A2.x * l.d2));
+                                const float dd = fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
+                                const float xy = fmaf(x0, y0, fmaf(x1, y1, x2 * y2));
+                                const float yy = fmaf(y0, y0, fmaf(y1, y1, y2 * y2));
+                                const float D2 = fmaxf(dd - xy * (xy / yy), 0.0f);
+                                // alpha = o exp(-D^2 / 2) = o 2^(-D^2 log2(e) / 2)
+                                const float araw = m.w * __builtin_amdgcn_exp2f(-0.7213475204444817f * D2);
+                                if (!(araw >= thr)) break;
+                                hit = true;
+                                hk = kk;
+                                ha = fminf(0.99f, araw);
+                            } while (false);
+                            const int nb = cnt - pb < lpr ? cnt - pb : lpr;
+                            for (int j = 0; j < nb; ++j) {
+                                const int src = ri + (j << lg);  // the lane of this ray testing pb + j
+                                const int hj = __shfl((int)hit, src, 64);
+                                if (!__any(hj)) continue;
+                                const uint32_t klo = __shfl((unsigned)(uint32_t)hk, src, 64);
+                                const uint32_t khi = __shfl((unsigned)(uint32_t)(hk >> 32), src, 64);
+                                const float aj = __shfl(ha, src, 64);
+                                uint64_t ck = ((uint64_t)khi << 32) | klo;
+                                if (!hj || ck >= key[kLidarK - 1]) continue;
+                                // insert in key order (the last entry drops out)
+                                float ca = aj;
 #pragma unroll
-                            for (int j = 0; j < kLidarK; ++j) {
-                                if (ck < key[j]) {
-                                    const uint64_t tk = key[j];
-                                    const float ta = al[j];
-                                    key[j] = ck;
-                                    al[j] = ca;
-                                    ck = tk;
-                                    ca = ta;
+                                for (int q = 0; q < kLidarK; ++q) {
+                                    if (ck < key[q]) {
+                                        const uint64_t tk = key[q];
+                                        const float ta = al[q];
+                                        key[q] = ck;
+                                        al[q] = ca;
+                                        ck = tk;
+                                        ca = ta;
+                                    }
                                 }
+                                found = found < kLidarK ? found + 1 : kLidarK;
                             }
-                            found = found < kLidarK ? found + 1 : kLidarK;
                         }
                         pop = true;
                     } else {

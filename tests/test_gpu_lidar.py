@@ -166,3 +166,25 @@ def test_composed_step_full_size_sampled_rays(gsr):
     ref = L.trace(L.WorldEnv(env), rays[pick])
     st = _compare(ref, rng[pick], alpha[pick], hits[pick])
     log("full size", st, "mean hits", float(ref["hits"].mean()))
+
+
+@pytest.mark.parametrize("beams,azimuths", [(35, 2000), (100, 3000), (150, 4000), (270, 4100)])
+def test_packet_sizes(gsr, ctx, beams, azimuths):
+    """Frames of 70k, 300k, 600k and 1.1M rays, which the tracer packs 4, 16, 32 and 64 rays to
+    a wavefront (16, 4, 2 and 1 lanes per ray sharing a leaf's primitive tests), on a small
+    posed scene; the oracle traces 150 seeded rays of each frame."""
+    import torch
+    bg = synth.gaussians_uniform_cube(3000, 71, sh_degree=1, half=1.0, log_scale=(-2.8, 0.5))
+    ob = synth.gaussians_object(600, 72, sh_degree=1, radius=0.25, log_scale=(-3.5, 0.4))
+    R = synth.random_rotation(synth.rng(73)).astype(np.float32)
+    env = dict(nodes=[bg, ob], poses=[(np.eye(3, dtype=np.float32), np.zeros(3, np.float32)),
+                                      (R, np.array([0.1, -0.2, -0.3], np.float32))], cams=[])
+    wl = dict(envs=[env], cams_per_env=1, width=8, height=8)
+    rays = _aim(synth.lidar_rays((0.0, 0.2, -2.6), beams, azimuths, elevation=(-25, 25), tmin=0.05, tmax=8.0),
+                (0, 0, 1), 1.5)
+    _, (rng, alpha, hits) = _run(gsr, ctx, wl, [rays])
+    pick = np.sort(np.random.default_rng(beams).choice(len(rays), 150, replace=False))
+    ref = L.trace(L.WorldEnv(env), rays[pick])
+    st = _compare(ref, rng[pick], alpha[pick], hits[pick])
+    log(f"{len(rays)} rays", st)
+    assert st["with_hits"] > 50

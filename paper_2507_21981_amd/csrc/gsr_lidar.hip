@@ -62,6 +62,22 @@ uint32_t spread10(uint32_t x) {
     return x;
 }
 
+// Box of a Gaussian (centre m, scales s, rotation R row-major, opacity o >= 1/255) holding the
+// ellipsoid inside which o exp(-D^2 / 2) reaches 1/255: Mahalanobis radius
+// k = sqrt(2 ln(255 o)) (3.33 at o = 1), half extent k sqrt(Sigma_jj) with
+// Sigma = R diag(s^2) R^T; k^2 is raised by 0.01 and the extent widened so that the FP32 alpha
+// test and slab test stay conservative.
+void gaussian_box(const double m[3], const double s[3], const double R[9], double o, float lo[3], float hi[3]) {
+    const double kr = std::sqrt(2.0 * std::log(255.0 * o) + 0.01);
+    for (int j = 0; j < 3; ++j) {
+        double sjj = 0.0;
+        for (int c = 0; c < 3; ++c) sjj += R[j * 3 + c] * R[j * 3 + c] * s[c] * s[c];
+        const double e = kr * std::sqrt(sjj) * (1.0 + 1e-4) + 1e-5 * (std::fabs(m[j]) + 1.0);
+        lo[j] = (float)(m[j] - e);
+        hi[j] = (float)(m[j] + e);
+    }
+}
+
 struct Builder {
     std::vector<uint64_t>* keys;        // (Morton code << 32 | index); ranges reordered by the splits
     const std::vector<float>* box;      // per primitive: lo[3], hi[3]
@@ -252,18 +268,9 @@ std::string lidar_build(const std::vector<Node>& nodes, LidarScene** out) {
             const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
                                  2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
                                  2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
-            // bounding box of the ellipsoid inside which o exp(-D^2 / 2) reaches 1/255: Mahalanobis
-            // radius k = sqrt(2 ln(255 o)) (3.33 at o = 1), half extent k sqrt(Sigma_jj); k^2 is
-            // raised by 0.01 and the extent widened so that the FP32 alpha test and slab test
-            // stay conservative
-            const double kr = std::sqrt(2.0 * std::log(255.0 * (double)op[i]) + 0.01);
             float lo[3], hi[3];
+            gaussian_box(m, s, R, op[i], lo, hi);
             for (int j = 0; j < 3; ++j) {
-                double sjj = 0.0;
-                for (int c = 0; c < 3; ++c) sjj += R[j * 3 + c] * R[j * 3 + c] * s[c] * s[c];
-                const double e = kr * std::sqrt(sjj) * (1.0 + 1e-4) + 1e-5 * (std::fabs(m[j]) + 1.0);
-                lo[j] = (float)(m[j] - e);
-                hi[j] = (float)(m[j] + e);
                 clo[j] = std::min(clo[j], m[j]);
                 chi[j] = std::max(chi[j], m[j]);
             }

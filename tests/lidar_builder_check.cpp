@@ -1,8 +1,14 @@
-// Host check of the LiDAR hierarchy builder (no GPU use): for seeded primitive sets (uniform,
-// clustered, on a line, all centres equal; 5 to 200k primitives) every primitive sits in
-// exactly one leaf of at most kLeafSize, the depth-first layout holds (left child next, right
-// child after the left subtree, skip = end of the subtree), every node box holds its
-// primitives' boxes and centres, and the depth stays within the tracer's stack.
+// Host check of the LiDAR hierarchy builder (no GPU use).
+// Boxes: for seeded anisotropic, rotated Gaussians of opacity 1/255 .. 1, a Gaussian's box
+// holds every point of its ellipsoid at the Mahalanobis radius sqrt(2 ln(255 o)) (where
+// o exp(-D^2 / 2) falls to 1/255; points sampled on it through M = R diag(s)), and is no more
+// than 1% wider than the ellipsoid's extreme points m +- k Sigma e_j / sqrt(Sigma_jj)
+// (Sigma = M M^T) plus its stated widening.
+// Trees: for seeded primitive sets (uniform, clustered, on a line, all centres equal; 5 to 200k
+// primitives) every primitive sits in exactly one leaf of at most kLeafSize, the depth-first
+// layout holds (left child next, right child after the left subtree, skip = end of the
+// subtree), every node box holds its primitives' boxes and centres, and the depth stays within
+// the tracer's stack.
 #include "../paper_2507_21981_amd/csrc/gsr_lidar.hip"
 
 #include <cstdio>
@@ -21,7 +27,74 @@ static int fails = 0;
         }                                 \
     } while (0)
 
+static void check_boxes() {
+    std::mt19937 g(5);
+    std::normal_distribution<double> N(0.0, 1.0);
+    std::uniform_real_distribution<double> U(0.0, 1.0);
+    for (int it = 0; it < 2000; ++it) {
+        double m[3], s[3], q[4];
+        for (int j = 0; j < 3; ++j) m[j] = 10.0 * N(g);
+        for (int j = 0; j < 3; ++j) s[j] = std::exp(-5.0 + 5.0 * U(g));
+        double qn = 0.0;
+        for (int j = 0; j < 4; ++j) {
+            q[j] = N(g);
+            qn += q[j] * q[j];
+        }
+        qn = std::sqrt(qn);
+        const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+        const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                             2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                             2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+        const double o = it == 0 ? 1.0 / 255.0 * 1.0001 : (it == 1 ? 1.0 : 1.0 / 255.0 + (1.0 - 1.0 / 255.0) * U(g));
+        float lo[3], hi[3];
+        gaussian_box(m, s, R, o, lo, hi);
+        const double k = std::sqrt(2.0 * std::log(255.0 * o));
+        double M[9], S[9];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) M[a * 3 + b] = R[a * 3 + b] * s[b];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                S[a * 3 + b] = 0.0;
+                for (int c = 0; c < 3; ++c) S[a * 3 + b] += M[a * 3 + c] * M[b * 3 + c];
+            }
+        // points of the ellipsoid: m + M (k u), |u| = 1
+        for (int t = 0; t < 64; ++t) {
+            double u[3], un = 0.0;
+            for (int j = 0; j < 3; ++j) {
+                u[j] = N(g);
+                un += u[j] * u[j];
+            }
+            un = std::sqrt(un);
+            for (int a = 0; a < 3; ++a) {
+                double p = m[a];
+                for (int c = 0; c < 3; ++c) p += M[a * 3 + c] * k * u[c] / un;
+                CHECK((double)lo[a] <= p && p <= (double)hi[a], "box %d misses an ellipsoid point on axis %d", it, a);
+            }
+        }
+        // the extreme points along each axis lie on the ellipsoid and bound the box's width
+        for (int j = 0; j < 3; ++j) {
+            const double ext = k * std::sqrt(S[j * 3 + j]);
+            double pe[3], v[3];
+            for (int a = 0; a < 3; ++a) pe[a] = k * S[a * 3 + j] / std::sqrt(S[j * 3 + j]);
+            // Mahalanobis radius of pe: |diag(1/s) R^T pe|
+            double r2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                v[c] = 0.0;
+                for (int a = 0; a < 3; ++a) v[c] += R[a * 3 + c] * pe[a];
+                v[c] /= s[c];
+                r2 += v[c] * v[c];
+            }
+            CHECK(std::fabs(std::sqrt(r2) - k) <= 1e-9 * (k + 1.0), "extreme point off the ellipsoid");
+            CHECK(std::fabs(pe[j] - ext) <= 1e-9 * (ext + 1e-30), "extreme point extent");
+            const double half = 0.5 * ((double)hi[j] - (double)lo[j]);
+            const double allowed = 1.01 * std::sqrt(k * k + 0.01) / k * ext + 1e-5 * (std::fabs(m[j]) + 1.0) + 1e-6 * (std::fabs(m[j]) + 1.0);
+            CHECK(half <= allowed, "box %d axis %d half-extent %g above %g", it, j, half, allowed);
+        }
+    }
+}
+
 int main() {
+    check_boxes();
     std::mt19937 g(11);
     for (int trial = 0; trial < 40; ++trial) {
         std::uniform_int_distribution<int> nd(5, trial < 10 ? 40 : (trial < 35 ? 5000 : 200000));

@@ -88,7 +88,6 @@ struct Builder {
     int max_depth = 0;
 
     static constexpr int kBins = 128;
-    static constexpr int kSahDepth = 24;  // below it, median splits bound the depth
 
     uint32_t prim(size_t i) const { return (uint32_t)((*keys)[i] & 0xffffffffu); }
     static double area(const float* lo, const float* hi) {
@@ -97,8 +96,12 @@ struct Builder {
     }
 
     // Where to split [lo, hi): binned surface-area heuristic over the centres along their
-    // longest extent (cost = box area x primitives, summed over the two sides), or, deeper than
-    // kSahDepth or when the bins cannot separate the range, the median along that extent.
+    // longest extent (cost = box area x primitives, summed over the two sides), or the median
+    // along that extent when the bins cannot separate the range or when the depth left needs
+    // halving: with lv the halvings that bring the range to kLeafSize, the heuristic is used
+    // only while depth + lv <= kLidarStack - 2, so every node keeps depth + lv <= kLidarStack - 1
+    // (a child of either split has no larger lv; a median child has one less) and leaves stay
+    // within the tracer's stack.
     size_t split(size_t lo, size_t hi, int depth) {
         float cmin[3] = {INFINITY, INFINITY, INFINITY}, cmax[3] = {-INFINITY, -INFINITY, -INFINITY};
         for (size_t i = lo; i < hi; ++i) {
@@ -120,7 +123,9 @@ struct Builder {
                              });
             return half;
         };
-        if (!(ext > 0.0) || depth > kSahDepth) return median();
+        int lv = 0;
+        while (((size_t)kLeafSize << lv) < hi - lo) ++lv;
+        if (!(ext > 0.0) || depth + lv > kLidarStack - 2) return median();
         auto bin = [&](uint32_t p) {
             const int b = (int)(((double)(*cen)[3 * p + ax] - (double)cmin[ax]) / ext * kBins);
             return std::min(kBins - 1, std::max(0, b));

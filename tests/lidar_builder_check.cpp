@@ -5,7 +5,8 @@
 // than 1% wider than the ellipsoid's extreme points m +- k Sigma e_j / sqrt(Sigma_jj)
 // (Sigma = M M^T) plus its stated widening.
 // Trees: for seeded primitive sets (uniform, clustered, on a line, all centres equal; 5 to 200k
-// primitives) every primitive sits in exactly one leaf of at most kLeafSize, the depth-first
+// primitives; and 120 centres at 2^i on a line, which the surface-area splits peel one at a
+// time) every primitive sits in exactly one leaf of at most kLeafSize, the depth-first
 // layout holds (left child next, right child after the left subtree, skip = end of the
 // subtree), every node box holds its primitives' boxes and centres, and the depth stays within
 // the tracer's stack.
@@ -96,22 +97,26 @@ static void check_boxes() {
 int main() {
     check_boxes();
     std::mt19937 g(11);
-    for (int trial = 0; trial < 40; ++trial) {
+    for (int trial = 0; trial < 41; ++trial) {
         std::uniform_int_distribution<int> nd(5, trial < 10 ? 40 : (trial < 35 ? 5000 : 200000));
-        const int m = nd(g);
+        // the last trial: 120 centres at 2^i on a line, where every surface-area split peels off
+        // one primitive, so only the depth rule keeps the tree within the stack
+        const bool chain = trial == 40;
+        const int m = chain ? 120 : nd(g);
         std::normal_distribution<float> N(0.f, 1.f);
         std::uniform_real_distribution<float> U(0.f, 1.f);
         std::vector<float> box, cen;
         for (int i = 0; i < m; ++i) {
             float c[3];
             for (int j = 0; j < 3; ++j) {
-                if (trial % 5 == 0) c[j] = 0.25f;
+                if (chain) c[j] = j == 0 ? std::ldexp(1.0f, i) : 0.f;
+                else if (trial % 5 == 0) c[j] = 0.25f;
                 else if (trial % 5 == 1) c[j] = (i % 3 == 0) ? 10.f + 0.01f * N(g) : N(g);
                 else if (trial % 5 == 2) c[j] = j == 0 ? U(g) * 100.f : 0.f;
                 else c[j] = N(g);
             }
             for (int j = 0; j < 3; ++j) cen.push_back(c[j]);
-            const float e = std::exp(-5.f + 4.f * U(g));
+            const float e = chain ? 1.0f : std::exp(-5.f + 4.f * U(g));
             for (int j = 0; j < 3; ++j) box.push_back(c[j] - e);
             for (int j = 0; j < 3; ++j) box.push_back(c[j] + e);
         }
@@ -125,6 +130,7 @@ int main() {
         B.prim_base = 0;
         B.make(0, m);
         CHECK(B.max_depth <= kLidarStack, "trial %d: depth %d", trial, B.max_depth);
+        if (chain) printf("chain of %d: depth %d\n", m, B.max_depth);
         std::vector<int> seen(m, 0);
         const int nn = (int)B.skip.size();
         std::function<void(int)> walk = [&](int id) {

@@ -31,11 +31,14 @@
 namespace gsr {
 
 constexpr int kLidarK = 16;      // hits per pass
-constexpr int kLeafSize = 6;     // primitives per BVH leaf at most
+constexpr int kLeafSize = 24;    // primitives per BVH leaf at most
+constexpr int kLeafShift = 27;   // a node's reference: leaf count << kLeafShift | first primitive, or
+                                 //   the right child's index (count 0)
+static_assert(kLeafSize < (1 << (32 - kLeafShift)), "a leaf's count fits its field");
 constexpr int kLidarStack = 48;  // traversal stack entries per ray (hierarchy depth at most)
 
 struct LidarScene {
-    float4* bnodes = nullptr;   // 4 per BVH node: (lo, skip), (hi, leaf: count << 28 | first prim, or right
+    float4* bnodes = nullptr;   // 4 per BVH node: (lo, skip), (hi, leaf: count << kLeafShift | first prim, or right
                                 //   child), the box of the centres (clo, -), (chi, -)
     float4* prims = nullptr;    // 4 per primitive: (mu, opacity), (A row 0, A10), (A11, A12, A20, A21), (A22, id)
     int2* roots = nullptr;      // per scene node: (first BVH node, BVH node count)
@@ -319,8 +322,10 @@ std::string lidar_build(const std::vector<Node>& nodes, LidarScene** out) {
         const int node_base = (int)(all_nodes.size() / 4);
         const size_t nb = B.skip.size();
         for (size_t i = 0; i < nb; ++i) {
-            // leaf: count << 28 | first primitive; internal: the right child (the left is next)
-            const int leaf = B.leaf_count[i] ? ((B.leaf_count[i] << 28) | B.leaf_first[i]) : node_base + B.right[i];
+            // leaf: count << kLeafShift | first primitive; internal: the right child (the left is next)
+            const int leaf = B.leaf_count[i]
+                                 ? (int)(((uint32_t)B.leaf_count[i] << kLeafShift) | (uint32_t)B.leaf_first[i])
+                                 : node_base + B.right[i];
             all_nodes.push_back(make_float4(B.nlo[3 * i], B.nlo[3 * i + 1], B.nlo[3 * i + 2], as_float(node_base + B.skip[i])));
             all_nodes.push_back(make_float4(B.nhi[3 * i], B.nhi[3 * i + 1], B.nhi[3 * i + 2], as_float(leaf)));
             all_nodes.push_back(make_float4(B.clo[3 * i], B.clo[3 * i + 1], B.clo[3 * i + 2], 0.0f));
@@ -331,7 +336,8 @@ std::string lidar_build(const std::vector<Node>& nodes, LidarScene** out) {
             for (int j = 0; j < 4; ++j) all_prims.push_back(prim[4 * src + j]);
         }
         roots[k] = make_int2(node_base, (int)nb);
-        if (all_prims.size() / 4 >= (1u << 28)) return "more than 2^28 primitives";
+        if (all_prims.size() / 4 >= (1u << kLeafShift)) return "more than 2^27 primitives";
+        if (all_nodes.size() / 4 >= (1u << kLeafShift)) return "more than 2^27 hierarchy nodes";
     }
     LidarScene* L = new LidarScene();
     L->n_bnodes = all_nodes.size() / 4;
@@ -480,8 +486,8 @@ __global__ __launch_bounds__(64, 3) void k_lidar(const float4* __restrict__ bnod
                 while (true) {
                     const int info = uniform(__float_as_int(bnodes[4 * cur + 1].w));
                     bool pop = false;
-                    if ((uint32_t)info >> 28) {
-                        const int cnt = (int)((uint32_t)info >> 28), p0 = info & 0x0fffffff;
+                    if ((uint32_t)info >> kLeafShift) {
+                        const int cnt = (int)((uint32_t)info >> kLeafShift), p0 = info & ((1 << kLeafShift) - 1);
                         // the leaf's primitives in batches of 64 / rpw: lane h of a ray tests
                         // primitive pb + h against the ray's hits as they stood at the batch's
                         // start, then every lane of the ray inserts the batch's hits in primitive

@@ -342,8 +342,8 @@ typedef struct {
    still give alpha >= 1/255 (3.33 sigma at opacity 1); poses are applied to
    the rays at trace time, so per-step pose updates need no rebuild.  Reads the Gaussian data back to
    the host; synchronous.  Call again after the Gaussian data changes or the
-   scene is recomposed.  Errors: GSR_E_INVALID, GSR_E_NOMEM (also when a
-   node's hierarchy would be deeper than 48 levels), GSR_E_HIP. */
+   scene is recomposed.  Errors: GSR_E_INVALID, GSR_E_NOMEM (also for more
+   than 2^27 Gaussians or hierarchy nodes in a scene), GSR_E_HIP. */
 int gsr_lidar_build(gsr_context* ctx, gsr_scene* scene);
 
 /* Trace rays_per_env rays per environment (rays: DEVICE [n_envs *

@@ -24,6 +24,8 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <system_error>
+#include <thread>
 #include <vector>
 
 #include "gsr_internal.h"
@@ -89,6 +91,8 @@ struct Builder {
     std::vector<int> skip, leaf_first, leaf_count, right;
     size_t prim_base = 0;
     int max_depth = 0;
+    int par_depth = 3;         // the right subtrees of nodes up to this depth are built on
+    size_t par_min = 65536;    // their own threads when they hold at least par_min primitives
 
     static constexpr int kBins = 128;
 
@@ -217,8 +221,30 @@ struct Builder {
             }
         } else {
             const size_t mid = split(lo, hi, depth);
-            const int l = make(lo, mid, depth + 1);
-            const int r = make(mid, hi, depth + 1);
+            int l = -1, r = -1;
+            if (depth <= par_depth && hi - mid >= par_min) {
+                // the two halves partition disjoint ranges of the keys; the right one is built
+                // by its own builder and appended where the serial walk would place it
+                Builder rb;
+                rb.keys = keys;
+                rb.box = box;
+                rb.cen = cen;
+                rb.prim_base = prim_base;
+                rb.par_depth = par_depth;
+                rb.par_min = par_min;
+                try {
+                    std::thread t([&rb, mid, hi, depth] { rb.make(mid, hi, depth + 1); });
+                    l = make(lo, mid, depth + 1);
+                    t.join();
+                    r = append(rb);
+                } catch (const std::system_error&) {
+                    if (l < 0) l = make(lo, mid, depth + 1);  // no thread: the serial walk
+                    r = make(mid, hi, depth + 1);
+                }
+            } else {
+                l = make(lo, mid, depth + 1);
+                r = make(mid, hi, depth + 1);
+            }
             right[id] = r;
             for (int j = 0; j < 3; ++j) {
                 nlo[3 * id + j] = std::min(nlo[3 * l + j], nlo[3 * r + j]);
@@ -229,6 +255,24 @@ struct Builder {
         }
         skip[id] = (int)skip.size();
         return id;
+    }
+
+    // Appends the nodes of a subtree built by another builder (root at its index 0), shifting
+    // its node references by the index its root lands at; returns that index.
+    int append(const Builder& b) {
+        const int off = (int)skip.size();
+        for (size_t i = 0; i < b.skip.size(); ++i) {
+            skip.push_back(b.skip[i] + off);
+            leaf_first.push_back(b.leaf_first[i]);
+            leaf_count.push_back(b.leaf_count[i]);
+            right.push_back(b.leaf_count[i] ? b.right[i] : b.right[i] + off);
+        }
+        nlo.insert(nlo.end(), b.nlo.begin(), b.nlo.end());
+        nhi.insert(nhi.end(), b.nhi.begin(), b.nhi.end());
+        clo.insert(clo.end(), b.clo.begin(), b.clo.end());
+        chi.insert(chi.end(), b.chi.begin(), b.chi.end());
+        max_depth = std::max(max_depth, b.max_depth);
+        return off;
     }
 };
 

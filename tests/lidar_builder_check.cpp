@@ -8,8 +8,9 @@
 // primitives; and 120 centres at 2^i on a line, which the surface-area splits peel one at a
 // time) every primitive sits in exactly one leaf of at most kLeafSize, the depth-first
 // layout holds (left child next, right child after the left subtree, skip = end of the
-// subtree), every node box holds its primitives' boxes and centres, and the depth stays within
-// the tracer's stack.
+// subtree), every node box holds its primitives' boxes and centres, the depth stays within
+// the tracer's stack, and building the top subtrees on their own threads gives the same tree
+// as one thread.
 #include "../paper_2507_21981_amd/csrc/gsr_lidar.hip"
 
 #include <cstdio>
@@ -123,12 +124,26 @@ int main() {
         std::vector<uint64_t> keys(m);
         for (int p = 0; p < m; ++p) keys[p] = ((uint64_t)(g() & 0x3fffffffu) << 32) | (uint64_t)p;
         std::sort(keys.begin(), keys.end());
+        std::vector<uint64_t> keys1 = keys;
         Builder B;
         B.keys = &keys;
         B.box = &box;
         B.cen = &cen;
         B.prim_base = 0;
+        B.par_min = 64;  // threads for the top subtrees of every trial but the smallest
         B.make(0, m);
+        // the same tree when every subtree is built on the calling thread
+        Builder B1;
+        B1.keys = &keys1;
+        B1.box = &box;
+        B1.cen = &cen;
+        B1.prim_base = 0;
+        B1.par_depth = 0;
+        B1.make(0, m);
+        CHECK(keys1 == keys && B1.skip == B.skip && B1.right == B.right && B1.leaf_first == B.leaf_first &&
+                  B1.leaf_count == B.leaf_count && B1.nlo == B.nlo && B1.nhi == B.nhi && B1.clo == B.clo &&
+                  B1.chi == B.chi && B1.max_depth == B.max_depth,
+              "trial %d: the threaded build differs from the serial one", trial);
         CHECK(B.max_depth <= kLidarStack, "trial %d: depth %d", trial, B.max_depth);
         if (chain) printf("chain of %d: depth %d\n", m, B.max_depth);
         std::vector<int> seen(m, 0);
